@@ -1,0 +1,476 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+The oracle (``oracle/lbe_oracle.c``) is the reference of every GPU parity test, so here it
+is tied to things other than itself: the paper's Table 1, closed forms, exactness of
+Gauss quadratures, moment identities of the force matrices, brute-force volumes computed
+with mpmath, and conservation / stationarity invariants of the discrete scheme.
+Citations are to arXiv:2403.15051 (sections and equation labels).
+"""
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build_oracle():
+    oracle.build(force=False)
+
+
+# ------------------------------------------------------------------ Sec. II closed forms
+def test_table1_knudsen_numbers():
+    """Sec. IV Table 1: Kn for C in {4,7,10} x eta0 in {0.01,0.1,0.2}, to the printed digits."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "table1_kn.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 9
+    for C, eta0, kn_txt in rows:
+        kn = oracle.knudsen(float(eta0), float(C))
+        decimals = len(kn_txt.split(".")[1])
+        assert round(kn, decimals) == pytest.approx(float(kn_txt), abs=0.51 * 10 ** -decimals), (C, eta0, kn)
+        # the inverse map recovers C
+        assert oracle.confinement(float(eta0), kn) == pytest.approx(float(C), rel=1e-14)
+
+
+def test_chi_carnahan_starling():
+    """eq. (chi): chi = (P/(n kT) - 1)/(n b) with the Carnahan-Starling compressibility
+    Z = (1 + eta + eta^2 - eta^3)/(1 - eta)^3 and n b = 4 eta."""
+    assert oracle.chi(0.0) == 1.0  # Boltzmann limit, Sec. II
+    assert oracle.chi(0.2) == pytest.approx(225 / 128, rel=1e-15)
+    for eta in np.linspace(0.01, 0.45, 37):
+        Z = (1 + eta + eta**2 - eta**3) / (1 - eta) ** 3
+        assert oracle.chi(eta) == pytest.approx((Z - 1) / (4 * eta), rel=1e-12)
+
+
+def test_prandtl_limits_and_ratio():
+    """eq. (prandtl): Pr -> 2/3 in the dilute limit, and Pr = c_P mu / lambda with the
+    mu, lambda brackets of eq. (viscosity) and mu0/lambda0 = (5/16)/(75/64) = 4/15."""
+    assert oracle.prandtl(0.0) == pytest.approx(2 / 3, rel=1e-15)
+    for x in (0.01, 0.3, 1.0, 2.5):
+        chi = 1.3
+        brho = x / chi
+        mu = 1 / chi + 0.8 * brho + 4 / 25 * (1 + 12 / math.pi) * brho**2 * chi
+        lam = 1 / chi + 1.2 * brho + 9 / 25 * (1 + 32 / (9 * math.pi)) * brho**2 * chi
+        assert oracle.prandtl(x) == pytest.approx(2.5 * (4 / 15) * mu / lam, rel=1e-13)
+
+
+def test_tau_from_physical_units():
+    """eqs. (viscosity), (tau): tau = mu/(n_phys T) in physical units, with
+    mu0 = 5/(16 sigma^2) sqrt(T/pi), n_phys = n * 6 eta0/(pi sigma^3), sigma = L/C."""
+    eta0, kn, L = 0.1, 0.5, 1.0
+    chi0 = oracle.chi(eta0)
+    C = oracle.confinement(eta0, kn)
+    sigma = L / C
+    for n, T, chi in ((1.0, 1.0, chi0), (0.7, 1.4, 1.2), (1.3, 0.8, 1.5)):
+        brho = 4 * eta0 * n
+        mu0 = 5 / (16 * sigma**2) * math.sqrt(T / math.pi)
+        mu = mu0 * (1 / chi + 0.8 * brho + 4 / 25 * (1 + 12 / math.pi) * brho**2 * chi)
+        nphys = n * 6 * eta0 / (math.pi * sigma**3)
+        assert oracle.tau(chi0, kn, L, n, T, chi, brho) == pytest.approx(mu / (nphys * T), rel=1e-13)
+
+
+# ------------------------------------------------------------------ Sec. III quadratures
+def _half_moment(s):
+    # int_0^inf x^s exp(-x^2/2)/sqrt(2 pi) dx
+    return 2 ** (s / 2 - 1) * math.gamma((s + 1) / 2) / math.sqrt(math.pi)
+
+
+@pytest.mark.parametrize("Q", [2, 4, 8, 12, 16, 24])
+def test_half_range_quadrature_exactness(Q):
+    x, w = oracle.quad_half(Q)
+    assert np.all(x[:Q] > 0) and np.all(np.diff(x[:Q]) > 0)
+    assert np.array_equal(x[Q:], -x[:Q]) and np.array_equal(w[Q:], w[:Q])
+    for s in range(2 * Q):
+        exact = _half_moment(s)
+        assert (w[:Q] * x[:Q] ** s).sum() == pytest.approx(exact, rel=2e-14), s
+
+
+def test_half_range_nodes_match_mpmath():
+    """Nodes and Christoffel weights from exact moments + Cholesky at 80 digits."""
+    mp.mp.dps = 80
+    for Q in (4, 8):
+        H = mp.matrix(Q + 1, Q + 1)
+        for i in range(Q + 1):
+            for j in range(Q + 1):
+                k = i + j
+                H[i, j] = mp.mpf(2) ** (mp.mpf(k) / 2 - 1) * mp.gamma(mp.mpf(k + 1) / 2) / mp.sqrt(mp.pi)
+        Linv = mp.inverse(mp.cholesky(H))
+        coeff = [Linv[Q, s] for s in range(Q + 1)]
+        roots = sorted(mp.re(r) for r in mp.polyroots(coeff[::-1], maxsteps=400, extraprec=400))
+        x, w = oracle.quad_half(Q)
+        for i, r in enumerate(roots):
+            hv = [sum(Linv[l, s] * r**s for s in range(l + 1)) for l in range(Q)]
+            wt = 1 / sum(h * h for h in hv)
+            assert x[i] == pytest.approx(float(r), rel=4e-16)
+            assert w[i] == pytest.approx(float(wt), rel=4e-15)
+
+
+@pytest.mark.parametrize("Q", [2, 3, 4, 8, 12])
+def test_full_range_quadrature_exactness(Q):
+    x, w = oracle.quad_full(Q)
+    assert np.allclose(x, -x[::-1], rtol=0, atol=1e-15)
+    for s in range(2 * Q):
+        exact = 0.0 if s % 2 else float(np.prod(np.arange(s - 1, 0, -2))) if s else 1.0
+        scale = (w * np.abs(x) ** s).sum()
+        assert abs((w * x**s).sum() - exact) <= 1e-14 * scale, s
+
+
+def test_half_range_recurrence_identity():
+    """Recurrence coefficients obey a_l + a_{l-1} = (h_l(0)^2 + h_{l-1}(0)^2)/sqrt(2 pi)
+    (the identity behind the printed K^h of eq. (force2)); h_0 = sqrt(2)."""
+    a, b, hc = oracle.half_poly(10)
+    assert hc[0, 0] == pytest.approx(math.sqrt(2), rel=1e-15)
+    for l in range(1, 10):
+        assert a[l] + a[l - 1] == pytest.approx((hc[l, 0] ** 2 + hc[l - 1, 0] ** 2) / math.sqrt(2 * math.pi), rel=1e-13)
+    # leading coefficient ratio a_l = h_{l+1,l+1}/h_{l,l} = 1/b_{l+1}
+    for l in range(9):
+        assert hc[l + 1, l + 1] / hc[l, l] == pytest.approx(1 / b[l + 1], rel=1e-13)
+
+
+# ------------------------------------------------------------------ Sec. III.B force terms
+def _phys_f(rng, x, w):
+    # physically scaled discrete distribution: weight times a random low-order polynomial
+    c = rng.standard_normal(4) * np.array([1, 0.3, 0.1, 0.03])
+    return w * (1.5 + c[0] + c[1] * x + c[2] * x**2 + c[3] * x**3)
+
+
+@pytest.mark.parametrize("Q", [3, 4, 8, 12, 16])
+def test_half_range_force_matrices_moments(Q):
+    """eq. (force1)/(force2): sum_i p_i^s (K1 f)_i = -s sum p^{s-1} f and
+    sum_i p_i^s (K2 f)_i = -s sum p^s f for s = 0..Q-1 (integration by parts)."""
+    rng = np.random.default_rng(Q)
+    x, w = oracle.quad_half(Q)
+    K1 = oracle.kmat_half(Q, 1)
+    K2 = oracle.kmat_half(Q, 2)
+    for _ in range(3):
+        f = _phys_f(rng, x, w)
+        for s in range(Q):
+            scale = (np.abs(x) ** s * np.abs(f)).sum() + (np.abs(x) ** max(s - 1, 0) * np.abs(f)).sum()
+            lhs1 = (x**s * (K1 @ f)).sum()
+            rhs1 = -s * (x ** (s - 1) * f).sum() if s else 0.0
+            lhs2 = (x**s * (K2 @ f)).sum()
+            rhs2 = -s * (x**s * f).sum()
+            assert abs(lhs1 - rhs1) <= 1e-12 * scale, (s, lhs1, rhs1)
+            assert abs(lhs2 - rhs2) <= 1e-12 * scale, (s, lhs2, rhs2)
+    # exact on the discrete rest Maxwellian g = w: K1 g = -p g and K2 g = (1 - p^2) g
+    assert np.allclose(K1 @ w, -x * w, rtol=0, atol=1e-14)
+    assert np.allclose(K2 @ w, (1 - x**2) * w, rtol=0, atol=1e-14)
+
+
+def test_half_range_force_matrix_is_projected_derivative():
+    """K1^h equals the projection of the distributional derivative with the jump at p = 0
+    split equally between the half-spaces, computed here independently in mpmath."""
+    mp.mp.dps = 60
+    Q = 5
+    H = mp.matrix(Q + 1, Q + 1)
+    for i in range(Q + 1):
+        for j in range(Q + 1):
+            k = i + j
+            H[i, j] = mp.mpf(2) ** (mp.mpf(k) / 2 - 1) * mp.gamma(mp.mpf(k + 1) / 2) / mp.sqrt(mp.pi)
+    Linv = mp.inverse(mp.cholesky(H))
+    h = lambda l, t: sum(Linv[l, s] * t**s for s in range(l + 1))
+    dh = lambda l, t: sum(s * Linv[l, s] * t ** (s - 1) for s in range(1, l + 1))
+    x, w = oracle.quad_half(Q)
+    X = [mp.mpf(v) for v in x]
+    W = [mp.mpf(v) for v in w]
+    om0 = 1 / mp.sqrt(2 * mp.pi)
+    n = 2 * Q
+    K = np.zeros((n, n))
+    for i in range(n):
+        si = 1 if x[i] > 0 else -1
+        for j in range(n):
+            sj = 1 if x[j] > 0 else -1
+            val = 0
+            for s in range(Q):
+                inner = -dh(s, abs(X[j])) if si == sj else 0
+                # f(0+) + f(0-) of the projected f from a unit entry at j, times h_s(0)/2
+                f0 = om0 * sum(h(l, 0) * h(l, abs(X[j])) for l in range(Q))
+                inner -= 0.5 * f0 * h(s, 0)
+                val += h(s, abs(X[i])) * inner
+            K[i, j] = float(W[i] * si * val)
+    assert np.allclose(oracle.kmat_half(Q, 1), K, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [3, 4, 8, 12])
+def test_full_range_force_matrices(Q):
+    x, w = oracle.quad_full(Q)
+    K1 = oracle.kmat_full(Q, 1)
+    K2 = oracle.kmat_full(Q, 2)
+    assert np.allclose(K1 @ w, -x * w, atol=1e-15)
+    assert np.allclose(K2 @ w, (1 - x**2) * w, atol=1e-15)
+    rng = np.random.default_rng(1)
+    f = _phys_f(rng, x, w)
+    for s in range(Q):
+        scale = (np.abs(x) ** s * np.abs(f)).sum() + 1
+        assert abs((x**s * (K1 @ f)).sum() + (s * (x ** (s - 1) * f).sum() if s else 0)) <= 1e-12 * scale
+        assert abs((x**s * (K2 @ f)).sum() + s * (x**s * f).sum()) <= 1e-12 * scale
+    # d(f p)/dp = (d/dp) applied to f p, as the He_Q(p_i) = 0 truncation makes exact
+    assert np.allclose(K2, K1 @ np.diag(x), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ Sec. III.C equilibrium
+@pytest.mark.parametrize("Q,N", [(2, 1), (4, 3), (8, 7), (12, 7)])
+def test_full_range_equilibrium_moments(Q, N):
+    """eq. (eq_gak_H): sum_k g_k p_k^s = E[N(u,T)^s] for s <= N."""
+    x, _ = oracle.quad_full(Q)
+    for u, T in ((0.0, 1.0), (0.3, 1.4), (-0.45, 0.7)):
+        g = oracle.geq(False, Q, N, u, T)
+        for s in range(N + 1):
+            exact = sum(math.comb(s, k) * u ** (s - k) * (0 if k % 2 else (T ** (k // 2) * np.prod(np.arange(k - 1, 0, -2)) if k else 1))
+                        for k in range(s + 1))
+            assert (g * x**s).sum() == pytest.approx(exact, rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("Q,N", [(4, 3), (8, 7), (16, 7)])
+def test_half_range_equilibrium_moments(Q, N):
+    """eq. (eq_gak_hh): sum over each half of g_k |p_k|^s equals the half-line moment of the
+    Gaussian N(u,T), M_s^+(u,T) resp. M_s^+(-u,T), for s <= N (computed in mpmath)."""
+    mp.mp.dps = 30
+    x, _ = oracle.quad_half(Q)
+    for u, T in ((0.0, 1.0), (0.3, 1.4), (-0.2, 0.8)):
+        g = oracle.geq(True, Q, N, u, T)
+        for s in range(N + 1):
+            Mp = mp.quad(lambda p: p**s * mp.exp(-(p - u) ** 2 / (2 * T)) / mp.sqrt(2 * mp.pi * T), [0, mp.inf])
+            Mm = mp.quad(lambda p: p**s * mp.exp(-(p + u) ** 2 / (2 * T)) / mp.sqrt(2 * mp.pi * T), [0, mp.inf])
+            assert (g[:Q] * x[:Q] ** s).sum() == pytest.approx(float(Mp), rel=1e-13)
+            assert (g[Q:] * np.abs(x[Q:]) ** s).sum() == pytest.approx(float(Mm), rel=1e-13)
+    # at u = 0, T = 1 the projected half-Gaussian is the weight itself
+    x, w = oracle.quad_half(Q)
+    assert np.allclose(oracle.geq(True, Q, N, 0.0, 1.0), w, rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------ App. A volumes
+def _vol_brute(s, R, b, geom):
+    """Plain mpmath integral: over the ball's radial coordinate rho (distance from the
+    ball centre, in the plane for the cylinder / in space for the sphere)."""
+    mp.mp.dps = 30
+    s, R, b = mp.mpf(s), mp.mpf(R), mp.mpf(b)
+    if geom == "sph":
+        # spherical shells of radius t about the ball centre: area fraction inside R
+        def frac(t):
+            if t == 0:
+                return 1 if b < R else 0
+            c = (R**2 - b**2 - t**2) / (2 * b * t)
+            if c >= 1:
+                return 1
+            if c <= -1:
+                return 0
+            return (1 + c) / 2
+        br = [t for t in (abs(R - b),) if 0 < t < s]
+        return mp.quad(lambda t: 4 * mp.pi * t**2 * frac(t), [0] + br + [s])
+    # cylinder: planar polar coordinates (t, angle) about the ball centre; height 2 sqrt(s^2 - t^2)
+    def ang(t):
+        if t == 0:
+            return 2 * mp.pi if b < R else 0
+        c = (R**2 - b**2 - t**2) / (2 * b * t)
+        if c >= 1:
+            return 2 * mp.pi
+        if c <= -1:
+            return 0
+        return 2 * mp.acos(-c)
+    br = [t for t in (abs(R - b),) if 0 < t < s]
+    return mp.quad(lambda t: 2 * mp.sqrt(s**2 - t**2) * t * ang(t), [0] + br + [s])
+
+
+def _vol_elliptic(r, R, b):
+    """Appendix A elliptic-integral formula (Lamarche-Leroy), evaluated with mpmath;
+    Pi(k, -alpha^2) with -alpha^2 = (B - C)/C in the paper's integrand convention."""
+    mp.mp.dps = 40
+    r, R, b = mp.mpf(r), mp.mpf(R), mp.mpf(b)
+    A = max(r**2, (b + R) ** 2)
+    B = min(r**2, (b + R) ** 2)
+    C = (b - R) ** 2
+    k2 = (B - C) / (A - C)
+    n = (B - C) / C  # integrand 1/(1 + n z^2)
+    s = (b + R) * (b - R)
+    Kk = mp.ellipk(k2)
+    Ek = mp.ellipe(k2)
+    Pk = mp.ellippi(-n, k2)
+    V = (4 * mp.pi / 3) * r**3 * (1 if R > b else 0)
+    V += 4 / (3 * mp.sqrt(A - C)) * (Pk * B**2 * s / C + Kk * (s * (A - 2 * B) + (A - B) * (3 * B - C - 2 * A) / 3)
+                                      + Ek * (A - C) * (-s + (2 * A + 2 * C - 4 * B) / 3))
+    return V
+
+
+def test_volume_sphere_sphere():
+    s = 0.3
+    for R, b in ((1.0, 0.8), (1.0, 1.0), (1.0, 1.2), (1.3, 1.05), (2.0, 1.71), (1.0, 0.69), (1.0, 1.31)):
+        assert oracle.vol_sph(s, R, b) == pytest.approx(float(_vol_brute(s, R, b, "sph")), rel=1e-13, abs=1e-15)
+
+
+def test_volume_cylinder_sphere():
+    s = 0.3
+    for R, b in ((1.0, 0.8), (1.0, 1.0 - 1e-3), (1.0, 1.2), (1.3, 1.05), (2.0, 1.71), (1.0, 0.69), (1.0, 1.31)):
+        vb = float(_vol_brute(s, R, b, "cyl"))
+        assert oracle.vol_cyl(s, R, b) == pytest.approx(vb, rel=2e-14, abs=1e-16)
+        if abs(R - b) < s:  # the paper's elliptic formula, valid while the surfaces cut
+            assert oracle.vol_cyl(s, R, b) == pytest.approx(float(_vol_elliptic(s, R, b)), rel=2e-14)
+
+
+# ------------------------------------------------------------------ Sec. III schemes
+def test_fd4_exact_on_quartics():
+    rng = np.random.default_rng(3)
+    nr, dr = 12, 0.1
+    r = np.arange(nr) * dr
+    c = rng.standard_normal(5)
+    phi = sum(c[k] * r**k for k in range(5))
+    dphi = sum(k * c[k] * r ** (k - 1) for k in range(1, 5))
+    for i in range(nr):
+        assert oracle.fd4(phi, i, dr) == pytest.approx(dphi[i], rel=1e-10, abs=1e-10)
+
+
+def test_fd4_order_four():
+    errs = []
+    for nr in (16, 32, 64):
+        dr = 1.0 / nr
+        r = (np.arange(nr) + 0.5) * dr
+        phi = np.sin(3 * r) + np.exp(r)
+        d = 3 * np.cos(3 * r) + np.exp(r)
+        errs.append(max(abs(oracle.fd4(phi, i, dr) - d[i]) for i in range(nr)))
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12
+
+
+def test_weno5_exact_for_quadratic_cell_averages_and_order5():
+    # cell averages of a quadratic over [k h, (k+1) h]: reconstruction at the right face of the
+    # centre cell is exact whatever the nonlinear weights are
+    h = 0.1
+    c = (0.3, -1.2, 2.0)
+    F = lambda x: c[0] * x + c[1] * x**2 / 2 + c[2] * x**3 / 3
+    avg = [(F((k + 1) * h) - F(k * h)) / h for k in range(5)]
+    exact = c[0] + c[1] * 3 * h + c[2] * (3 * h) ** 2
+    assert oracle.weno5(*avg) == pytest.approx(exact, rel=1e-13)
+    # fifth-order convergence on smooth cell averages
+    errs = []
+    for h in (0.04, 0.02, 0.01):
+        Fs = lambda x: -np.cos(x) / 1.0
+        avg = [(Fs(0.3 + (k + 1) * h) - Fs(0.3 + k * h)) / h for k in range(5)]
+        errs.append(abs(oracle.weno5(*avg) - np.sin(0.3 + 3 * h)))
+    assert errs[0] / errs[1] > 20 and errs[1] / errs[2] > 20
+
+
+# ------------------------------------------------------------------ whole-scheme invariants
+BASE = dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=0.1, t_wall_inner=1.0, t_wall_outer=1.0,
+            eta0=0.05, kn=0.1, nr=32, q_radial=4, q_t1=4, q_t2=4, cfl=0.25)
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_mass_conserved_to_roundoff(geometry):
+    p = dict(BASE, geometry=geometry, t_wall_outer=1.4, eta0=0.15, kn=0.2)
+    if geometry == 1:
+        p["u_wall_inner"] = 0.0
+    s = oracle.Solver(p)
+    m0 = s.mass()
+    s.step(150)
+    assert abs(s.mass() / m0 - 1) < 1e-13
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_uniform_maxwellian_is_stationary_in_the_dilute_limit(geometry):
+    """Free streaming + inertial force terms of the uniform rest Maxwellian cancel exactly
+    (flux form with exact shell measures); with eta0 -> 0 the collision terms vanish."""
+    p = dict(BASE, geometry=geometry, u_wall_inner=0.0, eta0=1e-12)
+    s = oracle.Solver(p)
+    f0 = s.get_f()
+    s.step(50)
+    assert np.abs(s.get_f() - f0).max() <= 4e-16 * np.abs(f0).max()
+
+
+def test_walls_nonorthogonal_terms_vanish_at_rest():
+    p = dict(BASE, u_wall_inner=0.0, eta0=1e-12)
+    s = oracle.Solver(p)
+    t = s.rhs_terms()
+    scale = np.abs(t["A"]).max()
+    assert scale > 1e-3
+    assert np.abs(t["A"] + t["I"]).max() <= 1e-14 * scale
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_collision_conserves_and_relaxes_like_shakhov(geometry):
+    """eq. (j0) with f^S: J0 conserves n, momentum and energy; the traceless stress relaxes at
+    rate 1/tau and the heat flux at Pr/tau (the Shakhov property; N_a >= 7 needed for the
+    heat-flux moment of the equilibrium to be exact)."""
+    p = dict(BASE, geometry=geometry, u_wall_inner=0.0 if geometry else 0.2, t_wall_outer=1.5, eta0=0.2, kn=0.3,
+             nr=16, q_radial=8, q_t1=8, q_t2=8)
+    s = oracle.Solver(p)
+    s.step(40)  # build up non-equilibrium near the walls
+    f = s.get_f()
+    t = s.rhs_terms()
+    m = s.moments()
+    nc = s.node_coeffs()
+    g = s.grid()
+    P0, P1, P2 = np.meshgrid(g["p0"], g["p1"], g["p2"], indexing="ij")
+    P0 = P0.transpose(2, 1, 0).reshape(-1)
+    P1 = P1.transpose(2, 1, 0).reshape(-1)
+    P2 = P2.transpose(2, 1, 0).reshape(-1)
+    for i in range(s.nr):
+        J0 = t["J0"][i]
+        fi = f[i]
+        u = np.array([m["u_r"][i], m["u_t1"][i], m["u_t2"][i]])
+        xi = np.stack([P0 - u[0], P1 - u[1], P2 - u[2]])
+        x2 = (xi**2).sum(0)
+        sc = np.abs(fi).sum()
+        assert abs(J0.sum()) < 1e-12 * sc / nc["tau"][i]
+        for a in range(3):
+            assert abs((J0 * xi[a]).sum()) < 1e-12 * sc / nc["tau"][i]
+        assert abs((J0 * x2).sum()) < 1e-11 * sc / nc["tau"][i]
+        Prt = (fi * xi[0] * xi[1]).sum()
+        assert (J0 * xi[0] * xi[1]).sum() == pytest.approx(-Prt / nc["tau"][i], rel=1e-9, abs=1e-12 * sc)
+        q0 = 0.5 * (fi * x2 * xi[0]).sum()
+        assert 0.5 * (J0 * x2 * xi[0]).sum() == pytest.approx(-nc["Pr"][i] * q0 / nc["tau"][i], rel=1e-9,
+                                                             abs=1e-12 * sc)
+
+
+def test_j1_vanishes_in_the_dilute_limit_and_scales_with_eta0():
+    """eq. (j1): J1 carries the factor b rho = 4 eta0 n."""
+    vals = []
+    for eta0 in (1e-4, 2e-4):
+        p = dict(BASE, u_wall_inner=0.3, t_wall_outer=1.3, eta0=eta0, kn=0.2)
+        s = oracle.Solver(p)
+        s.step(20)
+        vals.append(np.abs(s.rhs_terms()["J1"]).max())
+    assert 1.9 < vals[1] / vals[0] < 2.1
+
+
+def test_averaged_density_weights():
+    """eq. (fm) on cells: rows of nodes farther than sigma from both walls sum to 1; near a
+    wall the row sum is the fraction of the ball inside the computational domain."""
+    for geometry in (0, 1):
+        p = dict(BASE, geometry=geometry, u_wall_inner=0.0, eta0=0.1, kn=0.05, nr=40)
+        s = oracle.Solver(p)
+        W = s.W()
+        info = s.info()
+        g = s.grid()
+        rs = W.sum(1)
+        far = (g["r"] - info["rcl"] > info["sigma"]) & (info["rcr"] - g["r"] > info["sigma"])
+        assert far.any() and (~far).any()
+        assert np.allclose(rs[far], 1.0, atol=1e-14)
+        assert np.all(rs[~far] < 1) and np.all(rs[~far] > 0.45)
+        assert np.all(W >= -1e-15)
+
+
+def test_rest_state_enskog_pressure_balance():
+    """App. B gas at rest: the continuous model has the exact steady state f = n(r) g(0, T_w)
+    with n(1 + 4 eta0 n chi(nbar)) constant (the momentum moment of J1 balances the kinetic
+    pressure gradient).  The discrete steady state shows layering of n near both walls, keeps
+    that product flat to within a small fraction of the layering amplitude, and its
+    deviations of T from T_w and of u_R from 0 are truncation errors that halve when the
+    grid is refined (first-order wall treatment)."""
+    dev = []
+    for nr in (24, 48):
+        p = dict(BASE, u_wall_inner=0.0, eta0=0.2, kn=0.05, nr=nr, q_radial=6, q_t1=6, q_t2=4)
+        s = oracle.Solver(p)
+        rc, steps, res = s.run_to_steady(1e-6, 40000, 200)
+        assert rc == 0
+        m = s.moments()
+        pr = m["n"] * (1 + 4 * 0.2 * m["n"] * m["chi"])
+        prw = m["n"] * (1 - 4 * 0.2 * m["n"] * m["chi"])
+        assert np.ptp(m["n"]) > 0.08
+        assert np.ptp(pr) < 0.1 * np.ptp(m["n"])
+        assert np.ptp(prw) > 0.5 * np.ptp(m["n"])
+        dev.append((np.abs(m["T"] - 1).max(), np.abs(m["u_r"]).max()))
+    assert dev[1][0] < 0.6 * dev[0][0] and dev[1][1] < 0.6 * dev[0][1]
+    assert dev[1][0] < 3e-3 and dev[1][1] < 1e-3
