@@ -1,0 +1,144 @@
+"""Benchmark: site-velocity updates per second of the FDLB solver on one MI355X.
+
+A step is one full TVD-RK3 step (three stages of node kernel + stage kernel) of every instance
+of the workload; inputs are resident in HBM before the timed region.  Prints one JSON line.
+
+Default workload: the seeded parameter sweep of 256 uneven cylindrical Couette/Fourier
+instances (Nr 64..512, half-range orders 4..16), advanced together in one launch per kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def workload(name: str, n_inst: int):
+    from paper_2403_15051_amd import workloads as W
+
+    if name == "sweep":
+        ps, acc = W.sweep(n_inst)
+        desc = (f"parameter sweep: {n_inst} cylindrical Couette/Fourier instances, Nr U{{64..512}}, "
+                f"eta0 U(0.01,0.3), Kn 10^U(-2,1), Q in {{4,8,12,16}}, seed {W.SWEEP_SEED}")
+        return [W.solver_params(p) for p in ps], desc
+    if name == "fourier_sph":
+        return [W.FOURIER_SPH] * n_inst, f"spherical Fourier (Nr 256, 32x12x12 velocities) x {n_inst}"
+    if name == "fourier_cyl":
+        return [W.FOURIER_CYL] * n_inst, f"cylindrical Fourier (Nr 128, 16x8x4 velocities) x {n_inst}"
+    if name == "couette":
+        return [W.COUETTE_SMALL] * n_inst, f"cylindrical Couette (Nr 32, 8x4x2 velocities) x {n_inst}"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(params, budget_s: float):
+    """The oracle, as it stands, on a bounded sample of the same workload (host cores)."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    done = 0
+    t_run = 0.0
+    used = []
+    t_start = time.perf_counter()
+    for p in params:
+        if time.perf_counter() - t_start > budget_s:
+            break
+        s = oracle.Solver(p)
+        nv = s.nv
+        steps = 0
+        t0 = time.perf_counter()
+        while steps < 1000:
+            s.step(1)
+            steps += 1
+            if time.perf_counter() - t0 > budget_s / 4 or time.perf_counter() - t_start > budget_s:
+                break
+        t_run += time.perf_counter() - t0
+        done += p["nr"] * nv * steps
+        used.append((p["nr"], nv, steps))
+    desc = "; ".join(f"Nr {a} x Nv {b}: {c} steps" for a, b, c in used)
+    return {"value": done / t_run, "unit": "site-velocity updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(used)} instance(s) of the workload, FP64 oracle timed per step ({desc})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sweep")
+    ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this solver's batched path runs on a single MI355X; "
+              "instances of a sweep shard across GPUs without communication (not built).", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+
+    from paper_2403_15051_amd import lbe
+
+    torch.cuda.set_device(0)
+    params, desc = workload(args.workload, args.instances if args.workload == "sweep" else max(1, args.instances))
+    print(f"[bench] workload: {desc}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    solver = lbe.Solver(params)
+    t_init = time.perf_counter() - t0
+    infos = [solver.info(k) for k in range(solver.n_inst)]
+    sv = sum(int(i["nr"]) * int(i["nv"]) for i in infos)
+    print(f"[bench] init {t_init:.1f} s, {solver.n_inst} instances, {sv / 1e6:.2f} M site-velocities", file=sys.stderr,
+          flush=True)
+    solver.step(args.warmup)
+    solver.sync()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    solver.timing_start()
+    t0 = time.perf_counter()
+    solver.step(args.steps)
+    solver.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = solver.timing_stop()
+    dt = t1 - t0
+    value = sv * args.steps / dt
+    # algorithmic HBM bytes of one stage launch: stage 1 reads f^n and writes f1 (16 B per
+    # site-velocity in FP64), stages 2 and 3 read f_s and f^n and write (24 B): 64 B per step
+    bytes_per_launch = sv * 64.0 / 3
+    stage_avg_s = tm["stage_ms"] / tm["stage_launches"] / 1e3
+    achieved = bytes_per_launch / stage_avg_s / 1e9
+    line = {
+        "metric": "site-velocity updates/s",
+        "value": value,
+        "unit": "site-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances": solver.n_inst, "site_velocities": sv, "precision": "fp64",
+                   "parallelism": "single GPU, instances batched per launch"},
+        "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "stage_ms_avg": stage_avg_s * 1e3, "node_ms_avg": tm["node_ms"] / max(1, tm["node_launches"]),
+                     "stage_share_of_step": tm["stage_ms"] / (dt * 1e3)},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

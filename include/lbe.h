@@ -1,0 +1,149 @@
+/*
+ * lbe.h - C ABI of the MI355X (gfx950) finite-difference lattice Boltzmann solver for the
+ * simplified Enskog equation in vielbein (cylindrical / spherical) coordinates.
+ *
+ * Method: S. Busuioc, "Mesoscopic Lattice Boltzmann modeling of dense gas flows in
+ * curvilinear geometries", arXiv:2403.15051.  One time step advances the discrete
+ * distribution f(r_i, p_v) on Nr radial cells x a mixed half-range (radial momentum) /
+ * full-range (transverse momenta) Gauss-Hermite velocity set with TVD Runge-Kutta 3:
+ *   df/dt = - (flux-form radial advection, WENO-5)          Sec. II.B/II.C, Sec. III
+ *           - (vielbein inertial terms, K-matrix contractions) Sec. III.B eqs. (force1/2)
+ *           + J0 (Shakhov relaxation) + J1 (first-order Enskog) eqs. (j0), (j1)
+ * with chi evaluated at the ball-averaged density (eqs. (chi_ret), (fm), Appendix A) and
+ * diffuse-reflection walls at R_L + sigma/2 and R_R - sigma/2 (Sec. IV).
+ *
+ * Conventions
+ *   - Units: m = k_B = T_0 = 1; lengths as given (the paper's sigma follows from eta0, Kn
+ *     and L = r_outer - r_inner through Kn = 1/(6 sqrt2 eta0 chi(eta0) C), C = L/sigma);
+ *     the number density is normalised to mean 1 over the computational domain.
+ *   - Velocity index v = i0 + n0 * (i1 + n1 * i2), radial momentum innermost; n0 = 2 Q_r
+ *     (positive nodes ascending, then their mirrors), n1 = Q_t1, n2 = Q_t2 (ascending roots
+ *     of the probabilists' Hermite polynomials).  Cylinder: axes (R, phi, z); sphere:
+ *     (r, theta, phi).
+ *   - f of one instance is stored [nr][nv], velocity innermost (coalesced), in device
+ *     memory inside the caller's workspace.
+ *   - Ownership: the caller owns the device workspace (e.g. a torch uint8 tensor) and the
+ *     HIP stream; the context owns only host-side tables and never frees the workspace.
+ *     Host arrays passed in are copied; host arrays passed out are filled.
+ *   - Errors: every call returns an lbe_status and never throws across the ABI; arguments
+ *     are validated before any device work.  A non-finite f or n <= 0 detected on the
+ *     device latches LBE_ENAN until lbe_set_state replaces the state.
+ *   - Threading: one context per host thread; the library has no global mutable state.
+ */
+#ifndef LBE_H
+#define LBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbe_ctx lbe_ctx; /* opaque */
+
+typedef enum {
+    LBE_OK = 0,
+    LBE_EINVAL = -1,   /* invalid argument (nothing was done) */
+    LBE_ENOMEM = -2,   /* workspace too small / host allocation failed */
+    LBE_EDEVICE = -3,  /* HIP runtime error */
+    LBE_ENOTCONV = -4, /* lbe_run_to_steady reached max_steps before tol */
+    LBE_ENAN = -5,     /* non-finite state or n <= 0 detected (sticky) */
+    LBE_ESTATE = -6    /* call not valid in the current state */
+} lbe_status;
+
+enum { LBE_CYL = 0, LBE_SPH = 1 };
+enum { LBE_FP64 = 0 };
+
+/* Problem statement of one instance (Sec. IV set-up of the paper). */
+typedef struct {
+    int32_t geometry;     /* LBE_CYL (coaxial cylinders) | LBE_SPH (concentric spheres)      */
+    double r_inner;       /* physical wall radii R_L < R_R; L = R_R - R_L                     */
+    double r_outer;
+    double u_wall_inner;  /* tangential (phi) speed of the inner cylinder; must be 0 for LBE_SPH */
+    double t_wall_inner;  /* wall temperatures T_L, T_R (> 0)                                  */
+    double t_wall_outer;
+    double eta0;          /* mean packing fraction, 0 < eta0 < 0.5                            */
+    double kn;            /* Knudsen number on L (> 0); requires C = L/sigma > 1             */
+    int32_t nr;           /* radial cells, >= 8                                               */
+    int32_t q_radial;     /* half-range order Q_r (2 Q_r radial momenta), 2..64              */
+    int32_t q_t1;         /* full-range orders of the transverse axes, 2..64                  */
+    int32_t q_t2;
+    int32_t n_expand[3];  /* equilibrium expansion orders N_a; 0 -> min(7, Q_a - 1); N_a < Q_a */
+    double cfl;           /* dt = cfl * dr / max|p_r|  (> 0)                                  */
+} lbe_params;
+
+/* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),
+ * and the host memory the context will hold (host_bytes).  Host-only; no device work. */
+lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, size_t* host_bytes);
+
+/* Build the tables of every instance on the host (quadratures Sec. III, force matrices
+ * Sec. III.B, averaged-density weights eq. (fm) / Appendix A, wall Maxwellians), upload
+ * them into device_ws (>= lbe_query's device_bytes, 256-byte aligned) on hip_stream
+ * (a hipStream_t, or NULL for the default stream), set every instance to the rest start
+ * (n = 1, u = 0, T = 1) and compute its moments.  *out receives the context. */
+lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t ws_bytes, void* hip_stream,
+                    lbe_ctx** out);
+
+/* Enqueue nsteps full TVD-RK3 steps of every instance on the context's stream (async). */
+lbe_status lbe_step(lbe_ctx* c, int64_t nsteps);
+
+/* Wait for the stream; returns LBE_ENAN if the device flagged a non-finite state. */
+lbe_status lbe_sync(lbe_ctx* c);
+
+/* Macroscopic profiles of instance inst (synchronises): host_out[field * nr + i] for
+ * fields n, u_r, u_t1, u_t2, T, q_r, P_{r t1}, nbar, chi (eqs. (macro_def), (fm), (chi)),
+ * all FP64; cap >= 9 * nr doubles. */
+lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
+
+/* Step every instance until its one-step residual
+ *   rho = max_i max(|dn|, |du_r|, |du_t1|, |du_t2|, |dT|) / dt
+ * (changes over one full step), evaluated after every check_every-th step, is <= tol, or
+ * until max_steps.  Converged instances stop advancing.  steps_out[k], resid_out[k]
+ * (n_inst each, may be NULL) receive per-instance steps taken and the last residual.
+ * Returns LBE_OK when all converged, LBE_ENOTCONV otherwise. */
+lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t check_every, int64_t* steps_out,
+                             double* resid_out);
+
+/* Copy the FP64 state f[nr][nv] of instance inst out / in (synchronises).  Setting the
+ * state clears a latched LBE_ENAN. */
+lbe_status lbe_get_state(lbe_ctx* c, int32_t inst, double* host_f, int64_t cap);
+lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t len);
+
+/* Right-hand side L(f)[nr][nv] of the current state of instance inst (one evaluation of
+ * every term of one RK stage, without updating the state); synchronises. */
+lbe_status lbe_rhs(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
+
+/* Derived scalars of instance inst: [nr, nv, n0, n1, n2, chi0, C, L, sigma, rcl, rcr, dr,
+ * dt, steps, N0, N1, N2]; cap >= 17. */
+lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap);
+
+/* Host-only access to the tables lbe_init builds for one instance (no device needed):
+ *   which = 0: radial nodes+weights [2 n0]; 1: transverse-1 nodes+weights [2 n1];
+ *           2: transverse-2 nodes+weights [2 n2]; 3: K1 (d/dp_r, n0 x n0);
+ *           4: K2 of axis 1 (d(f p)/dp, n1 x n1); 5: K2 of axis 2 (n2 x n2);
+ *           6: dense averaged-density weights W (nr x nr); 7: wall Maxwellians [2 nv];
+ *           8: equilibrium factors at (u, T) = (extra[0], extra[1]) for the three axes
+ *              [n0 + n1 + n2];
+ *           9: cell volume of the ball of radius extra[0] centred at distance extra[2] from
+ *              the axis/origin inside radius extra[1] (geometry of p) [1];
+ *          10: d(f p)/dp matrix of the radial half-range axis (n0 x n0; not used by the
+ *              reduced equations, exported for checks).
+ * len_out receives the number of doubles written (or needed when cap is too small). */
+lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, double* out, int64_t cap,
+                      int64_t* len_out);
+
+/* Per-launch timing with HIP events on the context's stream.  enable = 1 starts recording
+ * (synchronises first); enable = 0 stops, synchronises and fills out[0..3] = [total ms of the
+ * stage-kernel launches, their count, total ms of the node-kernel launches, their count]
+ * (cap >= 4).  Recording adds two events per launch and is meant for benchmarks. */
+lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap);
+
+const char* lbe_last_error(const lbe_ctx* c);
+const char* lbe_status_string(lbe_status s);
+void lbe_free(lbe_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,674 @@
+// C ABI of liblbe (declared in include/lbe.h): context set-up, workspace carving, the RK3
+// driver, the steady-state driver and state access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <atomic>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lbe_internal.h"
+
+namespace lbe {
+hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s);
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s);
+hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
+                               double an, double bs, int mode, hipStream_t s);
+hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
+hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
+hipError_t set_stage_smem_limit(int maxnv);
+}  // namespace lbe
+
+using namespace lbe;
+
+// Largest velocity plane the stage kernel stages in LDS (FP64): 160 KB per CU.
+static constexpr int kMaxPlane = 20000;
+
+struct lbe_ctx {
+    std::vector<InstanceTables> tabs;
+    std::vector<DevInstance> host_desc;
+    DevInstance* dev_desc = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int ninst = 0, maxnr = 0, maxnv = 0;
+    std::vector<int64_t> steps;
+    std::vector<int32_t> active;
+    std::string err;
+    bool nan_latched = false;
+    // optional per-launch timing of the stage and node kernels (lbe_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;       // pool, reused
+    size_t ev_used = 0;
+    std::vector<std::pair<int, int>> stage_ev, node_ev;  // (start, stop) indices into ev
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte layout of one instance inside the workspace.
+struct Layout {
+    size_t f[3], mom, node, geq, snap, resid, flags, nw, scratch;
+    size_t p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
+    size_t total;
+};
+
+Layout make_layout(const InstanceTables& t, size_t base)
+{
+    Layout L;
+    size_t o = base;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t D = sizeof(double);
+    const size_t plane = (size_t)t.nr * t.nv * D;
+    for (int k = 0; k < 3; k++) L.f[k] = take(plane);
+    L.mom = take((size_t)t.nr * kMomStride * D);
+    L.node = take((size_t)t.nr * kNodeStride * D);
+    L.geq = take((size_t)t.nr * (t.n0 + t.n1 + t.n2) * D);
+    L.snap = take((size_t)t.nr * 5 * D);
+    L.resid = take(D);
+    L.flags = take(4 * sizeof(int32_t));
+    L.nw = take(2 * D);
+    L.scratch = take(plane);
+    L.p0 = take(t.n0 * D);
+    L.p1 = take(t.n1 * D);
+    L.p2 = take(t.n2 * D);
+    L.K1 = take(t.K1.size() * D);
+    L.K2a = take(t.K2a.size() * D);
+    L.K2b = take(t.K2b.size() * D);
+    L.w0 = take(t.n0 * D);
+    L.w1 = take(t.n1 * D);
+    L.w2 = take(t.n2 * D);
+    L.poly0 = take(t.ax[0].poly.size() * D);
+    L.poly1 = take(t.ax[1].poly.size() * D);
+    L.poly2 = take(t.ax[2].poly.size() * D);
+    L.qy0 = take(t.ax[0].qy.size() * D);
+    L.qlam0 = take(t.ax[0].qlam.size() * D);
+    L.qh0 = take(t.ax[0].qh.size() * D);
+    L.geo = take(t.geo.size() * D);
+    L.r = take(t.r.size() * D);
+    L.wlo = take(t.wlo.size() * sizeof(int32_t));
+    L.wb = take(t.wb.size() * D);
+    L.gwl = take(t.nv * D);
+    L.gwr = take(t.nv * D);
+    L.total = o;
+    return L;
+}
+
+// Sizes of a layout without building the tables (for lbe_query).
+size_t instance_bytes_estimate(const lbe_params& p)
+{
+    const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
+    const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
+    const int N = kMaxN + 2;
+    size_t b = 4 * align256(nr * nv * D) + align256(nr * kMomStride * D) + align256(nr * kNodeStride * D) +
+               align256(nr * (n0 + n1 + n2) * D) + align256(nr * 5 * D) + 3 * 256;
+    b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
+         align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
+    b += 3 * align256((size_t)std::max(n0, std::max(n1, n2)) * N * D);
+    const double Tmax = std::max(1.0, std::max(p.t_wall_inner, p.t_wall_outer));
+    const size_t M = (size_t)(16 * (std::ceil((3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner)) / 0.75) + 1));
+    b += 2 * align256(M * D) + align256(M * N * D);
+    b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
+    return b + 4096;
+}
+
+lbe_status dev_err(lbe_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LBE_OK;
+    if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBE_EDEVICE;
+}
+
+template <typename T>
+hipError_t put(char* ws, size_t off, const std::vector<T>& v, hipStream_t s)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+lbe_status upload_flags(lbe_ctx* c)
+{
+    for (int k = 0; k < c->ninst; k++) {
+        int32_t fl[4] = {0, c->active[k], 0, 0};
+        hipError_t e = hipMemcpyAsync(c->host_desc[k].flags, fl, sizeof(fl), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return dev_err(c, e, "flag upload");
+    }
+    return dev_err(c, hipStreamSynchronize(c->stream), "flag upload sync");
+}
+
+hipEvent_t next_event(lbe_ctx* c, int* idx)
+{
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev.push_back(e);
+    }
+    *idx = (int)c->ev_used;
+    return c->ev[c->ev_used++];
+}
+
+// Node kernel then stage kernel of one RK stage, with events around each when timing.
+hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int mode)
+{
+    int a = -1, b = -1, x = -1, y = -1;
+    hipError_t e;
+    if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
+    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->stream);
+    if (e != hipSuccess) return e;
+    if (c->timing) {
+        (void)hipEventRecord(next_event(c, &b), c->stream);
+        c->node_ev.push_back({a, b});
+        (void)hipEventRecord(next_event(c, &x), c->stream);
+    }
+    e = launch_stage_kernel(c->dev_desc, c->ninst, c->maxnr, c->maxnv, src, fn, dst, an, bs, mode, c->stream);
+    if (e != hipSuccess) return e;
+    if (c->timing) {
+        (void)hipEventRecord(next_event(c, &y), c->stream);
+        c->stage_ev.push_back({x, y});
+    }
+    return hipSuccess;
+}
+
+// One TVD-RK3 step (Shu-Osher) of every active instance:
+//   f1 = f + dt L(f);  f2 = 3/4 f + 1/4 (f1 + dt L(f1));  f <- 1/3 f + 2/3 (f2 + dt L(f2)).
+lbe_status enqueue_step(lbe_ctx* c)
+{
+    hipError_t e;
+    e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0);
+    if (e != hipSuccess) return dev_err(c, e, "stage 1");
+    e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0);
+    if (e != hipSuccess) return dev_err(c, e, "stage 2");
+    e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0);
+    if (e != hipSuccess) return dev_err(c, e, "stage 3");
+    return LBE_OK;
+}
+
+lbe_status check_nan(lbe_ctx* c)
+{
+    for (int k = 0; k < c->ninst; k++) {
+        int32_t fl = 0;
+        hipError_t e = hipMemcpy(&fl, c->host_desc[k].flags, sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return dev_err(c, e, "flag read");
+        if (fl) {
+            c->nan_latched = true;
+            c->err = "non-finite state or non-positive density/temperature in instance " + std::to_string(k);
+        }
+    }
+    return c->nan_latched ? LBE_ENAN : LBE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbe_status_string(lbe_status s)
+{
+    switch (s) {
+        case LBE_OK: return "ok";
+        case LBE_EINVAL: return "invalid argument";
+        case LBE_ENOMEM: return "out of memory / workspace too small";
+        case LBE_EDEVICE: return "HIP runtime error";
+        case LBE_ENOTCONV: return "not converged";
+        case LBE_ENAN: return "non-finite state";
+        case LBE_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* lbe_last_error(const lbe_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, size_t* host_bytes)
+{
+    if (!p || n_inst < 1) return LBE_EINVAL;
+    size_t total = align256(sizeof(DevInstance) * n_inst);
+    size_t host = sizeof(lbe_ctx);
+    for (int k = 0; k < n_inst; k++) {
+        lbe_params q;
+        lbe_status st = validate_params(p[k], &q, nullptr);
+        if (st != LBE_OK) return st;
+        if ((size_t)2 * q.q_radial * q.q_t1 * q.q_t2 > (size_t)kMaxPlane) return LBE_EINVAL;
+        total += instance_bytes_estimate(q);
+        host += instance_bytes_estimate(q) / 8 + 4096;
+    }
+    if (device_bytes) *device_bytes = total;
+    if (host_bytes) *host_bytes = host;
+    return LBE_OK;
+}
+
+lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t ws_bytes, void* hip_stream,
+                    lbe_ctx** out)
+{
+    if (!p || n_inst < 1 || !out || !device_ws) return LBE_EINVAL;
+    if (((uintptr_t)device_ws & 255) != 0) return LBE_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    lbe_status st = lbe_query(p, n_inst, &need, nullptr);
+    if (st != LBE_OK) return st;
+    if (ws_bytes < need) return LBE_ENOMEM;
+    lbe_ctx* c = new (std::nothrow) lbe_ctx;
+    if (!c) return LBE_ENOMEM;
+    c->ninst = n_inst;
+    c->ws = (char*)device_ws;
+    c->ws_bytes = ws_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    c->tabs.resize(n_inst);
+    c->host_desc.resize(n_inst);
+    c->steps.assign(n_inst, 0);
+    c->active.assign(n_inst, 1);
+    // host tables of the instances, built by a small pool of host threads
+    {
+        std::vector<lbe_status> sts(n_inst, LBE_OK);
+        std::vector<std::string> errs(n_inst);
+        std::atomic<int> next(0);
+        const int nth = std::max(1, std::min<int>(n_inst, (int)std::thread::hardware_concurrency()));
+        auto work = [&]() {
+            for (int k = next++; k < n_inst; k = next++) sts[k] = build_instance(p[k], &c->tabs[k], &errs[k]);
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth; t++) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+        for (int k = 0; k < n_inst; k++) {
+            if (sts[k] != LBE_OK) {
+                st = sts[k];
+                delete c;
+                return st;
+            }
+            c->maxnr = std::max(c->maxnr, c->tabs[k].nr);
+            c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
+        }
+    }
+    size_t off = align256(sizeof(DevInstance) * n_inst);
+    c->dev_desc = (DevInstance*)c->ws;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_inst && e == hipSuccess; k++) {
+        const InstanceTables& t = c->tabs[k];
+        Layout L = make_layout(t, off);
+        if (L.total > ws_bytes) {
+            delete c;
+            return LBE_ENOMEM;
+        }
+        off = L.total;
+        DevInstance& d = c->host_desc[k];
+        std::memset(&d, 0, sizeof(d));
+        d.nr = t.nr;
+        d.nv = t.nv;
+        d.n0 = t.n0;
+        d.n1 = t.n1;
+        d.n2 = t.n2;
+        d.geometry = t.prm.geometry;
+        d.N0 = t.ax[0].N;
+        d.N1 = t.ax[1].N;
+        d.N2 = t.ax[2].N;
+        d.wband = t.wband;
+        d.dt = t.dt;
+        d.dr = t.dr;
+        d.eta0 = t.prm.eta0;
+        d.kn = t.prm.kn;
+        d.chi0 = t.chi0;
+        d.L = t.L;
+        d.gin_l = t.gin_l;
+        d.gin_r = t.gin_r;
+        char* ws = c->ws;
+        for (int b = 0; b < 3; b++) d.f[b] = (double*)(ws + L.f[b]);
+        d.mom = (double*)(ws + L.mom);
+        d.node = (double*)(ws + L.node);
+        d.geq = (double*)(ws + L.geq);
+        d.snap = (double*)(ws + L.snap);
+        d.resid = (double*)(ws + L.resid);
+        d.flags = (int32_t*)(ws + L.flags);
+        d.nw = (double*)(ws + L.nw);
+        d.scratch = (double*)(ws + L.scratch);
+        d.p0 = (const double*)(ws + L.p0);
+        d.p1 = (const double*)(ws + L.p1);
+        d.p2 = (const double*)(ws + L.p2);
+        d.K1 = (const double*)(ws + L.K1);
+        d.K2a = (const double*)(ws + L.K2a);
+        d.K2b = (const double*)(ws + L.K2b);
+        d.w0 = (const double*)(ws + L.w0);
+        d.w1 = (const double*)(ws + L.w1);
+        d.w2 = (const double*)(ws + L.w2);
+        d.poly0 = (const double*)(ws + L.poly0);
+        d.poly1 = (const double*)(ws + L.poly1);
+        d.poly2 = (const double*)(ws + L.poly2);
+        d.qy0 = (const double*)(ws + L.qy0);
+        d.qlam0 = (const double*)(ws + L.qlam0);
+        d.qh0 = (const double*)(ws + L.qh0);
+        d.M0 = (int32_t)t.ax[0].qy.size();
+        d.geo = (const double*)(ws + L.geo);
+        d.r = (const double*)(ws + L.r);
+        d.wlo = (const int32_t*)(ws + L.wlo);
+        d.wb = (const double*)(ws + L.wb);
+        d.gwl = (const double*)(ws + L.gwl);
+        d.gwr = (const double*)(ws + L.gwr);
+        if (e == hipSuccess) e = put(ws, L.p0, t.ax[0].p, c->stream);
+        if (e == hipSuccess) e = put(ws, L.p1, t.ax[1].p, c->stream);
+        if (e == hipSuccess) e = put(ws, L.p2, t.ax[2].p, c->stream);
+        if (e == hipSuccess) e = put(ws, L.K1, t.K1, c->stream);
+        if (e == hipSuccess) e = put(ws, L.K2a, t.K2a, c->stream);
+        if (e == hipSuccess) e = put(ws, L.K2b, t.K2b, c->stream);
+        if (e == hipSuccess) e = put(ws, L.w0, t.ax[0].w, c->stream);
+        if (e == hipSuccess) e = put(ws, L.w1, t.ax[1].w, c->stream);
+        if (e == hipSuccess) e = put(ws, L.w2, t.ax[2].w, c->stream);
+        if (e == hipSuccess) e = put(ws, L.poly0, t.ax[0].poly, c->stream);
+        if (e == hipSuccess) e = put(ws, L.poly1, t.ax[1].poly, c->stream);
+        if (e == hipSuccess) e = put(ws, L.poly2, t.ax[2].poly, c->stream);
+        if (e == hipSuccess) e = put(ws, L.qy0, t.ax[0].qy, c->stream);
+        if (e == hipSuccess) e = put(ws, L.qlam0, t.ax[0].qlam, c->stream);
+        if (e == hipSuccess) e = put(ws, L.qh0, t.ax[0].qh, c->stream);
+        if (e == hipSuccess) e = put(ws, L.geo, t.geo, c->stream);
+        if (e == hipSuccess) e = put(ws, L.r, t.r, c->stream);
+        if (e == hipSuccess) e = put(ws, L.wlo, t.wlo, c->stream);
+        if (e == hipSuccess) e = put(ws, L.wb, t.wb, c->stream);
+        if (e == hipSuccess) e = put(ws, L.gwl, t.gwl, c->stream);
+        if (e == hipSuccess) e = put(ws, L.gwr, t.gwr, c->stream);
+        // rest start: n = 1, u = 0, T = 1
+        if (e == hipSuccess) {
+            std::vector<double> g0(t.n0), g1(t.n1), g2(t.n2), f((size_t)t.nr * t.nv);
+            equilibrium_axis(t.ax[0], 0.0, 1.0, g0.data());
+            equilibrium_axis(t.ax[1], 0.0, 1.0, g1.data());
+            equilibrium_axis(t.ax[2], 0.0, 1.0, g2.data());
+            for (int v = 0; v < t.nv; v++) {
+                const int i0 = v % t.n0, i1 = (v / t.n0) % t.n1, i2 = v / (t.n0 * t.n1);
+                const double val = g0[i0] * g1[i1] * g2[i2];
+                for (int i = 0; i < t.nr; i++) f[(size_t)i * t.nv + v] = val;
+            }
+            e = hipMemcpy(d.f[0], f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->dev_desc, c->host_desc.data(), sizeof(DevInstance) * n_inst, hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = set_stage_smem_limit(c->maxnv);
+    if (e != hipSuccess) {
+        st = dev_err(c, e, "lbe_init upload");
+        delete c;
+        return st;
+    }
+    st = upload_flags(c);
+    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, n_inst, c->maxnr, 0, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "lbe_init sync");
+    if (st != LBE_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBE_OK;
+}
+
+lbe_status lbe_step(lbe_ctx* c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return LBE_EINVAL;
+    if (c->nan_latched) return LBE_ENAN;
+    for (int64_t s = 0; s < nsteps; s++) {
+        lbe_status st = enqueue_step(c);
+        if (st != LBE_OK) return st;
+    }
+    for (int k = 0; k < c->ninst; k++)
+        if (c->active[k]) c->steps[k] += nsteps;
+    return LBE_OK;
+}
+
+lbe_status lbe_sync(lbe_ctx* c)
+{
+    if (!c) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    return check_nan(c);
+}
+
+lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !host_out) return LBE_EINVAL;
+    const DevInstance& d = c->host_desc[inst];
+    if (cap < 9 * (int64_t)d.nr) return LBE_EINVAL;
+    // refresh the node block from the moment sums of the state (one node-kernel pass on f[0])
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    std::vector<int32_t> saved = c->active;
+    std::fill(c->active.begin(), c->active.end(), 0);
+    c->active[inst] = 1;
+    st = upload_flags(c);
+    if (st == LBE_OK)
+        st = dev_err(c, run_stage(c, 0, 0, 0, 0, 0, 1), "moments pass");
+    std::vector<double> node((size_t)d.nr * kNodeStride);
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                       c->stream),
+                     "node read");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    c->active = saved;
+    lbe_status st2 = upload_flags(c);
+    if (st != LBE_OK) return st;
+    if (st2 != LBE_OK) return st2;
+    const int fields[9] = {NF_N, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_P01, NF_NBAR, NF_CHI};
+    for (int fi = 0; fi < 9; fi++)
+        for (int i = 0; i < d.nr; i++) host_out[fi * d.nr + i] = node[(size_t)i * kNodeStride + fields[fi]];
+    return check_nan(c);
+}
+
+lbe_status lbe_rhs(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !host_out) return LBE_EINVAL;
+    const DevInstance& d = c->host_desc[inst];
+    if (cap < (int64_t)d.nr * d.nv) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    std::vector<int32_t> saved = c->active;
+    std::fill(c->active.begin(), c->active.end(), 0);
+    c->active[inst] = 1;
+    st = upload_flags(c);
+    if (st == LBE_OK)
+        st = dev_err(c, run_stage(c, 0, 0, 0, 0, 0, 1), "rhs");
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpyAsync(host_out, d.scratch, (size_t)d.nr * d.nv * sizeof(double),
+                                       hipMemcpyDeviceToHost, c->stream),
+                     "rhs read");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    c->active = saved;
+    lbe_status st2 = upload_flags(c);
+    return st != LBE_OK ? st : st2;
+}
+
+lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t check_every, int64_t* steps_out,
+                             double* resid_out)
+{
+    if (!c || !(tol > 0) || max_steps < 1 || check_every < 1) return LBE_EINVAL;
+    if (c->nan_latched) return LBE_ENAN;
+    std::vector<int64_t> done(c->ninst, 0);
+    std::vector<double> res(c->ninst, -1.0);
+    std::fill(c->active.begin(), c->active.end(), 1);
+    lbe_status st = upload_flags(c);
+    if (st != LBE_OK) return st;
+    int64_t taken = 0;
+    bool all = false;
+    while (taken < max_steps && !all) {
+        int64_t chunk = std::min<int64_t>(check_every, max_steps - taken);
+        for (int64_t s = 0; s < chunk; s++) {
+            if (s == chunk - 1) {
+                st = dev_err(c, launch_snapshot(c->dev_desc, c->ninst, c->stream), "snapshot");
+                if (st != LBE_OK) return st;
+            }
+            st = enqueue_step(c);
+            if (st != LBE_OK) return st;
+        }
+        st = dev_err(c, launch_residual(c->dev_desc, c->ninst, c->stream), "residual");
+        if (st != LBE_OK) return st;
+        st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+        if (st != LBE_OK) return st;
+        st = check_nan(c);
+        if (st != LBE_OK) return st;
+        taken += chunk;
+        all = true;
+        for (int k = 0; k < c->ninst; k++) {
+            if (!c->active[k]) continue;
+            done[k] += chunk;
+            c->steps[k] += chunk;
+            double r = 0;
+            st = dev_err(c, hipMemcpy(&r, c->host_desc[k].resid, sizeof(double), hipMemcpyDeviceToHost), "resid");
+            if (st != LBE_OK) return st;
+            if (chunk == check_every) res[k] = r;
+            if (chunk == check_every && r <= tol)
+                c->active[k] = 0;
+            else
+                all = false;
+        }
+        st = upload_flags(c);
+        if (st != LBE_OK) return st;
+    }
+    std::fill(c->active.begin(), c->active.end(), 1);
+    st = upload_flags(c);
+    if (st != LBE_OK) return st;
+    bool conv = true;
+    for (int k = 0; k < c->ninst; k++) {
+        if (steps_out) steps_out[k] = done[k];
+        if (resid_out) resid_out[k] = res[k];
+        if (!(res[k] >= 0 && res[k] <= tol)) conv = false;
+    }
+    return conv ? LBE_OK : LBE_ENOTCONV;
+}
+
+lbe_status lbe_get_state(lbe_ctx* c, int32_t inst, double* host_f, int64_t cap)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !host_f) return LBE_EINVAL;
+    const DevInstance& d = c->host_desc[inst];
+    if (cap < (int64_t)d.nr * d.nv) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    return dev_err(c, hipMemcpy(host_f, d.f[0], (size_t)d.nr * d.nv * sizeof(double), hipMemcpyDeviceToHost),
+                   "state read");
+}
+
+lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t len)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !host_f) return LBE_EINVAL;
+    const DevInstance& d = c->host_desc[inst];
+    if (len != (int64_t)d.nr * d.nv) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    st = dev_err(c, hipMemcpy(d.f[0], host_f, (size_t)len * sizeof(double), hipMemcpyHostToDevice), "state write");
+    if (st != LBE_OK) return st;
+    c->nan_latched = false;
+    st = upload_flags(c);
+    if (st != LBE_OK) return st;
+    st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
+    if (st != LBE_OK) return st;
+    return dev_err(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !out || cap < 17) return LBE_EINVAL;
+    const InstanceTables& t = c->tabs[inst];
+    const double v[17] = {(double)t.nr, (double)t.nv, (double)t.n0, (double)t.n1, (double)t.n2, t.chi0, t.C, t.L,
+                          t.sigma, t.rcl, t.rcr, t.dr, t.dt, (double)c->steps[inst], (double)t.ax[0].N,
+                          (double)t.ax[1].N, (double)t.ax[2].N};
+    std::memcpy(out, v, sizeof(v));
+    return LBE_OK;
+}
+
+lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, double* out, int64_t cap,
+                      int64_t* len_out)
+{
+    if (!p) return LBE_EINVAL;
+    if (which == 9) {
+        if (!extra) return LBE_EINVAL;
+        if (len_out) *len_out = 1;
+        if (cap < 1 || !out) return LBE_EINVAL;
+        out[0] = p->geometry == LBE_CYL ? ball_in_cylinder(extra[0], extra[1], extra[2])
+                                        : ball_in_sphere(extra[0], extra[1], extra[2]);
+        return LBE_OK;
+    }
+    InstanceTables t;
+    std::string err;
+    lbe_status st = build_instance(*p, &t, &err);
+    if (st != LBE_OK) return st;
+    std::vector<double> v;
+    switch (which) {
+        case 0:
+        case 1:
+        case 2:
+            v = t.ax[which].p;
+            v.insert(v.end(), t.ax[which].w.begin(), t.ax[which].w.end());
+            break;
+        case 3: v = t.K1; break;
+        case 4: v = t.K2a; break;
+        case 5: v = t.K2b; break;
+        case 6:
+            v.assign((size_t)t.nr * t.nr, 0.0);
+            for (int i = 0; i < t.nr; i++)
+                for (int k = 0; k < t.wband; k++) {
+                    const int j = t.wlo[i] + k;
+                    if (j < t.nr) v[(size_t)i * t.nr + j] = t.wb[(size_t)i * t.wband + k];
+                }
+            break;
+        case 7:
+            v = t.gwl;
+            v.insert(v.end(), t.gwr.begin(), t.gwr.end());
+            break;
+        case 8: {
+            if (!extra) return LBE_EINVAL;
+            v.assign(t.n0 + t.n1 + t.n2, 0.0);
+            equilibrium_axis(t.ax[0], extra[0], extra[1], v.data());
+            equilibrium_axis(t.ax[1], extra[0], extra[1], v.data() + t.n0);
+            equilibrium_axis(t.ax[2], extra[0], extra[1], v.data() + t.n0 + t.n1);
+            break;
+        }
+        case 10: v = t.K2r; break;
+        default: return LBE_EINVAL;
+    }
+    if (len_out) *len_out = (int64_t)v.size();
+    if (!out || cap < (int64_t)v.size()) return LBE_EINVAL;
+    std::memcpy(out, v.data(), v.size() * sizeof(double));
+    return LBE_OK;
+}
+
+lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap)
+{
+    if (!c) return LBE_EINVAL;
+    if (enable) {
+        lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+        if (st != LBE_OK) return st;
+        c->ev_used = 0;
+        c->stage_ev.clear();
+        c->node_ev.clear();
+        c->timing = true;
+        return LBE_OK;
+    }
+    c->timing = false;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    if (!out || cap < 4) return LBE_EINVAL;
+    double sums[2] = {0, 0};
+    for (int which = 0; which < 2; which++) {
+        for (auto& pr : which == 0 ? c->stage_ev : c->node_ev) {
+            float ms = 0;
+            st = dev_err(c, hipEventElapsedTime(&ms, c->ev[pr.first], c->ev[pr.second]), "event time");
+            if (st != LBE_OK) return st;
+            sums[which] += ms;
+        }
+    }
+    out[0] = sums[0];
+    out[1] = (double)c->stage_ev.size();
+    out[2] = sums[1];
+    out[3] = (double)c->node_ev.size();
+    return LBE_OK;
+}
+
+void lbe_free(lbe_ctx* c)
+{
+    if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

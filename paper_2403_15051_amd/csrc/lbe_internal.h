@@ -1,0 +1,97 @@
+// Internal declarations of liblbe: host-side tables and the per-instance device descriptor.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbe.h"
+
+namespace lbe {
+
+constexpr int kMaxQ = 64;    // largest quadrature order per axis
+constexpr int kMaxN = 15;    // largest equilibrium expansion order
+constexpr int kNodeStride = 32;  // doubles per node in the node-coefficient block
+constexpr int kMomStride = 16;   // doubles per node in the moment-sum block
+
+// Node-coefficient block layout (doubles, per node), written by the node kernel.
+enum NodeField {
+    NF_N = 0, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_Q1, NF_Q2,
+    NF_TAU, NF_PR, NF_BRHOCHI, NF_D1, NF_D2, NF_DU0, NF_DU1, NF_DU2,
+    NF_NBAR, NF_CHI, NF_P01, NF_SHAK, NF_INVTAU, NF_DIVU, NF_SHEAR01, NF_UPHI_R,
+    NF_UR_R, NF_NW_L, NF_NW_R, NF_COUNT
+};
+
+// Moment-sum block layout (doubles, per node), written by the stage kernel: sums of f times
+// powers of xi' = p - c, where c is the shift stored with the block.
+enum MomField {
+    MF_S0 = 0, MF_S1X, MF_S1Y, MF_S1Z,
+    MF_SXX, MF_SYY, MF_SZZ, MF_SXY, MF_SXZ, MF_SYZ,
+    MF_S3X, MF_S3Y, MF_S3Z, MF_CX, MF_CY, MF_CZ
+};
+
+// Per-axis quadrature and the equilibrium tables of that axis.
+struct AxisTables {
+    bool half = false;
+    int Q = 0;      // order
+    int nq = 0;     // nodes (2Q for half-range)
+    int N = 0;      // expansion order
+    std::vector<double> p, w;    // nodes, weights
+    std::vector<double> poly;    // nq x (N+1): h_l(|p_k|) (half) or He_l(p_k) (full)
+    std::vector<double> qy, qlam;  // half-range: projection rule on [0, Y] (nodes, weights)
+    std::vector<double> qh;        // half-range: h_l(qy_m), M x (N+1)
+};
+
+// Everything the host precomputes for one instance.
+struct InstanceTables {
+    lbe_params prm{};
+    int nr = 0, nv = 0, n0 = 0, n1 = 0, n2 = 0;
+    double chi0 = 0, C = 0, L = 0, sigma = 0, rcl = 0, rcr = 0, dr = 0, dt = 0;
+    AxisTables ax[3];
+    std::vector<double> K1, K2a, K2b;     // force matrices used by the model
+    std::vector<double> K2r;              // d(f p)/dp along the radial axis (tables only)
+    std::vector<double> r, ri;            // node and interface radii
+    std::vector<double> geo;              // per node: adv_l, adv_r, force_fac, 1/r
+    int wband = 0;                        // band width of W
+    std::vector<int32_t> wlo;             // first column of each band row
+    std::vector<double> wb;               // nr x wband band of W
+    std::vector<double> gwl, gwr;         // unit wall Maxwellians [nv]
+    double gin_l = 0, gin_r = 0;          // sum over entering velocities of p_r * g_w
+};
+
+// Device descriptor of one instance (lives in device memory; pointers into the workspace).
+struct DevInstance {
+    int32_t nr, nv, n0, n1, n2, geometry;
+    int32_t N0, N1, N2, wband;
+    double dt, dr, eta0, kn, chi0, L, gin_l, gin_r;
+    double* f[3];           // state buffers [nr][nv]; f[0] holds the state between steps
+    double* mom;            // [nr][kMomStride] moment sums of the last written buffer
+    double* node;           // [nr][kNodeStride] node coefficients of the current stage
+    double* geq;            // [nr][n0 + n1 + n2] equilibrium factors of the current stage
+    const double* p0; const double* p1; const double* p2;
+    const double* K1; const double* K2a; const double* K2b;
+    const double* w0; const double* w1; const double* w2;
+    const double* poly0; const double* poly1; const double* poly2;
+    const double* qy0; const double* qlam0; const double* qh0;  // projection rule, M0 nodes
+    int32_t M0, pad0;
+    const double* geo;      // [nr][4]
+    const double* r;        // [nr]
+    const int32_t* wlo;     // [nr]
+    const double* wb;       // [nr][wband]
+    const double* gwl; const double* gwr;  // [nv]
+    double* snap;           // [nr][5] moments at the start of the last step (residual)
+    double* resid;          // [1] last residual
+    int32_t* flags;         // [4] 0: nan flag, 1: active (1) / frozen (0)
+    double* nw;             // [2] wall densities of the current stage
+    double* scratch;        // [nr][nv] rhs output (lbe_rhs)
+};
+
+// Host table construction (lbe_tables.cpp).
+lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err);
+lbe_status build_instance(const lbe_params& p, InstanceTables* t, std::string* err);
+void equilibrium_axis(const AxisTables& ax, double u, double T, double* g);
+double ball_in_cylinder(double s, double R, double b);
+double ball_in_sphere(double s, double R, double b);
+double chi_cs(double eta);
+
+}  // namespace lbe

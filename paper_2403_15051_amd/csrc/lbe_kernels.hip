@@ -1,0 +1,551 @@
+// Device kernels of liblbe (gfx950, FP64 state).
+//
+// One RK stage of every instance is two launches:
+//   k_node  - per-node coefficients from the moment sums of the stage input (eqs. (macro_def),
+//             (fm), (chi), (viscosity)-(tau), (prandtl)), 4th-order radial gradients (Sec. III),
+//             the discrete equilibrium factors (Sec. III.C) and, in two extra blocks, the wall
+//             densities of diffuse reflection (zero net mass flux through each wall);
+//   k_stage - one workgroup per (node, instance): the node's velocity plane is staged in LDS
+//             for the momentum-derivative contractions (eqs. (force1)/(force2)); each lane
+//             takes velocities v = lane, lane + 256, ... (coalesced), evaluates WENO-5 fluxes
+//             at both faces of the cell (flux form of Sec. II.B/II.C), the inertial terms,
+//             Shakhov + J1 collision (eqs. (j0), (j1)), combines the TVD-RK3 stage and stores,
+//             and the workgroup reduces the moment sums of the stored plane (no atomics, fixed
+//             order, so runs are bitwise reproducible).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lbe_equilibrium.h"
+#include "lbe_internal.h"
+
+namespace lbe {
+
+constexpr int kBlock = 256;
+constexpr int kNodeChunk = 32;  // nodes per node-kernel workgroup
+constexpr int kHalo = 4;        // gradient stencils reach 4 nodes (one-sided at the walls)
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline double weno5(double a, double b, double c, double d, double e)
+{
+    // Jiang-Shu WENO-5 reconstruction at the downwind face of c from (a, b, c, d, e) ordered
+    // along the upwind direction; smoothness indicators with epsilon = 1e-6, power 2.
+    const double eps = 1e-6;
+    const double q0 = (2 * a - 7 * b + 11 * c) * (1.0 / 6);
+    const double q1 = (-b + 5 * c + 2 * d) * (1.0 / 6);
+    const double q2 = (2 * c + 5 * d - e) * (1.0 / 6);
+    const double t0 = a - 2 * b + c, s0 = a - 4 * b + 3 * c;
+    const double t1 = b - 2 * c + d, s1 = b - d;
+    const double t2 = c - 2 * d + e, s2 = 3 * c - 4 * d + e;
+    const double b0 = (13.0 / 12) * t0 * t0 + 0.25 * s0 * s0;
+    const double b1 = (13.0 / 12) * t1 * t1 + 0.25 * s1 * s1;
+    const double b2 = (13.0 / 12) * t2 * t2 + 0.25 * s2 * s2;
+    const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    // alpha_k = d_k / (eps + beta_k)^2, written over the common denominator (e0 e1 e2)^2
+    const double p01 = e0 * e1, p02 = e0 * e2, p12 = e1 * e2;
+    const double a0 = 0.1 * p12 * p12, a1 = 0.6 * p02 * p02, a2 = 0.3 * p01 * p01;
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values per lane over the workgroup; result valid in red[0..NV) after the call.
+template <int NV>
+__device__ inline void block_sum(double* vals, double* red /* LDS, >= NV * 4 */)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        double s = wave_sum(vals[k]);
+        if (lane == 0) red[k * 4 + wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        red[k * 4 + 0] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+    }
+    __syncthreads();
+}
+
+// Conversion of the shifted moment sums of one node to n, u, T, q, P (eqs. (macro_def)).
+struct Macro {
+    double n, u[3], T, q[3], P01;
+};
+
+__device__ inline Macro macro_from_sums(const double* m)
+{
+    Macro o;
+    const double S0 = m[MF_S0];
+    const double S1[3] = {m[MF_S1X], m[MF_S1Y], m[MF_S1Z]};
+    const double S2[3][3] = {{m[MF_SXX], m[MF_SXY], m[MF_SXZ]}, {m[MF_SXY], m[MF_SYY], m[MF_SYZ]},
+                             {m[MF_SXZ], m[MF_SYZ], m[MF_SZZ]}};
+    const double S3[3] = {m[MF_S3X], m[MF_S3Y], m[MF_S3Z]};
+    const double c[3] = {m[MF_CX], m[MF_CY], m[MF_CZ]};
+    o.n = S0;
+    double d[3];
+    for (int a = 0; a < 3; a++) {
+        d[a] = S1[a] / S0;
+        o.u[a] = c[a] + d[a];
+    }
+    const double tr = S2[0][0] + S2[1][1] + S2[2][2];
+    const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    o.T = (tr - (S1[0] * d[0] + S1[1] * d[1] + S1[2] * d[2])) / (3 * S0);
+    for (int a = 0; a < 3; a++) {
+        const double S2d = S2[a][0] * d[0] + S2[a][1] * d[1] + S2[a][2] * d[2];
+        o.q[a] = 0.5 * (S3[a] - d[a] * tr - 2 * S2d + 2 * dd * d[a] * S0);
+    }
+    o.P01 = S2[0][1] - S1[0] * d[1];
+    return o;
+}
+
+__device__ inline double chi_of(double eta) { return (2 - eta) / (2 * (1 - eta) * (1 - eta) * (1 - eta)); }
+
+// Value of f at cell c (c may be a ghost: -2, -1, nr, nr+1) for velocity v with radial
+// momentum pr.  Entering velocities see n_w times the unit wall Maxwellian; leaving ones
+// the quadratic extrapolation of the three nearest cells.
+__device__ inline double fcell(const double* __restrict__ f, int c, int v, int nr, int nv, double pr, double nwl,
+                               double nwr, const double* __restrict__ gwl, const double* __restrict__ gwr)
+{
+    if (c >= 0 && c < nr) return f[(size_t)c * nv + v];
+    if (c < 0) {
+        if (pr > 0) return nwl * gwl[v];
+        const double f0 = f[v], f1 = f[nv + v], f2 = f[2 * (size_t)nv + v];
+        return c == -1 ? 3 * f0 - 3 * f1 + f2 : 6 * f0 - 8 * f1 + 3 * f2;
+    }
+    if (pr < 0) return nwr * gwr[v];
+    const double* fl = f + (size_t)(nr - 1) * nv;
+    const double a = fl[v], b = fl[v - nv], c3 = fl[v - 2 * (size_t)nv];
+    return c == nr ? 3 * a - 3 * b + c3 : 6 * a - 8 * b + 3 * c3;
+}
+
+// ------------------------------------------------------------------ moments of a state
+
+// Moment sums of buffer `buf` with shift 0 (used at start-up and after lbe_set_state).
+__global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restrict__ insts, int buf)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    const int i = blockIdx.x;
+    if (i >= I.nr) return;
+    __shared__ double red[16 * 4];
+    const double* fi = I.f[buf] + (size_t)i * I.nv;
+    double acc[13];
+#pragma unroll
+    for (int k = 0; k < 13; k++) acc[k] = 0;
+    for (int v = threadIdx.x; v < I.nv; v += kBlock) {
+        const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
+        const double x = I.p0[i0], y = I.p1[i1], z = I.p2[i2], fv = fi[v];
+        const double x2 = x * x + y * y + z * z;
+        acc[MF_S0] += fv;
+        acc[MF_S1X] += fv * x;
+        acc[MF_S1Y] += fv * y;
+        acc[MF_S1Z] += fv * z;
+        acc[MF_SXX] += fv * x * x;
+        acc[MF_SYY] += fv * y * y;
+        acc[MF_SZZ] += fv * z * z;
+        acc[MF_SXY] += fv * x * y;
+        acc[MF_SXZ] += fv * x * z;
+        acc[MF_SYZ] += fv * y * z;
+        acc[MF_S3X] += fv * x2 * x;
+        acc[MF_S3Y] += fv * x2 * y;
+        acc[MF_S3Z] += fv * x2 * z;
+    }
+    block_sum<13>(acc, red);
+    if (threadIdx.x < 16) {
+        const int k = threadIdx.x;
+        I.mom[(size_t)i * kMomStride + k] = k < 13 ? red[k * 4] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ node kernel
+
+__global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, int src)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    const int nr = I.nr;
+    const int nchunks = (nr + kNodeChunk - 1) / kNodeChunk;
+    const int bx = blockIdx.x;
+    __shared__ double red[16 * 4];
+    if (bx >= nchunks + 2) return;
+    const double* f = I.f[src];
+
+    if (bx >= nchunks) {
+        // Wall density of diffuse reflection: n_w = - sum_{leaving} p_r f_hat / sum_{entering} p_r g_w.
+        const int left = bx == nchunks;
+        double acc[1] = {0};
+        for (int v = threadIdx.x; v < I.nv; v += kBlock) {
+            const double pr = I.p0[v % I.n0];
+            if (left && pr < 0) {
+                const double f0 = f[v], f1 = f[I.nv + v], f2 = f[2 * (size_t)I.nv + v];
+                const double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
+                acc[0] += pr * weno5(f2, f1, f0, gm1, gm2);
+            } else if (!left && pr > 0) {
+                const double* fl = f + (size_t)(nr - 1) * I.nv;
+                const double a = fl[v], b = fl[v - I.nv], c = fl[v - 2 * (size_t)I.nv];
+                const double gp1 = 3 * a - 3 * b + c, gp2 = 6 * a - 8 * b + 3 * c;
+                acc[0] += pr * weno5(c, b, a, gp1, gp2);
+            }
+        }
+        block_sum<1>(acc, red);
+        if (threadIdx.x == 0) I.nw[left ? 0 : 1] = -red[0] / (left ? I.gin_l : I.gin_r);
+        return;
+    }
+
+    // Node chunk [c0, c1) with a halo of kHalo nodes for the gradient stencils.
+    const int c0 = bx * kNodeChunk, c1 = min(nr, c0 + kNodeChunk);
+    const int h0 = max(0, c0 - kHalo), h1 = min(nr, c1 + kHalo);
+    const int nh = h1 - h0;
+    __shared__ double sn[kNodeChunk + 2 * kHalo], sT[kNodeChunk + 2 * kHalo], su[3][kNodeChunk + 2 * kHalo];
+    __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo],
+        snbar[kNodeChunk + 2 * kHalo];
+    __shared__ Macro smac[kNodeChunk];
+    __shared__ double sI[kNodeChunk][2][kMaxN + 1], sc1[kNodeChunk][kMaxN + 2], sc2[kNodeChunk][kMaxN + 2];
+    __shared__ double sPart[kNodeChunk][2][4][kMaxN + 1];
+    for (int k = threadIdx.x; k < nh; k += kBlock) {
+        const int j = h0 + k;
+        const Macro m = macro_from_sums(I.mom + (size_t)j * kMomStride);
+        // averaged density, eq. (fm): nbar_j = sum_k W_jk n_k (band)
+        const int lo = I.wlo[j];
+        const double* wrow = I.wb + (size_t)j * I.wband;
+        double nb = 0;
+        for (int k2 = 0; k2 < I.wband; k2++) {
+            const int col = lo + k2;
+            if (col < nr) nb += wrow[k2] * I.mom[(size_t)col * kMomStride + MF_S0];
+        }
+        const double chi = chi_of(I.eta0 * nb);
+        sn[k] = m.n;
+        sT[k] = m.T;
+        for (int a = 0; a < 3; a++) su[a][k] = m.u[a];
+        schi[k] = chi;
+        snbar[k] = nb;
+        sG1[k] = log(m.n * m.n * chi * m.T);
+        sG2[k] = log(m.T);
+        if (j >= c0 && j < c1) smac[j - c0] = m;
+    }
+    __syncthreads();
+    const double inv12dr = 1.0 / (12 * I.dr);
+    const double kSqrt2Pi5_16 = 0.78332038861223477406;  // 5 sqrt(2 pi) / 16
+    const double kC1 = 4.0 / 25 * (1 + 12 / M_PI);
+    const double kD1 = 9.0 / 25 * (1 + 32 / (9 * M_PI));
+    for (int k = threadIdx.x; k < c1 - c0; k += kBlock) {
+        const int i = c0 + k;
+        const int li = i - h0;
+        const Macro& m = smac[k];
+        // gradient stencils read local arrays shifted so that index = global node - h0
+        auto g = [&](const double* arr) {
+            if (i == 0 || i == 1 || i == nr - 1 || i == nr - 2) {
+                double tmp[5];
+                const int base = (i <= 1) ? 0 : nr - 5;
+                for (int t = 0; t < 5; t++) tmp[t] = arr[base + t - h0];
+                if (i == 0) return (-25 * tmp[0] + 48 * tmp[1] - 36 * tmp[2] + 16 * tmp[3] - 3 * tmp[4]) * inv12dr;
+                if (i == 1) return (-3 * tmp[0] - 10 * tmp[1] + 18 * tmp[2] - 6 * tmp[3] + tmp[4]) * inv12dr;
+                if (i == nr - 1) return (25 * tmp[4] - 48 * tmp[3] + 36 * tmp[2] - 16 * tmp[1] + 3 * tmp[0]) * inv12dr;
+                return (3 * tmp[4] + 10 * tmp[3] - 18 * tmp[2] + 6 * tmp[1] - tmp[0]) * inv12dr;
+            }
+            return (arr[li - 2] - 8 * arr[li - 1] + 8 * arr[li + 1] - arr[li + 2]) * inv12dr;
+        };
+        const double D1 = g(sG1), D2 = g(sG2), du0 = g(su[0]), du1 = g(su[1]), du2 = g(su[2]);
+        const double n = m.n, T = m.T, chi = schi[li];
+        const double brho = 4 * I.eta0 * n;
+        const double brhochi = brho * chi;
+        const double bracket = 1 / chi + 0.8 * brho + kC1 * brho * brho * chi;
+        const double tau = kSqrt2Pi5_16 * I.chi0 * I.kn * I.L * bracket / (n * sqrt(T));
+        const double x = brhochi;
+        const double Pr = (2.0 / 3) * (1 + 0.8 * x + kC1 * x * x) / (1 + 1.2 * x + kD1 * x * x);
+        const double invr = I.geo[4 * i + 3];
+        double* nd = I.node + (size_t)i * kNodeStride;
+        nd[NF_N] = n;
+        nd[NF_U0] = m.u[0];
+        nd[NF_U1] = m.u[1];
+        nd[NF_U2] = m.u[2];
+        nd[NF_T] = T;
+        nd[NF_Q0] = m.q[0];
+        nd[NF_Q1] = m.q[1];
+        nd[NF_Q2] = m.q[2];
+        nd[NF_TAU] = tau;
+        nd[NF_PR] = Pr;
+        nd[NF_BRHOCHI] = brhochi;
+        nd[NF_D1] = D1;
+        nd[NF_D2] = D2;
+        nd[NF_DU0] = du0;
+        nd[NF_DU1] = du1;
+        nd[NF_DU2] = du2;
+        nd[NF_NBAR] = snbar[li];
+        nd[NF_CHI] = chi;
+        nd[NF_P01] = m.P01;
+        nd[NF_SHAK] = (1 - Pr) / (n * T * T);
+        nd[NF_INVTAU] = 1 / tau;
+        // divergence and the covariant shear pieces of zeta zeta : grad u (reading of eq. (j1))
+        if (I.geometry == LBE_CYL) {
+            nd[NF_DIVU] = du0 + m.u[0] * invr;
+            nd[NF_SHEAR01] = du1 - m.u[1] * invr;
+        } else {
+            nd[NF_DIVU] = du0 + 2 * m.u[0] * invr;
+            nd[NF_SHEAR01] = 0;
+        }
+        nd[NF_UR_R] = m.u[0] * invr;
+        if (!(n > 0) || !(T > 0) || !isfinite(n) || !isfinite(T)) I.flags[0] = 1;
+        // equilibrium coefficients of the full-range axes
+        full_coeffs<kMaxN>(m.u[1], T, I.N1, sc1[k]);
+        full_coeffs<kMaxN>(m.u[2], T, I.N2, sc2[k]);
+    }
+    // half-range projections: lanes = (node, side, quarter of the quadrature nodes)
+    {
+        const int k = threadIdx.x >> 3, side = (threadIdx.x >> 2) & 1, part = threadIdx.x & 3;
+        if (k < c1 - c0) {
+            const int M = I.M0, m0 = part * M / 4, m1 = (part + 1) * M / 4;
+            const double uu = side ? -smac[k].u[0] : smac[k].u[0];
+            half_projection_part(uu, smac[k].T, I.N0, m0, m1, I.qy0, I.qlam0, I.qh0, sPart[k][side][part]);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (c1 - c0) * 2 * (I.N0 + 1); t += kBlock) {
+        const int l = t % (I.N0 + 1), side = (t / (I.N0 + 1)) & 1, k = t / (2 * (I.N0 + 1));
+        sI[k][side][l] = ((sPart[k][side][0][l] + sPart[k][side][1][l]) + sPart[k][side][2][l]) + sPart[k][side][3][l];
+    }
+    __syncthreads();
+    // equilibrium factors g_R, g_1, g_2 of every node of the chunk
+    const int ng = I.n0 + I.n1 + I.n2;
+    for (int t = threadIdx.x; t < (c1 - c0) * ng; t += kBlock) {
+        const int k = t / ng, e = t % ng, i = c0 + k;
+        double val;
+        if (e < I.n0) {
+            const int N = I.N0;
+            const double* I_ = sI[k][I.p0[e] > 0 ? 0 : 1];
+            double acc = 0;
+            for (int l = 0; l <= N; l++) acc += I_[l] * I.poly0[e * (N + 1) + l];
+            val = I.w0[e] * acc;
+        } else if (e < I.n0 + I.n1) {
+            const int kk = e - I.n0, N = I.N1;
+            double acc = 0;
+            for (int l = 0; l <= N; l++) acc += sc1[k][l] * I.poly1[kk * (N + 1) + l];
+            val = I.w1[kk] * acc;
+        } else {
+            const int kk = e - I.n0 - I.n1, N = I.N2;
+            double acc = 0;
+            for (int l = 0; l <= N; l++) acc += sc2[k][l] * I.poly2[kk * (N + 1) + l];
+            val = I.w2[kk] * acc;
+        }
+        I.geq[(size_t)i * ng + e] = val;
+    }
+}
+
+// ------------------------------------------------------------------ stage kernel
+
+// mode 0: out = an * f[fn] + bs * (f[src] + dt L(f[src])) stored in f[dst], with moment sums;
+// mode 1: L(f[src]) stored in scratch (no state change).
+__global__ void __launch_bounds__(kBlock) k_stage(const DevInstance* __restrict__ insts, int src, int fn, int dst,
+                                                  double an, double bs, int mode)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    const int i = blockIdx.x;
+    const int nr = I.nr, nv = I.nv, n0 = I.n0, n1 = I.n1, n2 = I.n2;
+    if (i >= nr) return;
+    extern __shared__ double plane[];  // nv doubles
+    __shared__ double red[16 * 4];
+    __shared__ double snd[kNodeStride];
+    const double* __restrict__ f = I.f[src];
+    const double* fi = f + (size_t)i * nv;
+    for (int v = threadIdx.x; v < nv; v += kBlock) plane[v] = fi[v];
+    if (threadIdx.x < kNodeStride) snd[threadIdx.x] = I.node[(size_t)i * kNodeStride + threadIdx.x];
+    __syncthreads();
+
+    const int ng = n0 + n1 + n2;
+    const double* gR = I.geq + (size_t)i * ng;
+    const double* g1 = gR + n0;
+    const double* g2 = g1 + n1;
+    const double n = snd[NF_N], u0 = snd[NF_U0], u1 = snd[NF_U1], u2 = snd[NF_U2], T = snd[NF_T];
+    const double q0 = snd[NF_Q0], q1 = snd[NF_Q1], q2 = snd[NF_Q2];
+    const double invtau = snd[NF_INVTAU], shak = snd[NF_SHAK], brhochi = snd[NF_BRHOCHI];
+    const double D1 = snd[NF_D1], D2 = snd[NF_D2], du0 = snd[NF_DU0], du2 = snd[NF_DU2];
+    const double divu = snd[NF_DIVU], sh01 = snd[NF_SHEAR01], urr = snd[NF_UR_R];
+    const double inv2T = 1 / (2 * T), inv5T = 1 / (5 * T);
+    const double adv_l = I.geo[4 * i + 0], adv_r = I.geo[4 * i + 1], ffac = I.geo[4 * i + 2];
+    const double nwl = I.nw[0], nwr = I.nw[1];
+    const double dt = I.dt;
+    const bool cyl = I.geometry == LBE_CYL;
+    const double* fnp = I.f[fn] + (size_t)i * nv;
+    double* out = (mode == 0) ? I.f[dst] + (size_t)i * nv : I.scratch + (size_t)i * nv;
+
+    double acc[13];
+#pragma unroll
+    for (int k = 0; k < 13; k++) acc[k] = 0;
+
+    for (int v = threadIdx.x; v < nv; v += kBlock) {
+        const int i0 = v % n0, rest = v / n0, i1 = rest % n1, i2 = rest / n1;
+        const double pr = I.p0[i0], py = I.p1[i1], pz = I.p2[i2];
+        // ---- advection: flux form with WENO-5 face values, upwind by the sign of p_r
+        double Fl, Fr;
+        if (pr > 0) {
+            double c[6];  // cells i-3 .. i+2
+            for (int t = (i == 0 ? 1 : 0); t < 6; t++)
+                c[t] = fcell(f, i - 3 + t, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
+            Fl = (i == 0) ? pr * nwl * I.gwl[v] : pr * weno5(c[0], c[1], c[2], c[3], c[4]);
+            Fr = pr * weno5(c[1], c[2], c[3], c[4], c[5]);
+        } else {
+            double c[6];  // cells i-2 .. i+3
+            const int tmax = (i == nr - 1) ? 5 : 6;
+            for (int t = 0; t < tmax; t++) c[t] = fcell(f, i - 2 + t, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
+            Fl = pr * weno5(c[4], c[3], c[2], c[1], c[0]);
+            Fr = (i == nr - 1) ? pr * nwr * I.gwr[v] : pr * weno5(c[5], c[4], c[3], c[2], c[1]);
+        }
+        const double A = adv_r * Fr - adv_l * Fl;
+        // ---- inertial terms (momentum-derivative contractions on the LDS plane)
+        double d0 = 0, d1 = 0, d2 = 0;
+        {
+            const double* K = I.K1 + i0 * n0;
+            const double* col = plane + n0 * (i1 + n1 * i2);
+            for (int k = 0; k < n0; k++) d0 += K[k] * col[k];
+            const double* Ka = I.K2a + i1 * n1;
+            const double* rowa = plane + i0 + n0 * n1 * i2;
+            for (int k = 0; k < n1; k++) d1 += Ka[k] * rowa[n0 * k];
+            if (!cyl) {
+                const double* Kb = I.K2b + i2 * n2;
+                const double* rowb = plane + i0 + n0 * i1;
+                for (int k = 0; k < n2; k++) d2 += Kb[k] * rowb[n0 * n1 * k];
+            }
+        }
+        const double Iv = cyl ? ffac * (py * py * d0 - pr * d1) : ffac * ((py * py + pz * pz) * d0 - pr * (d1 + d2));
+        // ---- collision: Shakhov J0 and J1[f^MB] on the discrete equilibrium
+        const double fmb = n * gR[i0] * g1[i1] * g2[i2];
+        const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
+        const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
+        const double xq = x0 * q0 + x1 * q1 + x2 * q2;
+        const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
+        const double z2 = xi2 * inv2T;
+        const double zzgu = cyl ? (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T
+                                : (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T;
+        const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
+        const double fv = plane[v];
+        const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
+        if (mode == 1) {
+            out[v] = L;
+            continue;
+        }
+        const double o = an * fnp[v] + bs * (fv + dt * L);
+        out[v] = o;
+        // moment sums of the stored value, shifted by the current velocity
+        const double y0 = pr - u0, y1 = py - u1, y2 = pz - u2;
+        const double y2s = y0 * y0 + y1 * y1 + y2 * y2;
+        acc[MF_S0] += o;
+        acc[MF_S1X] += o * y0;
+        acc[MF_S1Y] += o * y1;
+        acc[MF_S1Z] += o * y2;
+        acc[MF_SXX] += o * y0 * y0;
+        acc[MF_SYY] += o * y1 * y1;
+        acc[MF_SZZ] += o * y2 * y2;
+        acc[MF_SXY] += o * y0 * y1;
+        acc[MF_SXZ] += o * y0 * y2;
+        acc[MF_SYZ] += o * y1 * y2;
+        acc[MF_S3X] += o * y2s * y0;
+        acc[MF_S3Y] += o * y2s * y1;
+        acc[MF_S3Z] += o * y2s * y2;
+    }
+    if (mode == 1) return;
+    block_sum<13>(acc, red);
+    if (threadIdx.x < 16) {
+        const int k = threadIdx.x;
+        double val;
+        if (k < 13)
+            val = red[k * 4];
+        else
+            val = (k == MF_CX) ? u0 : (k == MF_CY) ? u1 : u2;
+        I.mom[(size_t)i * kMomStride + k] = val;
+    }
+}
+
+// ------------------------------------------------------------------ residual
+
+// Snapshot n, u, T (from the current moment sums) before a checked step.
+__global__ void __launch_bounds__(kBlock) k_snapshot(const DevInstance* __restrict__ insts)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        const Macro m = macro_from_sums(I.mom + (size_t)i * kMomStride);
+        double* s = I.snap + (size_t)i * 5;
+        s[0] = m.n;
+        s[1] = m.u[0];
+        s[2] = m.u[1];
+        s[3] = m.u[2];
+        s[4] = m.T;
+    }
+}
+
+// rho = max_i max(|dn|, |du_r|, |du_1|, |du_2|, |dT|) / dt over the last step.
+__global__ void __launch_bounds__(kBlock) k_residual(const DevInstance* __restrict__ insts)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    __shared__ double smax[kBlock];
+    double r = 0;
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        const Macro m = macro_from_sums(I.mom + (size_t)i * kMomStride);
+        const double* s = I.snap + (size_t)i * 5;
+        const double d[5] = {m.n - s[0], m.u[0] - s[1], m.u[1] - s[2], m.u[2] - s[3], m.T - s[4]};
+        for (int k = 0; k < 5; k++) {
+            const double a = fabs(d[k]);
+            if (a > r || a != a) r = a;
+        }
+    }
+    smax[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = smax[threadIdx.x + w];
+            if (o > smax[threadIdx.x] || o != o) smax[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) I.resid[0] = smax[0] / I.dt;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_moments, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s)
+{
+    const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
+    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
+                               double an, double bs, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage, dim3(maxnr, ninst), dim3(kBlock), (size_t)maxnv * sizeof(double), s, d, src, fn, dst,
+                       an, bs, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_snapshot, dim3(1, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual, dim3(1, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t set_stage_smem_limit(int maxnv)
+{
+    return hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               maxnv * (int)sizeof(double));
+}
+
+}  // namespace lbe

@@ -1,0 +1,639 @@
+// Host precompute of liblbe: quadratures, force matrices, averaged-density weights, wall
+// Maxwellians and the derived scalars of one instance (arXiv:2403.15051, Secs. II-IV,
+// Appendix A).  Everything here runs once per lbe_init, in long double where accuracy
+// matters, and is uploaded to the device.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbe_equilibrium.h"
+#include "lbe_internal.h"
+
+namespace lbe {
+
+typedef long double ld;
+static const ld kPi = 3.141592653589793238462643383279502884L;
+
+// ------------------------------------------------------------------ closed forms (Sec. II)
+
+// Carnahan-Starling contact value, eq. (chi).
+double chi_cs(double eta) { return (2 - eta) / (2 * (1 - eta) * (1 - eta) * (1 - eta)); }
+
+// ------------------------------------------------------------------ quadratures (Sec. III)
+
+// Gauss-Legendre rule on [-1, 1] in long double (Newton on P_n).
+static void gauss_legendre(int n, std::vector<ld>& x, std::vector<ld>& w)
+{
+    x.assign(n, 0);
+    w.assign(n, 0);
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        ld z = cosl(kPi * (i + 0.75L) / (n + 0.5L)), dp = 0;
+        for (int it = 0; it < 100; it++) {
+            ld p0 = 1, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            ld dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2 / ((1 - z * z) * dp * dp);
+    }
+}
+
+// Recurrence x h_l = b_{l+1} h_{l+1} + a_l h_l + b_l h_{l-1} of the polynomials orthonormal on
+// [0, inf) with weight exp(-x^2/2)/sqrt(2 pi) (the half-range Hermite polynomials of the
+// paper), by the discretised Stieltjes procedure (Gautschi): the measure is replaced by a
+// composite 20-point Gauss-Legendre rule on panels of width 1/2.  Returns a[0..n-1],
+// b[0..n] with b[0] = mu_0 = 1/2.
+static void half_recurrence(int n, std::vector<ld>& a, std::vector<ld>& b)
+{
+    std::vector<ld> gx, gw;
+    const int P = 20;
+    gauss_legendre(P, gx, gw);
+    const ld X = sqrtl((ld)(2 * n + 1)) + 15;
+    const ld h = 0.5L;
+    const int npan = (int)ceill(X / h);
+    std::vector<ld> y, lam;
+    for (int p = 0; p < npan; p++)
+        for (int j = 0; j < P; j++) {
+            ld t = p * h + h * (gx[j] + 1) / 2;
+            y.push_back(t);
+            lam.push_back(gw[j] * h / 2 * expl(-t * t / 2) / sqrtl(2 * kPi));
+        }
+    const size_t M = y.size();
+    // orthonormal vectors on the discrete measure (stable form of Stieltjes)
+    std::vector<ld> prev(M, 0), cur(M), nxt(M);
+    ld mu0 = 0;
+    for (size_t m = 0; m < M; m++) mu0 += lam[m];
+    for (size_t m = 0; m < M; m++) cur[m] = 1 / sqrtl(mu0);
+    a.assign(n, 0);
+    b.assign(n + 1, 0);
+    b[0] = mu0;
+    for (int k = 0; k < n; k++) {
+        ld ak = 0;
+        for (size_t m = 0; m < M; m++) ak += lam[m] * y[m] * cur[m] * cur[m];
+        a[k] = ak;
+        ld nn = 0;
+        for (size_t m = 0; m < M; m++) {
+            nxt[m] = (y[m] - ak) * cur[m] - (k > 0 ? b[k] : 0) * prev[m];
+            nn += lam[m] * nxt[m] * nxt[m];
+        }
+        ld bk = sqrtl(nn);
+        b[k + 1] = bk;
+        for (size_t m = 0; m < M; m++) {
+            prev[m] = cur[m];
+            cur[m] = nxt[m] / bk;
+        }
+    }
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e[1..n-1]) by the
+// implicit QL algorithm with Wilkinson shifts.
+static void tridiag_eigenvalues(std::vector<ld> d, std::vector<ld> e, std::vector<ld>& ev)
+{
+    const int n = (int)d.size();
+    e.push_back(0);
+    for (int i = 0; i < n - 1; i++) e[i] = e[i + 1];
+    e[n - 1] = 0;
+    for (int l = 0; l < n; l++) {
+        for (int iter = 0; iter < 200; iter++) {
+            int m;
+            for (m = l; m < n - 1; m++) {
+                volatile ld dd = fabsl(d[m]) + fabsl(d[m + 1]);
+                volatile ld sum = fabsl(e[m]) + dd;
+                if (sum == dd) break;
+            }
+            if (m == l) break;
+            ld g = (d[l + 1] - d[l]) / (2 * e[l]);
+            ld r = hypotl(g, 1.0L);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? fabsl(r) : -fabsl(r)));
+            ld s = 1, c = 1, p = 0;
+            int i;
+            for (i = m - 1; i >= l; i--) {
+                ld f = s * e[i], bb = c * e[i];
+                r = hypotl(f, g);
+                e[i + 1] = r;
+                if (r == 0) {
+                    d[i + 1] -= p;
+                    e[m] = 0;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2 * c * bb;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - bb;
+            }
+            if (r == 0 && i >= l) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0;
+        }
+    }
+    ev = d;
+    std::sort(ev.begin(), ev.end());
+}
+
+// Values of the orthonormal half-range polynomials h_0..h_n at x and their derivatives.
+static void half_eval(int n, const std::vector<ld>& a, const std::vector<ld>& b, ld x, ld* h, ld* dh)
+{
+    h[0] = 1 / sqrtl(b[0]);
+    if (dh) dh[0] = 0;
+    if (n >= 1) {
+        h[1] = (x - a[0]) * h[0] / b[1];
+        if (dh) dh[1] = h[0] / b[1];
+    }
+    for (int l = 1; l < n; l++) {
+        h[l + 1] = ((x - a[l]) * h[l] - b[l] * h[l - 1]) / b[l + 1];
+        if (dh) dh[l + 1] = ((x - a[l]) * dh[l] + h[l] - b[l] * dh[l - 1]) / b[l + 1];
+    }
+}
+
+// Orthonormal probabilists' Hermite functions psi_l = He_l / sqrt(l!), l = 0..n.
+static void herm_eval(int n, ld x, ld* psi)
+{
+    psi[0] = 1;
+    if (n >= 1) psi[1] = x;
+    for (int l = 1; l < n; l++) psi[l + 1] = (x * psi[l] - sqrtl((ld)l) * psi[l - 1]) / sqrtl((ld)(l + 1));
+}
+
+// Half-range rule of order Q (Golub-Welsch on the Jacobi matrix, Newton-polished zeros,
+// Christoffel weights), with the derivative-projection force matrices of eq. (force1)/(force2).
+static void build_half_axis(int Q, int N, double Y, AxisTables* ax, std::vector<double>* K1, std::vector<double>* K2)
+{
+    std::vector<ld> a, b;
+    half_recurrence(Q + 1, a, b);
+    std::vector<ld> d(a.begin(), a.begin() + Q), e(Q, 0), roots;
+    for (int k = 1; k < Q; k++) e[k] = b[k];
+    tridiag_eigenvalues(d, e, roots);
+    std::vector<ld> h(Q + 2), dh(Q + 2);
+    for (int i = 0; i < Q; i++) {  // Newton polish on h_Q
+        ld x = roots[i];
+        for (int it = 0; it < 3; it++) {
+            half_eval(Q, a, b, x, h.data(), dh.data());
+            x -= h[Q] / dh[Q];
+        }
+        roots[i] = x;
+    }
+    ax->half = true;
+    ax->Q = Q;
+    ax->nq = 2 * Q;
+    ax->N = N;
+    ax->p.assign(2 * Q, 0);
+    ax->w.assign(2 * Q, 0);
+    std::vector<ld> pl(2 * Q), wl(2 * Q);
+    for (int i = 0; i < Q; i++) {
+        half_eval(Q, a, b, roots[i], h.data(), nullptr);
+        ld s = 0;
+        for (int l = 0; l < Q; l++) s += h[l] * h[l];
+        pl[i] = roots[i];
+        pl[Q + i] = -roots[i];
+        wl[i] = wl[Q + i] = 1 / s;
+    }
+    for (int k = 0; k < 2 * Q; k++) {
+        ax->p[k] = (double)pl[k];
+        ax->w[k] = (double)wl[k];
+    }
+    ax->poly.assign(2 * Q * (N + 1), 0);
+    for (int k = 0; k < 2 * Q; k++) {
+        half_eval(Q, a, b, fabsl(pl[k]), h.data(), nullptr);
+        for (int l = 0; l <= N; l++) ax->poly[k * (N + 1) + l] = (double)h[l];
+    }
+    // projection rule of the equilibrium: composite 16-point Gauss-Legendre on [0, Y], panels
+    // of width 3/4, with h_l at its nodes
+    {
+        std::vector<ld> gx, gw;
+        gauss_legendre(16, gx, gw);
+        const ld hw = 0.75L;
+        const int npan = (int)ceill(Y / hw);
+        ax->qy.clear();
+        ax->qlam.clear();
+        ax->qh.clear();
+        for (int pn = 0; pn < npan; pn++)
+            for (int j = 0; j < 16; j++) {
+                const ld t = pn * hw + hw * (gx[j] + 1) / 2;
+                ax->qy.push_back((double)t);
+                ax->qlam.push_back((double)(gw[j] * hw / 2));
+                half_eval(std::max(N, 1), a, b, t, h.data(), nullptr);
+                for (int l = 0; l <= N; l++) ax->qh.push_back((double)h[l]);
+            }
+    }
+    half_eval(Q, a, b, 0, h.data(), nullptr);
+    std::vector<ld> hzero(h.begin(), h.begin() + Q);
+
+    // Force matrices.  The projected derivative on each half-line, with the jump of f at
+    // p = 0 shared equally by the two halves, gives
+    //   K1_{ii'} = w_i s_i sum_{s<Q} h_s(|p_i|) [ -[s_i = s_i'] h_s'(|p_i'|)
+    //              - h_s(0) Phi(|p_i'|) / (2 sqrt(2 pi)) ],  Phi(y) = sum_{l<Q} h_l(0) h_l(y);
+    // d(f p)/dp has no jump, so K2_{ii'} = -w_i [s_i = s_i'] sum_{s<Q} h_s(|p_i|) |p_i'| h_s'(|p_i'|).
+    // (These are the printed K^h matrices of eqs. (force1)/(force2) rewritten without the
+    // monomial coefficients h_{l,s}.)
+    const int n = 2 * Q;
+    std::vector<ld> H(n * Q), DH(n * Q), PHI(n);
+    for (int k = 0; k < n; k++) {
+        half_eval(Q, a, b, fabsl(pl[k]), h.data(), dh.data());
+        ld phi = 0;
+        for (int l = 0; l < Q; l++) {
+            H[k * Q + l] = h[l];
+            DH[k * Q + l] = dh[l];
+            phi += hzero[l] * h[l];
+        }
+        PHI[k] = phi;
+    }
+    const ld om0 = 1 / sqrtl(2 * kPi);
+    K1->assign(n * n, 0);
+    K2->assign(n * n, 0);
+    for (int i = 0; i < n; i++) {
+        ld si = pl[i] > 0 ? 1 : -1;
+        for (int j = 0; j < n; j++) {
+            bool same = (pl[i] > 0) == (pl[j] > 0);
+            ld acc1 = 0, acc2 = 0;
+            for (int s = 0; s < Q; s++) {
+                ld t = -0.5L * om0 * hzero[s] * PHI[j];
+                if (same) t -= DH[j * Q + s];
+                acc1 += H[i * Q + s] * t;
+                if (same) acc2 += H[i * Q + s] * fabsl(pl[j]) * DH[j * Q + s];
+            }
+            (*K1)[i * n + j] = (double)(wl[i] * si * acc1);
+            (*K2)[i * n + j] = (double)(-wl[i] * acc2);
+        }
+    }
+}
+
+// Full-range rule of order Q (Golub-Welsch on the Hermite Jacobi matrix) and its force
+// matrix for d(f p)/dp, eq. (force2): K1_{ii'} = -w_i sum_l sqrt(l+1) psi_{l+1}(p_i) psi_l(p_i')
+// (the printed sum of He_{l+1}(p_i) He_l(p_i') / l!), and K2 = K1 diag(p) because the
+// He_Q(p_i) = 0 truncation makes the printed two-term form identical to it.
+static void build_full_axis(int Q, int N, AxisTables* ax, std::vector<double>* K2)
+{
+    std::vector<ld> d(Q, 0), e(Q, 0), roots;
+    for (int k = 1; k < Q; k++) e[k] = sqrtl((ld)k);
+    tridiag_eigenvalues(d, e, roots);
+    std::vector<ld> psi(Q + 2);
+    for (int i = 0; i < Q; i++) {
+        ld x = roots[i];
+        for (int it = 0; it < 3; it++) {
+            // He_Q and its derivative Q He_{Q-1} via psi
+            herm_eval(Q, x, psi.data());
+            ld val = psi[Q], der = sqrtl((ld)Q) * psi[Q - 1];
+            x -= val / der;
+        }
+        roots[i] = x;
+    }
+    // symmetric rule: enforce exact mirror symmetry of nodes
+    for (int i = 0; i < Q / 2; i++) {
+        ld m = (roots[Q - 1 - i] - roots[i]) / 2;
+        roots[i] = -m;
+        roots[Q - 1 - i] = m;
+    }
+    if (Q % 2) roots[Q / 2] = 0;
+    ax->half = false;
+    ax->Q = Q;
+    ax->nq = Q;
+    ax->N = N;
+    ax->p.assign(Q, 0);
+    ax->w.assign(Q, 0);
+    std::vector<ld> wl(Q);
+    for (int i = 0; i < Q; i++) {
+        herm_eval(Q, roots[i], psi.data());
+        ld s = 0;
+        for (int l = 0; l < Q; l++) s += psi[l] * psi[l];
+        wl[i] = 1 / s;
+        ax->p[i] = (double)roots[i];
+        ax->w[i] = (double)wl[i];
+    }
+    ax->poly.assign(Q * (N + 1), 0);
+    for (int k = 0; k < Q; k++) {
+        // He_l(p_k) = sqrt(l!) psi_l(p_k)
+        herm_eval(std::max(N, 1), roots[k], psi.data());
+        ld fact = 1;
+        for (int l = 0; l <= N; l++) {
+            if (l >= 2) fact *= l;
+            ax->poly[k * (N + 1) + l] = (double)(sqrtl(fact) * psi[l]);
+        }
+    }
+    K2->assign(Q * Q, 0);
+    std::vector<ld> P(Q * (Q + 1));
+    for (int k = 0; k < Q; k++) {
+        herm_eval(Q, roots[k], psi.data());
+        for (int l = 0; l <= Q; l++) P[k * (Q + 1) + l] = psi[l];
+    }
+    for (int i = 0; i < Q; i++)
+        for (int j = 0; j < Q; j++) {
+            ld acc = 0;
+            for (int l = 0; l <= Q - 2; l++) acc += sqrtl((ld)(l + 1)) * P[i * (Q + 1) + l + 1] * P[j * (Q + 1) + l];
+            (*K2)[i * Q + j] = (double)(-wl[i] * acc * roots[j]);
+        }
+}
+
+// ------------------------------------------------------------------ equilibrium (Sec. III.C)
+
+void equilibrium_axis(const AxisTables& ax, double u, double T, double* g)
+{
+    const int N = ax.N;
+    if (ax.half) {
+        double Ip[kMaxN + 2], Im[kMaxN + 2];
+        const int M = (int)ax.qy.size();
+        half_projection_part(u, T, N, 0, M, ax.qy.data(), ax.qlam.data(), ax.qh.data(), Ip);
+        half_projection_part(-u, T, N, 0, M, ax.qy.data(), ax.qlam.data(), ax.qh.data(), Im);
+        for (int k = 0; k < ax.nq; k++) {
+            const double* I = ax.p[k] > 0 ? Ip : Im;
+            double acc = 0;
+            for (int l = 0; l <= N; l++) acc += I[l] * ax.poly[k * (N + 1) + l];
+            g[k] = ax.w[k] * acc;
+        }
+    } else {
+        double c[kMaxN + 2];
+        full_coeffs<kMaxN>(u, T, N, c);
+        for (int k = 0; k < ax.nq; k++) {
+            double acc = 0;
+            for (int l = 0; l <= N; l++) acc += c[l] * ax.poly[k * (N + 1) + l];
+            g[k] = ax.w[k] * acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ volumes (Appendix A)
+
+// Carlson's symmetric elliptic integrals R_F, R_D, R_C, R_J by the duplication theorem with
+// the fifth-order Taylor tails (B. C. Carlson, Numer. Algorithms 10 (1995) 13-26).
+static ld carlson_rf(ld x, ld y, ld z)
+{
+    for (int it = 0; it < 100; it++) {
+        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
+        ld lam = sx * (sy + sz) + sy * sz;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        z = (z + lam) / 4;
+        ld mu = (x + y + z) / 3;
+        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu;
+        if (std::max(fabsl(dx), std::max(fabsl(dy), fabsl(dz))) < 2e-4L) {
+            ld e2 = dx * dy - dz * dz, e3 = dx * dy * dz;
+            return (1 - e2 / 10 + e3 / 14 + e2 * e2 / 24 - 3 * e2 * e3 / 44) / sqrtl(mu);
+        }
+    }
+    return NAN;
+}
+
+static ld carlson_rd(ld x, ld y, ld z)
+{
+    ld sum = 0, fac = 1;
+    for (int it = 0; it < 100; it++) {
+        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
+        ld lam = sx * (sy + sz) + sy * sz;
+        sum += fac / (sz * (z + lam));
+        fac /= 4;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        z = (z + lam) / 4;
+        ld mu = (x + y + 3 * z) / 5;
+        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu;
+        if (std::max(fabsl(dx), std::max(fabsl(dy), fabsl(dz))) < 2e-4L) {
+            ld ea = dx * dy, eb = dz * dz, ec = ea - eb, ed = ea - 6 * eb, ee = ed + ec + ec;
+            ld tail = 1 + ed * (-3.0L / 14 + 9.0L / 88 * ed - 9.0L / 52 * dz * ee) +
+                      dz * (ee / 6 + dz * (-9.0L / 22 * ec + 3.0L / 26 * dz * ea));
+            return 3 * sum + fac * tail / (mu * sqrtl(mu));
+        }
+    }
+    return NAN;
+}
+
+static ld carlson_rc(ld x, ld y)
+{
+    for (int it = 0; it < 100; it++) {
+        ld lam = 2 * sqrtl(x) * sqrtl(y) + y;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        ld mu = (x + y + y) / 3;
+        ld s = (y - mu) / mu;
+        if (fabsl(s) < 2e-4L)
+            return (1 + s * s * (0.3L + s * (1.0L / 7 + s * (0.375L + s * 9.0L / 22)))) / sqrtl(mu);
+    }
+    return NAN;
+}
+
+static ld carlson_rj(ld x, ld y, ld z, ld p)
+{
+    ld sum = 0, fac = 1;
+    for (int it = 0; it < 100; it++) {
+        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
+        ld lam = sx * (sy + sz) + sy * sz;
+        ld alpha = p * (sx + sy + sz) + sx * sy * sz;
+        alpha *= alpha;
+        ld beta = p * (p + lam) * (p + lam);
+        sum += fac * carlson_rc(alpha, beta);
+        fac /= 4;
+        x = (x + lam) / 4;
+        y = (y + lam) / 4;
+        z = (z + lam) / 4;
+        p = (p + lam) / 4;
+        ld mu = (x + y + z + p + p) / 5;
+        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu, dp = (mu - p) / mu;
+        ld m = std::max(std::max(fabsl(dx), fabsl(dy)), std::max(fabsl(dz), fabsl(dp)));
+        if (m < 2e-4L) {
+            ld ea = dx * (dy + dz) + dy * dz, eb = dx * dy * dz, ec = dp * dp, ed = ea - 3 * ec;
+            ld ee = eb + 2 * dp * (ea - ec);
+            const ld C1 = 3.0L / 14, C2 = 1.0L / 3, C3 = 3.0L / 22, C4 = 3.0L / 26;
+            const ld C5 = 0.75L * C3, C6 = 1.5L * C4, C7 = 0.5L * C2, C8 = C3 + C3;
+            ld tail = 1 + ed * (-C1 + C5 * ed - C6 * ee) + eb * (C7 + dp * (-C8 + dp * C4)) +
+                      dp * ea * (C2 - dp * C3) - C2 * dp * ec;
+            return 3 * sum + fac * tail / (mu * sqrtl(mu));
+        }
+    }
+    return NAN;
+}
+
+// Volume of the ball of radius s centred at distance b from the axis inside the cylinder of
+// radius R (Appendix A, the Lamarche-Leroy formula), valid as printed for s < R and
+// |b - R| < s; the other cases are the whole ball or nothing.
+double ball_in_cylinder(double s_, double R_, double b_)
+{
+    const ld s = s_, R = R_, b = b_;
+    const ld ball = 4 * kPi * s * s * s / 3;
+    if (R <= 0) return 0;
+    if (b + s <= R) return (double)ball;
+    if (b >= R + s) return 0;
+    const ld A = std::max(s * s, (b + R) * (b + R));
+    const ld B = std::min(s * s, (b + R) * (b + R));
+    const ld C = (b - R) * (b - R);
+    const ld k2 = (B - C) / (A - C);
+    const ld m = (B - C) / C;  // the paper's -alpha^2
+    const ld sg = (b + R) * (b - R);
+    const ld kc2 = 1 - k2;
+    const ld RF = carlson_rf(0, kc2, 1);
+    const ld Kk = RF;
+    const ld Ek = RF - k2 / 3 * carlson_rd(0, kc2, 1);
+    const ld Pk = RF - m / 3 * carlson_rj(0, kc2, 1, 1 + m);  // int dz/((1 + m z^2) sqrt..)
+    ld V = (R > b) ? ball : 0;
+    V += 4 / (3 * sqrtl(A - C)) *
+         (Pk * B * B * sg / C + Kk * (sg * (A - 2 * B) + (A - B) * (3 * B - C - 2 * A) / 3) +
+          Ek * (A - C) * (-sg + (2 * A + 2 * C - 4 * B) / 3));
+    return (double)V;
+}
+
+// Volume of the ball of radius s centred at distance b from the origin inside the ball of
+// radius R about the origin (Appendix A, lens of two spheres).
+double ball_in_sphere(double s_, double R_, double b_)
+{
+    const ld s = s_, R = R_, b = b_;
+    if (R <= 0) return 0;
+    if (b + s <= R) return (double)(4 * kPi * s * s * s / 3);
+    if (b >= R + s) return 0;
+    if (b + R <= s) return (double)(4 * kPi * R * R * R / 3);
+    const ld t = s + R - b;
+    return (double)(kPi * t * t * (b * b + 2 * b * (s + R) - 3 * (s - R) * (s - R)) / (12 * b));
+}
+
+// ------------------------------------------------------------------ instance set-up
+
+lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err)
+{
+    lbe_params p = in;
+    auto bad = [&](const char* m) {
+        if (err) *err = m;
+        return LBE_EINVAL;
+    };
+    if (p.geometry != LBE_CYL && p.geometry != LBE_SPH) return bad("geometry must be LBE_CYL or LBE_SPH");
+    if (!(p.r_inner > 0) || !(p.r_outer > p.r_inner) || !std::isfinite(p.r_outer))
+        return bad("need 0 < r_inner < r_outer");
+    if (!(p.eta0 > 0 && p.eta0 < 0.5)) return bad("eta0 must lie in (0, 0.5)");
+    if (!(p.kn > 0) || !std::isfinite(p.kn)) return bad("kn must be positive");
+    if (!(p.t_wall_inner > 0) || !(p.t_wall_outer > 0)) return bad("wall temperatures must be positive");
+    if (!(p.cfl > 0) || !std::isfinite(p.cfl)) return bad("cfl must be positive");
+    if (!std::isfinite(p.u_wall_inner)) return bad("u_wall_inner must be finite");
+    if (p.geometry == LBE_SPH && p.u_wall_inner != 0) return bad("a spherical instance cannot have a wall velocity");
+    if (p.nr < 8) return bad("nr must be >= 8");
+    const int Q[3] = {p.q_radial, p.q_t1, p.q_t2};
+    for (int a = 0; a < 3; a++) {
+        if (Q[a] < 2 || Q[a] > kMaxQ) return bad("quadrature orders must lie in [2, 64]");
+        int N = p.n_expand[a];
+        if (N == 0) N = std::min(7, Q[a] - 1);
+        if (N < 1 || N >= Q[a] || N > kMaxN) return bad("expansion orders need 1 <= N_a < Q_a and N_a <= 15");
+        p.n_expand[a] = N;
+    }
+    const double C = 1 / (6 * std::sqrt(2.0) * p.eta0 * chi_cs(p.eta0) * p.kn);
+    if (!(C > 1)) return bad("confinement ratio C = L/sigma must exceed 1 (sigma < L)");
+    if (out) *out = p;
+    return LBE_OK;
+}
+
+lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string* err)
+{
+    lbe_params p;
+    lbe_status st = validate_params(pin, &p, err);
+    if (st != LBE_OK) return st;
+    t->prm = p;
+    // the equilibrium projection rule covers Gaussians up to 1.5 times the hottest wall
+    const double Tmax = std::max(1.0, std::max(p.t_wall_inner, p.t_wall_outer));
+    const double Y = 3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner);
+    build_half_axis(p.q_radial, p.n_expand[0], Y, &t->ax[0], &t->K1, &t->K2r);
+    build_full_axis(p.q_t1, p.n_expand[1], &t->ax[1], &t->K2a);
+    build_full_axis(p.q_t2, p.n_expand[2], &t->ax[2], &t->K2b);
+    t->n0 = t->ax[0].nq;
+    t->n1 = t->ax[1].nq;
+    t->n2 = t->ax[2].nq;
+    t->nv = t->n0 * t->n1 * t->n2;
+    t->nr = p.nr;
+
+    // Kn map (Sec. II) and the computational domain (Sec. IV).
+    t->chi0 = chi_cs(p.eta0);
+    t->C = 1 / (6 * std::sqrt(2.0) * p.eta0 * t->chi0 * p.kn);
+    t->L = p.r_outer - p.r_inner;
+    t->sigma = t->L / t->C;
+    t->rcl = p.r_inner + t->sigma / 2;
+    t->rcr = p.r_outer - t->sigma / 2;
+    t->dr = (t->rcr - t->rcl) / t->nr;
+    const int nr = t->nr;
+    t->r.resize(nr);
+    t->ri.resize(nr + 1);
+    for (int i = 0; i <= nr; i++) t->ri[i] = t->rcl + i * t->dr;
+    for (int i = 0; i < nr; i++) t->r[i] = t->rcl + (i + 0.5) * t->dr;
+    double pmax = 0;
+    for (double v : t->ax[0].p) pmax = std::max(pmax, std::fabs(v));
+    t->dt = p.cfl * t->dr / pmax;
+
+    // Flux-form geometry: cell measure V_i (r_i dr, or (ri_{i+1}^3 - ri_i^3)/3), interface
+    // weights ri/V_i (cylinder) or ri^2/V_i (sphere), force-term factor 1/r_i (cylinder) or
+    // (ri_{i+1}^2 - ri_i^2)/(2 V_i) (sphere: balances the flux form exactly at rest).
+    t->geo.resize(4 * nr);
+    for (int i = 0; i < nr; i++) {
+        const ld rl = t->ri[i], rr = t->ri[i + 1], rc = t->r[i];
+        if (p.geometry == LBE_CYL) {
+            const ld V = rc * (ld)t->dr;
+            t->geo[4 * i + 0] = (double)(rl / V);
+            t->geo[4 * i + 1] = (double)(rr / V);
+            t->geo[4 * i + 2] = (double)(1 / rc);
+        } else {
+            const ld V = (rr * rr * rr - rl * rl * rl) / 3;
+            t->geo[4 * i + 0] = (double)(rl * rl / V);
+            t->geo[4 * i + 1] = (double)(rr * rr / V);
+            t->geo[4 * i + 2] = (double)((rr * rr - rl * rl) / (2 * V));
+        }
+        t->geo[4 * i + 3] = (double)(1 / rc);
+    }
+
+    // Averaged-density weights, eq. (fm) with n piecewise constant on cells and zero outside
+    // the computational domain: W_ij = [V(sigma; ri_{j+1}, r_i) - V(sigma; ri_j, r_i)] / ball.
+    {
+        const double s = t->sigma;
+        const ld ball = 4 * kPi * (ld)s * s * s / 3;
+        t->wlo.assign(nr, 0);
+        std::vector<int> whi(nr);
+        int wb = 1;
+        for (int i = 0; i < nr; i++) {
+            int lo = (int)std::floor((t->r[i] - s - t->rcl) / t->dr) - 1;
+            int hi = (int)std::floor((t->r[i] + s - t->rcl) / t->dr) + 1;
+            lo = std::max(lo, 0);
+            hi = std::min(hi, nr - 1);
+            t->wlo[i] = lo;
+            whi[i] = hi;
+            wb = std::max(wb, hi - lo + 1);
+        }
+        t->wband = wb;
+        t->wb.assign((size_t)nr * wb, 0);
+        for (int i = 0; i < nr; i++) {
+            const int lo = t->wlo[i], hi = whi[i];
+            std::vector<double> V(hi - lo + 2);
+            for (int j = lo; j <= hi + 1; j++)
+                V[j - lo] = p.geometry == LBE_CYL ? ball_in_cylinder(s, t->ri[j], t->r[i])
+                                                  : ball_in_sphere(s, t->ri[j], t->r[i]);
+            for (int j = lo; j <= hi; j++) t->wb[(size_t)i * wb + (j - lo)] = (double)(((ld)V[j + 1 - lo] - V[j - lo]) / ball);
+        }
+    }
+
+    // Unit wall Maxwellians g_r(0, T_w) g_1(u_w, T_w) g_2(0, T_w) and the entering flux sums.
+    t->gwl.resize(t->nv);
+    t->gwr.resize(t->nv);
+    {
+        std::vector<double> g0(t->n0), g1(t->n1), g2(t->n2);
+        for (int side = 0; side < 2; side++) {
+            const double Tw = side == 0 ? p.t_wall_inner : p.t_wall_outer;
+            const double uw = side == 0 ? p.u_wall_inner : 0.0;
+            equilibrium_axis(t->ax[0], 0.0, Tw, g0.data());
+            equilibrium_axis(t->ax[1], uw, Tw, g1.data());
+            equilibrium_axis(t->ax[2], 0.0, Tw, g2.data());
+            std::vector<double>& gw = side == 0 ? t->gwl : t->gwr;
+            ld gin = 0;
+            for (int v = 0; v < t->nv; v++) {
+                const int i0 = v % t->n0, i1 = (v / t->n0) % t->n1, i2 = v / (t->n0 * t->n1);
+                gw[v] = g0[i0] * g1[i1] * g2[i2];
+                const double pr = t->ax[0].p[i0];
+                if ((side == 0 && pr > 0) || (side == 1 && pr < 0)) gin += (ld)pr * gw[v];
+            }
+            (side == 0 ? t->gin_l : t->gin_r) = (double)gin;
+        }
+    }
+    return LBE_OK;
+}
+
+}  // namespace lbe

@@ -1,0 +1,231 @@
+"""Thin Python binding of liblbe (include/lbe.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of ``csrc/``; PyTorch provides the device
+workspace (a uint8 tensor) and the stream.  There is no CPU fallback: if the shared library
+is missing, importing or constructing a solver raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbe.so")
+
+LBE_OK, LBE_EINVAL, LBE_ENOMEM, LBE_EDEVICE, LBE_ENOTCONV, LBE_ENAN, LBE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+CYL, SPH = 0, 1
+FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
+INFO_KEYS = ("nr", "nv", "n0", "n1", "n2", "chi0", "C", "L", "sigma", "rcl", "rcr", "dr", "dt", "steps", "N0", "N1",
+             "N2")
+
+
+class LbeError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"liblbe status {status}: {msg}")
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``lbe_params`` (include/lbe.h)."""
+
+    _fields_ = [
+        ("geometry", ctypes.c_int32),
+        ("r_inner", ctypes.c_double),
+        ("r_outer", ctypes.c_double),
+        ("u_wall_inner", ctypes.c_double),
+        ("t_wall_inner", ctypes.c_double),
+        ("t_wall_outer", ctypes.c_double),
+        ("eta0", ctypes.c_double),
+        ("kn", ctypes.c_double),
+        ("nr", ctypes.c_int32),
+        ("q_radial", ctypes.c_int32),
+        ("q_t1", ctypes.c_int32),
+        ("q_t2", ctypes.c_int32),
+        ("n_expand", ctypes.c_int32 * 3),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+PARAM_KEYS = ("geometry", "r_inner", "r_outer", "u_wall_inner", "t_wall_inner", "t_wall_outer", "eta0", "kn", "nr",
+              "q_radial", "q_t1", "q_t2", "cfl")
+
+
+def make_params(d: dict) -> Params:
+    p = Params()
+    for k in PARAM_KEYS:
+        setattr(p, k, d[k])
+    ne = d.get("n_expand", (0, 0, 0))
+    for a in range(3):
+        p.n_expand[a] = int(ne[a])
+    return p
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P = ctypes.POINTER(Params)
+    lib.lbe_query.argtypes = [P, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.lbe_init.argtypes = [P, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.lbe_step.argtypes = [vp, i64]
+    lib.lbe_sync.argtypes = [vp]
+    lib.lbe_moments.argtypes = [vp, i32, _D, i64]
+    lib.lbe_run_to_steady.argtypes = [vp, ctypes.c_double, i64, i32, _I64, _D]
+    lib.lbe_get_state.argtypes = [vp, i32, _D, i64]
+    lib.lbe_set_state.argtypes = [vp, i32, _D, i64]
+    lib.lbe_rhs.argtypes = [vp, i32, _D, i64]
+    lib.lbe_info.argtypes = [vp, i32, _D, i64]
+    lib.lbe_tables.argtypes = [P, i32, _D, _D, i64, _I64]
+    lib.lbe_timing.argtypes = [vp, i32, _D, i64]
+    lib.lbe_last_error.argtypes = [vp]
+    lib.lbe_last_error.restype = ctypes.c_char_p
+    lib.lbe_status_string.argtypes = [ctypes.c_int]
+    lib.lbe_status_string.restype = ctypes.c_char_p
+    lib.lbe_free.argtypes = [vp]
+    lib.lbe_free.restype = None
+    for name in ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
+                 "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_status_string"):
+        if name != "lbe_status_string":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+EXPORTS = ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
+           "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_last_error", "lbe_status_string",
+           "lbe_free")
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def query(params: Sequence[dict]) -> tuple[int, int]:
+    lib = load()
+    arr = (Params * len(params))(*[make_params(p) for p in params])
+    dev = ctypes.c_size_t(0)
+    host = ctypes.c_size_t(0)
+    st = lib.lbe_query(arr, len(params), ctypes.byref(dev), ctypes.byref(host))
+    if st != LBE_OK:
+        raise LbeError(st, "lbe_query rejected the parameters")
+    return dev.value, host.value
+
+
+def tables(params: dict, which: int, extra: Iterable[float] | None = None) -> np.ndarray:
+    """Host-only tables of one instance (see lbe_tables in include/lbe.h)."""
+    lib = load()
+    p = make_params(params)
+    ex = np.ascontiguousarray(np.array(list(extra) if extra is not None else [0.0, 1.0, 0.0], dtype=np.float64))
+    n = ctypes.c_int64(0)
+    lib.lbe_tables(ctypes.byref(p), which, _ptr(ex), None, 0, ctypes.byref(n))
+    if n.value <= 0:
+        raise LbeError(LBE_EINVAL, f"lbe_tables({which}) rejected the parameters")
+    out = np.zeros(n.value)
+    st = lib.lbe_tables(ctypes.byref(p), which, _ptr(ex), _ptr(out), n.value, ctypes.byref(n))
+    if st != LBE_OK:
+        raise LbeError(st, f"lbe_tables({which})")
+    return out
+
+
+class Solver:
+    """A batch of FDLB instances on one GPU (the current torch device and stream)."""
+
+    def __init__(self, params: dict | Sequence[dict]):
+        import torch
+
+        if isinstance(params, dict):
+            params = [params]
+        self.params = [dict(p) for p in params]
+        lib = load()
+        self._lib = lib
+        dev_bytes, _ = query(self.params)
+        self._ws = torch.empty(dev_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) & ~255
+        arr = (Params * len(self.params))(*[make_params(p) for p in self.params])
+        stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p(0)
+        st = lib.lbe_init(arr, len(self.params), ctypes.c_void_p(aligned), dev_bytes, ctypes.c_void_p(stream),
+                          ctypes.byref(h))
+        if st != LBE_OK:
+            raise LbeError(st, "lbe_init failed")
+        self._h = h
+        self.n_inst = len(self.params)
+        self._infos = [self.info(k) for k in range(self.n_inst)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                self._lib.lbe_sync(h)
+            finally:
+                self._lib.lbe_free(h)
+            self._h = None
+
+    def _check(self, st: int, what: str) -> int:
+        if st not in (LBE_OK, LBE_ENOTCONV):
+            msg = self._lib.lbe_last_error(self._h).decode()
+            raise LbeError(st, f"{what}: {msg}")
+        return st
+
+    def info(self, inst: int = 0) -> dict:
+        out = np.zeros(17)
+        self._check(self._lib.lbe_info(self._h, inst, _ptr(out), 17), "lbe_info")
+        return dict(zip(INFO_KEYS, out.tolist()))
+
+    def step(self, n: int = 1) -> None:
+        self._check(self._lib.lbe_step(self._h, n), "lbe_step")
+
+    def sync(self) -> None:
+        self._check(self._lib.lbe_sync(self._h), "lbe_sync")
+
+    def moments(self, inst: int = 0) -> dict:
+        nr = int(self._infos[inst]["nr"])
+        out = np.zeros(9 * nr)
+        self._check(self._lib.lbe_moments(self._h, inst, _ptr(out), out.size), "lbe_moments")
+        out = out.reshape(9, nr)
+        return {k: out[i].copy() for i, k in enumerate(FIELDS)}
+
+    def run_to_steady(self, tol: float, max_steps: int, check_every: int):
+        steps = np.zeros(self.n_inst, dtype=np.int64)
+        res = np.zeros(self.n_inst)
+        st = self._lib.lbe_run_to_steady(self._h, tol, max_steps, check_every, steps.ctypes.data_as(_I64), _ptr(res))
+        self._check(st, "lbe_run_to_steady")
+        return st, steps, res
+
+    def get_state(self, inst: int = 0) -> np.ndarray:
+        nr, nv = int(self._infos[inst]["nr"]), int(self._infos[inst]["nv"])
+        out = np.zeros(nr * nv)
+        self._check(self._lib.lbe_get_state(self._h, inst, _ptr(out), out.size), "lbe_get_state")
+        return out.reshape(nr, nv)
+
+    def set_state(self, inst: int, f: np.ndarray) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        self._check(self._lib.lbe_set_state(self._h, inst, _ptr(f), f.size), "lbe_set_state")
+
+    def timing_start(self) -> None:
+        self._check(self._lib.lbe_timing(self._h, 1, None, 0), "lbe_timing")
+
+    def timing_stop(self) -> dict:
+        out = np.zeros(4)
+        self._check(self._lib.lbe_timing(self._h, 0, _ptr(out), 4), "lbe_timing")
+        return {"stage_ms": out[0], "stage_launches": int(out[1]), "node_ms": out[2], "node_launches": int(out[3])}
+
+    def rhs(self, inst: int = 0) -> np.ndarray:
+        nr, nv = int(self._infos[inst]["nr"]), int(self._infos[inst]["nv"])
+        out = np.zeros(nr * nv)
+        self._check(self._lib.lbe_rhs(self._h, inst, _ptr(out), out.size), "lbe_rhs")
+        return out.reshape(nr, nv)

@@ -1,0 +1,71 @@
+"""Seeded synthetic workloads: the problem statements the solver is run on.
+
+This module only describes inputs (geometry, radii, walls, packing fraction, Knudsen number,
+grid and quadrature orders); it holds none of the method's arithmetic except the closed-form
+confinement ratio C = 1/(6 sqrt2 eta0 chi(eta0) Kn) (Sec. II of arXiv:2403.15051), which the
+parameter sweep uses only to reject draws with sigma >= L / 1.5.  The paper measures on no
+public dataset; its own set-ups (Sec. IV) are reproduced as synthetic problem statements.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Cylindrical Couette, FP64: R1 = 1, R2 = 2, inner wall u_phi = 0.1, T = 1 walls, eta0 = 0.05,
+# Kn = 0.1, Nr = 32, half-range order 4 in p_R, orders 4 (p_phi) and 2 (p_z), 1000 RK3 steps.
+COUETTE_SMALL = dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=0.1, t_wall_inner=1.0, t_wall_outer=1.0,
+                     eta0=0.05, kn=0.1, nr=32, q_radial=4, q_t1=4, q_t2=2, cfl=0.25)
+COUETTE_SMALL_STEPS = 1000
+
+# Cylindrical Fourier: walls at rest, T1 = 1, T2 = 1.5, eta0 = 0.1, Kn = 0.5, Nr = 128,
+# half-range order 8, orders 8 (p_phi) and 4 (p_z).
+FOURIER_CYL = dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wall_inner=1.0, t_wall_outer=1.5,
+                   eta0=0.1, kn=0.5, nr=128, q_radial=8, q_t1=8, q_t2=4, cfl=0.25)
+
+# Spherical Fourier: T1 = 1, T2 = 2, eta0 = 0.2, Kn = 0.05, Nr = 256, half-range order 16,
+# orders 12 (p_theta) and 12 (p_phi): 32 x 12 x 12 = 4608 velocities.
+FOURIER_SPH = dict(geometry=1, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wall_inner=1.0, t_wall_outer=2.0,
+                   eta0=0.2, kn=0.05, nr=256, q_radial=16, q_t1=12, q_t2=12, cfl=0.25)
+
+SWEEP_SEED = 240315051
+SWEEP_ORDERS = (4, 8, 12, 16)
+
+
+def _confinement(eta0: float, kn: float) -> float:
+    chi = (2 - eta0) / (2 * (1 - eta0) ** 3)
+    return 1.0 / (6 * np.sqrt(2.0) * eta0 * chi * kn)
+
+
+def sweep(n: int = 256, seed: int = SWEEP_SEED, nr_range=(64, 512), c_min: float = 1.5):
+    """Parameter sweep of uneven instances (Couette/Fourier 50/50).
+
+    Per instance, in this order: geometry flag (Bernoulli 1/2: 0 Couette, 1 Fourier), Nr ~ U{64..512},
+    eta0 ~ U(0.01, 0.3), Kn = 10^U(-2, 1) (eta0, Kn redrawn together while C < c_min),
+    u_w ~ U(0, 0.5), T2/T1 ~ U(1, 2), Q ~ U{4, 8, 12, 16}.  Couette instances use u_w with
+    T2/T1 = 1, Fourier instances T2/T1 with u_w = 0; both draws are always consumed.
+    Velocities (2Q, Q, max(Q/2, 4)); cylindrical geometry, R1 = 1, R2 = 2, CFL 0.25.
+    Returns (params list, acceptance rate of the (eta0, Kn) draws).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    draws = 0
+    for _ in range(n):
+        flag = int(rng.integers(0, 2))
+        nr = int(rng.integers(nr_range[0], nr_range[1] + 1))
+        while True:
+            eta0 = float(rng.uniform(0.01, 0.3))
+            kn = float(10 ** rng.uniform(-2, 1))
+            draws += 1
+            if _confinement(eta0, kn) >= c_min:
+                break
+        uw = float(rng.uniform(0, 0.5))
+        tr = float(rng.uniform(1, 2))
+        q = int(SWEEP_ORDERS[int(rng.integers(0, 4))])
+        out.append(dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=uw if flag == 0 else 0.0,
+                        t_wall_inner=1.0, t_wall_outer=1.0 if flag == 0 else tr, eta0=eta0, kn=kn, nr=nr,
+                        q_radial=q, q_t1=q, q_t2=max(q // 2, 4), cfl=0.25, flag=flag))
+    return out, n / draws
+
+
+def solver_params(d: dict) -> dict:
+    """Drop bookkeeping keys that are not part of the problem statement."""
+    return {k: v for k, v in d.items() if k != "flag"}

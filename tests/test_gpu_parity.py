@@ -1,0 +1,149 @@
+"""GPU parity of the FP64 HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance: normwise relative error ||x_gpu - x_oracle||_inf / ||x_oracle||_inf <= 1e-12 per
+field and for f, at equal step counts.  Both sides compute the same discrete scheme in FP64 with
+different summation orders and table algorithms, so they differ by rounding only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15051_amd import lbe, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def nrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    lbe.load()
+
+
+def compare_profiles(mg, mo, fields=("n", "u_r", "u_t1", "T", "q_r", "P_rt1", "nbar", "chi"), tol=TOL, ctx=""):
+    for k in fields:
+        scale = np.abs(mo[k]).max()
+        if scale < 1e-13:  # a field that vanishes by symmetry: compare absolutely
+            assert np.abs(mg[k]).max() < 1e-12, (ctx, k)
+            continue
+        e = nrel(mg[k], mo[k])
+        print(f"{ctx} {k}: {e:.3e}", flush=True)
+        assert e <= tol, (ctx, k, e)
+
+
+SMALL_CYL = dict(workloads.COUETTE_SMALL, nr=16)
+SMALL_SPH = dict(workloads.FOURIER_SPH, nr=24, q_radial=4, q_t1=4, q_t2=4)
+
+
+@pytest.mark.parametrize("p", [SMALL_CYL, SMALL_SPH, dict(workloads.FOURIER_CYL, nr=24)])
+def test_rhs_parity_on_oracle_states(p):
+    """L(f) of the same f: the rest start and a non-equilibrium state reached by the oracle."""
+    print("case", p, flush=True)
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    assert nrel(g.get_state(), o.get_f()) < 1e-15
+    assert nrel(g.rhs(), o.rhs()) <= TOL
+    o.step(30)
+    f = o.get_f()
+    g.set_state(0, f)
+    e = nrel(g.rhs(), o.rhs())
+    print("rhs parity after 30 oracle steps", e, flush=True)
+    assert e <= TOL
+    compare_profiles(g.moments(), o.moments(), ctx="moments")
+
+
+def test_couette_small_1000_steps():
+    """Cylindrical Couette (R 1..2, u_w 0.1, eta0 0.05, Kn 0.1, Nr 32, (8,4,2) velocities),
+    1000 RK3 steps from the rest start: f and profiles match the oracle."""
+    p = workloads.COUETTE_SMALL
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    o.step(workloads.COUETTE_SMALL_STEPS)
+    g.step(workloads.COUETTE_SMALL_STEPS)
+    g.sync()
+    e = nrel(g.get_state(), o.get_f())
+    print("f parity", e, flush=True)
+    assert e <= TOL
+    compare_profiles(g.moments(), o.moments(), ctx="couette")
+
+
+def test_fourier_cyl_fixed_steps():
+    p = workloads.FOURIER_CYL
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    o.step(300)
+    g.step(300)
+    assert nrel(g.get_state(), o.get_f()) <= TOL
+    compare_profiles(g.moments(), o.moments(), ctx="fourier-cyl")
+
+
+def test_fourier_sph_full_size_fixed_steps():
+    """Spherical Fourier at its full size (Nr 256, 4608 velocities), 20 steps."""
+    p = workloads.FOURIER_SPH
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    o.step(20)
+    g.step(20)
+    assert nrel(g.get_state(), o.get_f()) <= TOL
+    compare_profiles(g.moments(), o.moments(), ctx="fourier-sph")
+
+
+def test_uneven_batch_matches_independent_solves():
+    """Instances of different geometry, Nr and velocity sets advance together in one launch."""
+    ps = [SMALL_CYL, SMALL_SPH, dict(workloads.FOURIER_CYL, nr=40, q_radial=6, q_t1=6, q_t2=4)]
+    g = lbe.Solver(ps)
+    g.step(60)
+    for k, p in enumerate(ps):
+        o = oracle.Solver(p)
+        o.step(60)
+        assert nrel(g.get_state(k), o.get_f()) <= TOL, k
+        compare_profiles(g.moments(k), o.moments(), ctx=f"batch{k}")
+
+
+def test_run_to_steady_matches_oracle():
+    p = dict(workloads.COUETTE_SMALL, nr=16, q_t2=4, kn=0.3)
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    rc_o, steps_o, res_o = o.run_to_steady(1e-5, 20000, 50)
+    st, steps_g, res_g = g.run_to_steady(1e-5, 20000, 50)
+    assert rc_o == 0 and st == lbe.LBE_OK
+    assert steps_g[0] == steps_o
+    assert res_g[0] == pytest.approx(res_o, rel=1e-6)
+    compare_profiles(g.moments(), o.moments(), ctx="steady")
+
+
+def test_mass_conserved_on_gpu():
+    p = dict(workloads.FOURIER_CYL, nr=32, q_radial=6, q_t1=6, q_t2=4)
+    g = lbe.Solver(p)
+    o = oracle.Solver(p)
+    vol = o.grid()["vol"]
+    m0 = (vol * g.moments()["n"]).sum()
+    g.step(200)
+    m1 = (vol * g.moments()["n"]).sum()
+    assert abs(m1 / m0 - 1) < 1e-13
+
+
+def test_nan_state_is_detected_and_latched():
+    p = SMALL_CYL
+    g = lbe.Solver(p)
+    f = g.get_state()
+    f[3, 5] = np.nan
+    g.set_state(0, f)
+    g.step(1)
+    with pytest.raises(lbe.LbeError) as e:
+        g.sync()
+    assert e.value.status == lbe.LBE_ENAN
+    with pytest.raises(lbe.LbeError):
+        g.step(1)
+    g.set_state(0, oracle.Solver(p).get_f())  # a finite state clears the latch
+    g.step(2)
+    g.sync()

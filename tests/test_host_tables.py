@@ -1,0 +1,128 @@
+"""CPU checks of liblbe's host side against the oracle: the library loads and exports every
+entry point of include/lbe.h, rejects invalid problem statements before any device work, and
+its once-per-solve tables (quadratures, force matrices, averaged-density weights, equilibrium
+factors, volumes) equal the oracle's, which were built by different algorithms."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15051_amd import lbe, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _libs():
+    oracle.build(force=False)
+    if not os.path.exists(lbe.LIB_PATH):
+        pytest.skip("liblbe.so not built")
+    lbe.load()
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "lbe.h")).read()
+    declared = set(re.findall(r"\b(lbe_[a-z_]+)\s*\(", header))
+    assert {"lbe_init", "lbe_step", "lbe_moments", "lbe_run_to_steady"} <= declared
+    lib = lbe.load()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(lbe.EXPORTS) == declared
+
+
+BAD = [
+    dict(eta0=0.0), dict(eta0=0.5), dict(kn=-1.0), dict(nr=7), dict(q_radial=1), dict(q_t1=65),
+    dict(n_expand=(4, 0, 0)), dict(cfl=0.0), dict(t_wall_outer=0.0), dict(r_outer=0.5),
+    dict(geometry=1, u_wall_inner=0.1), dict(geometry=2), dict(eta0=0.01, kn=100.0),  # C < 1
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_problem_statements_are_rejected(bad):
+    p = dict(workloads.COUETTE_SMALL, **bad)
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.query([p])
+    assert e.value.status == lbe.LBE_EINVAL
+
+
+def test_query_sizes_scale():
+    d1, _ = lbe.query([workloads.FOURIER_CYL])
+    d2, _ = lbe.query([workloads.FOURIER_CYL] * 2)
+    assert d1 > 4 * 128 * 512 * 8 and 1.9 * d1 < d2 < 2.1 * d1
+
+
+CASES = [workloads.COUETTE_SMALL, workloads.FOURIER_CYL, dict(workloads.FOURIER_SPH, nr=32),
+         dict(workloads.COUETTE_SMALL, q_radial=12, q_t1=6, q_t2=3, n_expand=(5, 4, 2))]
+
+
+@pytest.mark.parametrize("p", CASES)
+def test_quadratures_match_oracle(p):
+    Q = (p["q_radial"], p["q_t1"], p["q_t2"])
+    for axis in range(3):
+        t = lbe.tables(p, axis)
+        n = t.size // 2
+        x, w = oracle.quad_half(Q[0]) if axis == 0 else oracle.quad_full(Q[axis])
+        assert np.allclose(t[:n], x, rtol=4e-16, atol=4e-16)
+        assert np.allclose(t[n:], w, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("p", CASES)
+def test_force_matrices_match_oracle(p):
+    K1 = lbe.tables(p, 3).reshape(2 * p["q_radial"], -1)
+    assert np.allclose(K1, oracle.kmat_half(p["q_radial"], 1), rtol=1e-12, atol=1e-13 * np.abs(K1).max())
+    K2r = lbe.tables(p, 10).reshape(2 * p["q_radial"], -1)
+    assert np.allclose(K2r, oracle.kmat_half(p["q_radial"], 2), rtol=1e-12, atol=1e-13 * np.abs(K2r).max())
+    for axis, which in ((1, 4), (2, 5)):
+        Q = p["q_t1"] if axis == 1 else p["q_t2"]
+        K = lbe.tables(p, which).reshape(Q, Q)
+        assert np.allclose(K, oracle.kmat_full(Q, 2), rtol=1e-12, atol=1e-14 * max(1, np.abs(K).max()))
+
+
+@pytest.mark.parametrize("p", CASES)
+def test_equilibrium_factors_match_oracle(p):
+    N = p.get("n_expand", (0, 0, 0))
+    Q = (p["q_radial"], p["q_t1"], p["q_t2"])
+    Ns = [N[a] if N[a] else min(7, Q[a] - 1) for a in range(3)]
+    for u, T in ((0.0, 1.0), (0.31, 1.37), (-0.22, 0.81)):
+        g = lbe.tables(p, 8, [u, T, 0.0])
+        o = [oracle.geq(True, Q[0], Ns[0], u, T), oracle.geq(False, Q[1], Ns[1], u, T),
+             oracle.geq(False, Q[2], Ns[2], u, T)]
+        ref = np.concatenate(o)
+        # normwise per axis to a few ulps (the oracle is correctly rounded); pointwise the tail
+        # nodes (weights down to 1e-15) keep only the absolute accuracy of the projection sum
+        n0, n1 = len(o[0]), len(o[1])
+        for sl in (slice(0, n0), slice(n0, n0 + n1), slice(n0 + n1, None)):
+            assert np.abs(g[sl] - ref[sl]).max() <= 2e-15 * np.abs(ref[sl]).max()
+        assert np.allclose(g, ref, rtol=1e-13, atol=2e-17)
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_averaged_density_weights_match_oracle(geometry):
+    for p in (dict(workloads.COUETTE_SMALL, geometry=geometry, u_wall_inner=0.0),
+              dict(workloads.FOURIER_CYL, geometry=geometry, nr=48), dict(workloads.FOURIER_SPH, geometry=geometry,
+                                                                           nr=64)):
+        W = lbe.tables(p, 6).reshape(p["nr"], p["nr"])
+        Wo = oracle.Solver(oracle.make_params(**{k: v for k, v in p.items()})).W()
+        assert np.abs(W - Wo).max() < 2e-13, np.abs(W - Wo).max()
+
+
+def test_ball_cylinder_volume_elliptic_matches_slice_integral():
+    p = dict(workloads.COUETTE_SMALL)
+    s = 0.3
+    for R, b in ((1.0, 0.8), (1.0, 0.999), (1.0, 1.2), (1.3, 1.05), (2.0, 1.71), (1.0, 0.69), (1.0, 1.31), (1.5, 1.5001)):
+        v = lbe.tables(p, 9, [s, R, b])[0]
+        assert v == pytest.approx(oracle.vol_cyl(s, R, b), rel=5e-14, abs=1e-17)
+    p = dict(workloads.FOURIER_SPH)
+    for R, b in ((1.0, 0.8), (1.0, 1.2), (1.3, 1.05), (1.0, 1.31)):
+        assert lbe.tables(p, 9, [s, R, b])[0] == pytest.approx(oracle.vol_sph(s, R, b), rel=1e-14, abs=1e-17)
+
+
+def test_sweep_generator_is_seeded_and_valid():
+    a, acc = workloads.sweep(64)
+    b, _ = workloads.sweep(64)
+    assert a == b
+    assert 0.3 < acc < 0.8
+    for d in a:
+        lbe.query([workloads.solver_params(d)])
