@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     }
     __syncthreads();
     const double inv12dr = 1.0 / (12 * I.dr);
-    const double kSqrt2Pi5_16 = 0.78332038861223477406;  // 5 sqrt(2 pi) / 16
+    const double kSqrt2Pi5_16 = 5 * sqrt(2 * M_PI) / 16;
     const double kC1 = 4.0 / 25 * (1 + 12 / M_PI);
     const double kD1 = 9.0 / 25 * (1 + 32 / (9 * M_PI));
     for (int k = threadIdx.x; k < c1 - c0; k += kBlock) {
