@@ -21,6 +21,9 @@ hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int m
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t set_stage_smem_limit(int maxnv);
+hipError_t launch_stage2(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
+                         int dst, double an, double bs, hipStream_t s);
+hipError_t set_stage2_smem_limit();
 }  // namespace lbe
 
 using namespace lbe;
@@ -45,6 +48,12 @@ struct lbe_ctx {
     std::vector<hipEvent_t> ev;       // pool, reused
     size_t ev_used = 0;
     std::vector<std::pair<int, int>> stage_ev, node_ev;  // (start, stop) indices into ev
+    // stage-kernel launch groups and their work items (device copy in the workspace)
+    std::vector<StageGroup> groups;
+    std::vector<int> group_of;         // instance -> group
+    std::vector<int> item_off, item_cnt;
+    std::vector<WorkItem> items;
+    WorkItem* dev_items = nullptr;
 };
 
 namespace {
@@ -58,7 +67,7 @@ struct Layout {
     size_t total;
 };
 
-Layout make_layout(const InstanceTables& t, size_t base)
+Layout make_layout(const InstanceTables& t, int nslices, size_t base)
 {
     Layout L;
     size_t o = base;
@@ -70,7 +79,7 @@ Layout make_layout(const InstanceTables& t, size_t base)
     const size_t D = sizeof(double);
     const size_t plane = (size_t)t.nr * t.nv * D;
     for (int k = 0; k < 3; k++) L.f[k] = take(plane);
-    L.mom = take((size_t)t.nr * kMomStride * D);
+    L.mom = take((size_t)t.nr * nslices * kMomStride * D);
     L.node = take((size_t)t.nr * kNodeStride * D);
     L.geq = take((size_t)t.nr * (t.n0 + t.n1 + t.n2) * D);
     L.snap = take((size_t)t.nr * 5 * D);
@@ -109,7 +118,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
-    size_t b = 4 * align256(nr * nv * D) + align256(nr * kMomStride * D) + align256(nr * kNodeStride * D) +
+    size_t b = 4 * align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
                align256(nr * (n0 + n1 + n2) * D) + align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
@@ -118,7 +127,146 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const size_t M = (size_t)(16 * (std::ceil((3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner)) / 0.75) + 1));
     b += 2 * align256(M * D) + align256(M * N * D);
     b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
+    b += align256(nr * n2 * sizeof(WorkItem));
     return b + 4096;
+}
+
+// Launch groups of the stage kernel: instances with the same velocity set share one launch.
+// Per group: velocity slices S (a divisor of n2; raised while the whole batch has fewer than
+// two work items per compute unit), lanes per workgroup and velocities per lane (about 4),
+// nodes per tile, and the LDS layout.
+constexpr int kLdsDoubles = 160 * 1024 / 8;
+
+bool layout_group(StageGroup* G)
+{
+    const int n0 = G->n0, n1 = G->n1, n2 = G->n2;
+    G->ns2 = n2 / G->S;
+    G->nvs = G->nv / G->S;
+    G->ncols_s = n1 * G->ns2;
+    G->plane_cols = G->geometry == LBE_SPH ? n1 * n2 : G->ncols_s;
+    G->n0k = (n0 + 3) / 4 * 4;
+    G->n1k = (n1 + 3) / 4 * 4;
+    G->n2k = (n2 + 3) / 4 * 4;
+    G->n0p = (n0 + 15) / 16 * 16;
+    G->n1p = (n1 + 15) / 16 * 16;
+    G->ns2p = (G->ns2 + 15) / 16 * 16;
+    // one velocity per lane when the slice has at most 1024 velocities, else two
+    int block = std::min(1024, (G->nvs + 63) / 64 * 64);
+    block = std::max(block, 64);
+    G->block = block;
+    G->vpt = (G->nvs + block - 1) / block;
+    if (G->vpt > 2) return false;
+    const int W = block / 64, ng = n0 + n1 + n2, cs = n0 + 1;
+    for (int NT = 8; NT >= 1; NT /= 2) {
+        G->NT = NT;
+        int o = 0;
+        G->off_plane = o;
+        o += cs * G->plane_cols;
+        G->off_ibuf = o;
+        o += cs * G->ncols_s;
+        G->off_K1 = o;
+        o += G->n0p * G->n0k;
+        G->off_K2a = o;
+        o += G->n1p * G->n1k;
+        G->off_K2b = o;
+        o += (G->geometry == LBE_SPH) ? G->ns2p * G->n2k : 0;
+        G->off_node = o;
+        o += NT * kStageNodeStride;
+        G->off_geq = o;
+        o += NT * ng;
+        G->off_part = o;
+        o += NT * W * 13;
+        G->off_p = o;
+        o += ng;
+        G->lds_doubles = o;
+        if (o <= kLdsDoubles) return true;
+    }
+    return false;
+}
+
+lbe_status plan_groups(lbe_ctx* c)
+{
+    c->groups.clear();
+    c->group_of.assign(c->ninst, -1);
+    for (int k = 0; k < c->ninst; k++) {
+        const InstanceTables& t = c->tabs[k];
+        int g = -1;
+        for (size_t q = 0; q < c->groups.size(); q++) {
+            const StageGroup& G = c->groups[q];
+            if (G.n0 == t.n0 && G.n1 == t.n1 && G.n2 == t.n2 && G.geometry == t.prm.geometry) g = (int)q;
+        }
+        if (g < 0) {
+            StageGroup G;
+            std::memset(&G, 0, sizeof(G));
+            G.n0 = t.n0;
+            G.n1 = t.n1;
+            G.n2 = t.n2;
+            G.nv = t.nv;
+            G.geometry = t.prm.geometry;
+            G.S = 1;
+            c->groups.push_back(G);
+            g = (int)c->groups.size() - 1;
+        }
+        c->group_of[k] = g;
+    }
+    auto total_items = [&]() {
+        long tot = 0;
+        for (int k = 0; k < c->ninst; k++) {
+            const StageGroup& G = c->groups[c->group_of[k]];
+            tot += (long)((c->tabs[k].nr + 7) / 8) * G.S;
+        }
+        return tot;
+    };
+    // more slices while the batch is too small to fill the chip (two items per compute unit)
+    for (int guard = 0; guard < 64 && total_items() < 512; guard++) {
+        int best = -1;
+        for (size_t q = 0; q < c->groups.size(); q++) {
+            const StageGroup& G = c->groups[q];
+            int nextS = G.S + 1;
+            while (nextS <= G.n2 && G.n2 % nextS) nextS++;
+            if (nextS > G.n2 || G.nv / nextS < 256) continue;
+            if (best < 0 || G.nv / G.S > c->groups[best].nv / c->groups[best].S) best = (int)q;
+        }
+        if (best < 0) break;
+        StageGroup& G = c->groups[best];
+        int nextS = G.S + 1;
+        while (G.n2 % nextS) nextS++;
+        G.S = nextS;
+    }
+    for (StageGroup& G : c->groups) {
+        // prefer one velocity per lane: slice while a slice holds more than 1024 velocities
+        for (;;) {
+            int nextS = G.S + 1;
+            while (nextS <= G.n2 && G.n2 % nextS) nextS++;
+            if (G.nv / G.S <= 1024 || nextS > G.n2) break;
+            G.S = nextS;
+        }
+        // split further if the velocity set needs more than two per lane or the LDS does not fit
+        while (!layout_group(&G)) {
+            int nextS = G.S + 1;
+            while (nextS <= G.n2 && G.n2 % nextS) nextS++;
+            if (nextS > G.n2) {
+                c->err = "velocity set too large for the stage kernel";
+                return LBE_EINVAL;
+            }
+            G.S = nextS;
+        }
+    }
+    c->items.clear();
+    c->item_off.assign(c->groups.size(), 0);
+    c->item_cnt.assign(c->groups.size(), 0);
+    for (size_t q = 0; q < c->groups.size(); q++) {
+        const StageGroup& G = c->groups[q];
+        c->item_off[q] = (int)c->items.size();
+        for (int k = 0; k < c->ninst; k++) {
+            if (c->group_of[k] != (int)q) continue;
+            const int nr = c->tabs[k].nr;
+            for (int i0 = 0; i0 < nr; i0 += G.NT)
+                for (int sl = 0; sl < G.S; sl++) c->items.push_back({k, i0, std::min(G.NT, nr - i0), sl});
+        }
+        c->item_cnt[q] = (int)c->items.size() - c->item_off[q];
+    }
+    return LBE_OK;
 }
 
 lbe_status dev_err(lbe_ctx* c, hipError_t e, const char* what)
@@ -169,7 +317,13 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
         c->node_ev.push_back({a, b});
         (void)hipEventRecord(next_event(c, &x), c->stream);
     }
-    e = launch_stage_kernel(c->dev_desc, c->ninst, c->maxnr, c->maxnv, src, fn, dst, an, bs, mode, c->stream);
+    if (mode == 0) {
+        for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
+            e = launch_stage2(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an,
+                              bs, c->stream);
+    } else {
+        e = launch_stage_kernel(c->dev_desc, c->ninst, c->maxnr, c->maxnv, src, fn, dst, an, bs, mode, c->stream);
+    }
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &y), c->stream);
@@ -287,12 +441,25 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
             c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
         }
     }
+    st = plan_groups(c);
+    if (st != LBE_OK) {
+        delete c;
+        return st;
+    }
     size_t off = align256(sizeof(DevInstance) * n_inst);
     c->dev_desc = (DevInstance*)c->ws;
-    hipError_t e = hipSuccess;
+    c->dev_items = (WorkItem*)(c->ws + off);
+    off = align256(off + c->items.size() * sizeof(WorkItem));
+    if (off > ws_bytes) {
+        delete c;
+        return LBE_ENOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
+                                  hipMemcpyHostToDevice, c->stream);
     for (int k = 0; k < n_inst && e == hipSuccess; k++) {
         const InstanceTables& t = c->tabs[k];
-        Layout L = make_layout(t, off);
+        const int nsl = c->groups[c->group_of[k]].S;
+        Layout L = make_layout(t, nsl, off);
         if (L.total > ws_bytes) {
             delete c;
             return LBE_ENOMEM;
@@ -344,6 +511,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.qlam0 = (const double*)(ws + L.qlam0);
         d.qh0 = (const double*)(ws + L.qh0);
         d.M0 = (int32_t)t.ax[0].qy.size();
+        d.nslices = nsl;
         d.geo = (const double*)(ws + L.geo);
         d.r = (const double*)(ws + L.r);
         d.wlo = (const int32_t*)(ws + L.wlo);
@@ -389,6 +557,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         e = hipMemcpyAsync(c->dev_desc, c->host_desc.data(), sizeof(DevInstance) * n_inst, hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = set_stage_smem_limit(c->maxnv);
+    if (e == hipSuccess) e = set_stage2_smem_limit();
     if (e != hipSuccess) {
         st = dev_err(c, e, "lbe_init upload");
         delete c;

@@ -65,7 +65,7 @@ struct DevInstance {
     int32_t N0, N1, N2, wband;
     double dt, dr, eta0, kn, chi0, L, gin_l, gin_r;
     double* f[3];           // state buffers [nr][nv]; f[0] holds the state between steps
-    double* mom;            // [nr][kMomStride] moment sums of the last written buffer
+    double* mom;            // [nr][nslices][kMomStride] moment sums of the last written buffer (per slice)
     double* node;           // [nr][kNodeStride] node coefficients of the current stage
     double* geq;            // [nr][n0 + n1 + n2] equilibrium factors of the current stage
     const double* p0; const double* p1; const double* p2;
@@ -73,7 +73,7 @@ struct DevInstance {
     const double* w0; const double* w1; const double* w2;
     const double* poly0; const double* poly1; const double* poly2;
     const double* qy0; const double* qlam0; const double* qh0;  // projection rule, M0 nodes
-    int32_t M0, pad0;
+    int32_t M0, nslices;    // equilibrium projection nodes; velocity slices of the stage kernel
     const double* geo;      // [nr][4]
     const double* r;        // [nr]
     const int32_t* wlo;     // [nr]
@@ -85,6 +85,28 @@ struct DevInstance {
     double* nw;             // [2] wall densities of the current stage
     double* scratch;        // [nr][nv] rhs output (lbe_rhs)
 };
+
+// One unit of stage-kernel work: a tile of consecutive nodes of one instance, one velocity slice.
+struct WorkItem {
+    int32_t inst, i0, nt, slice;
+};
+
+// Launch group of the stage kernel: instances sharing one velocity set (n0, n1, n2, geometry).
+// All sizes are uniform over the group; LDS offsets are in doubles.
+struct StageGroup {
+    int32_t n0, n1, n2, nv, geometry;
+    int32_t S, ns2, nvs, ncols_s, plane_cols;  // slices, i2 per slice, velocities / columns per slice
+    int32_t n0k, n1k, n2k, n0p, n1p, ns2p;     // K padded to 4, M/N padded to 16
+    int32_t NT, block, vpt;
+    int32_t off_plane, off_ibuf, off_K1, off_K2a, off_K2b, off_node, off_geq, off_part, off_p, lds_doubles;
+};
+
+// Per-node fields the stage kernel stages in LDS (subset of the node block plus geometry).
+enum StageNodeField {
+    SN_N = 0, SN_U0, SN_U1, SN_U2, SN_T, SN_Q0, SN_Q1, SN_Q2, SN_INVTAU, SN_SHAK, SN_BRHOCHI, SN_D1, SN_D2,
+    SN_DU0, SN_DU2, SN_DIVU, SN_SH01, SN_URR, SN_ADVL, SN_ADVR, SN_FFAC, SN_COUNT
+};
+constexpr int kStageNodeStride = 24;
 
 // Host table construction (lbe_tables.cpp).
 lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err);

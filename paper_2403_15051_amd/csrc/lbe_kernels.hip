@@ -24,6 +24,7 @@ namespace lbe {
 constexpr int kBlock = 256;
 constexpr int kNodeChunk = 32;  // nodes per node-kernel workgroup
 constexpr int kHalo = 4;        // gradient stencils reach 4 nodes (one-sided at the walls)
+constexpr int kMaxNr = 1024;    // largest radial grid (node-kernel LDS)
 
 // ------------------------------------------------------------------ helpers
 
@@ -104,6 +105,22 @@ __device__ inline Macro macro_from_sums(const double* m)
     return o;
 }
 
+// Moment sums of node i summed over the velocity slices (fixed order); the shift is common.
+__device__ inline void node_sums(const DevInstance& I, int i, double* m)
+{
+    const double* b = I.mom + (size_t)i * I.nslices * kMomStride;
+    for (int k = 0; k < kMomStride; k++) m[k] = b[k];
+    for (int s = 1; s < I.nslices; s++)
+        for (int k = 0; k < 13; k++) m[k] += b[s * kMomStride + k];
+}
+
+__device__ inline Macro macro_of_node(const DevInstance& I, int i)
+{
+    double m[kMomStride];
+    node_sums(I, i, m);
+    return macro_from_sums(m);
+}
+
 __device__ inline double chi_of(double eta) { return (2 - eta) / (2 * (1 - eta) * (1 - eta) * (1 - eta)); }
 
 // Value of f at cell c (c may be a ghost: -2, -1, nr, nr+1) for velocity v with radial
@@ -156,10 +173,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
         acc[MF_S3Z] += fv * x2 * z;
     }
     block_sum<13>(acc, red);
-    if (threadIdx.x < 16) {
-        const int k = threadIdx.x;
-        I.mom[(size_t)i * kMomStride + k] = k < 13 ? red[k * 4] : 0.0;
-    }
+    for (int k = threadIdx.x; k < I.nslices * kMomStride; k += kBlock)
+        I.mom[(size_t)i * I.nslices * kMomStride + k] = (k < 13) ? red[k * 4] : 0.0;
 }
 
 // ------------------------------------------------------------------ node kernel
@@ -205,19 +220,42 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo],
         snbar[kNodeChunk + 2 * kHalo];
     __shared__ Macro smac[kNodeChunk];
+    __shared__ double sdens[kMaxNr];
+    __shared__ double snb[kNodeChunk + 2 * kHalo];
+    // densities of every node (slice sums), then the averaged density of the chunk + halo,
+    // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row
+    for (int j = threadIdx.x; j < nr; j += kBlock) {
+        const double* b = I.mom + (size_t)j * I.nslices * kMomStride;
+        double n = b[MF_S0];
+        for (int sl = 1; sl < I.nslices; sl++) n += b[sl * kMomStride + MF_S0];
+        sdens[j] = n;
+    }
+    __syncthreads();
+    {
+        const int grp = threadIdx.x >> 3, sub = threadIdx.x & 7;
+        for (int k = grp; k < nh; k += kBlock / 8) {
+            const int j = h0 + k;
+            const int lo = I.wlo[j];
+            const double* wrow = I.wb + (size_t)j * I.wband;
+            double part = 0;
+            for (int k2 = sub; k2 < I.wband; k2 += 8) {
+                const int col = lo + k2;
+                if (col < nr) part += wrow[k2] * sdens[col];
+            }
+            // combine the 8 partial sums of the group in a fixed order
+            part += __shfl_down(part, 4, 8);
+            part += __shfl_down(part, 2, 8);
+            part += __shfl_down(part, 1, 8);
+            if (sub == 0) snb[k] = part;
+        }
+    }
+    __syncthreads();
     __shared__ double sI[kNodeChunk][2][kMaxN + 1], sc1[kNodeChunk][kMaxN + 2], sc2[kNodeChunk][kMaxN + 2];
-    __shared__ double sPart[kNodeChunk][2][4][kMaxN + 1];
+    __shared__ double sPart[kNodeChunk][2][2][kMaxN + 1];
     for (int k = threadIdx.x; k < nh; k += kBlock) {
         const int j = h0 + k;
-        const Macro m = macro_from_sums(I.mom + (size_t)j * kMomStride);
-        // averaged density, eq. (fm): nbar_j = sum_k W_jk n_k (band)
-        const int lo = I.wlo[j];
-        const double* wrow = I.wb + (size_t)j * I.wband;
-        double nb = 0;
-        for (int k2 = 0; k2 < I.wband; k2++) {
-            const int col = lo + k2;
-            if (col < nr) nb += wrow[k2] * I.mom[(size_t)col * kMomStride + MF_S0];
-        }
+        const Macro m = macro_of_node(I, j);
+        const double nb = snb[k];
         const double chi = chi_of(I.eta0 * nb);
         sn[k] = m.n;
         sT[k] = m.T;
@@ -295,11 +333,11 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         full_coeffs<kMaxN>(m.u[1], T, I.N1, sc1[k]);
         full_coeffs<kMaxN>(m.u[2], T, I.N2, sc2[k]);
     }
-    // half-range projections: lanes = (node, side, quarter of the quadrature nodes)
+    // half-range projections: lanes = (node, side, half of the quadrature nodes)
     {
-        const int k = threadIdx.x >> 3, side = (threadIdx.x >> 2) & 1, part = threadIdx.x & 3;
+        const int k = threadIdx.x >> 2, side = (threadIdx.x >> 1) & 1, part = threadIdx.x & 1;
         if (k < c1 - c0) {
-            const int M = I.M0, m0 = part * M / 4, m1 = (part + 1) * M / 4;
+            const int M = I.M0, m0 = part * M / 2, m1 = (part + 1) * M / 2;
             const double uu = side ? -smac[k].u[0] : smac[k].u[0];
             half_projection_part(uu, smac[k].T, I.N0, m0, m1, I.qy0, I.qlam0, I.qh0, sPart[k][side][part]);
         }
@@ -307,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __syncthreads();
     for (int t = threadIdx.x; t < (c1 - c0) * 2 * (I.N0 + 1); t += kBlock) {
         const int l = t % (I.N0 + 1), side = (t / (I.N0 + 1)) & 1, k = t / (2 * (I.N0 + 1));
-        sI[k][side][l] = ((sPart[k][side][0][l] + sPart[k][side][1][l]) + sPart[k][side][2][l]) + sPart[k][side][3][l];
+        sI[k][side][l] = sPart[k][side][0][l] + sPart[k][side][1][l];
     }
     __syncthreads();
     // equilibrium factors g_R, g_1, g_2 of every node of the chunk
@@ -457,7 +495,369 @@ __global__ void __launch_bounds__(kBlock) k_stage(const DevInstance* __restrict_
             val = red[k * 4];
         else
             val = (k == MF_CX) ? u0 : (k == MF_CY) ? u1 : u2;
-        I.mom[(size_t)i * kMomStride + k] = val;
+        I.mom[(size_t)i * I.nslices * kMomStride + k] = val;
+    }
+}
+
+// ------------------------------------------------------------------ tiled stage kernel
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// 64-lane sum of a double with DPP row shifts (within 16-lane rows) and lane reads across the
+// four rows; the result is valid in every lane.  Fixed order, so reproducible.
+template <int CTRL, int BANK_MASK>
+__device__ inline double dpp_shift(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, BANK_MASK, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_total(double v)
+{
+    double s = v + dpp_shift<0x111, 0xf>(v);  // row_shr:1
+    s += dpp_shift<0x112, 0xf>(v);            // row_shr:2
+    s += dpp_shift<0x113, 0xf>(v);            // row_shr:3 -> 4 consecutive lanes
+    s += dpp_shift<0x114, 0xe>(s);            // row_shr:4 on banks 1..3
+    s += dpp_shift<0x118, 0xc>(s);            // row_shr:8 on banks 2..3 -> lane 15 of each row
+    const int lo = __double2loint(s), hi = __double2hiint(s);
+    double r0 = __hiloint2double(__builtin_amdgcn_readlane(hi, 15), __builtin_amdgcn_readlane(lo, 15));
+    double r1 = __hiloint2double(__builtin_amdgcn_readlane(hi, 31), __builtin_amdgcn_readlane(lo, 31));
+    double r2 = __hiloint2double(__builtin_amdgcn_readlane(hi, 47), __builtin_amdgcn_readlane(lo, 47));
+    double r3 = __hiloint2double(__builtin_amdgcn_readlane(hi, 63), __builtin_amdgcn_readlane(lo, 63));
+    return ((r0 + r1) + r2) + r3;
+}
+
+// One RK stage for a tile of NT consecutive nodes x one velocity slice of one instance.
+// Lanes own velocities v = vs0 + tid + block * j (j < VPT) for the whole tile and keep, per
+// velocity, a register window of the 7 cells i-3 .. i+3 around the current node i, so every
+// face flux is computed once and every value of f_src is read once (plus a 6-cell halo per
+// tile).  The node's plane is staged in LDS (column stride n0 + 1) and the three
+// momentum-derivative contractions run as FP64 MFMA 16x16x4 tiles over it:
+//   d0 = K1 P        (n0 x n0) x (n0 x columns)         rows = radial momentum
+//   d1 = K2a P_i2    (n1 x n1) x (n1 x n0) per i2
+//   d2 = K2b P'      (n2 x n2) x (n2 x n0 n1)           sphere only
+// accumulated, already multiplied by their momentum and geometry factors, into an LDS plane.
+template <int VPT>
+__global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__ insts,
+                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
+                                                  int fn, int dst, double an, double bs)
+{
+    extern __shared__ double lds[];
+    const WorkItem it = items[blockIdx.x];
+    const DevInstance& I = insts[it.inst];
+    if (!I.flags[1]) return;
+    const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2;
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6, W = B >> 6;
+    const int cs = n0 + 1;  // LDS column stride
+    const bool sph = G.geometry == LBE_SPH;
+    const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
+    const int c_s0 = it.slice * G.ncols_s;      // first global column (i1 + n1 i2) of the slice
+    const int cp0 = sph ? 0 : c_s0;            // first global column held in the LDS plane
+    const int i2s0 = it.slice * G.ns2;          // first i2 of the slice
+    double* plane = lds + G.off_plane;
+    double* ibuf = lds + G.off_ibuf;
+    double* K1s = lds + G.off_K1;
+    double* K2as = lds + G.off_K2a;
+    double* K2bs = lds + G.off_K2b;
+    double* snode = lds + G.off_node;
+    double* sgeq = lds + G.off_geq;
+    double* spart = lds + G.off_part;
+    const double* __restrict__ f = I.f[src];
+    const int ng = n0 + n1 + n2;
+
+    // ---- per-workgroup set-up: force matrices (zero-padded) and the tile's node data
+    for (int e = tid; e < G.n0p * G.n0k; e += B) {
+        const int r = e / G.n0k, k = e % G.n0k;
+        K1s[e] = (r < n0 && k < n0) ? I.K1[r * n0 + k] : 0.0;
+    }
+    for (int e = tid; e < 16 * ((n1 + 15) / 16) * G.n1k; e += B) {
+        const int r = e / G.n1k, k = e % G.n1k;
+        K2as[e] = (r < n1 && k < n1) ? I.K2a[r * n1 + k] : 0.0;
+    }
+    if (sph)
+        for (int e = tid; e < G.ns2p * G.n2k; e += B) {
+            const int r = e / G.n2k, k = e % G.n2k;
+            const int rg = i2s0 + r;
+            K2bs[e] = (r < G.ns2 && k < n2) ? I.K2b[rg * n2 + k] : 0.0;
+        }
+    for (int e = tid; e < it.nt * SN_COUNT; e += B) {
+        const int t = e / SN_COUNT, fld = e % SN_COUNT, i = it.i0 + t;
+        const double* nd = I.node + (size_t)i * kNodeStride;
+        double val;
+        switch (fld) {
+            case SN_N: val = nd[NF_N]; break;
+            case SN_U0: val = nd[NF_U0]; break;
+            case SN_U1: val = nd[NF_U1]; break;
+            case SN_U2: val = nd[NF_U2]; break;
+            case SN_T: val = nd[NF_T]; break;
+            case SN_Q0: val = nd[NF_Q0]; break;
+            case SN_Q1: val = nd[NF_Q1]; break;
+            case SN_Q2: val = nd[NF_Q2]; break;
+            case SN_INVTAU: val = nd[NF_INVTAU]; break;
+            case SN_SHAK: val = nd[NF_SHAK]; break;
+            case SN_BRHOCHI: val = nd[NF_BRHOCHI]; break;
+            case SN_D1: val = nd[NF_D1]; break;
+            case SN_D2: val = nd[NF_D2]; break;
+            case SN_DU0: val = nd[NF_DU0]; break;
+            case SN_DU2: val = nd[NF_DU2]; break;
+            case SN_DIVU: val = nd[NF_DIVU]; break;
+            case SN_SH01: val = nd[NF_SHEAR01]; break;
+            case SN_URR: val = nd[NF_UR_R]; break;
+            case SN_ADVL: val = I.geo[4 * i + 0]; break;
+            case SN_ADVR: val = I.geo[4 * i + 1]; break;
+            default: val = I.geo[4 * i + 2]; break;
+        }
+        snode[t * kStageNodeStride + fld] = val;
+    }
+    for (int e = tid; e < it.nt * ng; e += B) {
+        const int t = e / ng, k = e % ng;
+        sgeq[t * ng + k] = I.geq[(size_t)(it.i0 + t) * ng + k];
+    }
+
+    // momentum nodes of the three axes
+    double* sp = lds + G.off_p;
+    for (int e = tid; e < ng; e += B) sp[e] = e < n0 ? I.p0[e] : e < n0 + n1 ? I.p1[e - n0] : I.p2[e - n0 - n1];
+    // ---- per-lane velocities: v = vs0 + tid + B j; code = i0 | i1 << 8 | i2 << 16
+    const double nwl = I.nw[0], nwr = I.nw[1];
+    int code[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; j++) {
+        const int v = min(vs0 + tid + B * j, vs1 - 1);
+        const int i0 = v % n0, c = v / n0, i1 = c % n1, i2 = c / n1;
+        code[j] = i0 | (i1 << 8) | (i2 << 16);
+    }
+    __syncthreads();
+    // ---- window of cells i0-3 .. i0+3 around the first node of the tile
+    double w[VPT][7];
+    double Fl[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; j++) {
+        const int v = min(vs0 + tid + B * j, vs1 - 1);
+        const double pr = sp[code[j] & 0xff];
+#pragma unroll
+        for (int k = 0; k < 7; k++) w[j][k] = fcell(f, it.i0 - 3 + k, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
+        if (pr > 0)
+            Fl[j] = (it.i0 == 0) ? pr * nwl * I.gwl[v] : pr * weno5(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4]);
+        else
+            Fl[j] = pr * weno5(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1]);
+    }
+
+    const int nM1 = G.n0p / 16, nN1 = (G.ncols_s + 15) / 16;
+    const int nM2 = (n1 + 15) / 16, nN2 = G.n0p / 16;
+    const int nM3 = G.ns2p / 16, nN3 = (n0 * n1 + 15) / 16;
+    const int q16 = lane & 15, q4 = lane >> 4;
+
+    for (int t = 0; t < it.nt; t++) {
+        const int i = it.i0 + t;
+        const double* nd = snode + t * kStageNodeStride;
+        const double ffac = nd[SN_FFAC];
+        // prefetch the next window cell
+        double wnext[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; j++) {
+            const int v = min(vs0 + tid + B * j, vs1 - 1);
+            wnext[j] = fcell(f, i + 4, v, nr, nv, sp[code[j] & 0xff], nwl, nwr, I.gwl, I.gwr);
+        }
+        // stage the node's plane in LDS (own velocities; sphere slices also fetch the rest)
+#pragma unroll
+        for (int j = 0; j < VPT; j++) {
+            const int v = vs0 + tid + B * j;
+            if (v < vs1) {
+                const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
+                plane[i0 + cs * (c - cp0)] = w[j][3];
+            }
+        }
+        if (sph && G.S > 1) {
+            for (int v = tid; v < nv; v += B) {
+                if (v >= vs0 && v < vs1) continue;
+                plane[(v % n0) + cs * (v / n0)] = f[(size_t)i * nv + v];
+            }
+        }
+        // face flux at i + 1 (upwind WENO-5; entering flux at the outer wall)
+        double Fr[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; j++) {
+            const double pr = sp[code[j] & 0xff];
+            if (pr > 0)
+                Fr[j] = pr * weno5(w[j][1], w[j][2], w[j][3], w[j][4], w[j][5]);
+            else
+                Fr[j] = (i == nr - 1) ? pr * nwr * I.gwr[min(vs0 + tid + B * j, vs1 - 1)]
+                                      : pr * weno5(w[j][6], w[j][5], w[j][4], w[j][3], w[j][2]);
+        }
+        __syncthreads();
+        // ---- d0 = K1 P, scaled by ffac * (p_1^2 [+ p_2^2]) into ibuf
+        for (int tile = wave; tile < nM1 * nN1; tile += W) {
+            const int mt = tile / nN1, ntl = tile % nN1;
+            const int col = ntl * 16 + q16;  // column within the slice
+            const bool cok = col < G.ncols_s;
+            const double* bp = plane + cs * (c_s0 + (cok ? col : 0) - cp0);
+            const double* ap = K1s + (mt * 16 + q16) * G.n0k;
+            v4d acc = {0, 0, 0, 0};
+            for (int ks = 0; ks < G.n0k; ks += 4) {
+                const int k = ks + q4;
+                const double a = ap[k];
+                const double b = (cok && k < n0) ? bp[k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            if (cok) {
+                const int cg = c_s0 + col, ci1 = cg % n1, ci2 = cg / n1;
+                const double pyy = sp[n0 + ci1];
+                double fac = pyy * pyy;
+                if (sph) {
+                    const double pzz = sp[n0 + n1 + ci2];
+                    fac += pzz * pzz;
+                }
+                fac *= ffac;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int row = mt * 16 + q4 + 4 * r;
+                    if (row < n0) ibuf[row + cs * col] = fac * acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- d1 = K2a P_i2 for each i2 of the slice, ibuf -= ffac p_r d1
+        for (int tile = wave; tile < G.ns2 * nM2 * nN2; tile += W) {
+            const int i2l = tile / (nM2 * nN2), rem = tile % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
+            const int i0c = ntl * 16 + q16;
+            const bool iok = i0c < n0;
+            const double* ap = K2as + (mt * 16 + q16) * G.n1k;
+            const double* bp = plane + (iok ? i0c : 0) + cs * (n1 * (i2s0 + i2l) - cp0);
+            v4d acc = {0, 0, 0, 0};
+            for (int ks = 0; ks < G.n1k; ks += 4) {
+                const int k = ks + q4;
+                const double a = ap[k];
+                const double b = (iok && k < n1) ? bp[cs * k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            if (iok) {
+                const double fac = ffac * sp[i0c];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int jrow = mt * 16 + q4 + 4 * r;
+                    if (jrow < n1) ibuf[i0c + cs * (jrow + n1 * i2l)] -= fac * acc[r];
+                }
+            }
+        }
+        if (sph) {
+            __syncthreads();
+            // ---- d2 = K2b P' (rows: i2 of the slice, columns: i0 + n0 i1), ibuf -= ffac p_r d2
+            for (int tile = wave; tile < nM3 * nN3; tile += W) {
+                const int mt = tile / nN3, ntl = tile % nN3;
+                const int cp = ntl * 16 + q16;
+                const bool pok = cp < n0 * n1;
+                const int bi0 = pok ? cp % n0 : 0, bi1 = pok ? cp / n0 : 0;
+                const double* ap = K2bs + (mt * 16 + q16) * G.n2k;
+                const double* bp = plane + bi0 + cs * bi1;
+                v4d acc = {0, 0, 0, 0};
+                for (int ks = 0; ks < G.n2k; ks += 4) {
+                    const int k = ks + q4;
+                    const double a = ap[k];
+                    const double b = (pok && k < n2) ? bp[cs * n1 * k] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+                if (pok) {
+                    const double fac = ffac * sp[bi0];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int krow = mt * 16 + q4 + 4 * r;
+                        if (krow < G.ns2) ibuf[bi0 + cs * (bi1 + n1 * krow)] -= fac * acc[r];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- advection, collision, RK combine, store and moment sums of the stored values
+        const double n = nd[SN_N], u0 = nd[SN_U0], u1 = nd[SN_U1], u2 = nd[SN_U2], T = nd[SN_T];
+        const double q0 = nd[SN_Q0], q1 = nd[SN_Q1], q2 = nd[SN_Q2];
+        const double invtau = nd[SN_INVTAU], shak = nd[SN_SHAK], brhochi = nd[SN_BRHOCHI];
+        const double D1 = nd[SN_D1], D2 = nd[SN_D2], du0 = nd[SN_DU0], du2 = nd[SN_DU2];
+        const double divu = nd[SN_DIVU], sh01 = nd[SN_SH01], urr = nd[SN_URR];
+        const double adv_l = nd[SN_ADVL], adv_r = nd[SN_ADVR];
+        const double inv2T = 1 / (2 * T), inv5T = 1 / (5 * T);
+        const double* gR = sgeq + t * ng;
+        const double* g1 = gR + n0;
+        const double* g2 = g1 + n1;
+        double* out = I.f[dst] + (size_t)i * nv;
+        const double* fnp = I.f[fn] + (size_t)i * nv;
+#pragma unroll
+        for (int j = 0; j < VPT; j++) {
+            const int v = vs0 + tid + B * j;
+            const int i0 = code[j] & 0xff, i1 = code[j] >> 8 & 0xff, i2 = code[j] >> 16;
+            const int ib = i0 + cs * (i1 + n1 * i2 - c_s0);
+            const double pr = sp[i0], py = sp[n0 + i1], pz = sp[n0 + n1 + i2];
+            const double A = adv_r * Fr[j] - adv_l * Fl[j];
+            const double Iv = ibuf[ib];
+            const double fmb = n * gR[i0] * g1[i1] * g2[i2];
+            const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
+            const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
+            const double xq = x0 * q0 + x1 * q1 + x2 * q2;
+            const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
+            const double z2 = xi2 * inv2T;
+            const double zzgu = sph ? (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T
+                                    : (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T;
+            const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
+            const double fv = w[j][3];
+            const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
+            if (v < vs1) {
+                const double o = an * fnp[v] + bs * (fv + I.dt * L);
+                out[v] = o;
+                ibuf[ib] = o;  // the stored value, for the moment sums below
+            }
+        }
+        __syncthreads();
+        // moment sums of the stored plane of this slice, shifted by the node's velocity
+        {
+            double acc[13];
+#pragma unroll
+            for (int k = 0; k < 13; k++) acc[k] = 0;
+            for (int v = vs0 + tid; v < vs1; v += B) {
+                const int i0 = v % n0, c = v / n0, i1 = c % n1, i2 = c / n1;
+                const double o = ibuf[i0 + cs * (c - c_s0)];
+                const double x0 = sp[i0] - u0, x1 = sp[n0 + i1] - u1, x2 = sp[n0 + n1 + i2] - u2;
+                const double y2s = x0 * x0 + x1 * x1 + x2 * x2;
+                acc[MF_S0] += o;
+                acc[MF_S1X] += o * x0;
+                acc[MF_S1Y] += o * x1;
+                acc[MF_S1Z] += o * x2;
+                acc[MF_SXX] += o * x0 * x0;
+                acc[MF_SYY] += o * x1 * x1;
+                acc[MF_SZZ] += o * x2 * x2;
+                acc[MF_SXY] += o * x0 * x1;
+                acc[MF_SXZ] += o * x0 * x2;
+                acc[MF_SYZ] += o * x1 * x2;
+                acc[MF_S3X] += o * y2s * x0;
+                acc[MF_S3Y] += o * y2s * x1;
+                acc[MF_S3Z] += o * y2s * x2;
+            }
+#pragma unroll
+            for (int k = 0; k < 13; k++) {
+                const double tot = wave_total(acc[k]);
+                if (lane == 0) spart[(t * W + wave) * 13 + k] = tot;
+            }
+        }
+        // advance the window
+#pragma unroll
+        for (int j = 0; j < VPT; j++) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) w[j][k] = w[j][k + 1];
+            w[j][6] = wnext[j];
+            Fl[j] = Fr[j];
+        }
+    }
+    __syncthreads();
+    // ---- moment sums of the tile's nodes (waves summed in order) for this slice
+    for (int e = tid; e < it.nt * 16; e += B) {
+        const int t = e / 16, k = e % 16, i = it.i0 + t;
+        double val;
+        if (k < 13) {
+            val = 0;
+            for (int wv = 0; wv < W; wv++) val += spart[(t * W + wv) * 13 + k];
+        } else {
+            val = snode[t * kStageNodeStride + (k == MF_CX ? SN_U0 : k == MF_CY ? SN_U1 : SN_U2)];
+        }
+        I.mom[((size_t)i * I.nslices + it.slice) * kMomStride + k] = val;
     }
 }
 
@@ -469,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) k_snapshot(const DevInstance* __restri
     const DevInstance& I = insts[blockIdx.y];
     if (!I.flags[1]) return;
     for (int i = threadIdx.x; i < I.nr; i += kBlock) {
-        const Macro m = macro_from_sums(I.mom + (size_t)i * kMomStride);
+        const Macro m = macro_of_node(I, i);
         double* s = I.snap + (size_t)i * 5;
         s[0] = m.n;
         s[1] = m.u[0];
@@ -487,7 +887,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(const DevInstance* __restri
     __shared__ double smax[kBlock];
     double r = 0;
     for (int i = threadIdx.x; i < I.nr; i += kBlock) {
-        const Macro m = macro_from_sums(I.mom + (size_t)i * kMomStride);
+        const Macro m = macro_of_node(I, i);
         const double* s = I.snap + (size_t)i * 5;
         const double d[5] = {m.n - s[0], m.u[0] - s[1], m.u[1] - s[2], m.u[2] - s[3], m.T - s[4]};
         for (int k = 0; k < 5; k++) {
@@ -528,6 +928,34 @@ hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int m
     hipLaunchKernelGGL(k_stage, dim3(maxnr, ninst), dim3(kBlock), (size_t)maxnv * sizeof(double), s, d, src, fn, dst,
                        an, bs, mode);
     return hipGetLastError();
+}
+
+template <int VPT>
+static hipError_t launch_stage2_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
+                                  int fn, int dst, double an, double bs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage2<VPT>, dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d,
+                       items, G, src, fn, dst, an, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
+                         int dst, double an, double bs, hipStream_t s)
+{
+    switch (G.vpt) {
+        case 1: return launch_stage2_t<1>(d, items, nitems, G, src, fn, dst, an, bs, s);
+        case 2: return launch_stage2_t<2>(d, items, nitems, G, src, fn, dst, an, bs, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_stage2_smem_limit()
+{
+    const int bytes = 160 * 1024;
+    hipError_t e = hipSuccess;
+    e = hipFuncSetAttribute((const void*)k_stage2<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_stage2<2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
 }
 
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s)
