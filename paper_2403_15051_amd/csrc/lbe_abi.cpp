@@ -15,7 +15,8 @@
 
 namespace lbe {
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s);
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s);
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int lds_doubles, hipStream_t s);
+hipError_t set_node_smem_limit(int lds_doubles);
 hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
                                double an, double bs, int mode, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
@@ -39,6 +40,7 @@ struct lbe_ctx {
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int ninst = 0, maxnr = 0, maxnv = 0;
+    int node_lds = 0;  // doubles of dynamic LDS of the node kernel (instance tables)
     std::vector<int64_t> steps;
     std::vector<int32_t> active;
     std::string err;
@@ -157,13 +159,13 @@ bool layout_group(StageGroup* G)
     G->vpt = (G->nvs + block - 1) / block;
     if (G->vpt > 2) return false;
     const int W = block / 64, ng = n0 + n1 + n2, cs = n0 + 1;
-    for (int NT = 8; NT >= 1; NT /= 2) {
+    for (int NT = 16; NT >= 1; NT /= 2) {
         G->NT = NT;
         int o = 0;
         G->off_plane = o;
         o += cs * G->plane_cols;
-        G->off_ibuf = o;
-        o += cs * G->ncols_s;
+        G->off_ibuf = o;  // d0, d1 (, d2) term planes
+        o += (G->geometry == LBE_SPH ? 3 : 2) * cs * G->ncols_s;
         G->off_K1 = o;
         o += G->n0p * G->n0k;
         G->off_K2a = o;
@@ -213,7 +215,7 @@ lbe_status plan_groups(lbe_ctx* c)
         long tot = 0;
         for (int k = 0; k < c->ninst; k++) {
             const StageGroup& G = c->groups[c->group_of[k]];
-            tot += (long)((c->tabs[k].nr + 7) / 8) * G.S;
+            tot += (long)((c->tabs[k].nr + 15) / 16) * G.S;
         }
         return tot;
     };
@@ -310,7 +312,7 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->stream);
+    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->node_lds, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
@@ -439,6 +441,11 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
             }
             c->maxnr = std::max(c->maxnr, c->tabs[k].nr);
             c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
+            const InstanceTables& t = c->tabs[k];
+            const int M = (int)t.ax[0].qy.size();
+            const int need = M * (t.ax[0].N + 3) + t.n0 + t.n0 * (t.ax[0].N + 1) + t.n1 * (t.ax[1].N + 1) +
+                             t.n2 * (t.ax[2].N + 1) + t.n0 + t.n1 + t.n2;
+            c->node_lds = std::max(c->node_lds, need);
         }
     }
     st = plan_groups(c);
@@ -558,6 +565,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
                            c->stream);
     if (e == hipSuccess) e = set_stage_smem_limit(c->maxnv);
     if (e == hipSuccess) e = set_stage2_smem_limit();
+    if (e == hipSuccess) e = set_node_smem_limit(c->node_lds);
     if (e != hipSuccess) {
         st = dev_err(c, e, "lbe_init upload");
         delete c;

@@ -212,16 +212,40 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         return;
     }
 
+    // tables of the instance staged in LDS (coalesced loads, reused by every node of the chunk)
+    extern __shared__ double dyn[];
+    const int n0 = I.n0, n1 = I.n1, n2 = I.n2, N0 = I.N0, N1 = I.N1, N2 = I.N2, M = I.M0;
+    double* tqy = dyn;
+    double* tql = tqy + M;
+    double* tqh = tql + M;
+    double* tp0 = tqh + M * (N0 + 1);
+    double* tpoly0 = tp0 + n0;
+    double* tpoly1 = tpoly0 + n0 * (N0 + 1);
+    double* tpoly2 = tpoly1 + n1 * (N1 + 1);
+    double* tw = tpoly2 + n2 * (N2 + 1);  // w0 | w1 | w2
+    for (int e = threadIdx.x; e < M; e += kBlock) {
+        tqy[e] = I.qy0[e];
+        tql[e] = I.qlam0[e];
+    }
+    for (int e = threadIdx.x; e < M * (N0 + 1); e += kBlock) tqh[e] = I.qh0[e];
+    for (int e = threadIdx.x; e < n0; e += kBlock) tp0[e] = I.p0[e];
+    for (int e = threadIdx.x; e < n0 * (N0 + 1); e += kBlock) tpoly0[e] = I.poly0[e];
+    for (int e = threadIdx.x; e < n1 * (N1 + 1); e += kBlock) tpoly1[e] = I.poly1[e];
+    for (int e = threadIdx.x; e < n2 * (N2 + 1); e += kBlock) tpoly2[e] = I.poly2[e];
+    for (int e = threadIdx.x; e < n0 + n1 + n2; e += kBlock)
+        tw[e] = e < n0 ? I.w0[e] : e < n0 + n1 ? I.w1[e - n0] : I.w2[e - n0 - n1];
+
     // Node chunk [c0, c1) with a halo of kHalo nodes for the gradient stencils.
     const int c0 = bx * kNodeChunk, c1 = min(nr, c0 + kNodeChunk);
     const int h0 = max(0, c0 - kHalo), h1 = min(nr, c1 + kHalo);
     const int nh = h1 - h0;
-    __shared__ double sn[kNodeChunk + 2 * kHalo], sT[kNodeChunk + 2 * kHalo], su[3][kNodeChunk + 2 * kHalo];
-    __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo],
-        snbar[kNodeChunk + 2 * kHalo];
+    __shared__ double sT[kNodeChunk + 2 * kHalo], su[3][kNodeChunk + 2 * kHalo];
+    __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo];
     __shared__ Macro smac[kNodeChunk];
     __shared__ double sdens[kMaxNr];
     __shared__ double snb[kNodeChunk + 2 * kHalo];
+    __shared__ double sI[kNodeChunk][2][kMaxN + 1], sc1[kNodeChunk][kMaxN + 2], sc2[kNodeChunk][kMaxN + 2];
+    __shared__ double sPart[kNodeChunk][2][4][kMaxN + 1];
     // densities of every node (slice sums), then the averaged density of the chunk + halo,
     // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row
     for (int j = threadIdx.x; j < nr; j += kBlock) {
@@ -238,6 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
             const int lo = I.wlo[j];
             const double* wrow = I.wb + (size_t)j * I.wband;
             double part = 0;
+#pragma unroll 8
             for (int k2 = sub; k2 < I.wband; k2 += 8) {
                 const int col = lo + k2;
                 if (col < nr) part += wrow[k2] * sdens[col];
@@ -250,18 +275,14 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         }
     }
     __syncthreads();
-    __shared__ double sI[kNodeChunk][2][kMaxN + 1], sc1[kNodeChunk][kMaxN + 2], sc2[kNodeChunk][kMaxN + 2];
-    __shared__ double sPart[kNodeChunk][2][2][kMaxN + 1];
     for (int k = threadIdx.x; k < nh; k += kBlock) {
         const int j = h0 + k;
         const Macro m = macro_of_node(I, j);
         const double nb = snb[k];
         const double chi = chi_of(I.eta0 * nb);
-        sn[k] = m.n;
         sT[k] = m.T;
         for (int a = 0; a < 3; a++) su[a][k] = m.u[a];
         schi[k] = chi;
-        snbar[k] = nb;
         sG1[k] = log(m.n * m.n * chi * m.T);
         sG2[k] = log(m.T);
         if (j >= c0 && j < c1) smac[j - c0] = m;
@@ -314,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         nd[NF_DU0] = du0;
         nd[NF_DU1] = du1;
         nd[NF_DU2] = du2;
-        nd[NF_NBAR] = snbar[li];
+        nd[NF_NBAR] = snb[li];
         nd[NF_CHI] = chi;
         nd[NF_P01] = m.P01;
         nd[NF_SHAK] = (1 - Pr) / (n * T * T);
@@ -333,42 +354,47 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         full_coeffs<kMaxN>(m.u[1], T, I.N1, sc1[k]);
         full_coeffs<kMaxN>(m.u[2], T, I.N2, sc2[k]);
     }
-    // half-range projections: lanes = (node, side, half of the quadrature nodes)
+    // half-range projections: lanes = (node, side, quarter of the quadrature panels).  Panels
+    // farther than 9.6 sqrt(T) from u contribute below 1e-20 of the peak and are skipped.
     {
-        const int k = threadIdx.x >> 2, side = (threadIdx.x >> 1) & 1, part = threadIdx.x & 1;
+        const int k = threadIdx.x >> 3, side = (threadIdx.x >> 2) & 1, part = threadIdx.x & 3;
         if (k < c1 - c0) {
-            const int M = I.M0, m0 = part * M / 2, m1 = (part + 1) * M / 2;
             const double uu = side ? -smac[k].u[0] : smac[k].u[0];
-            half_projection_part(uu, smac[k].T, I.N0, m0, m1, I.qy0, I.qlam0, I.qh0, sPart[k][side][part]);
+            const double T = smac[k].T, reach = 9.6 * sqrt(T);
+            const int npan = M / 16;
+            int p0 = (int)floor((uu - reach) / 0.75), p1 = (int)ceil((uu + reach) / 0.75);
+            p0 = max(0, min(p0, npan));
+            p1 = max(p0, min(p1, npan));
+            const int pp0 = p0 + (p1 - p0) * part / 4, pp1 = p0 + (p1 - p0) * (part + 1) / 4;
+            half_projection_part(uu, T, N0, 16 * pp0, 16 * pp1, tqy, tql, tqh, sPart[k][side][part]);
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < (c1 - c0) * 2 * (I.N0 + 1); t += kBlock) {
-        const int l = t % (I.N0 + 1), side = (t / (I.N0 + 1)) & 1, k = t / (2 * (I.N0 + 1));
-        sI[k][side][l] = sPart[k][side][0][l] + sPart[k][side][1][l];
+    for (int t = threadIdx.x; t < (c1 - c0) * 2 * (N0 + 1); t += kBlock) {
+        const int l = t % (N0 + 1), side = (t / (N0 + 1)) & 1, k = t / (2 * (N0 + 1));
+        sI[k][side][l] = ((sPart[k][side][0][l] + sPart[k][side][1][l]) + sPart[k][side][2][l]) + sPart[k][side][3][l];
     }
     __syncthreads();
     // equilibrium factors g_R, g_1, g_2 of every node of the chunk
-    const int ng = I.n0 + I.n1 + I.n2;
+    const int ng = n0 + n1 + n2;
     for (int t = threadIdx.x; t < (c1 - c0) * ng; t += kBlock) {
         const int k = t / ng, e = t % ng, i = c0 + k;
         double val;
-        if (e < I.n0) {
-            const int N = I.N0;
-            const double* I_ = sI[k][I.p0[e] > 0 ? 0 : 1];
+        if (e < n0) {
+            const double* I_ = sI[k][tp0[e] > 0 ? 0 : 1];
             double acc = 0;
-            for (int l = 0; l <= N; l++) acc += I_[l] * I.poly0[e * (N + 1) + l];
-            val = I.w0[e] * acc;
-        } else if (e < I.n0 + I.n1) {
-            const int kk = e - I.n0, N = I.N1;
+            for (int l = 0; l <= N0; l++) acc += I_[l] * tpoly0[e * (N0 + 1) + l];
+            val = tw[e] * acc;
+        } else if (e < n0 + n1) {
+            const int kk = e - n0;
             double acc = 0;
-            for (int l = 0; l <= N; l++) acc += sc1[k][l] * I.poly1[kk * (N + 1) + l];
-            val = I.w1[kk] * acc;
+            for (int l = 0; l <= N1; l++) acc += sc1[k][l] * tpoly1[kk * (N1 + 1) + l];
+            val = tw[e] * acc;
         } else {
-            const int kk = e - I.n0 - I.n1, N = I.N2;
+            const int kk = e - n0 - n1;
             double acc = 0;
-            for (int l = 0; l <= N; l++) acc += sc2[k][l] * I.poly2[kk * (N + 1) + l];
-            val = I.w2[kk] * acc;
+            for (int l = 0; l <= N2; l++) acc += sc2[k][l] * tpoly2[kk * (N2 + 1) + l];
+            val = tw[e] * acc;
         }
         I.geq[(size_t)i * ng + e] = val;
     }
@@ -528,6 +554,62 @@ __device__ inline double wave_total(double v)
     return ((r0 + r1) + r2) + r3;
 }
 
+// A wave-uniform double moved to scalar registers (frees vector registers).
+__device__ inline double uniform(double x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// Reduce-scatter of 16 per-lane doubles over a wave64: after the call, every lane holds the
+// wave total of value (lane >> 2) & 15.  Lane halves are combined with v_permlane32_swap, row
+// pairs with v_permlane16_swap, then lanes xor 8, xor 4 (DPP row rotations / shifts) and the
+// quad (DPP quad_perm).  Fixed order, so reproducible.
+__device__ inline double swap32_sum(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+__device__ inline double swap16_sum(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+template <int CTRL, int BANK>
+__device__ inline double dpp_or_old(double old, double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, 0xf, BANK, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, 0xf, BANK, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double reduce_scatter16(const double* v, int lane)
+{
+    double r[8], t[4], u[2];
+#pragma unroll
+    for (int k = 0; k < 8; k++) r[k] = swap32_sum(v[k], v[k + 8]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) t[k] = swap16_sum(r[k], r[k + 4]);
+    const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double keep = b3 ? t[k + 2] : t[k], give = b3 ? t[k] : t[k + 2];
+        u[k] = keep + dpp_or_old<0x128, 0xf>(0.0, give);  // row_ror:8
+    }
+    const double keep = b2 ? u[1] : u[0], give = b2 ? u[0] : u[1];
+    double part = dpp_or_old<0x104, 0x5>(0.0, give);  // row_shl:4 on banks 0, 2
+    part = dpp_or_old<0x114, 0xa>(part, give);         // row_shr:4 on banks 1, 3
+    double w = keep + part;
+    w += dpp_or_old<0x4e, 0xf>(0.0, w);  // quad_perm [2,3,0,1]
+    w += dpp_or_old<0xb1, 0xf>(0.0, w);  // quad_perm [1,0,3,2]
+    return w;
+}
+
 // One RK stage for a tile of NT consecutive nodes x one velocity slice of one instance.
 // Lanes own velocities v = vs0 + tid + block * j (j < VPT) for the whole tile and keep, per
 // velocity, a register window of the 7 cells i-3 .. i+3 around the current node i, so every
@@ -537,7 +619,11 @@ __device__ inline double wave_total(double v)
 //   d0 = K1 P        (n0 x n0) x (n0 x columns)         rows = radial momentum
 //   d1 = K2a P_i2    (n1 x n1) x (n1 x n0) per i2
 //   d2 = K2b P'      (n2 x n2) x (n2 x n0 n1)           sphere only
-// accumulated, already multiplied by their momentum and geometry factors, into an LDS plane.
+// each into its own LDS plane, already multiplied by its momentum and geometry factor.
+// Two barriers per node: phase A (MFMA of node t, WENO face flux of node t) and phase B
+// (collision + RK combine + store of node t with its moment sums, reduced across the wave by
+// a register reduce-scatter; staging of node t+1's plane, prefetch of node t+2's window cell
+// and node t+1's f^n).
 template <int VPT>
 __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__ insts,
                                                   const WorkItem* __restrict__ items, const StageGroup G, int src,
@@ -551,36 +637,43 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6, W = B >> 6;
     const int cs = n0 + 1;  // LDS column stride
     const bool sph = G.geometry == LBE_SPH;
+    const bool need_fn = an != 0.0;  // stage 1 combines with f_src itself
     const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
     const int c_s0 = it.slice * G.ncols_s;      // first global column (i1 + n1 i2) of the slice
     const int cp0 = sph ? 0 : c_s0;            // first global column held in the LDS plane
     const int i2s0 = it.slice * G.ns2;          // first i2 of the slice
+    const int pslice = cs * G.ncols_s;          // size of one slice plane
     double* plane = lds + G.off_plane;
-    double* ibuf = lds + G.off_ibuf;
+    double* ib0 = lds + G.off_ibuf;             // d0 terms, then d1, d2 terms, then 2 output planes
+    double* ib1 = ib0 + pslice;
+    double* ib2 = ib1 + pslice;
     double* K1s = lds + G.off_K1;
     double* K2as = lds + G.off_K2a;
     double* K2bs = lds + G.off_K2b;
     double* snode = lds + G.off_node;
     double* sgeq = lds + G.off_geq;
     double* spart = lds + G.off_part;
+    double* sp = lds + G.off_p;
     const double* __restrict__ f = I.f[src];
+    const double* __restrict__ fN = I.f[fn];
+    double* __restrict__ fout = I.f[dst];
     const int ng = n0 + n1 + n2;
 
-    // ---- per-workgroup set-up: force matrices (zero-padded) and the tile's node data
+    // ---- per-workgroup set-up: force matrices (zero-padded), momentum nodes, node data
     for (int e = tid; e < G.n0p * G.n0k; e += B) {
         const int r = e / G.n0k, k = e % G.n0k;
         K1s[e] = (r < n0 && k < n0) ? I.K1[r * n0 + k] : 0.0;
     }
-    for (int e = tid; e < 16 * ((n1 + 15) / 16) * G.n1k; e += B) {
+    for (int e = tid; e < G.n1p * G.n1k; e += B) {
         const int r = e / G.n1k, k = e % G.n1k;
         K2as[e] = (r < n1 && k < n1) ? I.K2a[r * n1 + k] : 0.0;
     }
     if (sph)
         for (int e = tid; e < G.ns2p * G.n2k; e += B) {
             const int r = e / G.n2k, k = e % G.n2k;
-            const int rg = i2s0 + r;
-            K2bs[e] = (r < G.ns2 && k < n2) ? I.K2b[rg * n2 + k] : 0.0;
+            K2bs[e] = (r < G.ns2 && k < n2) ? I.K2b[(i2s0 + r) * n2 + k] : 0.0;
         }
+    for (int e = tid; e < ng; e += B) sp[e] = e < n0 ? I.p0[e] : e < n0 + n1 ? I.p1[e - n0] : I.p2[e - n0 - n1];
     for (int e = tid; e < it.nt * SN_COUNT; e += B) {
         const int t = e / SN_COUNT, fld = e % SN_COUNT, i = it.i0 + t;
         const double* nd = I.node + (size_t)i * kNodeStride;
@@ -615,70 +708,125 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
         sgeq[t * ng + k] = I.geq[(size_t)(it.i0 + t) * ng + k];
     }
 
-    // momentum nodes of the three axes
-    double* sp = lds + G.off_p;
-    for (int e = tid; e < ng; e += B) sp[e] = e < n0 ? I.p0[e] : e < n0 + n1 ? I.p1[e - n0] : I.p2[e - n0 - n1];
     // ---- per-lane velocities: v = vs0 + tid + B j; code = i0 | i1 << 8 | i2 << 16
     const double nwl = I.nw[0], nwr = I.nw[1];
     int code[VPT];
+    double prv[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
         const int v = min(vs0 + tid + B * j, vs1 - 1);
         const int i0 = v % n0, c = v / n0, i1 = c % n1, i2 = c / n1;
         code[j] = i0 | (i1 << 8) | (i2 << 16);
+        prv[j] = I.p0[i0];
     }
-    __syncthreads();
-    // ---- window of cells i0-3 .. i0+3 around the first node of the tile
-    double w[VPT][7];
-    double Fl[VPT];
+    // ---- window of cells i0-3 .. i0+3, f^n of the first node, the first node's plane
+    double w[VPT][7], Fl[VPT], wnext[VPT], fnv[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
         const int v = min(vs0 + tid + B * j, vs1 - 1);
-        const double pr = sp[code[j] & 0xff];
+        const double pr = prv[j];
 #pragma unroll
         for (int k = 0; k < 7; k++) w[j][k] = fcell(f, it.i0 - 3 + k, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
+        wnext[j] = fcell(f, it.i0 + 4, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
+        fnv[j] = need_fn ? fN[(size_t)it.i0 * nv + v] : 0.0;
         if (pr > 0)
             Fl[j] = (it.i0 == 0) ? pr * nwl * I.gwl[v] : pr * weno5(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4]);
         else
             Fl[j] = pr * weno5(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1]);
+        if (vs0 + tid + B * j < vs1) {
+            const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
+            plane[i0 + cs * (c - cp0)] = w[j][3];
+        }
     }
+    if (sph && G.S > 1)
+        for (int v = tid; v < nv; v += B)
+            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = f[(size_t)it.i0 * nv + v];
 
     const int nM1 = G.n0p / 16, nN1 = (G.ncols_s + 15) / 16;
-    const int nM2 = (n1 + 15) / 16, nN2 = G.n0p / 16;
+    const int nM2 = G.n1p / 16, nN2 = G.n0p / 16;
     const int nM3 = G.ns2p / 16, nN3 = (n0 * n1 + 15) / 16;
+    const int nT1 = nM1 * nN1, nT2 = G.ns2 * nM2 * nN2, nT3 = sph ? nM3 * nN3 : 0;
     const int q16 = lane & 15, q4 = lane >> 4;
 
+    __syncthreads();
     for (int t = 0; t < it.nt; t++) {
         const int i = it.i0 + t;
         const double* nd = snode + t * kStageNodeStride;
-        const double ffac = nd[SN_FFAC];
-        // prefetch the next window cell
-        double wnext[VPT];
+        const double ffac = uniform(nd[SN_FFAC]);
+        // ================= phase A: contractions of node t, face flux i+1, moments of node t-1
+        for (int tile = wave; tile < nT1 + nT2 + nT3; tile += W) {
+            v4d acc = {0, 0, 0, 0};
+            if (tile < nT1) {  // d0 = K1 P into ib0, times ffac (p_1^2 [+ p_2^2])
+                const int mt = tile / nN1, ntl = tile % nN1;
+                const int col = ntl * 16 + q16;
+                const bool cok = col < G.ncols_s;
+                const double* bp = plane + cs * (c_s0 + (cok ? col : 0) - cp0);
+                const double* ap = K1s + (mt * 16 + q16) * G.n0k;
+                for (int ks = 0; ks < G.n0k; ks += 4) {
+                    const int k = ks + q4;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (cok && k < n0) ? bp[k] : 0.0, acc, 0, 0, 0);
+                }
+                if (cok) {
+                    const int cg = c_s0 + col;
+                    const double pyy = sp[n0 + cg % n1];
+                    double fac = pyy * pyy;
+                    if (sph) {
+                        const double pzz = sp[n0 + n1 + cg / n1];
+                        fac += pzz * pzz;
+                    }
+                    fac *= ffac;
 #pragma unroll
-        for (int j = 0; j < VPT; j++) {
-            const int v = min(vs0 + tid + B * j, vs1 - 1);
-            wnext[j] = fcell(f, i + 4, v, nr, nv, sp[code[j] & 0xff], nwl, nwr, I.gwl, I.gwr);
-        }
-        // stage the node's plane in LDS (own velocities; sphere slices also fetch the rest)
+                    for (int r = 0; r < 4; r++) {
+                        const int row = mt * 16 + q4 + 4 * r;
+                        if (row < n0) ib0[row + cs * col] = fac * acc[r];
+                    }
+                }
+            } else if (tile < nT1 + nT2) {  // d1 = K2a P_i2 into ib1, times -ffac p_r
+                const int tl = tile - nT1;
+                const int i2l = tl / (nM2 * nN2), rem = tl % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
+                const int i0c = ntl * 16 + q16;
+                const bool iok = i0c < n0;
+                const double* ap = K2as + (mt * 16 + q16) * G.n1k;
+                const double* bp = plane + (iok ? i0c : 0) + cs * (n1 * (i2s0 + i2l) - cp0);
+                for (int ks = 0; ks < G.n1k; ks += 4) {
+                    const int k = ks + q4;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (iok && k < n1) ? bp[cs * k] : 0.0, acc, 0, 0, 0);
+                }
+                if (iok) {
+                    const double fac = -ffac * sp[i0c];
 #pragma unroll
-        for (int j = 0; j < VPT; j++) {
-            const int v = vs0 + tid + B * j;
-            if (v < vs1) {
-                const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
-                plane[i0 + cs * (c - cp0)] = w[j][3];
+                    for (int r = 0; r < 4; r++) {
+                        const int jrow = mt * 16 + q4 + 4 * r;
+                        if (jrow < n1) ib1[i0c + cs * (jrow + n1 * i2l)] = fac * acc[r];
+                    }
+                }
+            } else {  // d2 = K2b P' into ib2, times -ffac p_r (sphere)
+                const int tl = tile - nT1 - nT2;
+                const int mt = tl / nN3, ntl = tl % nN3;
+                const int cp = ntl * 16 + q16;
+                const bool pok = cp < n0 * n1;
+                const int bi0 = pok ? cp % n0 : 0, bi1 = pok ? cp / n0 : 0;
+                const double* ap = K2bs + (mt * 16 + q16) * G.n2k;
+                const double* bp = plane + bi0 + cs * bi1;
+                for (int ks = 0; ks < G.n2k; ks += 4) {
+                    const int k = ks + q4;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (pok && k < n2) ? bp[cs * n1 * k] : 0.0, acc, 0, 0,
+                                                               0);
+                }
+                if (pok) {
+                    const double fac = -ffac * sp[bi0];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int krow = mt * 16 + q4 + 4 * r;
+                        if (krow < G.ns2) ib2[bi0 + cs * (bi1 + n1 * krow)] = fac * acc[r];
+                    }
+                }
             }
         }
-        if (sph && G.S > 1) {
-            for (int v = tid; v < nv; v += B) {
-                if (v >= vs0 && v < vs1) continue;
-                plane[(v % n0) + cs * (v / n0)] = f[(size_t)i * nv + v];
-            }
-        }
-        // face flux at i + 1 (upwind WENO-5; entering flux at the outer wall)
         double Fr[VPT];
 #pragma unroll
         for (int j = 0; j < VPT; j++) {
-            const double pr = sp[code[j] & 0xff];
+            const double pr = prv[j];
             if (pr > 0)
                 Fr[j] = pr * weno5(w[j][1], w[j][2], w[j][3], w[j][4], w[j][5]);
             else
@@ -686,167 +834,91 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                                       : pr * weno5(w[j][6], w[j][5], w[j][4], w[j][3], w[j][2]);
         }
         __syncthreads();
-        // ---- d0 = K1 P, scaled by ffac * (p_1^2 [+ p_2^2]) into ibuf
-        for (int tile = wave; tile < nM1 * nN1; tile += W) {
-            const int mt = tile / nN1, ntl = tile % nN1;
-            const int col = ntl * 16 + q16;  // column within the slice
-            const bool cok = col < G.ncols_s;
-            const double* bp = plane + cs * (c_s0 + (cok ? col : 0) - cp0);
-            const double* ap = K1s + (mt * 16 + q16) * G.n0k;
-            v4d acc = {0, 0, 0, 0};
-            for (int ks = 0; ks < G.n0k; ks += 4) {
-                const int k = ks + q4;
-                const double a = ap[k];
-                const double b = (cok && k < n0) ? bp[k] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-            }
-            if (cok) {
-                const int cg = c_s0 + col, ci1 = cg % n1, ci2 = cg / n1;
-                const double pyy = sp[n0 + ci1];
-                double fac = pyy * pyy;
-                if (sph) {
-                    const double pzz = sp[n0 + n1 + ci2];
-                    fac += pzz * pzz;
-                }
-                fac *= ffac;
+        // ================= phase B: combine and store node t; stage node t+1
+        {
+            const double n = uniform(nd[SN_N]), u0 = uniform(nd[SN_U0]), u1 = uniform(nd[SN_U1]);
+            const double u2 = uniform(nd[SN_U2]), T = uniform(nd[SN_T]);
+            const double q0 = uniform(nd[SN_Q0]), q1 = uniform(nd[SN_Q1]), q2 = uniform(nd[SN_Q2]);
+            const double invtau = uniform(nd[SN_INVTAU]), shak = uniform(nd[SN_SHAK]);
+            const double brhochi = uniform(nd[SN_BRHOCHI]);
+            const double D1 = uniform(nd[SN_D1]), D2 = uniform(nd[SN_D2]), du0 = uniform(nd[SN_DU0]);
+            const double du2 = uniform(nd[SN_DU2]);
+            const double divu = uniform(nd[SN_DIVU]), sh01 = uniform(nd[SN_SH01]), urr = uniform(nd[SN_URR]);
+            const double adv_l = uniform(nd[SN_ADVL]), adv_r = uniform(nd[SN_ADVR]);
+            const double inv2T = uniform(1 / (2 * T)), inv5T = uniform(1 / (5 * T));
+            const double* gR = sgeq + t * ng;
+            const double* g1 = gR + n0;
+            const double* g2 = g1 + n1;
+            double acc[16];
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int row = mt * 16 + q4 + 4 * r;
-                    if (row < n0) ibuf[row + cs * col] = fac * acc[r];
-                }
-            }
-        }
-        __syncthreads();
-        // ---- d1 = K2a P_i2 for each i2 of the slice, ibuf -= ffac p_r d1
-        for (int tile = wave; tile < G.ns2 * nM2 * nN2; tile += W) {
-            const int i2l = tile / (nM2 * nN2), rem = tile % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
-            const int i0c = ntl * 16 + q16;
-            const bool iok = i0c < n0;
-            const double* ap = K2as + (mt * 16 + q16) * G.n1k;
-            const double* bp = plane + (iok ? i0c : 0) + cs * (n1 * (i2s0 + i2l) - cp0);
-            v4d acc = {0, 0, 0, 0};
-            for (int ks = 0; ks < G.n1k; ks += 4) {
-                const int k = ks + q4;
-                const double a = ap[k];
-                const double b = (iok && k < n1) ? bp[cs * k] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-            }
-            if (iok) {
-                const double fac = ffac * sp[i0c];
+            for (int k = 0; k < 16; k++) acc[k] = 0;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int jrow = mt * 16 + q4 + 4 * r;
-                    if (jrow < n1) ibuf[i0c + cs * (jrow + n1 * i2l)] -= fac * acc[r];
+            for (int j = 0; j < VPT; j++) {
+                const int v = vs0 + tid + B * j;
+                const int i0 = code[j] & 0xff, i1 = code[j] >> 8 & 0xff, i2 = code[j] >> 16;
+                const int ib = i0 + cs * (i1 + n1 * i2 - c_s0);
+                const double pr = prv[j], py = sp[n0 + i1], pz = sp[n0 + n1 + i2];
+                const double A = adv_r * Fr[j] - adv_l * Fl[j];
+                double Iv = ib0[ib] + ib1[ib];
+                if (sph) Iv += ib2[ib];
+                const double fmb = n * gR[i0] * g1[i1] * g2[i2];
+                const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
+                const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
+                const double xq = x0 * q0 + x1 * q1 + x2 * q2;
+                const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
+                const double z2 = xi2 * inv2T;
+                const double zzgu = sph ? (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T
+                                        : (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T;
+                const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
+                const double fv = w[j][3];
+                const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
+                const double o = (need_fn ? an * fnv[j] : 0.0) + bs * (fv + I.dt * L);
+                if (v < vs1) {
+                    fout[(size_t)i * nv + v] = o;
+                    // moment sums of the stored value, shifted by the node's velocity
+                    acc[MF_S0] += o;
+                    acc[MF_S1X] += o * x0;
+                    acc[MF_S1Y] += o * x1;
+                    acc[MF_S1Z] += o * x2;
+                    acc[MF_SXX] += o * x0 * x0;
+                    acc[MF_SYY] += o * x1 * x1;
+                    acc[MF_SZZ] += o * x2 * x2;
+                    acc[MF_SXY] += o * x0 * x1;
+                    acc[MF_SXZ] += o * x0 * x2;
+                    acc[MF_SYZ] += o * x1 * x2;
+                    acc[MF_S3X] += o * xi2 * x0;
+                    acc[MF_S3Y] += o * xi2 * x1;
+                    acc[MF_S3Z] += o * xi2 * x2;
                 }
             }
-        }
-        if (sph) {
-            __syncthreads();
-            // ---- d2 = K2b P' (rows: i2 of the slice, columns: i0 + n0 i1), ibuf -= ffac p_r d2
-            for (int tile = wave; tile < nM3 * nN3; tile += W) {
-                const int mt = tile / nN3, ntl = tile % nN3;
-                const int cp = ntl * 16 + q16;
-                const bool pok = cp < n0 * n1;
-                const int bi0 = pok ? cp % n0 : 0, bi1 = pok ? cp / n0 : 0;
-                const double* ap = K2bs + (mt * 16 + q16) * G.n2k;
-                const double* bp = plane + bi0 + cs * bi1;
-                v4d acc = {0, 0, 0, 0};
-                for (int ks = 0; ks < G.n2k; ks += 4) {
-                    const int k = ks + q4;
-                    const double a = ap[k];
-                    const double b = (pok && k < n2) ? bp[cs * n1 * k] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                }
-                if (pok) {
-                    const double fac = ffac * sp[bi0];
+            {
+                const double tot = reduce_scatter16(acc, lane);
+                const int which = (lane >> 2) & 15;
+                if ((lane & 3) == 0 && which < 13) spart[(t * W + wave) * 13 + which] = tot;
+            }
+            // advance the window to node t+1, stage its plane, prefetch ahead
+            if (t + 1 < it.nt) {
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int krow = mt * 16 + q4 + 4 * r;
-                        if (krow < G.ns2) ibuf[bi0 + cs * (bi1 + n1 * krow)] -= fac * acc[r];
+                for (int j = 0; j < VPT; j++) {
+                    const int v = min(vs0 + tid + B * j, vs1 - 1);
+#pragma unroll
+                    for (int k = 0; k < 6; k++) w[j][k] = w[j][k + 1];
+                    w[j][6] = wnext[j];
+                    Fl[j] = Fr[j];
+                    wnext[j] = fcell(f, i + 5, v, nr, nv, prv[j], nwl, nwr, I.gwl, I.gwr);
+                    fnv[j] = need_fn ? fN[(size_t)(i + 1) * nv + v] : 0.0;
+                    if (vs0 + tid + B * j < vs1) {
+                        const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
+                        plane[i0 + cs * (c - cp0)] = w[j][3];
                     }
                 }
+                if (sph && G.S > 1)
+                    for (int v = tid; v < nv; v += B)
+                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = f[(size_t)(i + 1) * nv + v];
             }
         }
         __syncthreads();
-        // ---- advection, collision, RK combine, store and moment sums of the stored values
-        const double n = nd[SN_N], u0 = nd[SN_U0], u1 = nd[SN_U1], u2 = nd[SN_U2], T = nd[SN_T];
-        const double q0 = nd[SN_Q0], q1 = nd[SN_Q1], q2 = nd[SN_Q2];
-        const double invtau = nd[SN_INVTAU], shak = nd[SN_SHAK], brhochi = nd[SN_BRHOCHI];
-        const double D1 = nd[SN_D1], D2 = nd[SN_D2], du0 = nd[SN_DU0], du2 = nd[SN_DU2];
-        const double divu = nd[SN_DIVU], sh01 = nd[SN_SH01], urr = nd[SN_URR];
-        const double adv_l = nd[SN_ADVL], adv_r = nd[SN_ADVR];
-        const double inv2T = 1 / (2 * T), inv5T = 1 / (5 * T);
-        const double* gR = sgeq + t * ng;
-        const double* g1 = gR + n0;
-        const double* g2 = g1 + n1;
-        double* out = I.f[dst] + (size_t)i * nv;
-        const double* fnp = I.f[fn] + (size_t)i * nv;
-#pragma unroll
-        for (int j = 0; j < VPT; j++) {
-            const int v = vs0 + tid + B * j;
-            const int i0 = code[j] & 0xff, i1 = code[j] >> 8 & 0xff, i2 = code[j] >> 16;
-            const int ib = i0 + cs * (i1 + n1 * i2 - c_s0);
-            const double pr = sp[i0], py = sp[n0 + i1], pz = sp[n0 + n1 + i2];
-            const double A = adv_r * Fr[j] - adv_l * Fl[j];
-            const double Iv = ibuf[ib];
-            const double fmb = n * gR[i0] * g1[i1] * g2[i2];
-            const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
-            const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
-            const double xq = x0 * q0 + x1 * q1 + x2 * q2;
-            const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
-            const double z2 = xi2 * inv2T;
-            const double zzgu = sph ? (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T
-                                    : (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T;
-            const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
-            const double fv = w[j][3];
-            const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
-            if (v < vs1) {
-                const double o = an * fnp[v] + bs * (fv + I.dt * L);
-                out[v] = o;
-                ibuf[ib] = o;  // the stored value, for the moment sums below
-            }
-        }
-        __syncthreads();
-        // moment sums of the stored plane of this slice, shifted by the node's velocity
-        {
-            double acc[13];
-#pragma unroll
-            for (int k = 0; k < 13; k++) acc[k] = 0;
-            for (int v = vs0 + tid; v < vs1; v += B) {
-                const int i0 = v % n0, c = v / n0, i1 = c % n1, i2 = c / n1;
-                const double o = ibuf[i0 + cs * (c - c_s0)];
-                const double x0 = sp[i0] - u0, x1 = sp[n0 + i1] - u1, x2 = sp[n0 + n1 + i2] - u2;
-                const double y2s = x0 * x0 + x1 * x1 + x2 * x2;
-                acc[MF_S0] += o;
-                acc[MF_S1X] += o * x0;
-                acc[MF_S1Y] += o * x1;
-                acc[MF_S1Z] += o * x2;
-                acc[MF_SXX] += o * x0 * x0;
-                acc[MF_SYY] += o * x1 * x1;
-                acc[MF_SZZ] += o * x2 * x2;
-                acc[MF_SXY] += o * x0 * x1;
-                acc[MF_SXZ] += o * x0 * x2;
-                acc[MF_SYZ] += o * x1 * x2;
-                acc[MF_S3X] += o * y2s * x0;
-                acc[MF_S3Y] += o * y2s * x1;
-                acc[MF_S3Z] += o * y2s * x2;
-            }
-#pragma unroll
-            for (int k = 0; k < 13; k++) {
-                const double tot = wave_total(acc[k]);
-                if (lane == 0) spart[(t * W + wave) * 13 + k] = tot;
-            }
-        }
-        // advance the window
-#pragma unroll
-        for (int j = 0; j < VPT; j++) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) w[j][k] = w[j][k + 1];
-            w[j][6] = wnext[j];
-            Fl[j] = Fr[j];
-        }
     }
-    __syncthreads();
     // ---- moment sums of the tile's nodes (waves summed in order) for this slice
     for (int e = tid; e < it.nt * 16; e += B) {
         const int t = e / 16, k = e % 16, i = it.i0 + t;
@@ -915,11 +987,18 @@ hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, h
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s)
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int lds_doubles, hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
-    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src);
+    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), (size_t)lds_doubles * sizeof(double), s, d,
+                       src);
     return hipGetLastError();
+}
+
+hipError_t set_node_smem_limit(int lds_doubles)
+{
+    return hipFuncSetAttribute((const void*)k_node, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds_doubles * (int)sizeof(double));
 }
 
 hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
