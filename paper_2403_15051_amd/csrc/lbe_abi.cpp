@@ -15,8 +15,7 @@
 
 namespace lbe {
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s);
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int lds_doubles, hipStream_t s);
-hipError_t set_node_smem_limit(int lds_doubles);
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, bool with_geq, hipStream_t s);
 hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
                                double an, double bs, int mode, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
@@ -40,7 +39,6 @@ struct lbe_ctx {
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int ninst = 0, maxnr = 0, maxnv = 0;
-    int node_lds = 0;  // doubles of dynamic LDS of the node kernel (instance tables)
     std::vector<int64_t> steps;
     std::vector<int32_t> active;
     std::string err;
@@ -159,7 +157,9 @@ bool layout_group(StageGroup* G)
     G->vpt = (G->nvs + block - 1) / block;
     if (G->vpt > 2) return false;
     const int W = block / 64, ng = n0 + n1 + n2, cs = n0 + 1;
-    for (int NT = 16; NT >= 1; NT /= 2) {
+    int nt0 = 16;
+    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(64, std::atoi(e)));
+    for (int NT = nt0; NT >= 1; NT /= 2) {
         G->NT = NT;
         int o = 0;
         G->off_plane = o;
@@ -167,11 +167,15 @@ bool layout_group(StageGroup* G)
         G->off_ibuf = o;  // d0, d1 (, d2) term planes
         o += (G->geometry == LBE_SPH ? 3 : 2) * cs * G->ncols_s;
         G->off_K1 = o;
-        o += G->n0p * G->n0k;
+        o += G->n0p * (G->n0k + 1);
         G->off_K2a = o;
-        o += G->n1p * G->n1k;
+        o += G->n1p * (G->n1k + 1);
         G->off_K2b = o;
-        o += (G->geometry == LBE_SPH) ? G->ns2p * G->n2k : 0;
+        o += (G->geometry == LBE_SPH) ? G->ns2p * (G->n2k + 1) : 0;
+        G->off_colfac = o;
+        o += G->ncols_s;
+        G->off_cpinfo = o;  // ints, two per double
+        o += (G->geometry == LBE_SPH) ? (n0 * n1 + 1) / 2 : 0;
         G->off_node = o;
         o += NT * kStageNodeStride;
         G->off_geq = o;
@@ -236,11 +240,14 @@ lbe_status plan_groups(lbe_ctx* c)
         G.S = nextS;
     }
     for (StageGroup& G : c->groups) {
-        // prefer one velocity per lane: slice while a slice holds more than 1024 velocities
+        // one velocity per lane and workgroups of at most `cap` lanes: slice while a slice holds
+        // more velocities than that (LBE_SLICE_CAP overrides the default for tuning)
+        int cap = 1024;
+        if (const char* e = std::getenv("LBE_SLICE_CAP")) cap = std::max(64, std::atoi(e));
         for (;;) {
             int nextS = G.S + 1;
             while (nextS <= G.n2 && G.n2 % nextS) nextS++;
-            if (G.nv / G.S <= 1024 || nextS > G.n2) break;
+            if (G.nv / G.S <= cap || nextS > G.n2) break;
             G.S = nextS;
         }
         // split further if the velocity set needs more than two per lane or the LDS does not fit
@@ -312,7 +319,7 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->node_lds, c->stream);
+    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, mode != 0, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
@@ -441,11 +448,6 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
             }
             c->maxnr = std::max(c->maxnr, c->tabs[k].nr);
             c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
-            const InstanceTables& t = c->tabs[k];
-            const int M = (int)t.ax[0].qy.size();
-            const int need = M * (t.ax[0].N + 3) + t.n0 + t.n0 * (t.ax[0].N + 1) + t.n1 * (t.ax[1].N + 1) +
-                             t.n2 * (t.ax[2].N + 1) + t.n0 + t.n1 + t.n2;
-            c->node_lds = std::max(c->node_lds, need);
         }
     }
     st = plan_groups(c);
@@ -565,7 +567,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
                            c->stream);
     if (e == hipSuccess) e = set_stage_smem_limit(c->maxnv);
     if (e == hipSuccess) e = set_stage2_smem_limit();
-    if (e == hipSuccess) e = set_node_smem_limit(c->node_lds);
+
     if (e != hipSuccess) {
         st = dev_err(c, e, "lbe_init upload");
         delete c;

@@ -11,7 +11,7 @@ namespace lbe {
 
 constexpr int kMaxQ = 64;    // largest quadrature order per axis
 constexpr int kMaxN = 15;    // largest equilibrium expansion order
-constexpr int kNodeStride = 32;  // doubles per node in the node-coefficient block
+constexpr int kNodeStride = 96;  // doubles per node in the node-coefficient block
 constexpr int kMomStride = 16;   // doubles per node in the moment-sum block
 
 // Node-coefficient block layout (doubles, per node), written by the node kernel.
@@ -19,7 +19,10 @@ enum NodeField {
     NF_N = 0, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_Q1, NF_Q2,
     NF_TAU, NF_PR, NF_BRHOCHI, NF_D1, NF_D2, NF_DU0, NF_DU1, NF_DU2,
     NF_NBAR, NF_CHI, NF_P01, NF_SHAK, NF_INVTAU, NF_DIVU, NF_SHEAR01, NF_UPHI_R,
-    NF_UR_R, NF_NW_L, NF_NW_R, NF_COUNT
+    NF_UR_R, NF_INV2T, NF_INV5T, NF_COUNT,
+    // equilibrium projection coefficients (Sec. III.C): half-range I_l^+ and I_l^- of the
+    // radial axis, full-range c_l of the two transverse axes (16 slots each)
+    NF_IPLUS = 32, NF_IMINUS = 48, NF_C1 = 64, NF_C2 = 80
 };
 
 // Moment-sum block layout (doubles, per node), written by the stage kernel: sums of f times
@@ -98,13 +101,14 @@ struct StageGroup {
     int32_t S, ns2, nvs, ncols_s, plane_cols;  // slices, i2 per slice, velocities / columns per slice
     int32_t n0k, n1k, n2k, n0p, n1p, ns2p;     // K padded to 4, M/N padded to 16
     int32_t NT, block, vpt;
-    int32_t off_plane, off_ibuf, off_K1, off_K2a, off_K2b, off_node, off_geq, off_part, off_p, lds_doubles;
+    int32_t off_plane, off_ibuf, off_K1, off_K2a, off_K2b, off_node, off_geq, off_part, off_p, off_colfac,
+        off_cpinfo, lds_doubles;
 };
 
 // Per-node fields the stage kernel stages in LDS (subset of the node block plus geometry).
 enum StageNodeField {
     SN_N = 0, SN_U0, SN_U1, SN_U2, SN_T, SN_Q0, SN_Q1, SN_Q2, SN_INVTAU, SN_SHAK, SN_BRHOCHI, SN_D1, SN_D2,
-    SN_DU0, SN_DU2, SN_DIVU, SN_SH01, SN_URR, SN_ADVL, SN_ADVR, SN_FFAC, SN_COUNT
+    SN_DU0, SN_DU2, SN_DIVU, SN_SH01, SN_URR, SN_ADVL, SN_ADVR, SN_FFAC, SN_INV2T, SN_INV5T, SN_COUNT
 };
 constexpr int kStageNodeStride = 24;
 

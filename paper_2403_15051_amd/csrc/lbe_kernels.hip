@@ -49,6 +49,14 @@ __device__ inline double weno5(double a, double b, double c, double d, double e)
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
+// Loads and stores through explicit global (address space 1) pointers: generic pointers
+// would compile to flat accesses, whose completion is tracked together with LDS traffic, so a
+// prefetch would stall the next LDS wait.
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ inline double gload(const double* p) { return *(gcdouble*)p; }
+__device__ inline void gstore(double* p, double v) { *(gdouble*)p = v; }
+
 template <typename T>
 __device__ inline T wave_sum(T v)
 {
@@ -129,16 +137,72 @@ __device__ inline double chi_of(double eta) { return (2 - eta) / (2 * (1 - eta) 
 __device__ inline double fcell(const double* __restrict__ f, int c, int v, int nr, int nv, double pr, double nwl,
                                double nwr, const double* __restrict__ gwl, const double* __restrict__ gwr)
 {
-    if (c >= 0 && c < nr) return f[(size_t)c * nv + v];
+    if (c >= 0 && c < nr) return gload(f + (size_t)c * nv + v);
     if (c < 0) {
-        if (pr > 0) return nwl * gwl[v];
-        const double f0 = f[v], f1 = f[nv + v], f2 = f[2 * (size_t)nv + v];
+        if (pr > 0) return nwl * gload(gwl + v);
+        const double f0 = gload(f + v), f1 = gload(f + nv + v), f2 = gload(f + 2 * (size_t)nv + v);
         return c == -1 ? 3 * f0 - 3 * f1 + f2 : 6 * f0 - 8 * f1 + 3 * f2;
     }
-    if (pr < 0) return nwr * gwr[v];
+    if (pr < 0) return nwr * gload(gwr + v);
     const double* fl = f + (size_t)(nr - 1) * nv;
-    const double a = fl[v], b = fl[v - nv], c3 = fl[v - 2 * (size_t)nv];
+    const double a = gload(fl + v), b = gload(fl + v - nv), c3 = gload(fl + v - 2 * (size_t)nv);
     return c == nr ? 3 * a - 3 * b + c3 : 6 * a - 8 * b + 3 * c3;
+}
+
+// A wave-uniform double moved to scalar registers (frees vector registers).
+__device__ inline double uniform(double x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// Reduce-scatter of 16 per-lane doubles over a wave64: after the call, every lane holds the
+// wave total of value (lane >> 2) & 15.  Lane halves are combined with v_permlane32_swap, row
+// pairs with v_permlane16_swap, then lanes xor 8, xor 4 (DPP row rotations / shifts) and the
+// quad (DPP quad_perm).  Fixed order, so reproducible.
+__device__ inline double swap32_sum(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+__device__ inline double swap16_sum(double a, double b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+template <int CTRL, int BANK>
+__device__ inline double dpp_or_old(double old, double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, 0xf, BANK, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, 0xf, BANK, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double reduce_scatter16(const double* v, int lane)
+{
+    double r[8], t[4], u[2];
+#pragma unroll
+    for (int k = 0; k < 8; k++) r[k] = swap32_sum(v[k], v[k + 8]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) t[k] = swap16_sum(r[k], r[k + 4]);
+    const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double keep = b3 ? t[k + 2] : t[k], give = b3 ? t[k] : t[k + 2];
+        u[k] = keep + dpp_or_old<0x128, 0xf>(0.0, give);  // row_ror:8
+    }
+    const double keep = b2 ? u[1] : u[0], give = b2 ? u[0] : u[1];
+    double part = dpp_or_old<0x104, 0x5>(0.0, give);  // row_shl:4 on banks 0, 2
+    part = dpp_or_old<0x114, 0xa>(part, give);         // row_shr:4 on banks 1, 3
+    double w = keep + part;
+    w += dpp_or_old<0x4e, 0xf>(0.0, w);  // quad_perm [2,3,0,1]
+    w += dpp_or_old<0xb1, 0xf>(0.0, w);  // quad_perm [1,0,3,2]
+    return w;
 }
 
 // ------------------------------------------------------------------ moments of a state
@@ -212,29 +276,6 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         return;
     }
 
-    // tables of the instance staged in LDS (coalesced loads, reused by every node of the chunk)
-    extern __shared__ double dyn[];
-    const int n0 = I.n0, n1 = I.n1, n2 = I.n2, N0 = I.N0, N1 = I.N1, N2 = I.N2, M = I.M0;
-    double* tqy = dyn;
-    double* tql = tqy + M;
-    double* tqh = tql + M;
-    double* tp0 = tqh + M * (N0 + 1);
-    double* tpoly0 = tp0 + n0;
-    double* tpoly1 = tpoly0 + n0 * (N0 + 1);
-    double* tpoly2 = tpoly1 + n1 * (N1 + 1);
-    double* tw = tpoly2 + n2 * (N2 + 1);  // w0 | w1 | w2
-    for (int e = threadIdx.x; e < M; e += kBlock) {
-        tqy[e] = I.qy0[e];
-        tql[e] = I.qlam0[e];
-    }
-    for (int e = threadIdx.x; e < M * (N0 + 1); e += kBlock) tqh[e] = I.qh0[e];
-    for (int e = threadIdx.x; e < n0; e += kBlock) tp0[e] = I.p0[e];
-    for (int e = threadIdx.x; e < n0 * (N0 + 1); e += kBlock) tpoly0[e] = I.poly0[e];
-    for (int e = threadIdx.x; e < n1 * (N1 + 1); e += kBlock) tpoly1[e] = I.poly1[e];
-    for (int e = threadIdx.x; e < n2 * (N2 + 1); e += kBlock) tpoly2[e] = I.poly2[e];
-    for (int e = threadIdx.x; e < n0 + n1 + n2; e += kBlock)
-        tw[e] = e < n0 ? I.w0[e] : e < n0 + n1 ? I.w1[e - n0] : I.w2[e - n0 - n1];
-
     // Node chunk [c0, c1) with a halo of kHalo nodes for the gradient stencils.
     const int c0 = bx * kNodeChunk, c1 = min(nr, c0 + kNodeChunk);
     const int h0 = max(0, c0 - kHalo), h1 = min(nr, c1 + kHalo);
@@ -244,10 +285,8 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __shared__ Macro smac[kNodeChunk];
     __shared__ double sdens[kMaxNr];
     __shared__ double snb[kNodeChunk + 2 * kHalo];
-    __shared__ double sI[kNodeChunk][2][kMaxN + 1], sc1[kNodeChunk][kMaxN + 2], sc2[kNodeChunk][kMaxN + 2];
-    __shared__ double sPart[kNodeChunk][2][4][kMaxN + 1];
     // densities of every node (slice sums), then the averaged density of the chunk + halo,
-    // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row
+    // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row, loads batched by 8
     for (int j = threadIdx.x; j < nr; j += kBlock) {
         const double* b = I.mom + (size_t)j * I.nslices * kMomStride;
         double n = b[MF_S0];
@@ -257,15 +296,24 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __syncthreads();
     {
         const int grp = threadIdx.x >> 3, sub = threadIdx.x & 7;
+        const int wband = I.wband;
         for (int k = grp; k < nh; k += kBlock / 8) {
             const int j = h0 + k;
             const int lo = I.wlo[j];
-            const double* wrow = I.wb + (size_t)j * I.wband;
+            const double* wrow = I.wb + (size_t)j * wband;
             double part = 0;
-#pragma unroll 8
-            for (int k2 = sub; k2 < I.wband; k2 += 8) {
-                const int col = lo + k2;
-                if (col < nr) part += wrow[k2] * sdens[col];
+            for (int base = sub; base < wband; base += 64) {
+                double wv[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int k2 = base + 8 * u;
+                    wv[u] = (k2 < wband) ? wrow[k2] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int col = lo + base + 8 * u;
+                    if (base + 8 * u < wband && col < nr) part += wv[u] * sdens[col];
+                }
             }
             // combine the 8 partial sums of the group in a fixed order
             part += __shfl_down(part, 4, 8);
@@ -349,52 +397,82 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
             nd[NF_SHEAR01] = 0;
         }
         nd[NF_UR_R] = m.u[0] * invr;
+        nd[NF_INV2T] = 1 / (2 * T);
+        nd[NF_INV5T] = 1 / (5 * T);
         if (!(n > 0) || !(T > 0) || !isfinite(n) || !isfinite(T)) I.flags[0] = 1;
-        // equilibrium coefficients of the full-range axes
-        full_coeffs<kMaxN>(m.u[1], T, I.N1, sc1[k]);
-        full_coeffs<kMaxN>(m.u[2], T, I.N2, sc2[k]);
+        // equilibrium coefficients of the full-range axes (eq. (eq_gak_H))
+        full_coeffs<kMaxN>(m.u[1], T, I.N1, nd + NF_C1);
+        full_coeffs<kMaxN>(m.u[2], T, I.N2, nd + NF_C2);
     }
-    // half-range projections: lanes = (node, side, quarter of the quadrature panels).  Panels
-    // farther than 9.6 sqrt(T) from u contribute below 1e-20 of the peak and are skipped.
-    {
-        const int k = threadIdx.x >> 3, side = (threadIdx.x >> 2) & 1, part = threadIdx.x & 3;
-        if (k < c1 - c0) {
-            const double uu = side ? -smac[k].u[0] : smac[k].u[0];
-            const double T = smac[k].T, reach = 9.6 * sqrt(T);
-            const int npan = M / 16;
-            int p0 = (int)floor((uu - reach) / 0.75), p1 = (int)ceil((uu + reach) / 0.75);
-            p0 = max(0, min(p0, npan));
-            p1 = max(p0, min(p1, npan));
-            const int pp0 = p0 + (p1 - p0) * part / 4, pp1 = p0 + (p1 - p0) * (part + 1) / 4;
-            half_projection_part(uu, T, N0, 16 * pp0, 16 * pp1, tqy, tql, tqh, sPart[k][side][part]);
+}
+
+// Half-range projection coefficients I_l^+- (Sec. III.C) of every node: one wave per node,
+// the 64 lanes share the quadrature nodes of the panels within 9.6 sqrt(T) of +-u (farther
+// panels contribute below 1e-20 of the peak), and the 2 (N0+1) <= 32 sums are reduced with
+// the register reduce-scatter.  Runs after k_node (needs u_r and T of the node).
+__global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= I.nr) return;
+    double* nd = I.node + (size_t)i * kNodeStride;
+    const double u = nd[NF_U0], T = nd[NF_T];
+    const int N0 = I.N0, M = I.M0, npan = M / 16;
+    const double reach = 9.6 * sqrt(T), c = kInvSqrt2Pi / sqrt(T), inv2T = 1 / (2 * T);
+    double acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; k++) acc[k] = 0;
+    for (int side = 0; side < 2; side++) {
+        const double uu = side ? -u : u;
+        int p0 = (int)floor((uu - reach) / 0.75), p1 = (int)ceil((uu + reach) / 0.75);
+        p0 = max(0, min(p0, npan));
+        p1 = max(p0, min(p1, npan));
+        for (int m = 16 * p0 + lane; m < 16 * p1; m += 64) {
+            const double d = I.qy0[m] - uu;
+            const double gw = I.qlam0[m] * c * exp(-d * d * inv2T);
+            const double* h = I.qh0 + (size_t)m * (N0 + 1);
+#pragma unroll
+            for (int l = 0; l < 16; l++)
+                if (l <= N0) acc[side * 16 + l] += gw * h[l];
         }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < (c1 - c0) * 2 * (N0 + 1); t += kBlock) {
-        const int l = t % (N0 + 1), side = (t / (N0 + 1)) & 1, k = t / (2 * (N0 + 1));
-        sI[k][side][l] = ((sPart[k][side][0][l] + sPart[k][side][1][l]) + sPart[k][side][2][l]) + sPart[k][side][3][l];
+    // two reduce-scatters of 16 values: lanes (l >> 2) & 15 = l-index hold the totals
+    const double totp = reduce_scatter16(acc, lane);
+    const double totm = reduce_scatter16(acc + 16, lane);
+    const int which = (lane >> 2) & 15;
+    if ((lane & 3) == 0 && which <= N0) {
+        nd[NF_IPLUS + which] = totp;
+        nd[NF_IMINUS + which] = totm;
     }
-    __syncthreads();
-    // equilibrium factors g_R, g_1, g_2 of every node of the chunk
-    const int ng = n0 + n1 + n2;
-    for (int t = threadIdx.x; t < (c1 - c0) * ng; t += kBlock) {
-        const int k = t / ng, e = t % ng, i = c0 + k;
+}
+
+// Equilibrium factors g_R, g_1, g_2 of every node into I.geq (for the reference stage kernel).
+__global__ void __launch_bounds__(kBlock) k_geq(const DevInstance* __restrict__ insts)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.flags[1]) return;
+    const int ng = I.n0 + I.n1 + I.n2;
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < I.nr * ng; t += gridDim.x * kBlock) {
+        const int i = t / ng, e = t % ng;
+        const double* nd = I.node + (size_t)i * kNodeStride;
         double val;
-        if (e < n0) {
-            const double* I_ = sI[k][tp0[e] > 0 ? 0 : 1];
+        if (e < I.n0) {
+            const double* Ic = nd + (I.p0[e] > 0 ? NF_IPLUS : NF_IMINUS);
             double acc = 0;
-            for (int l = 0; l <= N0; l++) acc += I_[l] * tpoly0[e * (N0 + 1) + l];
-            val = tw[e] * acc;
-        } else if (e < n0 + n1) {
-            const int kk = e - n0;
+            for (int l = 0; l <= I.N0; l++) acc += Ic[l] * I.poly0[e * (I.N0 + 1) + l];
+            val = I.w0[e] * acc;
+        } else if (e < I.n0 + I.n1) {
+            const int kk = e - I.n0;
             double acc = 0;
-            for (int l = 0; l <= N1; l++) acc += sc1[k][l] * tpoly1[kk * (N1 + 1) + l];
-            val = tw[e] * acc;
+            for (int l = 0; l <= I.N1; l++) acc += nd[NF_C1 + l] * I.poly1[kk * (I.N1 + 1) + l];
+            val = I.w1[kk] * acc;
         } else {
-            const int kk = e - n0 - n1;
+            const int kk = e - I.n0 - I.n1;
             double acc = 0;
-            for (int l = 0; l <= N2; l++) acc += sc2[k][l] * tpoly2[kk * (N2 + 1) + l];
-            val = tw[e] * acc;
+            for (int l = 0; l <= I.N2; l++) acc += nd[NF_C2 + l] * I.poly2[kk * (I.N2 + 1) + l];
+            val = I.w2[kk] * acc;
         }
         I.geq[(size_t)i * ng + e] = val;
     }
@@ -554,62 +632,6 @@ __device__ inline double wave_total(double v)
     return ((r0 + r1) + r2) + r3;
 }
 
-// A wave-uniform double moved to scalar registers (frees vector registers).
-__device__ inline double uniform(double x)
-{
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-
-// Reduce-scatter of 16 per-lane doubles over a wave64: after the call, every lane holds the
-// wave total of value (lane >> 2) & 15.  Lane halves are combined with v_permlane32_swap, row
-// pairs with v_permlane16_swap, then lanes xor 8, xor 4 (DPP row rotations / shifts) and the
-// quad (DPP quad_perm).  Fixed order, so reproducible.
-__device__ inline double swap32_sum(double a, double b)
-{
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-__device__ inline double swap16_sum(double a, double b)
-{
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-template <int CTRL, int BANK>
-__device__ inline double dpp_or_old(double old, double x)
-{
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, 0xf, BANK, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, 0xf, BANK, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ inline double reduce_scatter16(const double* v, int lane)
-{
-    double r[8], t[4], u[2];
-#pragma unroll
-    for (int k = 0; k < 8; k++) r[k] = swap32_sum(v[k], v[k + 8]);
-#pragma unroll
-    for (int k = 0; k < 4; k++) t[k] = swap16_sum(r[k], r[k + 4]);
-    const bool b3 = lane & 8, b2 = lane & 4;
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        const double keep = b3 ? t[k + 2] : t[k], give = b3 ? t[k] : t[k + 2];
-        u[k] = keep + dpp_or_old<0x128, 0xf>(0.0, give);  // row_ror:8
-    }
-    const double keep = b2 ? u[1] : u[0], give = b2 ? u[0] : u[1];
-    double part = dpp_or_old<0x104, 0x5>(0.0, give);  // row_shl:4 on banks 0, 2
-    part = dpp_or_old<0x114, 0xa>(part, give);         // row_shr:4 on banks 1, 3
-    double w = keep + part;
-    w += dpp_or_old<0x4e, 0xf>(0.0, w);  // quad_perm [2,3,0,1]
-    w += dpp_or_old<0xb1, 0xf>(0.0, w);  // quad_perm [1,0,3,2]
-    return w;
-}
-
 // One RK stage for a tile of NT consecutive nodes x one velocity slice of one instance.
 // Lanes own velocities v = vs0 + tid + block * j (j < VPT) for the whole tile and keep, per
 // velocity, a register window of the 7 cells i-3 .. i+3 around the current node i, so every
@@ -634,10 +656,12 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
     const DevInstance& I = insts[it.inst];
     if (!I.flags[1]) return;
     const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2;
-    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6, W = B >> 6;
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, W = B >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile math on scalars
     const int cs = n0 + 1;  // LDS column stride
     const bool sph = G.geometry == LBE_SPH;
     const bool need_fn = an != 0.0;  // stage 1 combines with f_src itself
+    const int k1s = G.n0k + 1, k2as = G.n1k + 1, k2bs = G.n2k + 1;  // odd LDS row strides of K
     const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
     const int c_s0 = it.slice * G.ncols_s;      // first global column (i1 + n1 i2) of the slice
     const int cp0 = sph ? 0 : c_s0;            // first global column held in the LDS plane
@@ -660,19 +684,35 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
     const int ng = n0 + n1 + n2;
 
     // ---- per-workgroup set-up: force matrices (zero-padded), momentum nodes, node data
-    for (int e = tid; e < G.n0p * G.n0k; e += B) {
-        const int r = e / G.n0k, k = e % G.n0k;
+    for (int e = tid; e < G.n0p * k1s; e += B) {
+        const int r = e / k1s, k = e % k1s;
         K1s[e] = (r < n0 && k < n0) ? I.K1[r * n0 + k] : 0.0;
     }
-    for (int e = tid; e < G.n1p * G.n1k; e += B) {
-        const int r = e / G.n1k, k = e % G.n1k;
+    for (int e = tid; e < G.n1p * k2as; e += B) {
+        const int r = e / k2as, k = e % k2as;
         K2as[e] = (r < n1 && k < n1) ? I.K2a[r * n1 + k] : 0.0;
     }
     if (sph)
-        for (int e = tid; e < G.ns2p * G.n2k; e += B) {
-            const int r = e / G.n2k, k = e % G.n2k;
+        for (int e = tid; e < G.ns2p * k2bs; e += B) {
+            const int r = e / k2bs, k = e % k2bs;
             K2bs[e] = (r < G.ns2 && k < n2) ? I.K2b[(i2s0 + r) * n2 + k] : 0.0;
         }
+    // per-column factor of d0 (p_1^2 [+ p_2^2]) and, for the sphere, the (i0, i1) split of the
+    // d2 columns with their factor -p_r: avoids per-node integer division
+    double* colfac = lds + G.off_colfac;
+    int* cpinfo = (int*)(lds + G.off_cpinfo);
+    for (int e = tid; e < G.ncols_s; e += B) {
+        const int cg = c_s0 + e;
+        const double pyy = I.p1[cg % n1];
+        double fac = pyy * pyy;
+        if (sph) {
+            const double pzz = I.p2[cg / n1];
+            fac += pzz * pzz;
+        }
+        colfac[e] = fac;
+    }
+    if (sph)
+        for (int e = tid; e < n0 * n1; e += B) cpinfo[e] = (e % n0) | ((e / n0) << 8);
     for (int e = tid; e < ng; e += B) sp[e] = e < n0 ? I.p0[e] : e < n0 + n1 ? I.p1[e - n0] : I.p2[e - n0 - n1];
     for (int e = tid; e < it.nt * SN_COUNT; e += B) {
         const int t = e / SN_COUNT, fld = e % SN_COUNT, i = it.i0 + t;
@@ -699,13 +739,48 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
             case SN_URR: val = nd[NF_UR_R]; break;
             case SN_ADVL: val = I.geo[4 * i + 0]; break;
             case SN_ADVR: val = I.geo[4 * i + 1]; break;
+            case SN_INV2T: val = nd[NF_INV2T]; break;
+            case SN_INV5T: val = nd[NF_INV5T]; break;
             default: val = I.geo[4 * i + 2]; break;
         }
         snode[t * kStageNodeStride + fld] = val;
     }
+    // equilibrium factors of the tile's nodes from their projection coefficients (the l sums
+    // are unrolled to the largest order so their loads issue together)
     for (int e = tid; e < it.nt * ng; e += B) {
         const int t = e / ng, k = e % ng;
-        sgeq[t * ng + k] = I.geq[(size_t)(it.i0 + t) * ng + k];
+        const double* nd = I.node + (size_t)(it.i0 + t) * kNodeStride;
+        const double *cf, *poly, *wt;
+        int N, kk;
+        if (k < n0) {
+            cf = nd + (I.p0[k] > 0 ? NF_IPLUS : NF_IMINUS);
+            N = I.N0;
+            kk = k;
+            poly = I.poly0;
+            wt = I.w0;
+        } else if (k < n0 + n1) {
+            cf = nd + NF_C1;
+            N = I.N1;
+            kk = k - n0;
+            poly = I.poly1;
+            wt = I.w1;
+        } else {
+            cf = nd + NF_C2;
+            N = I.N2;
+            kk = k - n0 - n1;
+            poly = I.poly2;
+            wt = I.w2;
+        }
+        double cv[kMaxN + 1], pv[kMaxN + 1];
+#pragma unroll
+        for (int l = 0; l <= kMaxN; l++) {
+            cv[l] = l <= N ? cf[l] : 0.0;
+            pv[l] = l <= N ? poly[kk * (N + 1) + l] : 0.0;
+        }
+        double acc = 0;
+#pragma unroll
+        for (int l = 0; l <= kMaxN; l++) acc += cv[l] * pv[l];
+        sgeq[t * ng + k] = wt[kk] * acc;
     }
 
     // ---- per-lane velocities: v = vs0 + tid + B j; code = i0 | i1 << 8 | i2 << 16
@@ -728,9 +803,10 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
 #pragma unroll
         for (int k = 0; k < 7; k++) w[j][k] = fcell(f, it.i0 - 3 + k, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
         wnext[j] = fcell(f, it.i0 + 4, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
-        fnv[j] = need_fn ? fN[(size_t)it.i0 * nv + v] : 0.0;
+        fnv[j] = need_fn ? gload(fN + (size_t)it.i0 * nv + v) : 0.0;
         if (pr > 0)
-            Fl[j] = (it.i0 == 0) ? pr * nwl * I.gwl[v] : pr * weno5(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4]);
+            Fl[j] = (it.i0 == 0) ? pr * nwl * gload(I.gwl + v)
+                                 : pr * weno5(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4]);
         else
             Fl[j] = pr * weno5(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1]);
         if (vs0 + tid + B * j < vs1) {
@@ -740,7 +816,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
     }
     if (sph && G.S > 1)
         for (int v = tid; v < nv; v += B)
-            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = f[(size_t)it.i0 * nv + v];
+            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = gload(f + (size_t)it.i0 * nv + v);
 
     const int nM1 = G.n0p / 16, nN1 = (G.ncols_s + 15) / 16;
     const int nM2 = G.n1p / 16, nN2 = G.n0p / 16;
@@ -761,20 +837,14 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                 const int col = ntl * 16 + q16;
                 const bool cok = col < G.ncols_s;
                 const double* bp = plane + cs * (c_s0 + (cok ? col : 0) - cp0);
-                const double* ap = K1s + (mt * 16 + q16) * G.n0k;
+                const double* ap = K1s + (mt * 16 + q16) * k1s;
+                const int kval = cok ? n0 : 0;
                 for (int ks = 0; ks < G.n0k; ks += 4) {
                     const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (cok && k < n0) ? bp[k] : 0.0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[k] : 0.0, acc, 0, 0, 0);
                 }
                 if (cok) {
-                    const int cg = c_s0 + col;
-                    const double pyy = sp[n0 + cg % n1];
-                    double fac = pyy * pyy;
-                    if (sph) {
-                        const double pzz = sp[n0 + n1 + cg / n1];
-                        fac += pzz * pzz;
-                    }
-                    fac *= ffac;
+                    const double fac = colfac[col] * ffac;
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int row = mt * 16 + q4 + 4 * r;
@@ -786,11 +856,12 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                 const int i2l = tl / (nM2 * nN2), rem = tl % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
                 const int i0c = ntl * 16 + q16;
                 const bool iok = i0c < n0;
-                const double* ap = K2as + (mt * 16 + q16) * G.n1k;
+                const double* ap = K2as + (mt * 16 + q16) * k2as;
                 const double* bp = plane + (iok ? i0c : 0) + cs * (n1 * (i2s0 + i2l) - cp0);
+                const int kval = iok ? n1 : 0;
                 for (int ks = 0; ks < G.n1k; ks += 4) {
                     const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (iok && k < n1) ? bp[cs * k] : 0.0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[cs * k] : 0.0, acc, 0, 0, 0);
                 }
                 if (iok) {
                     const double fac = -ffac * sp[i0c];
@@ -805,13 +876,14 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                 const int mt = tl / nN3, ntl = tl % nN3;
                 const int cp = ntl * 16 + q16;
                 const bool pok = cp < n0 * n1;
-                const int bi0 = pok ? cp % n0 : 0, bi1 = pok ? cp / n0 : 0;
-                const double* ap = K2bs + (mt * 16 + q16) * G.n2k;
+                const int info = pok ? cpinfo[cp] : 0;
+                const int bi0 = info & 0xff, bi1 = info >> 8;
+                const double* ap = K2bs + (mt * 16 + q16) * k2bs;
                 const double* bp = plane + bi0 + cs * bi1;
+                const int kval = pok ? n2 : 0;
                 for (int ks = 0; ks < G.n2k; ks += 4) {
                     const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (pok && k < n2) ? bp[cs * n1 * k] : 0.0, acc, 0, 0,
-                                                               0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[cs * n1 * k] : 0.0, acc, 0, 0, 0);
                 }
                 if (pok) {
                     const double fac = -ffac * sp[bi0];
@@ -830,7 +902,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
             if (pr > 0)
                 Fr[j] = pr * weno5(w[j][1], w[j][2], w[j][3], w[j][4], w[j][5]);
             else
-                Fr[j] = (i == nr - 1) ? pr * nwr * I.gwr[min(vs0 + tid + B * j, vs1 - 1)]
+                Fr[j] = (i == nr - 1) ? pr * nwr * gload(I.gwr + min(vs0 + tid + B * j, vs1 - 1))
                                       : pr * weno5(w[j][6], w[j][5], w[j][4], w[j][3], w[j][2]);
         }
         __syncthreads();
@@ -845,7 +917,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
             const double du2 = uniform(nd[SN_DU2]);
             const double divu = uniform(nd[SN_DIVU]), sh01 = uniform(nd[SN_SH01]), urr = uniform(nd[SN_URR]);
             const double adv_l = uniform(nd[SN_ADVL]), adv_r = uniform(nd[SN_ADVR]);
-            const double inv2T = uniform(1 / (2 * T)), inv5T = uniform(1 / (5 * T));
+            const double inv2T = uniform(nd[SN_INV2T]), inv5T = uniform(nd[SN_INV5T]);
             const double* gR = sgeq + t * ng;
             const double* g1 = gR + n0;
             const double* g2 = g1 + n1;
@@ -874,7 +946,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                 const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
                 const double o = (need_fn ? an * fnv[j] : 0.0) + bs * (fv + I.dt * L);
                 if (v < vs1) {
-                    fout[(size_t)i * nv + v] = o;
+                    gstore(fout + (size_t)i * nv + v, o);
                     // moment sums of the stored value, shifted by the node's velocity
                     acc[MF_S0] += o;
                     acc[MF_S1X] += o * x0;
@@ -906,7 +978,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                     w[j][6] = wnext[j];
                     Fl[j] = Fr[j];
                     wnext[j] = fcell(f, i + 5, v, nr, nv, prv[j], nwl, nwr, I.gwl, I.gwr);
-                    fnv[j] = need_fn ? fN[(size_t)(i + 1) * nv + v] : 0.0;
+                    fnv[j] = need_fn ? gload(fN + (size_t)(i + 1) * nv + v) : 0.0;
                     if (vs0 + tid + B * j < vs1) {
                         const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
                         plane[i0 + cs * (c - cp0)] = w[j][3];
@@ -914,7 +986,7 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
                 }
                 if (sph && G.S > 1)
                     for (int v = tid; v < nv; v += B)
-                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = f[(size_t)(i + 1) * nv + v];
+                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = gload(f + (size_t)(i + 1) * nv + v);
             }
         }
         __syncthreads();
@@ -987,18 +1059,17 @@ hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, h
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int lds_doubles, hipStream_t s)
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, bool with_geq, hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
-    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), (size_t)lds_doubles * sizeof(double), s, d,
-                       src);
+    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
+    e = hipGetLastError();
+    if (e != hipSuccess || !with_geq) return e;
+    hipLaunchKernelGGL(k_geq, dim3(64, ninst), dim3(kBlock), 0, s, d);
     return hipGetLastError();
-}
-
-hipError_t set_node_smem_limit(int lds_doubles)
-{
-    return hipFuncSetAttribute((const void*)k_node, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds_doubles * (int)sizeof(double));
 }
 
 hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
