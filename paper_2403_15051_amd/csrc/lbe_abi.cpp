@@ -15,15 +15,12 @@
 
 namespace lbe {
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s);
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, bool with_geq, hipStream_t s);
-hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
-                               double an, double bs, int mode, hipStream_t s);
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
-hipError_t set_stage_smem_limit(int maxnv);
-hipError_t launch_stage2(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
-                         int dst, double an, double bs, hipStream_t s);
-hipError_t set_stage2_smem_limit();
+hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
+                        int dst, double an, double bs, int rhs, hipStream_t s);
+hipError_t set_stage_smem_limit();
 }  // namespace lbe
 
 using namespace lbe;
@@ -62,7 +59,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte layout of one instance inside the workspace.
 struct Layout {
-    size_t f[3], mom, node, geq, snap, resid, flags, nw, scratch;
+    size_t f[3], mom, node, snap, resid, flags, nw, scratch;
     size_t p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
     size_t total;
 };
@@ -81,7 +78,6 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t base)
     for (int k = 0; k < 3; k++) L.f[k] = take(plane);
     L.mom = take((size_t)t.nr * nslices * kMomStride * D);
     L.node = take((size_t)t.nr * kNodeStride * D);
-    L.geq = take((size_t)t.nr * (t.n0 + t.n1 + t.n2) * D);
     L.snap = take((size_t)t.nr * 5 * D);
     L.resid = take(D);
     L.flags = take(4 * sizeof(int32_t));
@@ -119,7 +115,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
     size_t b = 4 * align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
-               align256(nr * (n0 + n1 + n2) * D) + align256(nr * 5 * D) + 3 * 256;
+               align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
     b += 3 * align256((size_t)std::max(n0, std::max(n1, n2)) * N * D);
@@ -140,50 +136,75 @@ constexpr int kLdsDoubles = 160 * 1024 / 8;
 bool layout_group(StageGroup* G)
 {
     const int n0 = G->n0, n1 = G->n1, n2 = G->n2;
+    const bool sph = G->geometry == LBE_SPH;
     G->ns2 = n2 / G->S;
     G->nvs = G->nv / G->S;
     G->ncols_s = n1 * G->ns2;
-    G->plane_cols = G->geometry == LBE_SPH ? n1 * n2 : G->ncols_s;
+    G->ncols16 = (G->ncols_s + 15) / 16 * 16;
+    G->ncp16 = sph ? (n0 * n1 + 15) / 16 * 16 : 0;
+    G->plane_cols = sph ? n1 * n2 : G->ncols_s;
     G->n0k = (n0 + 3) / 4 * 4;
     G->n1k = (n1 + 3) / 4 * 4;
     G->n2k = (n2 + 3) / 4 * 4;
     G->n0p = (n0 + 15) / 16 * 16;
     G->n1p = (n1 + 15) / 16 * 16;
     G->ns2p = (G->ns2 + 15) / 16 * 16;
-    // one velocity per lane when the slice has at most 1024 velocities, else two
-    int block = std::min(1024, (G->nvs + 63) / 64 * 64);
-    block = std::max(block, 64);
-    G->block = block;
-    G->vpt = (G->nvs + block - 1) / block;
-    if (G->vpt > 2) return false;
-    const int W = block / 64, ng = n0 + n1 + n2, cs = n0 + 1;
+    // lanes: wh waves for the velocities with p_r > 0, wh for p_r < 0, one or two per lane
+    const int nh = (n0 / 2) * G->ncols_s;
+    if (nh <= 512) {
+        G->vpt = 1;
+        G->wh = (nh + 63) / 64;
+    } else if (nh <= 1024) {
+        G->vpt = 2;
+        G->wh = (nh + 127) / 128;
+    } else {
+        return false;
+    }
+    G->block = 128 * G->wh;
+    const int ng = n0 + n1 + n2, cs = n0 + 1;
+    // extent of the plane read by the MFMA operands, padding included (d0, d1, d2)
+    const int c_last = sph ? (G->S - 1) * G->ncols_s : 0;
+    int pmax = (G->n0k - 1) + cs * (c_last + G->ncols16 - 1);
+    pmax = std::max(pmax, (G->n0p - 1) + cs * ((sph ? n1 * (n2 - 1) : n1 * (G->ns2 - 1)) + G->n1k - 1));
+    if (sph) pmax = std::max(pmax, (n0 - 1) + cs * ((n1 - 1) + n1 * (G->n2k - 1)));
+    pmax = std::max(pmax, cs * G->plane_cols - 1);
+    const int op_sz = std::max((G->n0k - 1) + cs * (G->ncols16 - 1) + 1, cs * G->ncols_s);
+    const int nTm = G->ncols16 / 16;
+    const int nTall = nTm + (G->n0p / 16) * (G->ncols16 / 16) + G->ns2 * (G->n1p / 16) * (G->n0p / 16) +
+                      (sph ? (G->ns2p / 16) * (G->ncp16 / 16) : 0);
     int nt0 = 16;
-    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(64, std::atoi(e)));
+    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(16, std::atoi(e)));
     for (int NT = nt0; NT >= 1; NT /= 2) {
         G->NT = NT;
         int o = 0;
         G->off_plane = o;
-        o += cs * G->plane_cols;
+        o += pmax + 1;
+        G->off_op = o;
+        o += op_sz;
         G->off_ibuf = o;  // d0, d1 (, d2) term planes
-        o += (G->geometry == LBE_SPH ? 3 : 2) * cs * G->ncols_s;
+        o += (sph ? 3 : 2) * cs * G->ncols_s;
         G->off_K1 = o;
         o += G->n0p * (G->n0k + 1);
         G->off_K2a = o;
         o += G->n1p * (G->n1k + 1);
         G->off_K2b = o;
-        o += (G->geometry == LBE_SPH) ? G->ns2p * (G->n2k + 1) : 0;
-        G->off_colfac = o;
-        o += G->ncols_s;
+        o += sph ? G->ns2p * (G->n2k + 1) : 0;
+        G->off_colfac = o;  // d0 column factors, -p_r per radial node, -p_r per d2 column
+        o += G->ncols16 + G->n0p + G->ncp16;
         G->off_cpinfo = o;  // ints, two per double
-        o += (G->geometry == LBE_SPH) ? (n0 * n1 + 1) / 2 : 0;
-        G->off_node = o;
-        o += NT * kStageNodeStride;
+        o += (G->ncp16 + 1) / 2;
+        G->off_tdesc = o;   // ints
+        o += (nTall * 16 + 1) / 2;
+        G->off_y0p = o;
+        o += G->n0k * 16;
+        G->off_psi = o;
+        o += G->ncols16 * 16;
+        G->off_coef = o;
+        o += NT * kCoefStride;
         G->off_geq = o;
         o += NT * ng;
         G->off_part = o;
-        o += NT * W * 13;
-        G->off_p = o;
-        o += ng;
+        o += NT * nTm * 36;
         G->lds_doubles = o;
         if (o <= kLdsDoubles) return true;
     }
@@ -314,25 +335,21 @@ hipEvent_t next_event(lbe_ctx* c, int* idx)
 }
 
 // Node kernel then stage kernel of one RK stage, with events around each when timing.
-hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int mode)
+hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int rhs)
 {
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, mode != 0, c->stream);
+    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
         c->node_ev.push_back({a, b});
         (void)hipEventRecord(next_event(c, &x), c->stream);
     }
-    if (mode == 0) {
-        for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
-            e = launch_stage2(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an,
-                              bs, c->stream);
-    } else {
-        e = launch_stage_kernel(c->dev_desc, c->ninst, c->maxnr, c->maxnv, src, fn, dst, an, bs, mode, c->stream);
-    }
+    for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
+        e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an, bs,
+                         rhs, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &y), c->stream);
@@ -498,7 +515,6 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         for (int b = 0; b < 3; b++) d.f[b] = (double*)(ws + L.f[b]);
         d.mom = (double*)(ws + L.mom);
         d.node = (double*)(ws + L.node);
-        d.geq = (double*)(ws + L.geq);
         d.snap = (double*)(ws + L.snap);
         d.resid = (double*)(ws + L.resid);
         d.flags = (int32_t*)(ws + L.flags);
@@ -565,8 +581,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dev_desc, c->host_desc.data(), sizeof(DevInstance) * n_inst, hipMemcpyHostToDevice,
                            c->stream);
-    if (e == hipSuccess) e = set_stage_smem_limit(c->maxnv);
-    if (e == hipSuccess) e = set_stage2_smem_limit();
+    if (e == hipSuccess) e = set_stage_smem_limit();
 
     if (e != hipSuccess) {
         st = dev_err(c, e, "lbe_init upload");
@@ -618,7 +633,7 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     c->active[inst] = 1;
     st = upload_flags(c);
     if (st == LBE_OK)
-        st = dev_err(c, run_stage(c, 0, 0, 0, 0, 0, 1), "moments pass");
+        st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments pass");
     std::vector<double> node((size_t)d.nr * kNodeStride);
     if (st == LBE_OK)
         st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,

@@ -70,7 +70,6 @@ struct DevInstance {
     double* f[3];           // state buffers [nr][nv]; f[0] holds the state between steps
     double* mom;            // [nr][nslices][kMomStride] moment sums of the last written buffer (per slice)
     double* node;           // [nr][kNodeStride] node coefficients of the current stage
-    double* geq;            // [nr][n0 + n1 + n2] equilibrium factors of the current stage
     const double* p0; const double* p1; const double* p2;
     const double* K1; const double* K2a; const double* K2b;
     const double* w0; const double* w1; const double* w2;
@@ -98,19 +97,16 @@ struct WorkItem {
 // All sizes are uniform over the group; LDS offsets are in doubles.
 struct StageGroup {
     int32_t n0, n1, n2, nv, geometry;
-    int32_t S, ns2, nvs, ncols_s, plane_cols;  // slices, i2 per slice, velocities / columns per slice
-    int32_t n0k, n1k, n2k, n0p, n1p, ns2p;     // K padded to 4, M/N padded to 16
-    int32_t NT, block, vpt;
-    int32_t off_plane, off_ibuf, off_K1, off_K2a, off_K2b, off_node, off_geq, off_part, off_p, off_colfac,
-        off_cpinfo, lds_doubles;
+    int32_t S, ns2, nvs, ncols_s, ncols16, plane_cols;  // slices, i2 / velocities / columns per slice
+    int32_t ncp16;                                       // d2 columns (n0 n1, sphere) padded to 16
+    int32_t n0k, n1k, n2k, n0p, n1p, ns2p;              // K padded to 4, M/N padded to 16
+    int32_t NT, block, vpt, wh;                          // nodes per tile, lanes, velocities per lane,
+                                                         // waves per sign of the radial momentum
+    int32_t off_plane, off_op, off_ibuf, off_K1, off_K2a, off_K2b, off_colfac, off_cpinfo, off_tdesc, off_y0p,
+        off_psi, off_coef, off_geq, off_part, lds_doubles;
 };
 
-// Per-node fields the stage kernel stages in LDS (subset of the node block plus geometry).
-enum StageNodeField {
-    SN_N = 0, SN_U0, SN_U1, SN_U2, SN_T, SN_Q0, SN_Q1, SN_Q2, SN_INVTAU, SN_SHAK, SN_BRHOCHI, SN_D1, SN_D2,
-    SN_DU0, SN_DU2, SN_DIVU, SN_SH01, SN_URR, SN_ADVL, SN_ADVR, SN_FFAC, SN_INV2T, SN_INV5T, SN_COUNT
-};
-constexpr int kStageNodeStride = 24;
+constexpr int kCoefStride = 18;  // doubles per node of the stage kernel's coefficient block
 
 // Host table construction (lbe_tables.cpp).
 lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err);

@@ -1,17 +1,18 @@
 // Device kernels of liblbe (gfx950, FP64 state).
 //
-// One RK stage of every instance is two launches:
+// One RK stage of every instance is three launches:
 //   k_node  - per-node coefficients from the moment sums of the stage input (eqs. (macro_def),
-//             (fm), (chi), (viscosity)-(tau), (prandtl)), 4th-order radial gradients (Sec. III),
-//             the discrete equilibrium factors (Sec. III.C) and, in two extra blocks, the wall
-//             densities of diffuse reflection (zero net mass flux through each wall);
-//   k_stage - one workgroup per (node, instance): the node's velocity plane is staged in LDS
-//             for the momentum-derivative contractions (eqs. (force1)/(force2)); each lane
-//             takes velocities v = lane, lane + 256, ... (coalesced), evaluates WENO-5 fluxes
-//             at both faces of the cell (flux form of Sec. II.B/II.C), the inertial terms,
-//             Shakhov + J1 collision (eqs. (j0), (j1)), combines the TVD-RK3 stage and stores,
-//             and the workgroup reduces the moment sums of the stored plane (no atomics, fixed
-//             order, so runs are bitwise reproducible).
+//             (fm), (chi), (viscosity)-(tau), (prandtl)), 4th-order radial gradients (Sec. III)
+//             and, in two extra blocks, the wall densities of diffuse reflection (zero net mass
+//             flux through each wall);
+//   k_proj  - the half-range equilibrium projection coefficients of every node (Sec. III.C);
+//   k_stage - per launch group (instances sharing a velocity set), one workgroup per tile of
+//             consecutive nodes x velocity slice: WENO-5 fluxes in flux form (Sec. II.B/II.C),
+//             the momentum-derivative contractions (eqs. (force1)/(force2)) as FP64 MFMA tiles
+//             over an LDS plane, Shakhov + J1 collision (eqs. (j0), (j1)) as one cubic per
+//             lane, the TVD-RK3 combination, the store, and the moment sums of the stored
+//             plane (again MFMA tiles; no atomics, fixed order, so runs are bitwise
+//             reproducible).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -54,8 +55,6 @@ __device__ inline double weno5(double a, double b, double c, double d, double e)
 // prefetch would stall the next LDS wait.
 typedef __attribute__((address_space(1))) const double gcdouble;
 typedef __attribute__((address_space(1))) double gdouble;
-__device__ inline double gload(const double* p) { return *(gcdouble*)p; }
-__device__ inline void gstore(double* p, double v) { *(gdouble*)p = v; }
 
 template <typename T>
 __device__ inline T wave_sum(T v)
@@ -130,32 +129,6 @@ __device__ inline Macro macro_of_node(const DevInstance& I, int i)
 }
 
 __device__ inline double chi_of(double eta) { return (2 - eta) / (2 * (1 - eta) * (1 - eta) * (1 - eta)); }
-
-// Value of f at cell c (c may be a ghost: -2, -1, nr, nr+1) for velocity v with radial
-// momentum pr.  Entering velocities see n_w times the unit wall Maxwellian; leaving ones
-// the quadratic extrapolation of the three nearest cells.
-__device__ inline double fcell(const double* __restrict__ f, int c, int v, int nr, int nv, double pr, double nwl,
-                               double nwr, const double* __restrict__ gwl, const double* __restrict__ gwr)
-{
-    if (c >= 0 && c < nr) return gload(f + (size_t)c * nv + v);
-    if (c < 0) {
-        if (pr > 0) return nwl * gload(gwl + v);
-        const double f0 = gload(f + v), f1 = gload(f + nv + v), f2 = gload(f + 2 * (size_t)nv + v);
-        return c == -1 ? 3 * f0 - 3 * f1 + f2 : 6 * f0 - 8 * f1 + 3 * f2;
-    }
-    if (pr < 0) return nwr * gload(gwr + v);
-    const double* fl = f + (size_t)(nr - 1) * nv;
-    const double a = gload(fl + v), b = gload(fl + v - nv), c3 = gload(fl + v - 2 * (size_t)nv);
-    return c == nr ? 3 * a - 3 * b + c3 : 6 * a - 8 * b + 3 * c3;
-}
-
-// A wave-uniform double moved to scalar registers (frees vector registers).
-__device__ inline double uniform(double x)
-{
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
 
 // Reduce-scatter of 16 per-lane doubles over a wave64: after the call, every lane holds the
 // wave total of value (lane >> 2) & 15.  Lane halves are combined with v_permlane32_swap, row
@@ -448,242 +421,238 @@ __global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__
     }
 }
 
-// Equilibrium factors g_R, g_1, g_2 of every node into I.geq (for the reference stage kernel).
-__global__ void __launch_bounds__(kBlock) k_geq(const DevInstance* __restrict__ insts)
-{
-    const DevInstance& I = insts[blockIdx.y];
-    if (!I.flags[1]) return;
-    const int ng = I.n0 + I.n1 + I.n2;
-    for (int t = blockIdx.x * kBlock + threadIdx.x; t < I.nr * ng; t += gridDim.x * kBlock) {
-        const int i = t / ng, e = t % ng;
-        const double* nd = I.node + (size_t)i * kNodeStride;
-        double val;
-        if (e < I.n0) {
-            const double* Ic = nd + (I.p0[e] > 0 ? NF_IPLUS : NF_IMINUS);
-            double acc = 0;
-            for (int l = 0; l <= I.N0; l++) acc += Ic[l] * I.poly0[e * (I.N0 + 1) + l];
-            val = I.w0[e] * acc;
-        } else if (e < I.n0 + I.n1) {
-            const int kk = e - I.n0;
-            double acc = 0;
-            for (int l = 0; l <= I.N1; l++) acc += nd[NF_C1 + l] * I.poly1[kk * (I.N1 + 1) + l];
-            val = I.w1[kk] * acc;
-        } else {
-            const int kk = e - I.n0 - I.n1;
-            double acc = 0;
-            for (int l = 0; l <= I.N2; l++) acc += nd[NF_C2 + l] * I.poly2[kk * (I.N2 + 1) + l];
-            val = I.w2[kk] * acc;
-        }
-        I.geq[(size_t)i * ng + e] = val;
-    }
-}
-
 // ------------------------------------------------------------------ stage kernel
-
-// mode 0: out = an * f[fn] + bs * (f[src] + dt L(f[src])) stored in f[dst], with moment sums;
-// mode 1: L(f[src]) stored in scratch (no state change).
-__global__ void __launch_bounds__(kBlock) k_stage(const DevInstance* __restrict__ insts, int src, int fn, int dst,
-                                                  double an, double bs, int mode)
-{
-    const DevInstance& I = insts[blockIdx.y];
-    if (!I.flags[1]) return;
-    const int i = blockIdx.x;
-    const int nr = I.nr, nv = I.nv, n0 = I.n0, n1 = I.n1, n2 = I.n2;
-    if (i >= nr) return;
-    extern __shared__ double plane[];  // nv doubles
-    __shared__ double red[16 * 4];
-    __shared__ double snd[kNodeStride];
-    const double* __restrict__ f = I.f[src];
-    const double* fi = f + (size_t)i * nv;
-    for (int v = threadIdx.x; v < nv; v += kBlock) plane[v] = fi[v];
-    if (threadIdx.x < kNodeStride) snd[threadIdx.x] = I.node[(size_t)i * kNodeStride + threadIdx.x];
-    __syncthreads();
-
-    const int ng = n0 + n1 + n2;
-    const double* gR = I.geq + (size_t)i * ng;
-    const double* g1 = gR + n0;
-    const double* g2 = g1 + n1;
-    const double n = snd[NF_N], u0 = snd[NF_U0], u1 = snd[NF_U1], u2 = snd[NF_U2], T = snd[NF_T];
-    const double q0 = snd[NF_Q0], q1 = snd[NF_Q1], q2 = snd[NF_Q2];
-    const double invtau = snd[NF_INVTAU], shak = snd[NF_SHAK], brhochi = snd[NF_BRHOCHI];
-    const double D1 = snd[NF_D1], D2 = snd[NF_D2], du0 = snd[NF_DU0], du2 = snd[NF_DU2];
-    const double divu = snd[NF_DIVU], sh01 = snd[NF_SHEAR01], urr = snd[NF_UR_R];
-    const double inv2T = 1 / (2 * T), inv5T = 1 / (5 * T);
-    const double adv_l = I.geo[4 * i + 0], adv_r = I.geo[4 * i + 1], ffac = I.geo[4 * i + 2];
-    const double nwl = I.nw[0], nwr = I.nw[1];
-    const double dt = I.dt;
-    const bool cyl = I.geometry == LBE_CYL;
-    const double* fnp = I.f[fn] + (size_t)i * nv;
-    double* out = (mode == 0) ? I.f[dst] + (size_t)i * nv : I.scratch + (size_t)i * nv;
-
-    double acc[13];
-#pragma unroll
-    for (int k = 0; k < 13; k++) acc[k] = 0;
-
-    for (int v = threadIdx.x; v < nv; v += kBlock) {
-        const int i0 = v % n0, rest = v / n0, i1 = rest % n1, i2 = rest / n1;
-        const double pr = I.p0[i0], py = I.p1[i1], pz = I.p2[i2];
-        // ---- advection: flux form with WENO-5 face values, upwind by the sign of p_r
-        double Fl, Fr;
-        if (pr > 0) {
-            double c[6];  // cells i-3 .. i+2
-            for (int t = (i == 0 ? 1 : 0); t < 6; t++)
-                c[t] = fcell(f, i - 3 + t, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
-            Fl = (i == 0) ? pr * nwl * I.gwl[v] : pr * weno5(c[0], c[1], c[2], c[3], c[4]);
-            Fr = pr * weno5(c[1], c[2], c[3], c[4], c[5]);
-        } else {
-            double c[6];  // cells i-2 .. i+3
-            const int tmax = (i == nr - 1) ? 5 : 6;
-            for (int t = 0; t < tmax; t++) c[t] = fcell(f, i - 2 + t, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
-            Fl = pr * weno5(c[4], c[3], c[2], c[1], c[0]);
-            Fr = (i == nr - 1) ? pr * nwr * I.gwr[v] : pr * weno5(c[5], c[4], c[3], c[2], c[1]);
-        }
-        const double A = adv_r * Fr - adv_l * Fl;
-        // ---- inertial terms (momentum-derivative contractions on the LDS plane)
-        double d0 = 0, d1 = 0, d2 = 0;
-        {
-            const double* K = I.K1 + i0 * n0;
-            const double* col = plane + n0 * (i1 + n1 * i2);
-            for (int k = 0; k < n0; k++) d0 += K[k] * col[k];
-            const double* Ka = I.K2a + i1 * n1;
-            const double* rowa = plane + i0 + n0 * n1 * i2;
-            for (int k = 0; k < n1; k++) d1 += Ka[k] * rowa[n0 * k];
-            if (!cyl) {
-                const double* Kb = I.K2b + i2 * n2;
-                const double* rowb = plane + i0 + n0 * i1;
-                for (int k = 0; k < n2; k++) d2 += Kb[k] * rowb[n0 * n1 * k];
-            }
-        }
-        const double Iv = cyl ? ffac * (py * py * d0 - pr * d1) : ffac * ((py * py + pz * pz) * d0 - pr * (d1 + d2));
-        // ---- collision: Shakhov J0 and J1[f^MB] on the discrete equilibrium
-        const double fmb = n * gR[i0] * g1[i1] * g2[i2];
-        const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
-        const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
-        const double xq = x0 * q0 + x1 * q1 + x2 * q2;
-        const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
-        const double z2 = xi2 * inv2T;
-        const double zzgu = cyl ? (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T
-                                : (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T;
-        const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
-        const double fv = plane[v];
-        const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
-        if (mode == 1) {
-            out[v] = L;
-            continue;
-        }
-        const double o = an * fnp[v] + bs * (fv + dt * L);
-        out[v] = o;
-        // moment sums of the stored value, shifted by the current velocity
-        const double y0 = pr - u0, y1 = py - u1, y2 = pz - u2;
-        const double y2s = y0 * y0 + y1 * y1 + y2 * y2;
-        acc[MF_S0] += o;
-        acc[MF_S1X] += o * y0;
-        acc[MF_S1Y] += o * y1;
-        acc[MF_S1Z] += o * y2;
-        acc[MF_SXX] += o * y0 * y0;
-        acc[MF_SYY] += o * y1 * y1;
-        acc[MF_SZZ] += o * y2 * y2;
-        acc[MF_SXY] += o * y0 * y1;
-        acc[MF_SXZ] += o * y0 * y2;
-        acc[MF_SYZ] += o * y1 * y2;
-        acc[MF_S3X] += o * y2s * y0;
-        acc[MF_S3Y] += o * y2s * y1;
-        acc[MF_S3Z] += o * y2s * y2;
-    }
-    if (mode == 1) return;
-    block_sum<13>(acc, red);
-    if (threadIdx.x < 16) {
-        const int k = threadIdx.x;
-        double val;
-        if (k < 13)
-            val = red[k * 4];
-        else
-            val = (k == MF_CX) ? u0 : (k == MF_CY) ? u1 : u2;
-        I.mom[(size_t)i * I.nslices * kMomStride + k] = val;
-    }
-}
-
-// ------------------------------------------------------------------ tiled stage kernel
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// 64-lane sum of a double with DPP row shifts (within 16-lane rows) and lane reads across the
-// four rows; the result is valid in every lane.  Fixed order, so reproducible.
-template <int CTRL, int BANK_MASK>
-__device__ inline double dpp_shift(double x)
+// Global accesses of the stage kernel go through buffer resources: a uniform base and byte
+// extent in scalar registers, a per-lane byte offset and a uniform row offset.  Offsets beyond
+// the extent read as zero and drop stores instead of faulting.
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ inline rsrc_t make_rsrc(const void* base, size_t bytes)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, BANK_MASK, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, BANK_MASK, true);
-    return __hiloint2double(hi, lo);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double bload(rsrc_t r, unsigned voff, int soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ inline void bstore(rsrc_t r, unsigned voff, int soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
 }
 
-__device__ inline double wave_total(double v)
+// p_r times the WENO-5 reconstruction (Jiang-Shu, eps = 1e-6, power 2) at the downwind face of c
+// from (a, b, c, d, e) ordered along the upwind direction; pr6 = p_r / 6.  Written with the cell
+// differences: the three candidates are c + m_k / 6, the smoothness indicators
+// 12 beta_k = 13 t_k^2 + 3 s_k^2, and the weights d_k / (eps + beta_k)^2 are taken over their
+// common denominator.  The reciprocal is the hardware estimate refined by two Newton steps.
+__device__ inline double weno_flux(double a, double b, double c, double d, double e, double pr, double pr6)
 {
-    double s = v + dpp_shift<0x111, 0xf>(v);  // row_shr:1
-    s += dpp_shift<0x112, 0xf>(v);            // row_shr:2
-    s += dpp_shift<0x113, 0xf>(v);            // row_shr:3 -> 4 consecutive lanes
-    s += dpp_shift<0x114, 0xe>(s);            // row_shr:4 on banks 1..3
-    s += dpp_shift<0x118, 0xc>(s);            // row_shr:8 on banks 2..3 -> lane 15 of each row
-    const int lo = __double2loint(s), hi = __double2hiint(s);
-    double r0 = __hiloint2double(__builtin_amdgcn_readlane(hi, 15), __builtin_amdgcn_readlane(lo, 15));
-    double r1 = __hiloint2double(__builtin_amdgcn_readlane(hi, 31), __builtin_amdgcn_readlane(lo, 31));
-    double r2 = __hiloint2double(__builtin_amdgcn_readlane(hi, 47), __builtin_amdgcn_readlane(lo, 47));
-    double r3 = __hiloint2double(__builtin_amdgcn_readlane(hi, 63), __builtin_amdgcn_readlane(lo, 63));
-    return ((r0 + r1) + r2) + r3;
+    const double d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
+    const double t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
+    const double s0 = fma(2.0, d2, t0), s1 = d2 + d3, s2 = fma(-2.0, d3, t2);
+    const double e0 = fma(13.0 * t0, t0, fma(3.0 * s0, s0, 1.2e-5));
+    const double e1 = fma(13.0 * t1, t1, fma(3.0 * s1, s1, 1.2e-5));
+    const double e2 = fma(13.0 * t2, t2, fma(3.0 * s2, s2, 1.2e-5));
+    const double E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
+    const double w0 = E1 * E2, w1 = E0 * E2, w2 = E0 * E1;
+    const double den = fma(0.1, w0, fma(0.6, w1, 0.3 * w2));
+    // 0.1 m0, 0.6 m1, 0.3 m2 with m0 = 5 d2 - 2 d1, m1 = d2 + 2 d3, m2 = 4 d3 - d4
+    const double num =
+        fma(w0, fma(0.5, d2, -0.2 * d1), fma(w1, fma(1.2, d3, 0.6 * d2), w2 * fma(1.2, d3, -0.3 * d4)));
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    return fma(pr6, num * r, pr * c);
 }
 
-// One RK stage for a tile of NT consecutive nodes x one velocity slice of one instance.
-// Lanes own velocities v = vs0 + tid + block * j (j < VPT) for the whole tile and keep, per
-// velocity, a register window of the 7 cells i-3 .. i+3 around the current node i, so every
-// face flux is computed once and every value of f_src is read once (plus a 6-cell halo per
-// tile).  The node's plane is staged in LDS (column stride n0 + 1) and the three
-// momentum-derivative contractions run as FP64 MFMA 16x16x4 tiles over it:
-//   d0 = K1 P        (n0 x n0) x (n0 x columns)         rows = radial momentum
-//   d1 = K2a P_i2    (n1 x n1) x (n1 x n0) per i2
-//   d2 = K2b P'      (n2 x n2) x (n2 x n0 n1)           sphere only
-// each into its own LDS plane, already multiplied by its momentum and geometry factor.
-// Two barriers per node: phase A (MFMA of node t, WENO face flux of node t) and phase B
-// (collision + RK combine + store of node t with its moment sums, reduced across the wave by
-// a register reduce-scatter; staging of node t+1's plane, prefetch of node t+2's window cell
-// and node t+1's f^n).
+// f at cell c (c may be a ghost: -3 .. -1, nr .. nr + 4) for the lane's velocity (byte offset
+// voff in a row of rowb bytes); `pos` is the sign of the radial momenta of the whole wave, so
+// every branch is wave-uniform.  Entering velocities see n_w times the unit wall Maxwellian,
+// leaving ones the quadratic extrapolation of the three nearest cells.
+__device__ inline double fcell(rsrc_t rf, int rowb, int c, unsigned voff, int nr, bool pos, double nwl, double nwr,
+                               rsrc_t rgl, rsrc_t rgr)
+{
+    if (c >= 0 && c < nr) return bload(rf, voff, c * rowb);
+    if (c < 0) {
+        if (pos) return nwl * bload(rgl, voff, 0);
+        const double f0 = bload(rf, voff, 0), f1 = bload(rf, voff, rowb), f2 = bload(rf, voff, 2 * rowb);
+        return c == -1 ? 3 * f0 - 3 * f1 + f2 : 6 * f0 - 8 * f1 + 3 * f2;
+    }
+    if (!pos) return nwr * bload(rgr, voff, 0);
+    const int last = (nr - 1) * rowb;
+    const double a = bload(rf, voff, last), b = bload(rf, voff, last - rowb), c3 = bload(rf, voff, last - 2 * rowb);
+    return c == nr ? 3 * a - 3 * b + c3 : 6 * a - 8 * b + 3 * c3;
+}
+
+// Descriptor of one MFMA tile of the stage kernel (ints in LDS, built in the set-up).  A tile
+// accumulates D = A B over nk rows of k, 4 per MFMA, with per-lane operand offsets
+//   A: abase + q16 * arow + q4 + k,   B: bbase + col + (q4 + k) * bk,
+// where col = q16 * bcol, or the table ctab[q16] when bcol = 0.  Contraction tiles then write
+// fac * D[q4 + 4r][q16] (fac = ffac * lftab[q16], lanes q16 < okl, rows q4 + 4r < rowlim) to
+// out + obase + col + (q4 + 4r) * orow.  Moment tiles (type 1) chain a second MFMA instead.
+enum TileDesc {
+    TD_TYPE = 0, TD_ABASE, TD_AROW, TD_BBASE, TD_BK, TD_NK, TD_BCOL, TD_CTAB, TD_LFTAB, TD_OKL, TD_OBASE, TD_OROW,
+    TD_ROWLIM, TD_OUT, TD_CT, TD_COUNT
+};
+constexpr int kTileDescStride = 16;
+
+// Per-node coefficients of the stage update, written by the workgroup set-up:
+//   o = an f^n + CF f + fmb P(y) - (AR F_r - AL F_l) - I
+// with y = p - c (c: velocity shift of the tile), fmb = gR(i0) g1(i1) g2(i2) the discrete
+// equilibrium without its density, I the inertial contractions (scaled by FFAC) and the cubic
+//   P(y) = C0 + y0 (G0 + E00 y0 + E01 y1 + E02 y2) + y1 (G1 + E11 y1 + E12 y2) + y2 (G2 + E22 y2)
+//          + |y|^2 (H0 y0 + H1 y1 + H2 y2).
+enum StageCoef {
+    SC_C0 = 0, SC_G0, SC_G1, SC_G2, SC_E00, SC_E01, SC_E02, SC_E11, SC_E12, SC_E22, SC_H0, SC_H1, SC_H2,
+    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_COUNT
+};
+static_assert(SC_COUNT <= kCoefStride, "stage coefficient block");
+
+// With x = p - u the right-hand side is L = -A - I - f / tau + n g P_u(x), where
+//   P_u(x) = (1 + (1 - Pr) / (n T^2) (|x|^2 / (5T) - 1) q.x) / tau - b rho chi S(x)
+// collects the Shakhov relaxation (eq. (j0)) and the first-order Enskog term (eq. (j1)) with
+//   S(x) = x_r (D1 + 3/5 (z^2 - 5/2) D2) + 2/5 (2 zz:grad u + (z^2 - 5/2) div u), z^2 = |x|^2/(2T),
+// D1 = d ln(n^2 chi T)/dr, D2 = d ln T/dr (the node coefficients).  P_u is a cubic
+// C0 + g.x + x'Hx + |x|^2 h.x; it is re-expanded about y = x - d, d = c - u, and scaled by
+// n * sigma (sigma = bs dt for an RK stage, 1 for the bare right-hand side).
+__device__ inline void stage_coefs(const double* nd, const double* geo4, const double c[3], bool sph, double sigma,
+                                   double bsv, double* out)
+{
+    const double n = nd[NF_N];
+    const double u[3] = {nd[NF_U0], nd[NF_U1], nd[NF_U2]};
+    const double q[3] = {nd[NF_Q0], nd[NF_Q1], nd[NF_Q2]};
+    const double itau = nd[NF_INVTAU], shak = nd[NF_SHAK], brc = nd[NF_BRHOCHI];
+    const double D1 = nd[NF_D1], D2 = nd[NF_D2], divu = nd[NF_DIVU];
+    const double i2T = nd[NF_INV2T], i5T = nd[NF_INV5T];
+    const double C0 = itau + brc * divu;
+    double g[3], h[3], H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 3; a++) {
+        g[a] = -itau * shak * q[a];
+        h[a] = itau * shak * i5T * q[a];
+    }
+    g[0] -= brc * (D1 - 1.5 * D2);
+    h[0] -= 0.6 * brc * D2 * i2T;
+    const double iso = -0.4 * brc * divu * i2T, k8 = -0.8 * brc * i2T;
+    H[0][0] = k8 * nd[NF_DU0] + iso;
+    if (sph) {
+        H[1][1] = H[2][2] = k8 * nd[NF_UR_R] + iso;
+    } else {
+        H[1][1] = k8 * nd[NF_UR_R] + iso;
+        H[2][2] = iso;
+        H[0][1] = H[1][0] = 0.5 * k8 * nd[NF_SHEAR01];
+        H[0][2] = H[2][0] = 0.5 * k8 * nd[NF_DU2];
+    }
+    double d[3], Hd[3];
+    for (int a = 0; a < 3; a++) d[a] = c[a] - u[a];
+    double hd = 0, dd = 0, gd = 0, dHd = 0;
+    for (int a = 0; a < 3; a++) {
+        Hd[a] = H[a][0] * d[0] + H[a][1] * d[1] + H[a][2] * d[2];
+        hd += h[a] * d[a];
+        dd += d[a] * d[a];
+        gd += g[a] * d[a];
+    }
+    for (int a = 0; a < 3; a++) dHd += d[a] * Hd[a];
+    double gs[3], Hs[3][3];
+    for (int a = 0; a < 3; a++) {
+        gs[a] = g[a] + 2 * Hd[a] + 2 * hd * d[a] + dd * h[a];
+        for (int b = 0; b < 3; b++) Hs[a][b] = H[a][b] + (a == b ? hd : 0.0) + d[a] * h[b] + h[a] * d[b];
+    }
+    const double s = n * sigma;
+    out[SC_C0] = s * (C0 + gd + dHd + dd * hd);
+    out[SC_G0] = s * gs[0];
+    out[SC_G1] = s * gs[1];
+    out[SC_G2] = s * gs[2];
+    out[SC_E00] = s * Hs[0][0];
+    out[SC_E01] = s * 2 * Hs[0][1];
+    out[SC_E02] = s * 2 * Hs[0][2];
+    out[SC_E11] = s * Hs[1][1];
+    out[SC_E12] = s * 2 * Hs[1][2];
+    out[SC_E22] = s * Hs[2][2];
+    out[SC_H0] = s * h[0];
+    out[SC_H1] = s * h[1];
+    out[SC_H2] = s * h[2];
+    out[SC_CF] = bsv - sigma * itau;
+    out[SC_AL] = sigma * geo4[0];
+    out[SC_AR] = sigma * geo4[1];
+    out[SC_FFAC] = sigma * geo4[2];
+}
+
+// One RK stage (or the bare right-hand side, rhs != 0) for a tile of consecutive nodes x one
+// velocity slice of one instance.
+//
+// Lanes: the first wh waves take the velocities with p_r > 0, the next wh those with p_r < 0
+// (element e of a half: radial index e % Q, column e / Q of the slice), so the upwind
+// direction is uniform per wave.  Each lane keeps, per velocity, a register window of the
+// cells i-2 .. i+3 around the current node i plus one prefetched cell, so every face flux is
+// computed once and every value of f_src is read once (plus a halo per tile).
+//
+// Per node, two phases separated by barriers:
+//   A: FP64 MFMA 16x16x4 tiles over the node's LDS plane P (column stride n0 + 1)
+//        d0 = K1 P (n0 x n0 times n0 x columns), d1 = K2a P_i2 (per i2), d2 = K2b P' (sphere),
+//      each times its momentum and geometry factor into its own plane; the moment sums of the
+//      previous node's output plane O as two chained MFMAs, D1 = O^T Y0 (Y0: powers 0..3 of
+//      y_r per radial node) and D2 = Psi^T D1 (Psi: the transverse factors 1, y1, y2, y1^2,
+//      y2^2, y1 y2, rho, y1 rho, y2 rho with rho = y1^2 + y2^2, per column); the WENO face
+//      flux at i + 1/2;
+//   B: the update of every velocity (one cubic per lane, coefficients from the set-up), the
+//      store to HBM and to O, and the staging of node i+1's plane and prefetches.
+// The moment sums are taken about the tile shift c and written per slice (no atomics; fixed
+// order, so runs are bitwise reproducible).
 template <int VPT>
-__global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__ insts,
-                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
-                                                  int fn, int dst, double an, double bs)
+__global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
+                                                 const WorkItem* __restrict__ items, const StageGroup G, int src,
+                                                 int fn, int dst, double an, double bs, int rhs)
 {
     extern __shared__ double lds[];
     const WorkItem it = items[blockIdx.x];
     const DevInstance& I = insts[it.inst];
     if (!I.flags[1]) return;
-    const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2;
+    const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2, hq = n0 >> 1;
     const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, W = B >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile math on scalars
-    const int cs = n0 + 1;  // LDS column stride
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wh = G.wh;
+    const bool pos = wave < wh;
+    const int cs = n0 + 1;  // LDS column stride of the planes
     const bool sph = G.geometry == LBE_SPH;
-    const bool need_fn = an != 0.0;  // stage 1 combines with f_src itself
+    const bool need_fn = an != 0.0;
+    const double sigma = rhs ? 1.0 : bs * I.dt, bsv = rhs ? 0.0 : bs;
     const int k1s = G.n0k + 1, k2as = G.n1k + 1, k2bs = G.n2k + 1;  // odd LDS row strides of K
     const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
-    const int c_s0 = it.slice * G.ncols_s;      // first global column (i1 + n1 i2) of the slice
-    const int cp0 = sph ? 0 : c_s0;            // first global column held in the LDS plane
-    const int i2s0 = it.slice * G.ns2;          // first i2 of the slice
-    const int pslice = cs * G.ncols_s;          // size of one slice plane
+    const int ncol = G.ncols_s;
+    const int c_s0 = it.slice * ncol;  // first global column (i1 + n1 i2) of the slice
+    const int cp0 = sph ? 0 : c_s0;    // first global column held in the plane
+    const int i2s0 = it.slice * G.ns2;
+    const int nTm = rhs ? 0 : G.ncols16 / 16;
     double* plane = lds + G.off_plane;
-    double* ib0 = lds + G.off_ibuf;             // d0 terms, then d1, d2 terms, then 2 output planes
-    double* ib1 = ib0 + pslice;
-    double* ib2 = ib1 + pslice;
+    double* op = lds + G.off_op;
     double* K1s = lds + G.off_K1;
     double* K2as = lds + G.off_K2a;
     double* K2bs = lds + G.off_K2b;
-    double* snode = lds + G.off_node;
+    double* scoef = lds + G.off_coef;
     double* sgeq = lds + G.off_geq;
     double* spart = lds + G.off_part;
-    double* sp = lds + G.off_p;
-    const double* __restrict__ f = I.f[src];
-    const double* __restrict__ fN = I.f[fn];
-    double* __restrict__ fout = I.f[dst];
+    double* colfac = lds + G.off_colfac;   // d0 column factors, then -p_r per radial node (d1)
+    double* nsp = colfac + G.ncols16;
+    double* cpfac = nsp + G.n0p;           // -p_r per d2 column (sphere)
+    int* cpoff = (int*)(lds + G.off_cpinfo);
+    int* tdesc = (int*)(lds + G.off_tdesc);
+    double* y0p = lds + G.off_y0p;
+    double* psi = lds + G.off_psi;
+    const int rowb = nv * (int)sizeof(double);
+    const rsrc_t rf = make_rsrc(I.f[src], (size_t)nr * rowb);
+    const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
+    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * rowb);
+    const rsrc_t rgl = make_rsrc(I.gwl, rowb), rgr = make_rsrc(I.gwr, rowb);
     const int ng = n0 + n1 + n2;
+    // velocity shift of the tile: the velocity of its first node (common to all its slices)
+    const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
+    const double csh[3] = {ndc[NF_U0], ndc[NF_U1], ndc[NF_U2]};
 
-    // ---- per-workgroup set-up: force matrices (zero-padded), momentum nodes, node data
+    // ---- set-up.  The planes are zeroed first: the MFMA tiles read their padding.
+    for (int e = tid; e < G.off_ibuf - G.off_plane; e += B) plane[e] = 0.0;
     for (int e = tid; e < G.n0p * k1s; e += B) {
         const int r = e / k1s, k = e % k1s;
         K1s[e] = (r < n0 && k < n0) ? I.K1[r * n0 + k] : 0.0;
@@ -697,56 +666,132 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
             const int r = e / k2bs, k = e % k2bs;
             K2bs[e] = (r < G.ns2 && k < n2) ? I.K2b[(i2s0 + r) * n2 + k] : 0.0;
         }
-    // per-column factor of d0 (p_1^2 [+ p_2^2]) and, for the sphere, the (i0, i1) split of the
-    // d2 columns with their factor -p_r: avoids per-node integer division
-    double* colfac = lds + G.off_colfac;
-    int* cpinfo = (int*)(lds + G.off_cpinfo);
-    for (int e = tid; e < G.ncols_s; e += B) {
-        const int cg = c_s0 + e;
-        const double pyy = I.p1[cg % n1];
-        double fac = pyy * pyy;
-        if (sph) {
-            const double pzz = I.p2[cg / n1];
-            fac += pzz * pzz;
+    // lane factors of the contraction tiles: p_1^2 [+ p_2^2] per d0 column, -p_r per radial
+    // node (d1) and per d2 column; plane offsets of the d2 columns (i0 + cs i1)
+    for (int e = tid; e < G.ncols16; e += B) {
+        double fac = 0.0;
+        if (e < ncol) {
+            const int cg = c_s0 + e;
+            const double pyy = I.p1[cg % n1];
+            fac = pyy * pyy;
+            if (sph) {
+                const double pzz = I.p2[cg / n1];
+                fac += pzz * pzz;
+            }
         }
         colfac[e] = fac;
     }
+    for (int e = tid; e < G.n0p; e += B) nsp[e] = e < n0 ? -I.p0[e] : 0.0;
     if (sph)
-        for (int e = tid; e < n0 * n1; e += B) cpinfo[e] = (e % n0) | ((e / n0) << 8);
-    for (int e = tid; e < ng; e += B) sp[e] = e < n0 ? I.p0[e] : e < n0 + n1 ? I.p1[e - n0] : I.p2[e - n0 - n1];
-    for (int e = tid; e < it.nt * SN_COUNT; e += B) {
-        const int t = e / SN_COUNT, fld = e % SN_COUNT, i = it.i0 + t;
-        const double* nd = I.node + (size_t)i * kNodeStride;
-        double val;
-        switch (fld) {
-            case SN_N: val = nd[NF_N]; break;
-            case SN_U0: val = nd[NF_U0]; break;
-            case SN_U1: val = nd[NF_U1]; break;
-            case SN_U2: val = nd[NF_U2]; break;
-            case SN_T: val = nd[NF_T]; break;
-            case SN_Q0: val = nd[NF_Q0]; break;
-            case SN_Q1: val = nd[NF_Q1]; break;
-            case SN_Q2: val = nd[NF_Q2]; break;
-            case SN_INVTAU: val = nd[NF_INVTAU]; break;
-            case SN_SHAK: val = nd[NF_SHAK]; break;
-            case SN_BRHOCHI: val = nd[NF_BRHOCHI]; break;
-            case SN_D1: val = nd[NF_D1]; break;
-            case SN_D2: val = nd[NF_D2]; break;
-            case SN_DU0: val = nd[NF_DU0]; break;
-            case SN_DU2: val = nd[NF_DU2]; break;
-            case SN_DIVU: val = nd[NF_DIVU]; break;
-            case SN_SH01: val = nd[NF_SHEAR01]; break;
-            case SN_URR: val = nd[NF_UR_R]; break;
-            case SN_ADVL: val = I.geo[4 * i + 0]; break;
-            case SN_ADVR: val = I.geo[4 * i + 1]; break;
-            case SN_INV2T: val = nd[NF_INV2T]; break;
-            case SN_INV5T: val = nd[NF_INV5T]; break;
-            default: val = I.geo[4 * i + 2]; break;
+        for (int e = tid; e < G.ncp16; e += B) {
+            const bool ok = e < n0 * n1;
+            cpoff[e] = ok ? (e % n0) + cs * (e / n0) : 0;
+            cpfac[e] = ok ? -I.p0[e % n0] : 0.0;
         }
-        snode[t * kStageNodeStride + fld] = val;
+    for (int t = tid; t < it.nt; t += B) {
+        const int i = it.i0 + t;
+        stage_coefs(I.node + (size_t)i * kNodeStride, I.geo + 4 * i, csh, sph, sigma, bsv, scoef + t * kCoefStride);
     }
-    // equilibrium factors of the tile's nodes from their projection coefficients (the l sums
-    // are unrolled to the largest order so their loads issue together)
+    // moment-sum operands: powers of y_r per radial node, transverse factors per column
+    for (int e = tid; e < G.n0k * 16; e += B) {
+        const int r = e >> 4, a = e & 15;
+        double val = 0.0;
+        if (r < n0 && a < 4) {
+            const double y = I.p0[r] - csh[0];
+            val = a == 0 ? 1.0 : a == 1 ? y : a == 2 ? y * y : y * y * y;
+        }
+        y0p[e] = val;
+    }
+    for (int e = tid; e < G.ncols16 * 16; e += B) {
+        const int col = e >> 4, m = e & 15;
+        double val = 0.0;
+        if (col < ncol && m < 9) {
+            const int cg = c_s0 + col;
+            const double y1 = I.p1[cg % n1] - csh[1], y2 = I.p2[cg / n1] - csh[2];
+            const double rho = y1 * y1 + y2 * y2;
+            switch (m) {
+                case 0: val = 1.0; break;
+                case 1: val = y1; break;
+                case 2: val = y2; break;
+                case 3: val = y1 * y1; break;
+                case 4: val = y2 * y2; break;
+                case 5: val = y1 * y2; break;
+                case 6: val = rho; break;
+                case 7: val = y1 * rho; break;
+                default: val = y2 * rho; break;
+            }
+        }
+        psi[e] = val;
+    }
+    // tile descriptors: moment tiles, then d0, d1, d2 tiles
+    const int nM1 = G.n0p / 16, nN1 = G.ncols16 / 16;
+    const int nM2 = G.n1p / 16, nN2 = G.n0p / 16;
+    const int nM3 = G.ns2p / 16, nN3 = G.ncp16 / 16;
+    const int nT1 = nM1 * nN1, nT2 = G.ns2 * nM2 * nN2, nT3 = sph ? nM3 * nN3 : 0;
+    const int nTall = nTm + nT1 + nT2 + nT3;
+    for (int tile = tid; tile < nTall; tile += B) {
+        int* d = tdesc + tile * kTileDescStride;
+        for (int k = 0; k < kTileDescStride; k++) d[k] = 0;
+        if (tile < nTm) {
+            d[TD_TYPE] = 1;
+            d[TD_ABASE] = G.off_op + cs * 16 * tile;
+            d[TD_AROW] = cs;
+            d[TD_BBASE] = G.off_y0p;
+            d[TD_BK] = 16;
+            d[TD_NK] = G.n0k;
+            d[TD_BCOL] = 1;
+            d[TD_CT] = tile;
+            continue;
+        }
+        const int tl = tile - nTm;
+        if (tl < nT1) {  // d0 = K1 P into ib0
+            const int mt = tl / nN1, ntl = tl % nN1;
+            d[TD_ABASE] = G.off_K1 + 16 * mt * k1s;
+            d[TD_AROW] = k1s;
+            d[TD_BBASE] = G.off_plane + cs * (c_s0 - cp0 + 16 * ntl);
+            d[TD_BK] = 1;
+            d[TD_NK] = G.n0k;
+            d[TD_BCOL] = cs;
+            d[TD_LFTAB] = G.off_colfac + 16 * ntl;
+            d[TD_OKL] = ncol - 16 * ntl;
+            d[TD_OBASE] = 16 * mt + cs * 16 * ntl;
+            d[TD_OROW] = 1;
+            d[TD_ROWLIM] = n0 - 16 * mt;
+            d[TD_OUT] = G.off_ibuf;
+        } else if (tl < nT1 + nT2) {  // d1 = K2a P_i2 into ib1
+            const int tl2 = tl - nT1;
+            const int i2l = tl2 / (nM2 * nN2), rem = tl2 % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
+            d[TD_ABASE] = G.off_K2a + 16 * mt * k2as;
+            d[TD_AROW] = k2as;
+            d[TD_BBASE] = G.off_plane + 16 * ntl + cs * (n1 * (i2s0 + i2l) - cp0);
+            d[TD_BK] = cs;
+            d[TD_NK] = G.n1k;
+            d[TD_BCOL] = 1;
+            d[TD_LFTAB] = G.off_colfac + G.ncols16 + 16 * ntl;
+            d[TD_OKL] = n0 - 16 * ntl;
+            d[TD_OBASE] = 16 * ntl + cs * (16 * mt + n1 * i2l);
+            d[TD_OROW] = cs;
+            d[TD_ROWLIM] = n1 - 16 * mt;
+            d[TD_OUT] = G.off_ibuf + cs * ncol;
+        } else {  // d2 = K2b P' into ib2 (sphere)
+            const int tl3 = tl - nT1 - nT2;
+            const int mt = tl3 / nN3, ntl = tl3 % nN3;
+            d[TD_ABASE] = G.off_K2b + 16 * mt * k2bs;
+            d[TD_AROW] = k2bs;
+            d[TD_BBASE] = G.off_plane;
+            d[TD_BK] = cs * n1;
+            d[TD_NK] = G.n2k;
+            d[TD_BCOL] = 0;
+            d[TD_CTAB] = 2 * G.off_cpinfo + 16 * ntl;  // in ints
+            d[TD_LFTAB] = G.off_colfac + G.ncols16 + G.n0p + 16 * ntl;
+            d[TD_OKL] = n0 * n1 - 16 * ntl;
+            d[TD_OBASE] = cs * n1 * 16 * mt;
+            d[TD_OROW] = cs * n1;
+            d[TD_ROWLIM] = G.ns2 - 16 * mt;
+            d[TD_OUT] = G.off_ibuf + 2 * cs * ncol;
+        }
+    }
+    // equilibrium factors of the tile's nodes from their projection coefficients
     for (int e = tid; e < it.nt * ng; e += B) {
         const int t = e / ng, k = e % ng;
         const double* nd = I.node + (size_t)(it.i0 + t) * kNodeStride;
@@ -771,237 +816,212 @@ __global__ void __launch_bounds__(1024) k_stage2(const DevInstance* __restrict__
             poly = I.poly2;
             wt = I.w2;
         }
-        double cv[kMaxN + 1], pv[kMaxN + 1];
-#pragma unroll
-        for (int l = 0; l <= kMaxN; l++) {
-            cv[l] = l <= N ? cf[l] : 0.0;
-            pv[l] = l <= N ? poly[kk * (N + 1) + l] : 0.0;
-        }
         double acc = 0;
-#pragma unroll
-        for (int l = 0; l <= kMaxN; l++) acc += cv[l] * pv[l];
+        for (int l = 0; l <= N; l++) acc += cf[l] * poly[kk * (N + 1) + l];
         sgeq[t * ng + k] = wt[kk] * acc;
     }
 
-    // ---- per-lane velocities: v = vs0 + tid + B j; code = i0 | i1 << 8 | i2 << 16
-    const double nwl = I.nw[0], nwr = I.nw[1];
-    int code[VPT];
-    double prv[VPT];
+    // ---- per-lane velocities
+    const int nh = hq * ncol;
+    unsigned voff[VPT];
+    int ibx[VPT], gx0[VPT], gx1[VPT], gx2[VPT];
+    bool valid[VPT];
+    double prv[VPT], y0[VPT], y1[VPT], y2[VPT], yy[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
-        const int v = min(vs0 + tid + B * j, vs1 - 1);
-        const int i0 = v % n0, c = v / n0, i1 = c % n1, i2 = c / n1;
-        code[j] = i0 | (i1 << 8) | (i2 << 16);
+        const int eh = (wave - (pos ? 0 : wh)) * 64 + lane + 64 * wh * j;
+        valid[j] = eh < nh;
+        const int e = min(eh, nh - 1);
+        const int i0h = e % hq, col = e / hq;
+        const int i0 = pos ? i0h : hq + i0h;
+        const int cg = c_s0 + col, i1 = cg % n1, i2 = cg / n1;
+        voff[j] = (unsigned)(i0 + n0 * cg) * 8u;
+        ibx[j] = i0 + cs * col;
+        gx0[j] = i0;
+        gx1[j] = n0 + i1;
+        gx2[j] = n0 + n1 + i2;
         prv[j] = I.p0[i0];
+        y0[j] = prv[j] - csh[0];
+        y1[j] = I.p1[i1] - csh[1];
+        y2[j] = I.p2[i2] - csh[2];
+        yy[j] = y0[j] * y0[j] + y1[j] * y1[j] + y2[j] * y2[j];
     }
-    // ---- window of cells i0-3 .. i0+3, f^n of the first node, the first node's plane
-    double w[VPT][7], Fl[VPT], wnext[VPT], fnv[VPT];
+    const int pshift = cs * (c_s0 - cp0);  // plane index = ibx + pshift
+    __syncthreads();  // planes zeroed before the first plane is staged
+
+    // ---- window of cells i0-2 .. i0+3, the prefetched cell, f^n and F_l of the first node
+    const double nwl = I.nw[0], nwr = I.nw[1];
+    double w[VPT][6], wnext[VPT], fnv[VPT], Fl[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
-        const int v = min(vs0 + tid + B * j, vs1 - 1);
-        const double pr = prv[j];
 #pragma unroll
-        for (int k = 0; k < 7; k++) w[j][k] = fcell(f, it.i0 - 3 + k, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
-        wnext[j] = fcell(f, it.i0 + 4, v, nr, nv, pr, nwl, nwr, I.gwl, I.gwr);
-        fnv[j] = need_fn ? gload(fN + (size_t)it.i0 * nv + v) : 0.0;
-        if (pr > 0)
-            Fl[j] = (it.i0 == 0) ? pr * nwl * gload(I.gwl + v)
-                                 : pr * weno5(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4]);
-        else
-            Fl[j] = pr * weno5(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1]);
-        if (vs0 + tid + B * j < vs1) {
-            const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
-            plane[i0 + cs * (c - cp0)] = w[j][3];
+        for (int k = 0; k < 6; k++) w[j][k] = fcell(rf, rowb, it.i0 - 2 + k, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+        wnext[j] = fcell(rf, rowb, it.i0 + 4, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+        fnv[j] = need_fn ? bload(rfn, voff[j], it.i0 * rowb) : 0.0;
+        const double pr6 = prv[j] * (1.0 / 6);
+        if (pos) {
+            if (it.i0 == 0) {
+                Fl[j] = prv[j] * nwl * bload(rgl, voff[j], 0);
+            } else {
+                const double cm3 = fcell(rf, rowb, it.i0 - 3, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+                Fl[j] = weno_flux(cm3, w[j][0], w[j][1], w[j][2], w[j][3], prv[j], pr6);
+            }
+        } else {
+            Fl[j] = weno_flux(w[j][4], w[j][3], w[j][2], w[j][1], w[j][0], prv[j], pr6);
         }
+        if (valid[j]) plane[ibx[j] + pshift] = w[j][2];
     }
     if (sph && G.S > 1)
         for (int v = tid; v < nv; v += B)
-            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = gload(f + (size_t)it.i0 * nv + v);
+            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, it.i0 * rowb);
 
-    const int nM1 = G.n0p / 16, nN1 = (G.ncols_s + 15) / 16;
-    const int nM2 = G.n1p / 16, nN2 = G.n0p / 16;
-    const int nM3 = G.ns2p / 16, nN3 = (n0 * n1 + 15) / 16;
-    const int nT1 = nM1 * nN1, nT2 = G.ns2 * nM2 * nN2, nT3 = sph ? nM3 * nN3 : 0;
     const int q16 = lane & 15, q4 = lane >> 4;
+    const int* ctabs = (const int*)lds;
+
+    // one tile of phase A (descriptor td) for node t (contractions) or tm (moments)
+    auto run_tile = [&](int tile, int t, double ffac) {
+        const int* td = tdesc + tile * kTileDescStride;
+        const int type = __builtin_amdgcn_readfirstlane(td[TD_TYPE]);
+        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]);
+        const int arow = __builtin_amdgcn_readfirstlane(td[TD_AROW]);
+        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]);
+        const int bk = __builtin_amdgcn_readfirstlane(td[TD_BK]);
+        const int nk = __builtin_amdgcn_readfirstlane(td[TD_NK]);
+        const int bcol = __builtin_amdgcn_readfirstlane(td[TD_BCOL]);
+        const int col = bcol ? q16 * bcol : ctabs[__builtin_amdgcn_readfirstlane(td[TD_CTAB]) + q16];
+        const double* ap = lds + abase + q16 * arow + q4;
+        const double* bp = lds + bbase + col + q4 * bk;
+        v4d acc = {0, 0, 0, 0};
+        for (int ks = 0; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
+        if (type == 0) {
+            const int okl = __builtin_amdgcn_readfirstlane(td[TD_OKL]);
+            if (q16 < okl) {
+                const int lftab = __builtin_amdgcn_readfirstlane(td[TD_LFTAB]);
+                const int obase = __builtin_amdgcn_readfirstlane(td[TD_OBASE]);
+                const int orow = __builtin_amdgcn_readfirstlane(td[TD_OROW]);
+                const int rowlim = __builtin_amdgcn_readfirstlane(td[TD_ROWLIM]);
+                const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]);
+                const double fac = ffac * lds[lftab + q16];
+                double* o = lds + out + obase + col + q4 * orow;
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
+            }
+        } else {
+            // D2 = Psi^T D1 over the tile's 16 columns; lane holds D2[m = q4 + 4r][a = q16]
+            const int ct = __builtin_amdgcn_readfirstlane(td[TD_CT]);
+            v4d d2 = {0, 0, 0, 0};
+            const double* pp = psi + (ct * 16 + q4) * 16 + q16;
+            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[0], acc[0], d2, 0, 0, 0);
+            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[64], acc[1], d2, 0, 0, 0);
+            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[128], acc[2], d2, 0, 0, 0);
+            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[192], acc[3], d2, 0, 0, 0);
+            if (q16 < 4) {
+                double* dst4 = spart + (t * nTm + ct) * 36 + q16;
+                dst4[q4 * 4] = d2[0];
+                dst4[(4 + q4) * 4] = d2[1];
+                if (q4 == 0) dst4[32] = d2[2];
+            }
+        }
+    };
 
     __syncthreads();
     for (int t = 0; t < it.nt; t++) {
         const int i = it.i0 + t;
-        const double* nd = snode + t * kStageNodeStride;
-        const double ffac = uniform(nd[SN_FFAC]);
-        // ================= phase A: contractions of node t, face flux i+1, moments of node t-1
-        for (int tile = wave; tile < nT1 + nT2 + nT3; tile += W) {
-            v4d acc = {0, 0, 0, 0};
-            if (tile < nT1) {  // d0 = K1 P into ib0, times ffac (p_1^2 [+ p_2^2])
-                const int mt = tile / nN1, ntl = tile % nN1;
-                const int col = ntl * 16 + q16;
-                const bool cok = col < G.ncols_s;
-                const double* bp = plane + cs * (c_s0 + (cok ? col : 0) - cp0);
-                const double* ap = K1s + (mt * 16 + q16) * k1s;
-                const int kval = cok ? n0 : 0;
-                for (int ks = 0; ks < G.n0k; ks += 4) {
-                    const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[k] : 0.0, acc, 0, 0, 0);
-                }
-                if (cok) {
-                    const double fac = colfac[col] * ffac;
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int row = mt * 16 + q4 + 4 * r;
-                        if (row < n0) ib0[row + cs * col] = fac * acc[r];
-                    }
-                }
-            } else if (tile < nT1 + nT2) {  // d1 = K2a P_i2 into ib1, times -ffac p_r
-                const int tl = tile - nT1;
-                const int i2l = tl / (nM2 * nN2), rem = tl % (nM2 * nN2), mt = rem / nN2, ntl = rem % nN2;
-                const int i0c = ntl * 16 + q16;
-                const bool iok = i0c < n0;
-                const double* ap = K2as + (mt * 16 + q16) * k2as;
-                const double* bp = plane + (iok ? i0c : 0) + cs * (n1 * (i2s0 + i2l) - cp0);
-                const int kval = iok ? n1 : 0;
-                for (int ks = 0; ks < G.n1k; ks += 4) {
-                    const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[cs * k] : 0.0, acc, 0, 0, 0);
-                }
-                if (iok) {
-                    const double fac = -ffac * sp[i0c];
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int jrow = mt * 16 + q4 + 4 * r;
-                        if (jrow < n1) ib1[i0c + cs * (jrow + n1 * i2l)] = fac * acc[r];
-                    }
-                }
-            } else {  // d2 = K2b P' into ib2, times -ffac p_r (sphere)
-                const int tl = tile - nT1 - nT2;
-                const int mt = tl / nN3, ntl = tl % nN3;
-                const int cp = ntl * 16 + q16;
-                const bool pok = cp < n0 * n1;
-                const int info = pok ? cpinfo[cp] : 0;
-                const int bi0 = info & 0xff, bi1 = info >> 8;
-                const double* ap = K2bs + (mt * 16 + q16) * k2bs;
-                const double* bp = plane + bi0 + cs * bi1;
-                const int kval = pok ? n2 : 0;
-                for (int ks = 0; ks < G.n2k; ks += 4) {
-                    const int k = ks + q4;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[k], (k < kval) ? bp[cs * n1 * k] : 0.0, acc, 0, 0, 0);
-                }
-                if (pok) {
-                    const double fac = -ffac * sp[bi0];
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int krow = mt * 16 + q4 + 4 * r;
-                        if (krow < G.ns2) ib2[bi0 + cs * (bi1 + n1 * krow)] = fac * acc[r];
-                    }
-                }
-            }
+        // ================= phase A
+        {
+            const double ffac = scoef[t * kCoefStride + SC_FFAC];
+            for (int tile = (t == 0 ? nTm : 0) + wave; tile < nTall; tile += W)
+                run_tile(tile, tile < nTm ? t - 1 : t, ffac);
         }
         double Fr[VPT];
 #pragma unroll
         for (int j = 0; j < VPT; j++) {
-            const double pr = prv[j];
-            if (pr > 0)
-                Fr[j] = pr * weno5(w[j][1], w[j][2], w[j][3], w[j][4], w[j][5]);
+            const double pr6 = prv[j] * (1.0 / 6);
+            if (pos)
+                Fr[j] = weno_flux(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4], prv[j], pr6);
+            else if (i == nr - 1)
+                Fr[j] = prv[j] * nwr * bload(rgr, voff[j], 0);
             else
-                Fr[j] = (i == nr - 1) ? pr * nwr * gload(I.gwr + min(vs0 + tid + B * j, vs1 - 1))
-                                      : pr * weno5(w[j][6], w[j][5], w[j][4], w[j][3], w[j][2]);
+                Fr[j] = weno_flux(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1], prv[j], pr6);
         }
         __syncthreads();
-        // ================= phase B: combine and store node t; stage node t+1
+        // ================= phase B: update, store, stage node t+1
         {
-            const double n = uniform(nd[SN_N]), u0 = uniform(nd[SN_U0]), u1 = uniform(nd[SN_U1]);
-            const double u2 = uniform(nd[SN_U2]), T = uniform(nd[SN_T]);
-            const double q0 = uniform(nd[SN_Q0]), q1 = uniform(nd[SN_Q1]), q2 = uniform(nd[SN_Q2]);
-            const double invtau = uniform(nd[SN_INVTAU]), shak = uniform(nd[SN_SHAK]);
-            const double brhochi = uniform(nd[SN_BRHOCHI]);
-            const double D1 = uniform(nd[SN_D1]), D2 = uniform(nd[SN_D2]), du0 = uniform(nd[SN_DU0]);
-            const double du2 = uniform(nd[SN_DU2]);
-            const double divu = uniform(nd[SN_DIVU]), sh01 = uniform(nd[SN_SH01]), urr = uniform(nd[SN_URR]);
-            const double adv_l = uniform(nd[SN_ADVL]), adv_r = uniform(nd[SN_ADVR]);
-            const double inv2T = uniform(nd[SN_INV2T]), inv5T = uniform(nd[SN_INV5T]);
-            const double* gR = sgeq + t * ng;
-            const double* g1 = gR + n0;
-            const double* g2 = g1 + n1;
-            double acc[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) acc[k] = 0;
+            const double* cf = scoef + t * kCoefStride;
+            const double* gq = sgeq + t * ng;
+            const double* ib0 = lds + G.off_ibuf;
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
-                const int v = vs0 + tid + B * j;
-                const int i0 = code[j] & 0xff, i1 = code[j] >> 8 & 0xff, i2 = code[j] >> 16;
-                const int ib = i0 + cs * (i1 + n1 * i2 - c_s0);
-                const double pr = prv[j], py = sp[n0 + i1], pz = sp[n0 + n1 + i2];
-                const double A = adv_r * Fr[j] - adv_l * Fl[j];
-                double Iv = ib0[ib] + ib1[ib];
-                if (sph) Iv += ib2[ib];
-                const double fmb = n * gR[i0] * g1[i1] * g2[i2];
-                const double x0 = pr - u0, x1 = py - u1, x2 = pz - u2;
-                const double xi2 = x0 * x0 + x1 * x1 + x2 * x2;
-                const double xq = x0 * q0 + x1 * q1 + x2 * q2;
-                const double fS = fmb * (1 + shak * (xi2 * inv5T - 1) * xq);
-                const double z2 = xi2 * inv2T;
-                const double zzgu = sph ? (x0 * x0 * du0 + (x1 * x1 + x2 * x2) * urr) * inv2T
-                                        : (x0 * x0 * du0 + x0 * x1 * sh01 + x1 * x1 * urr + x0 * x2 * du2) * inv2T;
-                const double S = x0 * (D1 + 0.6 * (z2 - 2.5) * D2) + 0.4 * (2 * zzgu + (z2 - 2.5) * divu);
-                const double fv = w[j][3];
-                const double L = -A - Iv - (fv - fS) * invtau - brhochi * fmb * S;
-                const double o = (need_fn ? an * fnv[j] : 0.0) + bs * (fv + I.dt * L);
-                if (v < vs1) {
-                    gstore(fout + (size_t)i * nv + v, o);
-                    // moment sums of the stored value, shifted by the node's velocity
-                    acc[MF_S0] += o;
-                    acc[MF_S1X] += o * x0;
-                    acc[MF_S1Y] += o * x1;
-                    acc[MF_S1Z] += o * x2;
-                    acc[MF_SXX] += o * x0 * x0;
-                    acc[MF_SYY] += o * x1 * x1;
-                    acc[MF_SZZ] += o * x2 * x2;
-                    acc[MF_SXY] += o * x0 * x1;
-                    acc[MF_SXZ] += o * x0 * x2;
-                    acc[MF_SYZ] += o * x1 * x2;
-                    acc[MF_S3X] += o * xi2 * x0;
-                    acc[MF_S3Y] += o * xi2 * x1;
-                    acc[MF_S3Z] += o * xi2 * x2;
+                double Iv = ib0[ibx[j]] + ib0[ibx[j] + cs * ncol];
+                if (sph) Iv += ib0[ibx[j] + 2 * cs * ncol];
+                const double fmb = gq[gx0[j]] * gq[gx1[j]] * gq[gx2[j]];
+                const double Y0 = y0[j], Y1 = y1[j], Y2 = y2[j];
+                const double a0 = fma(cf[SC_E02], Y2, fma(cf[SC_E01], Y1, fma(cf[SC_E00], Y0, cf[SC_G0])));
+                const double a1 = fma(cf[SC_E12], Y2, fma(cf[SC_E11], Y1, cf[SC_G1]));
+                const double a2 = fma(cf[SC_E22], Y2, cf[SC_G2]);
+                const double hy = fma(cf[SC_H2], Y2, fma(cf[SC_H1], Y1, cf[SC_H0] * Y0));
+                const double P = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
+                const double A = fma(cf[SC_AR], Fr[j], -cf[SC_AL] * Fl[j]);
+                double o = fma(fmb, P, -(A + Iv));
+                o = fma(cf[SC_CF], w[j][2], o);
+                if (need_fn) o = fma(an, fnv[j], o);
+                if (valid[j]) {
+                    bstore(ro, voff[j], i * rowb, o);
+                    if (!rhs) op[ibx[j]] = o;
                 }
             }
-            {
-                const double tot = reduce_scatter16(acc, lane);
-                const int which = (lane >> 2) & 15;
-                if ((lane & 3) == 0 && which < 13) spart[(t * W + wave) * 13 + which] = tot;
-            }
-            // advance the window to node t+1, stage its plane, prefetch ahead
             if (t + 1 < it.nt) {
 #pragma unroll
                 for (int j = 0; j < VPT; j++) {
-                    const int v = min(vs0 + tid + B * j, vs1 - 1);
 #pragma unroll
-                    for (int k = 0; k < 6; k++) w[j][k] = w[j][k + 1];
-                    w[j][6] = wnext[j];
+                    for (int k = 0; k < 5; k++) w[j][k] = w[j][k + 1];
+                    w[j][5] = wnext[j];
                     Fl[j] = Fr[j];
-                    wnext[j] = fcell(f, i + 5, v, nr, nv, prv[j], nwl, nwr, I.gwl, I.gwr);
-                    fnv[j] = need_fn ? gload(fN + (size_t)(i + 1) * nv + v) : 0.0;
-                    if (vs0 + tid + B * j < vs1) {
-                        const int i0 = code[j] & 0xff, c = (code[j] >> 8 & 0xff) + n1 * (code[j] >> 16);
-                        plane[i0 + cs * (c - cp0)] = w[j][3];
-                    }
+                    wnext[j] = fcell(rf, rowb, i + 5, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+                    fnv[j] = need_fn ? bload(rfn, voff[j], (i + 1) * rowb) : 0.0;
+                    if (valid[j]) plane[ibx[j] + pshift] = w[j][2];
                 }
                 if (sph && G.S > 1)
                     for (int v = tid; v < nv; v += B)
-                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = gload(f + (size_t)(i + 1) * nv + v);
+                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, (i + 1) * rowb);
             }
         }
         __syncthreads();
     }
-    // ---- moment sums of the tile's nodes (waves summed in order) for this slice
+    if (rhs) return;
+    // ---- moment sums of the last node, then per node and slice: combine the column tiles and
+    // map the (transverse factor, power of y_r) products to the moment block
+    for (int tile = wave; tile < nTm; tile += W) run_tile(tile, it.nt - 1, 0.0);
+    __syncthreads();
     for (int e = tid; e < it.nt * 16; e += B) {
-        const int t = e / 16, k = e % 16, i = it.i0 + t;
+        const int t = e >> 4, k = e & 15;
+        const double* base = spart + t * nTm * 36;
+        auto D = [&](int m, int a) {
+            double s = 0;
+            for (int ct = 0; ct < nTm; ct++) s += base[ct * 36 + m * 4 + a];
+            return s;
+        };
         double val;
-        if (k < 13) {
-            val = 0;
-            for (int wv = 0; wv < W; wv++) val += spart[(t * W + wv) * 13 + k];
-        } else {
-            val = snode[t * kStageNodeStride + (k == MF_CX ? SN_U0 : k == MF_CY ? SN_U1 : SN_U2)];
+        switch (k) {
+            case MF_S0: val = D(0, 0); break;
+            case MF_S1X: val = D(0, 1); break;
+            case MF_S1Y: val = D(1, 0); break;
+            case MF_S1Z: val = D(2, 0); break;
+            case MF_SXX: val = D(0, 2); break;
+            case MF_SYY: val = D(3, 0); break;
+            case MF_SZZ: val = D(4, 0); break;
+            case MF_SXY: val = D(1, 1); break;
+            case MF_SXZ: val = D(2, 1); break;
+            case MF_SYZ: val = D(5, 0); break;
+            case MF_S3X: val = D(0, 3) + D(6, 1); break;
+            case MF_S3Y: val = D(1, 2) + D(7, 0); break;
+            case MF_S3Z: val = D(2, 2) + D(8, 0); break;
+            case MF_CX: val = csh[0]; break;
+            case MF_CY: val = csh[1]; break;
+            default: val = csh[2]; break;
         }
-        I.mom[((size_t)i * I.nslices + it.slice) * kMomStride + k] = val;
+        I.mom[((size_t)(it.i0 + t) * I.nslices + it.slice) * kMomStride + k] = val;
     }
 }
 
@@ -1059,52 +1079,40 @@ hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, h
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, bool with_geq, hipStream_t s)
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
     hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
-    e = hipGetLastError();
-    if (e != hipSuccess || !with_geq) return e;
-    hipLaunchKernelGGL(k_geq, dim3(64, ninst), dim3(kBlock), 0, s, d);
-    return hipGetLastError();
-}
-
-hipError_t launch_stage_kernel(const DevInstance* d, int ninst, int maxnr, int maxnv, int src, int fn, int dst,
-                               double an, double bs, int mode, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_stage, dim3(maxnr, ninst), dim3(kBlock), (size_t)maxnv * sizeof(double), s, d, src, fn, dst,
-                       an, bs, mode);
     return hipGetLastError();
 }
 
 template <int VPT>
-static hipError_t launch_stage2_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
-                                  int fn, int dst, double an, double bs, hipStream_t s)
+static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
+                                 int fn, int dst, double an, double bs, int rhs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage2<VPT>, dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d,
-                       items, G, src, fn, dst, an, bs);
+    hipLaunchKernelGGL(k_stage<VPT>, dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d, items,
+                       G, src, fn, dst, an, bs, rhs);
     return hipGetLastError();
 }
 
-hipError_t launch_stage2(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
-                         int dst, double an, double bs, hipStream_t s)
+hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
+                        int dst, double an, double bs, int rhs, hipStream_t s)
 {
     switch (G.vpt) {
-        case 1: return launch_stage2_t<1>(d, items, nitems, G, src, fn, dst, an, bs, s);
-        case 2: return launch_stage2_t<2>(d, items, nitems, G, src, fn, dst, an, bs, s);
+        case 1: return launch_stage_t<1>(d, items, nitems, G, src, fn, dst, an, bs, rhs, s);
+        case 2: return launch_stage_t<2>(d, items, nitems, G, src, fn, dst, an, bs, rhs, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t set_stage2_smem_limit()
+hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-    hipError_t e = hipSuccess;
-    e = hipFuncSetAttribute((const void*)k_stage2<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_stage2<2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_stage<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_stage<2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 
@@ -1118,12 +1126,6 @@ hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_residual, dim3(1, ninst), dim3(kBlock), 0, s, d);
     return hipGetLastError();
-}
-
-hipError_t set_stage_smem_limit(int maxnv)
-{
-    return hipFuncSetAttribute((const void*)k_stage, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               maxnv * (int)sizeof(double));
 }
 
 }  // namespace lbe
