@@ -75,7 +75,9 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t base)
     };
     const size_t D = sizeof(double);
     const size_t plane = (size_t)t.nr * t.nv * D;
-    for (int k = 0; k < 3; k++) L.f[k] = take(plane);
+    // state buffers: nr rows plus two ghost rows on each side (filled by the node kernel);
+    // L.f points at row 0
+    for (int k = 0; k < 3; k++) L.f[k] = take(plane + 4 * t.nv * D) + 2 * t.nv * D;
     L.mom = take((size_t)t.nr * nslices * kMomStride * D);
     L.node = take((size_t)t.nr * kNodeStride * D);
     L.snap = take((size_t)t.nr * 5 * D);
@@ -114,7 +116,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
-    size_t b = 4 * align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
+    size_t b = 3 * align256((nr + 4) * nv * D) + align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
                align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
@@ -172,17 +174,55 @@ bool layout_group(StageGroup* G)
     const int nTm = G->ncols16 / 16;
     const int nTall = nTm + (G->n0p / 16) * (G->ncols16 / 16) + G->ns2 * (G->n1p / 16) * (G->n0p / 16) +
                       (sph ? (G->ns2p / 16) * (G->ncp16 / 16) : 0);
+    // slot order of the MFMA tiles: heaviest first, each into the free slot whose SIMD (slot is
+    // run by wave slot % W, on SIMD wave % 4) has the least MFMA work so far
+    {
+        const int W = G->block / 64;
+        const int nT1 = (G->n0p / 16) * (G->ncols16 / 16), nT2 = G->ns2 * (G->n1p / 16) * (G->n0p / 16);
+        std::vector<std::pair<int, int>> tiles;  // (weight in MFMAs, logical tile)
+        for (int k = 0; k < nTall; k++) {
+            int wgt;
+            if (k < nTm) wgt = G->n0k / 4 + 4;
+            else if (k < nTm + nT1) wgt = G->n0k / 4;
+            else if (k < nTm + nT1 + nT2) wgt = G->n1k / 4;
+            else wgt = G->n2k / 4;
+            tiles.push_back({wgt, k});
+        }
+        std::stable_sort(tiles.begin(), tiles.end(), [](auto& a, auto& b) { return a.first > b.first; });
+        if (nTall <= kMaxTilePerm) {
+            std::vector<int> used(nTall, 0);
+            long load[4] = {0, 0, 0, 0};
+            for (auto& tw : tiles) {
+                int best = -1;
+                for (int sl = 0; sl < nTall; sl++) {
+                    if (used[sl]) continue;
+                    if (best < 0 || load[(sl % W) % 4] < load[(best % W) % 4]) best = sl;
+                }
+                used[best] = 1;
+                G->perm[best] = (int16_t)tw.second;
+                load[(best % W) % 4] += tw.first;
+            }
+            G->nperm = nTall;
+        } else {
+            G->nperm = 0;
+        }
+    }
     int nt0 = 16;
-    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(16, std::atoi(e)));
+    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(64, std::atoi(e)));
     for (int NT = nt0; NT >= 1; NT /= 2) {
         G->NT = NT;
         int o = 0;
+        // two of each: plane of the node being contracted, output plane of the node whose
+        // moments are taken, inertial-term planes (d0, d1 (, d2)) of the node being updated
+        G->plane_sz = pmax + 1;
+        G->op_sz = op_sz;
+        G->ib_sz = (sph ? 3 : 2) * cs * G->ncols_s;
         G->off_plane = o;
-        o += pmax + 1;
+        o += 2 * G->plane_sz;
         G->off_op = o;
-        o += op_sz;
-        G->off_ibuf = o;  // d0, d1 (, d2) term planes
-        o += (sph ? 3 : 2) * cs * G->ncols_s;
+        o += 2 * G->op_sz;
+        G->off_ibuf = o;
+        o += 2 * G->ib_sz;
         G->off_K1 = o;
         o += G->n0p * (G->n0k + 1);
         G->off_K2a = o;
@@ -194,7 +234,7 @@ bool layout_group(StageGroup* G)
         G->off_cpinfo = o;  // ints, two per double
         o += (G->ncp16 + 1) / 2;
         G->off_tdesc = o;   // ints
-        o += (nTall * 16 + 1) / 2;
+        o += (nTall * kTileDescStride + 1) / 2;
         G->off_y0p = o;
         o += G->n0k * 16;
         G->off_psi = o;

@@ -93,15 +93,21 @@ struct WorkItem {
     int32_t inst, i0, nt, slice;
 };
 
+constexpr int kMaxTilePerm = 128;  // largest tile count with a balanced slot order
+constexpr int kTileDescStride = 16;  // ints per MFMA tile descriptor of the stage kernel
+
 // Launch group of the stage kernel: instances sharing one velocity set (n0, n1, n2, geometry).
 // All sizes are uniform over the group; LDS offsets are in doubles.
 struct StageGroup {
     int32_t n0, n1, n2, nv, geometry;
     int32_t S, ns2, nvs, ncols_s, ncols16, plane_cols;  // slices, i2 / velocities / columns per slice
     int32_t ncp16;                                       // d2 columns (n0 n1, sphere) padded to 16
+    int32_t plane_sz, op_sz, ib_sz;                      // doubles per plane / output / term buffer
     int32_t n0k, n1k, n2k, n0p, n1p, ns2p;              // K padded to 4, M/N padded to 16
     int32_t NT, block, vpt, wh;                          // nodes per tile, lanes, velocities per lane,
                                                          // waves per sign of the radial momentum
+    int32_t nperm;                                       // MFMA tiles when perm is used, else 0
+    int16_t perm[kMaxTilePerm];                          // logical tile of each launch slot
     int32_t off_plane, off_op, off_ibuf, off_K1, off_K2a, off_K2b, off_colfac, off_cpinfo, off_tdesc, off_y0p,
         off_psi, off_coef, off_geq, off_part, lds_doubles;
 };

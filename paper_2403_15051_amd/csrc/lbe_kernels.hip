@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "lbe_equilibrium.h"
 #include "lbe_internal.h"
@@ -245,7 +246,40 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
             }
         }
         block_sum<1>(acc, red);
-        if (threadIdx.x == 0) I.nw[left ? 0 : 1] = -red[0] / (left ? I.gin_l : I.gin_r);
+        const double nw = -red[0] / (left ? I.gin_l : I.gin_r);
+        if (threadIdx.x == 0) I.nw[left ? 0 : 1] = nw;
+        // ghost cells of this wall (cells -1, -2, or nr, nr + 1, stored in the two rows the
+        // state buffers hold on each side): n_w g_w for entering velocities, the quadratic
+        // extrapolation of the three nearest cells for leaving ones
+        double* fw = I.f[src];
+        const size_t nv = I.nv;
+        for (int v = threadIdx.x; v < I.nv; v += kBlock) {
+            const double pr = I.p0[v % I.n0];
+            if (left) {
+                double g1, g2;
+                if (pr > 0) {
+                    g1 = g2 = nw * I.gwl[v];
+                } else {
+                    const double f0 = f[v], f1 = f[nv + v], f2 = f[2 * nv + v];
+                    g1 = 3 * f0 - 3 * f1 + f2;
+                    g2 = 6 * f0 - 8 * f1 + 3 * f2;
+                }
+                fw[v - nv] = g1;
+                fw[v - 2 * nv] = g2;
+            } else {
+                const double* fl = f + (size_t)(nr - 1) * nv;
+                double g1, g2;
+                if (pr < 0) {
+                    g1 = g2 = nw * I.gwr[v];
+                } else {
+                    const double a = fl[v], b = fl[v - nv], c = fl[v - 2 * nv];
+                    g1 = 3 * a - 3 * b + c;
+                    g2 = 6 * a - 8 * b + 3 * c;
+                }
+                fw[(size_t)nr * nv + v] = g1;
+                fw[(size_t)(nr + 1) * nv + v] = g2;
+            }
+        }
         return;
     }
 
@@ -468,25 +502,6 @@ __device__ inline double weno_flux(double a, double b, double c, double d, doubl
     return fma(pr6, num * r, pr * c);
 }
 
-// f at cell c (c may be a ghost: -3 .. -1, nr .. nr + 4) for the lane's velocity (byte offset
-// voff in a row of rowb bytes); `pos` is the sign of the radial momenta of the whole wave, so
-// every branch is wave-uniform.  Entering velocities see n_w times the unit wall Maxwellian,
-// leaving ones the quadratic extrapolation of the three nearest cells.
-__device__ inline double fcell(rsrc_t rf, int rowb, int c, unsigned voff, int nr, bool pos, double nwl, double nwr,
-                               rsrc_t rgl, rsrc_t rgr)
-{
-    if (c >= 0 && c < nr) return bload(rf, voff, c * rowb);
-    if (c < 0) {
-        if (pos) return nwl * bload(rgl, voff, 0);
-        const double f0 = bload(rf, voff, 0), f1 = bload(rf, voff, rowb), f2 = bload(rf, voff, 2 * rowb);
-        return c == -1 ? 3 * f0 - 3 * f1 + f2 : 6 * f0 - 8 * f1 + 3 * f2;
-    }
-    if (!pos) return nwr * bload(rgr, voff, 0);
-    const int last = (nr - 1) * rowb;
-    const double a = bload(rf, voff, last), b = bload(rf, voff, last - rowb), c3 = bload(rf, voff, last - 2 * rowb);
-    return c == nr ? 3 * a - 3 * b + c3 : 6 * a - 8 * b + 3 * c3;
-}
-
 // Descriptor of one MFMA tile of the stage kernel (ints in LDS, built in the set-up).  A tile
 // accumulates D = A B over nk rows of k, 4 per MFMA, with per-lane operand offsets
 //   A: abase + q16 * arow + q4 + k,   B: bbase + col + (q4 + k) * bk,
@@ -497,7 +512,6 @@ enum TileDesc {
     TD_TYPE = 0, TD_ABASE, TD_AROW, TD_BBASE, TD_BK, TD_NK, TD_BCOL, TD_CTAB, TD_LFTAB, TD_OKL, TD_OBASE, TD_OROW,
     TD_ROWLIM, TD_OUT, TD_CT, TD_COUNT
 };
-constexpr int kTileDescStride = 16;
 
 // Per-node coefficients of the stage update, written by the workgroup set-up:
 //   o = an f^n + CF f + fmb P(y) - (AR F_r - AL F_l) - I
@@ -625,7 +639,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     const int c_s0 = it.slice * ncol;  // first global column (i1 + n1 i2) of the slice
     const int cp0 = sph ? 0 : c_s0;    // first global column held in the plane
     const int i2s0 = it.slice * G.ns2;
-    const int nTm = rhs ? 0 : G.ncols16 / 16;
+    const int nTm = G.ncols16 / 16;  // moment tiles (skipped for the bare right-hand side)
     double* plane = lds + G.off_plane;
     double* op = lds + G.off_op;
     double* K1s = lds + G.off_K1;
@@ -642,10 +656,11 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     double* y0p = lds + G.off_y0p;
     double* psi = lds + G.off_psi;
     const int rowb = nv * (int)sizeof(double);
-    const rsrc_t rf = make_rsrc(I.f[src], (size_t)nr * rowb);
+    // f_src with its two ghost rows on each side: cell c at byte row offset (c + 2) rowb
+    const rsrc_t rf = make_rsrc(I.f[src] - 2 * (size_t)nv, (size_t)(nr + 4) * rowb);
     const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
     const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * rowb);
-    const rsrc_t rgl = make_rsrc(I.gwl, rowb), rgr = make_rsrc(I.gwr, rowb);
+    auto cell = [&](int c, unsigned vo) { return bload(rf, vo, (min(c, nr + 1) + 2) * rowb); };
     const int ng = n0 + n1 + n2;
     // velocity shift of the tile: the velocity of its first node (common to all its slices)
     const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
@@ -723,14 +738,16 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         }
         psi[e] = val;
     }
-    // tile descriptors: moment tiles, then d0, d1, d2 tiles
+    // tile descriptors: logical tiles are the moment tiles, then d0, d1, d2 tiles; slot s (run
+    // by wave s mod W) holds logical tile perm[s], which balances the MFMA work over the SIMDs
     const int nM1 = G.n0p / 16, nN1 = G.ncols16 / 16;
     const int nM2 = G.n1p / 16, nN2 = G.n0p / 16;
     const int nM3 = G.ns2p / 16, nN3 = G.ncp16 / 16;
     const int nT1 = nM1 * nN1, nT2 = G.ns2 * nM2 * nN2, nT3 = sph ? nM3 * nN3 : 0;
     const int nTall = nTm + nT1 + nT2 + nT3;
-    for (int tile = tid; tile < nTall; tile += B) {
-        int* d = tdesc + tile * kTileDescStride;
+    for (int slot = tid; slot < nTall; slot += B) {
+        const int tile = G.nperm ? G.perm[slot] : slot;
+        int* d = tdesc + slot * kTileDescStride;
         for (int k = 0; k < kTileDescStride; k++) d[k] = 0;
         if (tile < nTm) {
             d[TD_TYPE] = 1;
@@ -816,8 +833,16 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             poly = I.poly2;
             wt = I.w2;
         }
+        // the l sums are unrolled to the largest order so that their loads issue together
+        double cv[kMaxN + 1], pv[kMaxN + 1];
+#pragma unroll
+        for (int l = 0; l <= kMaxN; l++) {
+            cv[l] = l <= N ? cf[l] : 0.0;
+            pv[l] = l <= N ? poly[kk * (N + 1) + l] : 0.0;
+        }
         double acc = 0;
-        for (int l = 0; l <= N; l++) acc += cf[l] * poly[kk * (N + 1) + l];
+#pragma unroll
+        for (int l = 0; l <= kMaxN; l++) acc += cv[l] * pv[l];
         sgeq[t * ng + k] = wt[kk] * acc;
     }
 
@@ -849,50 +874,78 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     const int pshift = cs * (c_s0 - cp0);  // plane index = ibx + pshift
     __syncthreads();  // planes zeroed before the first plane is staged
 
-    // ---- window of cells i0-2 .. i0+3, the prefetched cell, f^n and F_l of the first node
-    const double nwl = I.nw[0], nwr = I.nw[1];
-    double w[VPT][6], wnext[VPT], fnv[VPT], Fl[VPT];
+    // ---- window of cells i0-2 .. i0+3, the prefetched cell i0+4, f^n and F_l of the first node.
+    // The seven cells live in a ring of registers: at node t (phase P = t mod 7) cell i-2+k is
+    // slot (P + k) mod 7, and the cell loaded ahead for node t+1 goes into the slot of cell i-2,
+    // so the ring never moves data and no load has to complete before the next node.
+    // At a wall the face flux of the entering velocities is p_r times the ghost value (n_w g_w).
+    // The planes of nodes 0 and 1 of the tile are staged into plane buffers 0 and 1.
+    double sl[VPT][7], fnv[VPT], Fl[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
 #pragma unroll
-        for (int k = 0; k < 6; k++) w[j][k] = fcell(rf, rowb, it.i0 - 2 + k, voff[j], nr, pos, nwl, nwr, rgl, rgr);
-        wnext[j] = fcell(rf, rowb, it.i0 + 4, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+        for (int k = 0; k < 7; k++) sl[j][k] = cell(it.i0 - 2 + k, voff[j]);
         fnv[j] = need_fn ? bload(rfn, voff[j], it.i0 * rowb) : 0.0;
         const double pr6 = prv[j] * (1.0 / 6);
         if (pos) {
             if (it.i0 == 0) {
-                Fl[j] = prv[j] * nwl * bload(rgl, voff[j], 0);
+                Fl[j] = prv[j] * sl[j][1];
             } else {
-                const double cm3 = fcell(rf, rowb, it.i0 - 3, voff[j], nr, pos, nwl, nwr, rgl, rgr);
-                Fl[j] = weno_flux(cm3, w[j][0], w[j][1], w[j][2], w[j][3], prv[j], pr6);
+                const double cm3 = cell(it.i0 - 3, voff[j]);
+                Fl[j] = weno_flux(cm3, sl[j][0], sl[j][1], sl[j][2], sl[j][3], prv[j], pr6);
             }
         } else {
-            Fl[j] = weno_flux(w[j][4], w[j][3], w[j][2], w[j][1], w[j][0], prv[j], pr6);
+            Fl[j] = weno_flux(sl[j][4], sl[j][3], sl[j][2], sl[j][1], sl[j][0], prv[j], pr6);
         }
-        if (valid[j]) plane[ibx[j] + pshift] = w[j][2];
+        if (valid[j]) {
+            plane[ibx[j] + pshift] = sl[j][2];
+            if (it.nt > 1) plane[G.plane_sz + ibx[j] + pshift] = sl[j][3];
+        }
     }
-    if (sph && G.S > 1)
+    // other slices' columns of a plane (sphere: the d2 contraction runs over all i2)
+    auto fill_other_slices = [&](int t, int buf) {
+        double* pl = plane + buf * G.plane_sz;
         for (int v = tid; v < nv; v += B)
-            if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, it.i0 * rowb);
+            if (v < vs0 || v >= vs1) pl[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, (it.i0 + t + 2) * rowb);
+    };
+    if (sph && G.S > 1) {
+        fill_other_slices(0, 0);
+        if (it.nt > 1) fill_other_slices(1, 1);
+    }
 
     const int q16 = lane & 15, q4 = lane >> 4;
     const int* ctabs = (const int*)lds;
 
-    // one tile of phase A (descriptor td) for node t (contractions) or tm (moments)
-    auto run_tile = [&](int tile, int t, double ffac) {
+    // One MFMA tile (descriptor slot): a contraction of node t (plane and term buffers t mod 2)
+    // or the moment sums of node t (output buffer t mod 2).
+    auto run_tile = [&](int tile, int t) {
         const int* td = tdesc + tile * kTileDescStride;
         const int type = __builtin_amdgcn_readfirstlane(td[TD_TYPE]);
-        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]);
+        const int buf = t & 1;
+        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]) + (type == 1 ? buf * G.op_sz : 0);
         const int arow = __builtin_amdgcn_readfirstlane(td[TD_AROW]);
-        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]);
+        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]) + (type == 0 ? buf * G.plane_sz : 0);
         const int bk = __builtin_amdgcn_readfirstlane(td[TD_BK]);
         const int nk = __builtin_amdgcn_readfirstlane(td[TD_NK]);
         const int bcol = __builtin_amdgcn_readfirstlane(td[TD_BCOL]);
         const int col = bcol ? q16 * bcol : ctabs[__builtin_amdgcn_readfirstlane(td[TD_CTAB]) + q16];
         const double* ap = lds + abase + q16 * arow + q4;
         const double* bp = lds + bbase + col + q4 * bk;
+        // operands of four k-steps are read together, then their MFMAs issue back to back
         v4d acc = {0, 0, 0, 0};
-        for (int ks = 0; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
+        for (int ks = 0; ks < nk; ks += 16) {
+            double a[4], b[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const bool ok = ks + 4 * m < nk;
+                a[m] = ok ? ap[ks + 4 * m] : 0.0;
+                b[m] = ok ? bp[(ks + 4 * m) * bk] : 0.0;
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
+#pragma unroll
+            for (int m = 1; m < 4; m++)
+                if (ks + 4 * m < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
+        }
         if (type == 0) {
             const int okl = __builtin_amdgcn_readfirstlane(td[TD_OKL]);
             if (q16 < okl) {
@@ -900,8 +953,8 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 const int obase = __builtin_amdgcn_readfirstlane(td[TD_OBASE]);
                 const int orow = __builtin_amdgcn_readfirstlane(td[TD_OROW]);
                 const int rowlim = __builtin_amdgcn_readfirstlane(td[TD_ROWLIM]);
-                const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]);
-                const double fac = ffac * lds[lftab + q16];
+                const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]) + buf * G.ib_sz;
+                const double fac = scoef[t * kCoefStride + SC_FFAC] * lds[lftab + q16];
                 double* o = lds + out + obase + col + q4 * orow;
 #pragma unroll
                 for (int r = 0; r < 4; r++)
@@ -924,33 +977,48 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             }
         }
     };
-
-    __syncthreads();
-    for (int t = 0; t < it.nt; t++) {
-        const int i = it.i0 + t;
-        // ================= phase A
-        {
-            const double ffac = scoef[t * kCoefStride + SC_FFAC];
-            for (int tile = (t == 0 ? nTm : 0) + wave; tile < nTall; tile += W)
-                run_tile(tile, tile < nTm ? t - 1 : t, ffac);
+    // the wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0)
+    auto run_tiles = [&](int tc, int tm) {
+        for (int slot = wave; slot < nTall; slot += W) {
+            const bool mom = __builtin_amdgcn_readfirstlane(tdesc[slot * kTileDescStride + TD_TYPE]) == 1;
+            if (mom ? (tm >= 0 && !rhs) : (tc >= 0 && tc < it.nt)) run_tile(slot, mom ? tm : tc);
         }
+    };
+
+    // One node t at ring phase P, in one interval between barriers: the MFMA tiles of node t+1
+    // (its plane was staged one node earlier) and the moment sums of node t-1 run alongside the
+    // WENO fluxes and the update of node t, which reads the terms the tiles of the previous
+    // interval wrote; then node t+2's plane is staged and the loads ahead are issued.
+    auto node_step = [&](int t, auto phase) {
+        constexpr int P = decltype(phase)::value;
+        const int i = it.i0 + t;
+        const int buf = t & 1;
+        run_tiles(t + 1, t - 1);
         double Fr[VPT];
 #pragma unroll
         for (int j = 0; j < VPT; j++) {
+            const double* w = sl[j];
             const double pr6 = prv[j] * (1.0 / 6);
             if (pos)
-                Fr[j] = weno_flux(w[j][0], w[j][1], w[j][2], w[j][3], w[j][4], prv[j], pr6);
+                Fr[j] = weno_flux(w[P % 7], w[(P + 1) % 7], w[(P + 2) % 7], w[(P + 3) % 7], w[(P + 4) % 7], prv[j], pr6);
             else if (i == nr - 1)
-                Fr[j] = prv[j] * nwr * bload(rgr, voff[j], 0);
+                Fr[j] = prv[j] * w[(P + 3) % 7];
             else
-                Fr[j] = weno_flux(w[j][5], w[j][4], w[j][3], w[j][2], w[j][1], prv[j], pr6);
+                Fr[j] = weno_flux(w[(P + 5) % 7], w[(P + 4) % 7], w[(P + 3) % 7], w[(P + 2) % 7], w[(P + 1) % 7], prv[j],
+                                  pr6);
         }
-        __syncthreads();
-        // ================= phase B: update, store, stage node t+1
+        // node t+2's plane (into the buffer node t used) from the register ring, before this
+        // node's store is issued: a wait for an older load also waits for every later store
+        if (sph && G.S > 1 && t + 2 < it.nt) fill_other_slices(t + 2, buf);
+        if (t + 2 < it.nt) {
+#pragma unroll
+            for (int j = 0; j < VPT; j++)
+                if (valid[j]) plane[buf * G.plane_sz + ibx[j] + pshift] = sl[j][(P + 4) % 7];
+        }
         {
             const double* cf = scoef + t * kCoefStride;
             const double* gq = sgeq + t * ng;
-            const double* ib0 = lds + G.off_ibuf;
+            const double* ib0 = lds + G.off_ibuf + buf * G.ib_sz;
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
                 double Iv = ib0[ibx[j]] + ib0[ibx[j] + cs * ncol];
@@ -961,38 +1029,44 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 const double a1 = fma(cf[SC_E12], Y2, fma(cf[SC_E11], Y1, cf[SC_G1]));
                 const double a2 = fma(cf[SC_E22], Y2, cf[SC_G2]);
                 const double hy = fma(cf[SC_H2], Y2, fma(cf[SC_H1], Y1, cf[SC_H0] * Y0));
-                const double P = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
+                const double Pc = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
                 const double A = fma(cf[SC_AR], Fr[j], -cf[SC_AL] * Fl[j]);
-                double o = fma(fmb, P, -(A + Iv));
-                o = fma(cf[SC_CF], w[j][2], o);
+                double o = fma(fmb, Pc, -(A + Iv));
+                o = fma(cf[SC_CF], sl[j][(P + 2) % 7], o);
                 if (need_fn) o = fma(an, fnv[j], o);
                 if (valid[j]) {
                     bstore(ro, voff[j], i * rowb, o);
-                    if (!rhs) op[ibx[j]] = o;
+                    if (!rhs) op[buf * G.op_sz + ibx[j]] = o;
                 }
             }
             if (t + 1 < it.nt) {
 #pragma unroll
                 for (int j = 0; j < VPT; j++) {
-#pragma unroll
-                    for (int k = 0; k < 5; k++) w[j][k] = w[j][k + 1];
-                    w[j][5] = wnext[j];
                     Fl[j] = Fr[j];
-                    wnext[j] = fcell(rf, rowb, i + 5, voff[j], nr, pos, nwl, nwr, rgl, rgr);
+                    sl[j][P % 7] = cell(i + 5, voff[j]);
                     fnv[j] = need_fn ? bload(rfn, voff[j], (i + 1) * rowb) : 0.0;
-                    if (valid[j]) plane[ibx[j] + pshift] = w[j][2];
                 }
-                if (sph && G.S > 1)
-                    for (int v = tid; v < nv; v += B)
-                        if (v < vs0 || v >= vs1) plane[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, (i + 1) * rowb);
             }
         }
         __syncthreads();
+    };
+
+    __syncthreads();
+    run_tiles(0, -1);  // contractions of node 0
+    __syncthreads();
+    for (int t0 = 0; t0 < it.nt; t0 += 7) {
+        node_step(t0, std::integral_constant<int, 0>{});
+        if (t0 + 1 < it.nt) node_step(t0 + 1, std::integral_constant<int, 1>{});
+        if (t0 + 2 < it.nt) node_step(t0 + 2, std::integral_constant<int, 2>{});
+        if (t0 + 3 < it.nt) node_step(t0 + 3, std::integral_constant<int, 3>{});
+        if (t0 + 4 < it.nt) node_step(t0 + 4, std::integral_constant<int, 4>{});
+        if (t0 + 5 < it.nt) node_step(t0 + 5, std::integral_constant<int, 5>{});
+        if (t0 + 6 < it.nt) node_step(t0 + 6, std::integral_constant<int, 6>{});
     }
     if (rhs) return;
     // ---- moment sums of the last node, then per node and slice: combine the column tiles and
     // map the (transverse factor, power of y_r) products to the moment block
-    for (int tile = wave; tile < nTm; tile += W) run_tile(tile, it.nt - 1, 0.0);
+    run_tiles(-1, it.nt - 1);
     __syncthreads();
     for (int e = tid; e < it.nt * 16; e += B) {
         const int t = e >> 4, k = e & 15;
