@@ -9,6 +9,7 @@ instances (Nr 64..512, half-range orders 4..16), advanced together in one launch
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,6 +19,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+# HBM traffic of the stage kernel measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE, each
+# scaled by the same counter on a plain copy of known size); valid only for the kernel source it
+# was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_sweep256_fp64.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_15051_amd", "csrc", "lbe_kernels.hip")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic():
+    """Bytes per stage launch from the committed counter measurement, or None when the kernel
+    source has changed since (or no measurement exists)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t["traffic_bytes_per_launch"] if t.get("kernel_source_sha256") == kernel_sha() else None
+
+
+def copy_calibration(nbytes: int, reps: int) -> None:
+    """A plain device-to-device copy of nbytes (reads nbytes, writes nbytes), for scaling the
+    HBM counters."""
+    import torch
+
+    torch.cuda.set_device(0)
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def workload(name: str, n_inst: int):
@@ -76,7 +113,11 @@ def main():
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0, help="only run a plain copy of this size (calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes, max(1, args.steps))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver's batched path runs on a single MI355X; "
               "instances of a sweep shard across GPUs without communication (not built).", file=sys.stderr)
@@ -131,7 +172,7 @@ def main():
         "config": {"workload": desc, "instances": solver.n_inst, "site_velocities": sv, "precision": "fp64",
                    "parallelism": "single GPU, instances batched per launch"},
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "stage_ms_avg": stage_avg_s * 1e3, "node_ms_avg": tm["node_ms"] / max(1, tm["node_launches"]),
                      "stage_share_of_step": tm["stage_ms"] / (dt * 1e3)},
     }
