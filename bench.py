@@ -74,34 +74,52 @@ def workload(name: str, n_inst: int):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(params, budget_s: float):
-    """The oracle, as it stands, on a bounded sample of the same workload (host cores)."""
+def cpu_baseline(params, budget_s: float, threads: int = 0):
+    """The oracle, as it stands, on a bounded sample of the same workload (host cores; threads=0
+    keeps the oracle's default of all host threads)."""
     import oracle
 
     oracle.build(force=False)
-    threads = oracle.get_threads()
+    default = oracle.get_threads()
+    if threads:
+        oracle.set_threads(threads)
+    used_threads = oracle.get_threads()
     done = 0
     t_run = 0.0
     used = []
     t_start = time.perf_counter()
-    for p in params:
-        if time.perf_counter() - t_start > budget_s:
-            break
-        s = oracle.Solver(p)
-        nv = s.nv
-        steps = 0
-        t0 = time.perf_counter()
-        while steps < 1000:
-            s.step(1)
-            steps += 1
-            if time.perf_counter() - t0 > budget_s / 4 or time.perf_counter() - t_start > budget_s:
+    try:
+        for p in params:
+            if time.perf_counter() - t_start > budget_s:
                 break
-        t_run += time.perf_counter() - t0
-        done += p["nr"] * nv * steps
-        used.append((p["nr"], nv, steps))
+            s = oracle.Solver(p)
+            nv = s.nv
+            steps = 0
+            t0 = time.perf_counter()
+            while steps < 1000:
+                s.step(1)
+                steps += 1
+                if time.perf_counter() - t0 > budget_s / 4 or time.perf_counter() - t_start > budget_s:
+                    break
+            t_run += time.perf_counter() - t0
+            done += p["nr"] * nv * steps
+            used.append((p["nr"], nv, steps))
+    finally:
+        oracle.set_threads(default)
     desc = "; ".join(f"Nr {a} x Nv {b}: {c} steps" for a, b, c in used)
-    return {"value": done / t_run, "unit": "site-velocity updates/s", "cores": threads, "kind": "oracle",
+    return {"value": done / t_run, "unit": "site-velocity updates/s", "cores": used_threads, "kind": "oracle",
             "sample": f"{len(used)} instance(s) of the workload, FP64 oracle timed per step ({desc})"}
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -141,16 +159,23 @@ def main():
     solver.sync()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
+    # timed region: the captured RK3 step replayed K times
     torch.cuda.synchronize()
-    solver.timing_start()
     t0 = time.perf_counter()
     solver.step(args.steps)
     solver.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tm = solver.timing_stop()
     dt = t1 - t0
     value = sv * args.steps / dt
+    print(f"[bench] timed {args.steps} steps: {dt * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    # a second pass with HIP events around every launch (launched one by one) for the roofline
+    solver.timing_start()
+    t2 = time.perf_counter()
+    solver.step(args.steps)
+    solver.sync()
+    t3 = time.perf_counter()
+    tm = solver.timing_stop()
     # algorithmic HBM bytes of one stage launch: stage 1 reads f^n and writes f1 (16 B per
     # site-velocity in FP64), stages 2 and 3 read f_s and f^n and write (24 B): 64 B per step
     bytes_per_launch = sv * 64.0 / 3
@@ -174,10 +199,14 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "stage_ms_avg": stage_avg_s * 1e3, "node_ms_avg": tm["node_ms"] / max(1, tm["node_launches"]),
-                     "stage_share_of_step": tm["stage_ms"] / (dt * 1e3)},
+                     "stage_share_of_step": tm["stage_ms"] / ((t3 - t2) * 1e3),
+                     "ms_per_step_eager_timed": (t3 - t2) * 1e3 / args.steps},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
+        one = cpu_baseline(params, args.cpu_seconds / 3, threads=1)
+        line["cpu_baseline"]["single_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+        line["cpu_baseline"]["host"] = f"{host_cpu()}, {os.cpu_count()} logical CPUs visible"
     print(json.dumps(line), flush=True)
 
 

@@ -85,7 +85,9 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
 lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t ws_bytes, void* hip_stream,
                     lbe_ctx** out);
 
-/* Enqueue nsteps full TVD-RK3 steps of every instance on the context's stream (async). */
+/* Enqueue nsteps full TVD-RK3 steps of every instance on the context's stream (async).  The
+ * launches of one step are captured once into a HIP graph and replayed (set LBE_GRAPH=0 in the
+ * environment before lbe_init to launch them one by one). */
 lbe_status lbe_step(lbe_ctx* c, int64_t nsteps);
 
 /* Wait for the stream; returns LBE_ENAN if the device flagged a non-finite state. */
@@ -101,7 +103,9 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
  * (changes over one full step), evaluated after every check_every-th step, is <= tol, or
  * until max_steps.  Converged instances stop advancing.  steps_out[k], resid_out[k]
  * (n_inst each, may be NULL) receive per-instance steps taken and the last residual.
- * Returns LBE_OK when all converged, LBE_ENOTCONV otherwise. */
+ * Returns LBE_OK when all converged, LBE_ENOTCONV otherwise.  One check interval (the steps,
+ * the residual and the freeze test, all on the device) is one captured HIP graph; the host reads
+ * one status array per interval. */
 lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t check_every, int64_t* steps_out,
                              double* resid_out);
 
@@ -138,6 +142,16 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
  * stage-kernel launches, their count, total ms of the node-kernel launches, their count]
  * (cap >= 4).  Recording adds two events per launch and is meant for benchmarks. */
 lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap);
+
+/* Tile autotuner of the stage kernel (batched sweeps: instances with one velocity set share a
+ * launch group).  For every launch group, times `reps` stage launches (after one warm-up) for
+ * each candidate tile height (4, 8, 16, 32, 64 nodes per work item, where the LDS allows) and
+ * keeps the fastest.  The state and its moment sums are kept.  The tile height changes only
+ * the velocity shift of each tile's collision polynomial and moment sums, so results change at
+ * rounding level.  out[4 q ..] = (velocities of group q, chosen nodes per tile, its ms per
+ * launch, the ms of the tile height in use before the call); cap >= 4 * groups (out may be NULL);
+ * *ngroups_out (may be NULL) receives the number of groups.  Synchronises. */
+lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int32_t* ngroups_out);
 
 const char* lbe_last_error(const lbe_ctx* c);
 const char* lbe_status_string(lbe_status s);

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <atomic>
@@ -18,6 +19,8 @@ hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, h
 hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
+hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chunk, int judge, double* st,
+                           hipStream_t s);
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
                         int dst, double an, double bs, int rhs, hipStream_t s);
 hipError_t set_stage_smem_limit();
@@ -27,6 +30,9 @@ using namespace lbe;
 
 // Largest velocity plane the stage kernel stages in LDS (FP64): 160 KB per CU.
 static constexpr int kMaxPlane = 20000;
+// Tile heights (nodes per stage work item) lbe_autotune tries.
+static constexpr int kTileCandidates[] = {4, 8, 16, 32, 64};
+static constexpr int kMinTileNodes = 4;
 
 struct lbe_ctx {
     std::vector<InstanceTables> tabs;
@@ -51,6 +57,16 @@ struct lbe_ctx {
     std::vector<int> item_off, item_cnt;
     std::vector<WorkItem> items;
     WorkItem* dev_items = nullptr;
+    size_t items_cap = 0;              // work items the device list has room for
+    // steady-state bookkeeping [ninst][4] (residual, steps, nan flag, active), device side
+    double* dev_status = nullptr;
+    // captured launch sequences: one RK3 step, and one steady-state chunk (chunk steps, the
+    // residual and the freeze test), replayed on `stream`; captured on a private stream
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t g_step = nullptr, g_chunk = nullptr;
+    int g_chunk_n = 0;
+    double g_chunk_tol = 0;
 };
 
 namespace {
@@ -135,7 +151,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
 // nodes per tile, and the LDS layout.
 constexpr int kLdsDoubles = 160 * 1024 / 8;
 
-bool layout_group(StageGroup* G)
+bool layout_group(StageGroup* G, int nt0)
 {
     const int n0 = G->n0, n1 = G->n1, n2 = G->n2;
     const bool sph = G->geometry == LBE_SPH;
@@ -207,8 +223,6 @@ bool layout_group(StageGroup* G)
             G->nperm = 0;
         }
     }
-    int nt0 = 16;
-    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(64, std::atoi(e)));
     for (int NT = nt0; NT >= 1; NT /= 2) {
         G->NT = NT;
         int o = 0;
@@ -249,6 +263,33 @@ bool layout_group(StageGroup* G)
         if (o <= kLdsDoubles) return true;
     }
     return false;
+}
+
+// Default nodes per stage work item (LBE_TILE_NODES overrides it; lbe_autotune picks per group).
+int default_tile_nodes()
+{
+    int nt0 = 16;
+    if (const char* e = std::getenv("LBE_TILE_NODES")) nt0 = std::max(1, std::min(64, std::atoi(e)));
+    return nt0;
+}
+
+// Work items of every group: tiles of G.NT consecutive nodes x velocity slices, grouped by launch.
+void build_items(lbe_ctx* c)
+{
+    c->items.clear();
+    c->item_off.assign(c->groups.size(), 0);
+    c->item_cnt.assign(c->groups.size(), 0);
+    for (size_t q = 0; q < c->groups.size(); q++) {
+        const StageGroup& G = c->groups[q];
+        c->item_off[q] = (int)c->items.size();
+        for (int k = 0; k < c->ninst; k++) {
+            if (c->group_of[k] != (int)q) continue;
+            const int nr = c->tabs[k].nr;
+            for (int i0 = 0; i0 < nr; i0 += G.NT)
+                for (int sl = 0; sl < G.S; sl++) c->items.push_back({k, i0, std::min(G.NT, nr - i0), sl});
+        }
+        c->item_cnt[q] = (int)c->items.size() - c->item_off[q];
+    }
 }
 
 lbe_status plan_groups(lbe_ctx* c)
@@ -312,7 +353,7 @@ lbe_status plan_groups(lbe_ctx* c)
             G.S = nextS;
         }
         // split further if the velocity set needs more than two per lane or the LDS does not fit
-        while (!layout_group(&G)) {
+        while (!layout_group(&G, default_tile_nodes())) {
             int nextS = G.S + 1;
             while (nextS <= G.n2 && G.n2 % nextS) nextS++;
             if (nextS > G.n2) {
@@ -322,20 +363,12 @@ lbe_status plan_groups(lbe_ctx* c)
             G.S = nextS;
         }
     }
-    c->items.clear();
-    c->item_off.assign(c->groups.size(), 0);
-    c->item_cnt.assign(c->groups.size(), 0);
-    for (size_t q = 0; q < c->groups.size(); q++) {
-        const StageGroup& G = c->groups[q];
-        c->item_off[q] = (int)c->items.size();
-        for (int k = 0; k < c->ninst; k++) {
-            if (c->group_of[k] != (int)q) continue;
-            const int nr = c->tabs[k].nr;
-            for (int i0 = 0; i0 < nr; i0 += G.NT)
-                for (int sl = 0; sl < G.S; sl++) c->items.push_back({k, i0, std::min(G.NT, nr - i0), sl});
-        }
-        c->item_cnt[q] = (int)c->items.size() - c->item_off[q];
-    }
+    build_items(c);
+    // room for the work items of the smallest tile height lbe_autotune tries
+    c->items_cap = 0;
+    for (int k = 0; k < c->ninst; k++)
+        c->items_cap += (size_t)((c->tabs[k].nr + kMinTileNodes - 1) / kMinTileNodes) * c->groups[c->group_of[k]].S;
+    c->items_cap = std::max(c->items_cap, c->items.size());
     return LBE_OK;
 }
 
@@ -400,16 +433,83 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
 
 // One TVD-RK3 step (Shu-Osher) of every active instance:
 //   f1 = f + dt L(f);  f2 = 3/4 f + 1/4 (f1 + dt L(f1));  f <- 1/3 f + 2/3 (f2 + dt L(f2)).
+hipError_t launch_step(lbe_ctx* c)
+{
+    hipError_t e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0);
+    if (e == hipSuccess) e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0);
+    if (e == hipSuccess) e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0);
+    return e;
+}
+
+// `chunk` steps with the moment snapshot taken before the last one, then the residual of that
+// step and the freeze test of every instance (lbe_run_to_steady).
+hipError_t launch_chunk(lbe_ctx* c, int chunk, double tol, int judge)
+{
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < chunk && e == hipSuccess; s++) {
+        if (s == chunk - 1) e = launch_snapshot(c->dev_desc, c->ninst, c->stream);
+        if (e == hipSuccess) e = launch_step(c);
+    }
+    if (e == hipSuccess) e = launch_residual(c->dev_desc, c->ninst, c->stream);
+    if (e == hipSuccess) e = launch_converge(c->dev_desc, c->ninst, tol, chunk, judge, c->dev_status, c->stream);
+    return e;
+}
+
+void drop_graphs(lbe_ctx* c)
+{
+    if (c->g_step) (void)hipGraphExecDestroy(c->g_step);
+    if (c->g_chunk) (void)hipGraphExecDestroy(c->g_chunk);
+    c->g_step = c->g_chunk = nullptr;
+    c->g_chunk_n = 0;
+}
+
+// Record the launches `body` makes on the context's stream into an executable graph: the body
+// runs with the context's stream swapped for a private capturing stream (nothing executes).
+template <typename F>
+hipError_t capture(lbe_ctx* c, F&& body, hipGraphExec_t* out)
+{
+    hipError_t e = hipSuccess;
+    if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipError_t eb = body();
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (eb != hipSuccess) e = eb;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+// Enqueue one RK3 step: replay of the captured step, or the launches themselves while the
+// per-launch timing is on or graphs are disabled (LBE_GRAPH=0).
 lbe_status enqueue_step(lbe_ctx* c)
 {
-    hipError_t e;
-    e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0);
-    if (e != hipSuccess) return dev_err(c, e, "stage 1");
-    e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0);
-    if (e != hipSuccess) return dev_err(c, e, "stage 2");
-    e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0);
-    if (e != hipSuccess) return dev_err(c, e, "stage 3");
-    return LBE_OK;
+    if (!c->use_graph || c->timing) return dev_err(c, launch_step(c), "step");
+    if (!c->g_step) {
+        lbe_status st = dev_err(c, capture(c, [&]() { return launch_step(c); }, &c->g_step), "step capture");
+        if (st != LBE_OK) return st;
+    }
+    return dev_err(c, hipGraphLaunch(c->g_step, c->stream), "step launch");
+}
+
+lbe_status enqueue_chunk(lbe_ctx* c, int chunk, double tol, int judge)
+{
+    if (!c->use_graph || c->timing || !judge) return dev_err(c, launch_chunk(c, chunk, tol, judge), "chunk");
+    if (!c->g_chunk || c->g_chunk_n != chunk || c->g_chunk_tol != tol) {
+        if (c->g_chunk) (void)hipGraphExecDestroy(c->g_chunk);
+        c->g_chunk = nullptr;
+        lbe_status st = dev_err(
+            c, capture(c, [&]() { return launch_chunk(c, chunk, tol, judge); }, &c->g_chunk), "chunk capture");
+        if (st != LBE_OK) return st;
+        c->g_chunk_n = chunk;
+        c->g_chunk_tol = tol;
+    }
+    return dev_err(c, hipGraphLaunch(c->g_chunk, c->stream), "chunk launch");
 }
 
 lbe_status check_nan(lbe_ctx* c)
@@ -449,7 +549,7 @@ const char* lbe_last_error(const lbe_ctx* c) { return c ? c->err.c_str() : "null
 lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, size_t* host_bytes)
 {
     if (!p || n_inst < 1) return LBE_EINVAL;
-    size_t total = align256(sizeof(DevInstance) * n_inst);
+    size_t total = align256(sizeof(DevInstance) * n_inst) + align256(4 * sizeof(double) * (size_t)n_inst);
     size_t host = sizeof(lbe_ctx);
     for (int k = 0; k < n_inst; k++) {
         lbe_params q;
@@ -484,6 +584,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     c->host_desc.resize(n_inst);
     c->steps.assign(n_inst, 0);
     c->active.assign(n_inst, 1);
+    if (const char* g = std::getenv("LBE_GRAPH")) c->use_graph = std::atoi(g) != 0;
     // host tables of the instances, built by a small pool of host threads
     {
         std::vector<lbe_status> sts(n_inst, LBE_OK);
@@ -515,7 +616,9 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     size_t off = align256(sizeof(DevInstance) * n_inst);
     c->dev_desc = (DevInstance*)c->ws;
     c->dev_items = (WorkItem*)(c->ws + off);
-    off = align256(off + c->items.size() * sizeof(WorkItem));
+    off = align256(off + c->items_cap * sizeof(WorkItem));
+    c->dev_status = (double*)(c->ws + off);
+    off = align256(off + 4 * sizeof(double) * (size_t)n_inst);
     if (off > ws_bytes) {
         delete c;
         return LBE_ENOMEM;
@@ -718,55 +821,52 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
 {
     if (!c || !(tol > 0) || max_steps < 1 || check_every < 1) return LBE_EINVAL;
     if (c->nan_latched) return LBE_ENAN;
-    std::vector<int64_t> done(c->ninst, 0);
-    std::vector<double> res(c->ninst, -1.0);
     std::fill(c->active.begin(), c->active.end(), 1);
     lbe_status st = upload_flags(c);
+    if (st != LBE_OK) return st;
+    // per instance: residual (-1 until judged), steps, nan flag, active
+    std::vector<double> stv(4 * (size_t)c->ninst, 0.0);
+    for (int k = 0; k < c->ninst; k++) {
+        stv[4 * k] = -1.0;
+        stv[4 * k + 3] = 1.0;
+    }
+    st = dev_err(c, hipMemcpyAsync(c->dev_status, stv.data(), stv.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   c->stream),
+                 "status upload");
     if (st != LBE_OK) return st;
     int64_t taken = 0;
     bool all = false;
     while (taken < max_steps && !all) {
-        int64_t chunk = std::min<int64_t>(check_every, max_steps - taken);
-        for (int64_t s = 0; s < chunk; s++) {
-            if (s == chunk - 1) {
-                st = dev_err(c, launch_snapshot(c->dev_desc, c->ninst, c->stream), "snapshot");
-                if (st != LBE_OK) return st;
-            }
-            st = enqueue_step(c);
-            if (st != LBE_OK) return st;
-        }
-        st = dev_err(c, launch_residual(c->dev_desc, c->ninst, c->stream), "residual");
+        const int chunk = (int)std::min<int64_t>(check_every, max_steps - taken);
+        st = enqueue_chunk(c, chunk, tol, chunk == check_every);
         if (st != LBE_OK) return st;
-        st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
-        if (st != LBE_OK) return st;
-        st = check_nan(c);
+        st = dev_err(c, hipMemcpyAsync(stv.data(), c->dev_status, stv.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, c->stream),
+                     "status read");
+        if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
         if (st != LBE_OK) return st;
         taken += chunk;
         all = true;
         for (int k = 0; k < c->ninst; k++) {
-            if (!c->active[k]) continue;
-            done[k] += chunk;
-            c->steps[k] += chunk;
-            double r = 0;
-            st = dev_err(c, hipMemcpy(&r, c->host_desc[k].resid, sizeof(double), hipMemcpyDeviceToHost), "resid");
-            if (st != LBE_OK) return st;
-            if (chunk == check_every) res[k] = r;
-            if (chunk == check_every && r <= tol)
-                c->active[k] = 0;
-            else
-                all = false;
+            if (stv[4 * k + 2] != 0) {
+                c->nan_latched = true;
+                c->err = "non-finite state or non-positive density/temperature in instance " + std::to_string(k);
+                return LBE_ENAN;
+            }
+            if (stv[4 * k + 3] != 0) all = false;
         }
-        st = upload_flags(c);
-        if (st != LBE_OK) return st;
     }
     std::fill(c->active.begin(), c->active.end(), 1);
     st = upload_flags(c);
     if (st != LBE_OK) return st;
     bool conv = true;
     for (int k = 0; k < c->ninst; k++) {
-        if (steps_out) steps_out[k] = done[k];
-        if (resid_out) resid_out[k] = res[k];
-        if (!(res[k] >= 0 && res[k] <= tol)) conv = false;
+        const int64_t done = (int64_t)stv[4 * k + 1];
+        const double r = stv[4 * k];
+        c->steps[k] += done;
+        if (steps_out) steps_out[k] = done;
+        if (resid_out) resid_out[k] = r;
+        if (!(r >= 0 && r <= tol)) conv = false;
     }
     return conv ? LBE_OK : LBE_ENOTCONV;
 }
@@ -866,6 +966,91 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
     return LBE_OK;
 }
 
+lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int32_t* ngroups_out)
+{
+    if (!c || reps < 1) return LBE_EINVAL;
+    const int ng = (int)c->groups.size();
+    if (ngroups_out) *ngroups_out = ng;
+    if (out && cap < 4 * (int64_t)ng) return LBE_EINVAL;
+    if (c->nan_latched) return LBE_ENAN;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    // the stage launches below overwrite the moment sums and buffer 1; keep the sums
+    std::vector<std::vector<double>> mom(c->ninst);
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
+        const DevInstance& d = c->host_desc[k];
+        mom[k].resize((size_t)d.nr * d.nslices * kMomStride);
+        st = dev_err(c, hipMemcpy(mom[k].data(), d.mom, mom[k].size() * sizeof(double), hipMemcpyDeviceToHost),
+                     "moment save");
+    }
+    if (st != LBE_OK) return st;
+    // coefficients of the state, so that the timed launches see the real data
+    st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "node");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e0), "event");
+    if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e1), "event");
+    auto time_group = [&](int q, double* ms) -> lbe_status {
+        build_items(c);
+        if (c->items.size() > c->items_cap) return LBE_EINVAL;
+        hipError_t e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
+                                      hipMemcpyHostToDevice, c->stream);
+        auto one = [&]() {
+            return launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], 0, 0, 1,
+                                0.0, 1.0, 0, c->stream);
+        };
+        if (e == hipSuccess) e = one();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; r++) e = one();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+        return dev_err(c, e, "autotune launch");
+    };
+    for (int q = 0; q < ng && st == LBE_OK; q++) {
+        const StageGroup base = c->groups[q];
+        StageGroup best = base;
+        double best_ms = 0, base_ms = 0;
+        st = time_group(q, &base_ms);
+        best_ms = base_ms;
+        for (int cand : kTileCandidates) {
+            if (st != LBE_OK || cand == base.NT) continue;
+            StageGroup G = base;
+            if (!layout_group(&G, cand) || G.NT != cand) continue;
+            c->groups[q] = G;
+            double ms = 0;
+            st = time_group(q, &ms);
+            if (st == LBE_OK && ms < best_ms) {
+                best_ms = ms;
+                best = G;
+            }
+        }
+        c->groups[q] = best;
+        if (out) {
+            out[4 * q] = base.nv;
+            out[4 * q + 1] = best.NT;
+            out[4 * q + 2] = best_ms;
+            out[4 * q + 3] = base_ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    build_items(c);
+    lbe_status st2 = dev_err(c, hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
+                                               hipMemcpyHostToDevice, c->stream),
+                             "items upload");
+    for (int k = 0; k < c->ninst && st2 == LBE_OK; k++)
+        st2 = dev_err(c, hipMemcpyAsync(c->host_desc[k].mom, mom[k].data(), mom[k].size() * sizeof(double),
+                                        hipMemcpyHostToDevice, c->stream),
+                      "moment restore");
+    if (st2 == LBE_OK) st2 = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    drop_graphs(c);
+    if (st != LBE_OK) return st;
+    if (st2 != LBE_OK) return st2;
+    return check_nan(c);
+}
+
 lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap)
 {
     if (!c) return LBE_EINVAL;
@@ -902,6 +1087,8 @@ void lbe_free(lbe_ctx* c)
 {
     if (!c) return;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 

@@ -1145,6 +1145,32 @@ __global__ void __launch_bounds__(kBlock) k_residual(const DevInstance* __restri
     if (threadIdx.x == 0) I.resid[0] = smax[0] / I.dt;
 }
 
+// Steady-state bookkeeping after a chunk of `chunk` steps, one thread per instance: every
+// active instance counts the steps; when `judge` is set its residual is recorded and it is frozen
+// once the residual is <= tol.  st[4 k ..]: residual, steps taken, nan flag, active after the call.
+__global__ void __launch_bounds__(kBlock)
+    k_converge(const DevInstance* __restrict__ insts, int ninst, double tol, int chunk, int judge, double* st)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= ninst) return;
+    const DevInstance& I = insts[k];
+    double* o = st + 4 * (size_t)k;
+    int active = I.flags[1];
+    if (active) {
+        o[1] += chunk;
+        if (judge) {
+            const double r = I.resid[0];
+            o[0] = r;
+            if (r <= tol) {
+                active = 0;
+                I.flags[1] = 0;
+            }
+        }
+    }
+    o[2] = (double)I.flags[0];
+    o[3] = (double)active;
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s)
@@ -1199,6 +1225,14 @@ hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s)
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_residual, dim3(1, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chunk, int judge, double* st,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_converge, dim3((ninst + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, ninst, tol, chunk,
+                       judge, st);
     return hipGetLastError();
 }
 

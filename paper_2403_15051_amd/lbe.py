@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
     lib.lbe_info.argtypes = [vp, i32, _D, i64]
     lib.lbe_tables.argtypes = [P, i32, _D, _D, i64, _I64]
     lib.lbe_timing.argtypes = [vp, i32, _D, i64]
+    lib.lbe_autotune.argtypes = [vp, i32, _D, i64, ctypes.POINTER(i32)]
     lib.lbe_last_error.argtypes = [vp]
     lib.lbe_last_error.restype = ctypes.c_char_p
     lib.lbe_status_string.argtypes = [ctypes.c_int]
@@ -96,7 +97,8 @@ def load() -> ctypes.CDLL:
     lib.lbe_free.argtypes = [vp]
     lib.lbe_free.restype = None
     for name in ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
-                 "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_status_string"):
+                 "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune",
+                 "lbe_status_string"):
         if name != "lbe_status_string":
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -104,8 +106,8 @@ def load() -> ctypes.CDLL:
 
 
 EXPORTS = ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
-           "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_last_error", "lbe_status_string",
-           "lbe_free")
+           "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune", "lbe_last_error",
+           "lbe_status_string", "lbe_free")
 
 
 def _ptr(a: np.ndarray):
@@ -223,6 +225,13 @@ class Solver:
         out = np.zeros(4)
         self._check(self._lib.lbe_timing(self._h, 0, _ptr(out), 4), "lbe_timing")
         return {"stage_ms": out[0], "stage_launches": int(out[1]), "node_ms": out[2], "node_launches": int(out[3])}
+
+    def autotune(self, reps: int = 3) -> list[dict]:
+        ng = ctypes.c_int32(0)
+        out = np.zeros(4 * self.n_inst)  # at most one launch group per instance
+        self._check(self._lib.lbe_autotune(self._h, reps, _ptr(out), out.size, ctypes.byref(ng)), "lbe_autotune")
+        return [{"nv": int(out[4 * q]), "tile_nodes": int(out[4 * q + 1]), "ms": out[4 * q + 2],
+                 "ms_before": out[4 * q + 3]} for q in range(ng.value)]
 
     def rhs(self, inst: int = 0) -> np.ndarray:
         nr, nv = int(self._infos[inst]["nr"]), int(self._infos[inst]["nv"])
