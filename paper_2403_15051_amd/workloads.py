@@ -69,3 +69,55 @@ def sweep(n: int = 256, seed: int = SWEEP_SEED, nr_range=(64, 512), c_min: float
 def solver_params(d: dict) -> dict:
     """Drop bookkeeping keys that are not part of the problem statement."""
     return {k: v for k, v in d.items() if k != "flag"}
+
+
+# ---------------------------------------------------------------- learned warm start inputs
+MLP_LAYERS = ((6, 256), (256, 256), (256, 256), (256, 256), (256, 5))
+WARM_TRAIN_SEED = 240315052
+WARM_HELDOUT_SEED = 240315053
+
+
+def mlp_params(seed: int) -> np.ndarray:
+    """Random network parameters (uniform, Glorot scale, FP32-representable), packed layer by
+    layer as W [fan_out][fan_in] then b [fan_out]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fin, fout in MLP_LAYERS:
+        a = np.sqrt(6.0 / (fin + fout))
+        parts.append(rng.uniform(-a, a, size=fin * fout))
+        parts.append(rng.uniform(-0.1, 0.1, size=fout))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
+def mlp_batch(seed: int, rows: int):
+    """Random inputs (rows x 6) and targets (rows x 5), FP32-representable."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((rows, 6)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((rows, 5)).astype(np.float32).astype(np.float64)
+    return X, T
+
+
+def mlp_grad_vector(seed: int, n: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(n) * 1e-2).astype(np.float32).astype(np.float64)
+
+
+def smooth_profile(nr: int, seed: int) -> dict:
+    """A smooth synthetic profile (n, u_t1, T, q_r, P_rt1) on nr nodes, for the warm-start state."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nr) + 0.5) / nr
+    a = rng.uniform(-1, 1, size=5)
+    return {"n": 1.0 + 0.2 * a[0] * np.cos(np.pi * x), "u_t1": 0.1 * a[1] * (1 - x),
+            "T": 1.0 + 0.3 * abs(a[2]) * x, "q_r": 0.02 * a[3] * np.sin(np.pi * x),
+            "P_rt1": 0.01 * a[4] * (1 + x)}
+
+
+def warm_sweep(n: int, seed: int, nr_range=(24, 48), orders=(4,)):
+    """Training / held-out instances of the warm start: the sweep's physical draws (flag, eta0, Kn,
+    u_w, T2/T1) with a reduced grid and velocity set (Nr and Q drawn from the given ranges)."""
+    ps, acc = sweep(n, seed=seed, nr_range=nr_range)
+    rng = np.random.default_rng(seed + 1)
+    for p in ps:
+        q = int(orders[int(rng.integers(0, len(orders)))])
+        p.update(q_radial=q, q_t1=q, q_t2=max(q // 2, 4))
+    return ps, acc
