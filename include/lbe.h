@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct lbe_ctx lbe_ctx; /* opaque */
+typedef struct lbe_mlp lbe_mlp; /* opaque: network of the learned warm start */
 
 typedef enum {
     LBE_OK = 0,
@@ -54,6 +55,7 @@ typedef enum {
 
 enum { LBE_CYL = 0, LBE_SPH = 1 };
 enum { LBE_FP64 = 0 };
+enum { LBE_GEMM_BF16 = 0, LBE_GEMM_FP32 = 1 }; /* matrix-core operand type of the network */
 
 /* Problem statement of one instance (Sec. IV set-up of the paper). */
 typedef struct {
@@ -152,6 +154,78 @@ lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap);
  * launch, the ms of the tile height in use before the call); cap >= 4 * groups (out may be NULL);
  * *ngroups_out (may be NULL) receives the number of groups.  Synchronises. */
 lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int32_t* ngroups_out);
+
+/* ---------------------------------------------------------------- learned warm start
+ * Not part of the paper: a network maps (geometry flag, eta0, Kn, u_w, T2/T1, r_hat) to the
+ * steady profile (n, u_t1, T, q_r, P_r,t1) at one node, trained on steady states this solver
+ * computes.  The solver only starts from its prediction: the state is the Grad 13-moment
+ * distribution on the collision term's discrete equilibrium, scaled to the rest start's mass,
+ * and it is kept only where its one-step residual beats the rest start's.
+ *
+ * Network: 6 -> 256 -> 256 -> 256 -> 256 -> 5, SiLU hidden activations, linear output; 200 453
+ * FP32 parameters packed per layer as W [fan_out][fan_in] (row-major) then b [fan_out].  Every
+ * matrix product runs on the matrix cores with BF16 operands and FP32 accumulation
+ * (LBE_GEMM_BF16), or FP32 operands (LBE_GEMM_FP32).  Outputs are standardised targets:
+ * profile = mean + scale * output, per field.  Device pointers (dev_*) are float arrays in
+ * device memory owned by the caller, row-major [rows][6] inputs and [rows][5] outputs/targets.
+ */
+
+/* Device workspace of a network that processes up to max_rows rows per pass; *n_params receives
+ * the parameter count (both may be NULL). */
+lbe_status lbe_mlp_query(int32_t max_rows, size_t* device_bytes, int64_t* n_params);
+/* Network in device_ws (256-byte aligned, >= lbe_mlp_query's bytes; zeroed) on hip_stream. */
+lbe_status lbe_mlp_init(int32_t max_rows, int32_t gemm_kind, void* device_ws, size_t ws_bytes, void* hip_stream,
+                        lbe_mlp** out);
+/* Uniform Glorot initialisation of the weights from a seeded host generator, zero biases; resets
+ * the Adam state. */
+lbe_status lbe_mlp_init_params(lbe_mlp* m, uint64_t seed);
+/* Parameters in / out (host FP32, len / cap >= parameter count); setting resets the Adam state. */
+lbe_status lbe_mlp_set_params(lbe_mlp* m, const float* host, int64_t len);
+lbe_status lbe_mlp_get_params(lbe_mlp* m, float* host, int64_t cap);
+/* Target standardisation (5 means, 5 positive scales, FP64). */
+lbe_status lbe_mlp_set_scaling(lbe_mlp* m, const double* mean, const double* scale);
+lbe_status lbe_mlp_get_scaling(lbe_mlp* m, double* mean, double* scale);
+/* Outputs of rows <= max_rows input rows (async on the network's stream). */
+lbe_status lbe_mlp_forward(lbe_mlp* m, const float* dev_x, int32_t rows, float* dev_y);
+/* Mean-squared error of the outputs against standardised targets dev_t over rows x 5 and its
+ * gradient with respect to every parameter (kept for lbe_mlp_adam_step; copied to host_grad when
+ * it is not NULL, cap >= parameter count); synchronises. */
+lbe_status lbe_mlp_loss_grad(lbe_mlp* m, const float* dev_x, const float* dev_t, int32_t rows, double* loss,
+                             float* host_grad, int64_t cap);
+/* Replace the kept gradient (host FP32, len = parameter count). */
+lbe_status lbe_mlp_set_grads(lbe_mlp* m, const float* host, int64_t len);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the kept gradient. */
+lbe_status lbe_mlp_adam_step(lbe_mlp* m, float lr);
+/* Training on n rows (dev_x [n][6], dev_t [n][5] unstandardised profiles): sets the target
+ * standardisation from the data (mean and standard deviation per field), then `epochs` passes of
+ * minibatches of `batch` rows (<= max_rows) in a seeded affine permutation of the rows, each a
+ * forward pass, the loss, the backward pass and an Adam step; the learning rate falls from lr to
+ * lr / 10 on a cosine over the epochs.  host_loss[epoch] (may be NULL) receives each epoch's mean
+ * loss.  Synchronises once per epoch. */
+lbe_status lbe_mlp_train(lbe_mlp* m, const float* dev_x, const float* dev_t, int64_t n, int32_t epochs, int32_t batch,
+                         float lr, uint64_t seed, double* host_loss);
+const char* lbe_mlp_last_error(const lbe_mlp* m);
+void lbe_mlp_free(lbe_mlp* m);
+
+/* Network inputs of every node of every instance, rows instance-major (instance k's nodes start
+ * at row sum_{j<k} nr_j): geometry flag, then (eta0 - 0.155) / s1, (log10 Kn + 0.5) / s2,
+ * (u_w - 0.25) / s3, (T2/T1 - 1.5) / s4, (r_hat - 0.5) / s5 with s = (b - a) / sqrt(12) of the
+ * ranges U(0.01, 0.3), U(-2, 1), U(0, 0.5), U(1, 2), U(0, 1); r_hat = (r_i - R_L - sigma/2) /
+ * (L - sigma).  *rows_out (may be NULL) receives the row count; cap_rows >= it; synchronises. */
+lbe_status lbe_features(lbe_ctx* c, float* dev_x, int64_t cap_rows, int64_t* rows_out);
+/* Profiles (n, u_t1, T, q_r, P_r,t1) of the current states, rows as in lbe_features (training
+ * targets); synchronises. */
+lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows);
+/* Start instance inst from a given profile host_in[field * nr + i], fields n, u_t1, T, q_r,
+ * P_r,t1 (n, T > 0; u_r = u_t2 = 0): Grad-13 state, scaled to the rest start's total mass
+ * sum_i V_i n_i = sum_i V_i.  Synchronises; clears a latched LBE_ENAN. */
+lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in, int64_t len);
+/* Start every instance from the network's prediction (n, T kept within [0.05, 20]).  With judge
+ * set, one step is taken from the rest start and one from the predicted state, and an instance
+ * keeps the prediction only if its residual (as in lbe_run_to_steady) is the smaller; the others
+ * get the rest start.  kept[k] (may be NULL) receives 1 / 0; rho[2k], rho[2k+1] (may be NULL)
+ * the two residuals (-1 without judge).  Step counters are unchanged.  Synchronises. */
+lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, double* rho);
 
 const char* lbe_last_error(const lbe_ctx* c);
 const char* lbe_status_string(lbe_status s);

@@ -24,6 +24,15 @@ hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chun
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
                         int dst, double an, double bs, int rhs, hipStream_t s);
 hipError_t set_stage_smem_limit();
+hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s);
+hipError_t launch_warm_profile_net(const DevInstance* d, const int32_t* rowoff, int ninst, int r0, int rows,
+                                   float* X, const float* Y, const double* mean, const double* scale,
+                                   const int32_t* mask, int features_only, hipStream_t s);
+hipError_t launch_profile_from_host(const DevInstance* d, int inst, hipStream_t s);
+hipError_t launch_grad13(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s);
+hipError_t launch_rest(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s);
+hipError_t launch_renorm(const DevInstance* d, int ninst, const int32_t* mask, hipStream_t s);
+hipError_t launch_collect_resid(const DevInstance* d, int ninst, double* out, hipStream_t s);
 }  // namespace lbe
 
 using namespace lbe;
@@ -60,6 +69,11 @@ struct lbe_ctx {
     size_t items_cap = 0;              // work items the device list has room for
     // steady-state bookkeeping [ninst][4] (residual, steps, nan flag, active), device side
     double* dev_status = nullptr;
+    // warm start: first row (node) of every instance [ninst + 1], instance mask [ninst], residuals
+    int32_t* dev_rowoff = nullptr;
+    int32_t* dev_mask = nullptr;
+    double* dev_vec = nullptr;
+    std::vector<int32_t> rowoff;
     // captured launch sequences: one RK3 step, and one steady-state chunk (chunk steps, the
     // residual and the freeze test), replayed on `stream`; captured on a private stream
     bool use_graph = true;
@@ -76,7 +90,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Byte layout of one instance inside the workspace.
 struct Layout {
     size_t f[3], mom, node, snap, resid, flags, nw, scratch;
-    size_t p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
+    size_t rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
     size_t total;
 };
 
@@ -101,6 +115,7 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t base)
     L.flags = take(4 * sizeof(int32_t));
     L.nw = take(2 * D);
     L.scratch = take(plane);
+    L.rest = take((size_t)(t.n0 + t.n1 + t.n2) * D);
     L.p0 = take(t.n0 * D);
     L.p1 = take(t.n1 * D);
     L.p2 = take(t.n2 * D);
@@ -132,7 +147,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
-    size_t b = 3 * align256((nr + 4) * nv * D) + align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
+    size_t b = align256((size_t)(n0 + n1 + n2) * D) + 3 * align256((nr + 4) * nv * D) + align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
                align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
@@ -549,7 +564,9 @@ const char* lbe_last_error(const lbe_ctx* c) { return c ? c->err.c_str() : "null
 lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, size_t* host_bytes)
 {
     if (!p || n_inst < 1) return LBE_EINVAL;
-    size_t total = align256(sizeof(DevInstance) * n_inst) + align256(4 * sizeof(double) * (size_t)n_inst);
+    size_t total = align256(sizeof(DevInstance) * n_inst) + align256(4 * sizeof(double) * (size_t)n_inst) +
+                   align256(sizeof(int32_t) * (size_t)(n_inst + 1)) + align256(sizeof(int32_t) * (size_t)n_inst) +
+                   align256(2 * sizeof(double) * (size_t)n_inst);
     size_t host = sizeof(lbe_ctx);
     for (int k = 0; k < n_inst; k++) {
         lbe_params q;
@@ -619,12 +636,23 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     off = align256(off + c->items_cap * sizeof(WorkItem));
     c->dev_status = (double*)(c->ws + off);
     off = align256(off + 4 * sizeof(double) * (size_t)n_inst);
+    c->dev_rowoff = (int32_t*)(c->ws + off);
+    off = align256(off + sizeof(int32_t) * (size_t)(n_inst + 1));
+    c->dev_mask = (int32_t*)(c->ws + off);
+    off = align256(off + sizeof(int32_t) * (size_t)n_inst);
+    c->dev_vec = (double*)(c->ws + off);
+    off = align256(off + 2 * sizeof(double) * (size_t)n_inst);
+    c->rowoff.assign(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; k++) c->rowoff[k + 1] = c->rowoff[k] + c->tabs[k].nr;
     if (off > ws_bytes) {
         delete c;
         return LBE_ENOMEM;
     }
     hipError_t e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
                                   hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->dev_rowoff, c->rowoff.data(), c->rowoff.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           c->stream);
     for (int k = 0; k < n_inst && e == hipSuccess; k++) {
         const InstanceTables& t = c->tabs[k];
         const int nsl = c->groups[c->group_of[k]].S;
@@ -654,6 +682,10 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.L = t.L;
         d.gin_l = t.gin_l;
         d.gin_r = t.gin_r;
+        d.rcl = t.rcl;
+        d.rcr = t.rcr;
+        d.uw = t.prm.u_wall_inner;
+        d.tratio = t.prm.t_wall_outer / t.prm.t_wall_inner;
         char* ws = c->ws;
         for (int b = 0; b < 3; b++) d.f[b] = (double*)(ws + L.f[b]);
         d.mom = (double*)(ws + L.mom);
@@ -663,6 +695,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.flags = (int32_t*)(ws + L.flags);
         d.nw = (double*)(ws + L.nw);
         d.scratch = (double*)(ws + L.scratch);
+        d.rest = (const double*)(ws + L.rest);
         d.p0 = (const double*)(ws + L.p0);
         d.p1 = (const double*)(ws + L.p1);
         d.p2 = (const double*)(ws + L.p2);
@@ -707,18 +740,22 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         if (e == hipSuccess) e = put(ws, L.wb, t.wb, c->stream);
         if (e == hipSuccess) e = put(ws, L.gwl, t.gwl, c->stream);
         if (e == hipSuccess) e = put(ws, L.gwr, t.gwr, c->stream);
-        // rest start: n = 1, u = 0, T = 1
+        // rest start: n = 1, u = 0, T = 1 (its axis factors are kept for resets on the device)
         if (e == hipSuccess) {
             std::vector<double> g0(t.n0), g1(t.n1), g2(t.n2), f((size_t)t.nr * t.nv);
             equilibrium_axis(t.ax[0], 0.0, 1.0, g0.data());
             equilibrium_axis(t.ax[1], 0.0, 1.0, g1.data());
             equilibrium_axis(t.ax[2], 0.0, 1.0, g2.data());
+            std::vector<double> rest(g0);
+            rest.insert(rest.end(), g1.begin(), g1.end());
+            rest.insert(rest.end(), g2.begin(), g2.end());
+            e = hipMemcpy(ws + L.rest, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice);
             for (int v = 0; v < t.nv; v++) {
                 const int i0 = v % t.n0, i1 = (v / t.n0) % t.n1, i2 = v / (t.n0 * t.n1);
                 const double val = g0[i0] * g1[i1] * g2[i2];
                 for (int i = 0; i < t.nr; i++) f[(size_t)i * t.nv + v] = val;
             }
-            e = hipMemcpy(d.f[0], f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(d.f[0], f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
         }
     }
     if (e == hipSuccess)
@@ -964,6 +1001,182 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
     if (!out || cap < (int64_t)v.size()) return LBE_EINVAL;
     std::memcpy(out, v.data(), v.size() * sizeof(double));
     return LBE_OK;
+}
+
+lbe_status lbe_features(lbe_ctx* c, float* dev_x, int64_t cap_rows, int64_t* rows_out)
+{
+    if (!c) return LBE_EINVAL;
+    const int rows = c->rowoff[c->ninst];
+    if (rows_out) *rows_out = rows;
+    if (!dev_x || cap_rows < rows) return LBE_EINVAL;
+    lbe_status st = dev_err(c, launch_warm_profile_net(c->dev_desc, c->dev_rowoff, c->ninst, 0, rows, dev_x, nullptr,
+                                                       nullptr, nullptr, nullptr, 1, c->stream),
+                            "features");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    return st;
+}
+
+lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows)
+{
+    if (!c || !dev_t) return LBE_EINVAL;
+    const int rows = c->rowoff[c->ninst];
+    if (cap_rows < rows) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    std::vector<int32_t> saved = c->active;
+    std::fill(c->active.begin(), c->active.end(), 1);
+    st = upload_flags(c);
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "node pass");
+    std::vector<float> out((size_t)rows * 5);
+    const int fields[5] = {NF_N, NF_U1, NF_T, NF_Q0, NF_P01};
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
+        const DevInstance& d = c->host_desc[k];
+        std::vector<double> node((size_t)d.nr * kNodeStride);
+        st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                       c->stream),
+                     "node read");
+        if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+        for (int i = 0; i < d.nr && st == LBE_OK; i++)
+            for (int q = 0; q < 5; q++)
+                out[((size_t)c->rowoff[k] + i) * 5 + q] = (float)node[(size_t)i * kNodeStride + fields[q]];
+    }
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpyAsync(dev_t, out.data(), out.size() * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                     "target upload");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    c->active = saved;
+    lbe_status st2 = upload_flags(c);
+    if (st != LBE_OK) return st;
+    if (st2 != LBE_OK) return st2;
+    return check_nan(c);
+}
+
+namespace {
+
+lbe_status upload_mask(lbe_ctx* c, const std::vector<int32_t>& mask)
+{
+    return dev_err(c, hipMemcpyAsync(c->dev_mask, mask.data(), mask.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                     c->stream),
+                   "mask upload");
+}
+
+// Grad-13 state of the masked instances from the profiles in their node blocks, then the mass
+// renormalisation and the moment sums of the new state.
+hipError_t build_warm_state(lbe_ctx* c)
+{
+    hipError_t e = launch_proj(c->dev_desc, c->ninst, c->maxnr, c->stream);
+    if (e == hipSuccess) e = launch_grad13(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream);
+    if (e == hipSuccess) e = launch_renorm(c->dev_desc, c->ninst, c->dev_mask, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream);
+    return e;
+}
+
+// Network prediction of every node of the masked instances into their node blocks, in chunks of
+// the network's row capacity, then their warm state.
+hipError_t predict_warm_state(lbe_ctx* c, lbe_mlp* m)
+{
+    const int rows = c->rowoff[c->ninst], R = mlp_max_rows(m);
+    double mean[5], scale[5];
+    mlp_scaling(m, mean, scale);
+    hipError_t e = hipSuccess;
+    for (int r0 = 0; r0 < rows && e == hipSuccess; r0 += R) {
+        const int n = std::min(R, rows - r0);
+        e = launch_warm_profile_net(c->dev_desc, c->dev_rowoff, c->ninst, r0, n, mlp_input(m), nullptr, nullptr,
+                                    nullptr, nullptr, 1, c->stream);
+        if (e == hipSuccess) e = mlp_forward_rows(m, mlp_input(m), n, c->stream);
+        if (e == hipSuccess)
+            e = launch_warm_profile_net(c->dev_desc, c->dev_rowoff, c->ninst, r0, n, nullptr, mlp_output(m), mean,
+                                        scale, c->dev_mask, 0, c->stream);
+    }
+    if (e == hipSuccess) e = build_warm_state(c);
+    return e;
+}
+
+// One full step of every instance from its current state and the residual of that step.
+lbe_status one_step_residual(lbe_ctx* c, std::vector<double>& out)
+{
+    lbe_status st = dev_err(c, launch_snapshot(c->dev_desc, c->ninst, c->stream), "snapshot");
+    if (st == LBE_OK) st = enqueue_step(c);
+    if (st == LBE_OK) st = dev_err(c, launch_residual(c->dev_desc, c->ninst, c->stream), "residual");
+    if (st == LBE_OK) st = dev_err(c, launch_collect_resid(c->dev_desc, c->ninst, c->dev_vec, c->stream), "collect");
+    out.assign(c->ninst, 0.0);
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpyAsync(out.data(), c->dev_vec, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                       c->stream),
+                     "residual read");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    return st;
+}
+
+}  // namespace
+
+lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in, int64_t len)
+{
+    if (!c || inst < 0 || inst >= c->ninst || !host_in) return LBE_EINVAL;
+    const DevInstance& d = c->host_desc[inst];
+    if (len != 5 * (int64_t)d.nr) return LBE_EINVAL;
+    for (int i = 0; i < d.nr; i++)
+        if (!(host_in[i] > 0) || !(host_in[2 * d.nr + i] > 0)) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    st = dev_err(c, hipMemcpy(d.scratch, host_in, (size_t)len * sizeof(double), hipMemcpyHostToDevice), "profile");
+    if (st != LBE_OK) return st;
+    // only this instance is active while its state is rebuilt
+    std::fill(c->active.begin(), c->active.end(), 0);
+    c->active[inst] = 1;
+    st = upload_flags(c);
+    std::vector<int32_t> mask(c->ninst, 0);
+    mask[inst] = 1;
+    if (st == LBE_OK) st = upload_mask(c, mask);
+    if (st == LBE_OK) st = dev_err(c, launch_profile_from_host(c->dev_desc, inst, c->stream), "profile");
+    if (st == LBE_OK) st = dev_err(c, build_warm_state(c), "warm state");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    std::fill(c->active.begin(), c->active.end(), 1);
+    lbe_status st2 = upload_flags(c);
+    c->nan_latched = false;
+    return st != LBE_OK ? st : st2;
+}
+
+lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, double* rho)
+{
+    if (!c || !m) return LBE_EINVAL;
+    if (c->nan_latched) return LBE_ENAN;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    std::fill(c->active.begin(), c->active.end(), 1);
+    st = upload_flags(c);
+    if (st != LBE_OK) return st;
+    std::vector<int32_t> keep(c->ninst, 1);
+    std::vector<double> r_rest(c->ninst, -1.0), r_warm(c->ninst, -1.0);
+    if (judge) {
+        // one step from the rest start and one from the predicted state
+        st = dev_err(c, launch_rest(c->dev_desc, c->ninst, c->maxnr, nullptr, c->stream), "rest");
+        if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
+        if (st == LBE_OK) st = one_step_residual(c, r_rest);
+        if (st == LBE_OK) st = upload_mask(c, keep);
+        if (st == LBE_OK) st = dev_err(c, predict_warm_state(c, m), "prediction");
+        if (st == LBE_OK) st = one_step_residual(c, r_warm);
+        if (st != LBE_OK) return st;
+        for (int k = 0; k < c->ninst; k++) keep[k] = (r_warm[k] < r_rest[k]) ? 1 : 0;  // NaN falls back
+    }
+    // final state: the prediction where kept, the rest start elsewhere
+    st = upload_mask(c, keep);
+    if (st == LBE_OK) st = dev_err(c, predict_warm_state(c, m), "prediction");
+    if (st == LBE_OK) st = dev_err(c, launch_rest(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream), "rest");
+    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    // a judged state that went non-finite has been replaced: clear the device flags
+    st = upload_flags(c);
+    for (int k = 0; k < c->ninst; k++) {
+        if (kept) kept[k] = keep[k];
+        if (rho) {
+            rho[2 * k] = r_warm[k];
+            rho[2 * k + 1] = r_rest[k];
+        }
+    }
+    return st;
 }
 
 lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int32_t* ngroups_out)

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/lbe.h"
 
 namespace lbe {
@@ -67,6 +69,7 @@ struct DevInstance {
     int32_t nr, nv, n0, n1, n2, geometry;
     int32_t N0, N1, N2, wband;
     double dt, dr, eta0, kn, chi0, L, gin_l, gin_r;
+    double rcl, rcr, uw, tratio;  // computational walls, inner wall speed, T_outer / T_inner
     double* f[3];           // state buffers [nr][nv]; f[0] holds the state between steps
     double* mom;            // [nr][nslices][kMomStride] moment sums of the last written buffer (per slice)
     double* node;           // [nr][kNodeStride] node coefficients of the current stage
@@ -85,7 +88,8 @@ struct DevInstance {
     double* resid;          // [1] last residual
     int32_t* flags;         // [4] 0: nan flag, 1: active (1) / frozen (0)
     double* nw;             // [2] wall densities of the current stage
-    double* scratch;        // [nr][nv] rhs output (lbe_rhs)
+    double* scratch;        // [nr][nv] rhs output (lbe_rhs); staging of lbe_set_init_moments
+    const double* rest;     // [n0 + n1 + n2] equilibrium factors at rest (n = 1, u = 0, T = 1)
 };
 
 // One unit of stage-kernel work: a tile of consecutive nodes of one instance, one velocity slice.
@@ -113,6 +117,14 @@ struct StageGroup {
 };
 
 constexpr int kCoefStride = 18;  // doubles per node of the stage kernel's coefficient block
+
+// Network of the learned warm start (lbe_mlp.hip): buffers and the forward pass used by
+// lbe_warm_start.  Outputs are standardised: physical = mean + scale * output.
+int mlp_max_rows(const lbe_mlp* m);
+float* mlp_input(lbe_mlp* m);
+const float* mlp_output(const lbe_mlp* m);
+void mlp_scaling(const lbe_mlp* m, double* mean, double* scale);
+hipError_t mlp_forward_rows(lbe_mlp* m, const float* X, int rows, hipStream_t s);
 
 // Host table construction (lbe_tables.cpp).
 lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err);

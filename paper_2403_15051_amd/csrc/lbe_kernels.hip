@@ -1171,6 +1171,187 @@ __global__ void __launch_bounds__(kBlock)
     o[3] = (double)active;
 }
 
+// ------------------------------------------------------------------ warm start
+
+// Instance of global row `row` (rows are the nodes of all instances, instance-major).
+__device__ inline int row_instance(const int32_t* rowoff, int ninst, int row)
+{
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rowoff[mid] <= row) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Network inputs of rows [r0, r0 + rows): geometry flag, then eta0, log10 Kn, u_w, T2/T1 and the
+// node's position r_hat in [0, 1] between the walls, each standardised for the sweep's uniform
+// draws (eta0 ~ U(0.01, 0.3), log10 Kn ~ U(-2, 1), u_w ~ U(0, 0.5), T2/T1 ~ U(1, 2),
+// r_hat ~ U(0, 1): subtract the mean, divide by (b - a) / sqrt(12)).
+__global__ void __launch_bounds__(kBlock) k_features(const DevInstance* __restrict__ insts,
+                                                     const int32_t* __restrict__ rowoff, int ninst, int r0, int rows,
+                                                     float* __restrict__ X)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= rows) return;
+    const int row = r0 + t;
+    const int k = row_instance(rowoff, ninst, row);
+    const DevInstance& I = insts[k];
+    const int i = row - rowoff[k];
+    const double s12 = 3.4641016151377545870548926830117447;  // sqrt(12)
+    const double rh = (I.r[i] - I.rcl) / (I.rcr - I.rcl);
+    float* x = X + (size_t)t * 6;
+    x[0] = (float)I.geometry;
+    x[1] = (float)((I.eta0 - 0.155) * s12 / 0.29);
+    x[2] = (float)((log10(I.kn) + 0.5) * s12 / 3.0);
+    x[3] = (float)((I.uw - 0.25) * s12 / 0.5);
+    x[4] = (float)((I.tratio - 1.5) * s12);
+    x[5] = (float)((rh - 0.5) * s12);
+}
+
+struct Scale5 {
+    double mean[5], scale[5];
+};
+
+// Node blocks of the masked instances from a profile (n, u_t1, T, q_r, P_r,t1) per node: either
+// standardised network outputs Y of rows [r0, r0 + rows) (src_kind 0), or an FP64 profile
+// [5][nr] in the instance's scratch (src_kind 1, one instance).  n and T are kept within
+// [0.05, 20]; u_r = u_t2 = 0.  Writes n, u, T, q_r, P and the full-range equilibrium coefficients.
+__device__ inline void set_node_profile(const DevInstance& I, int i, double n, double ut, double T, double q, double P)
+{
+    n = fmin(fmax(n, 0.05), 20.0);
+    T = fmin(fmax(T, 0.05), 20.0);
+    double* nd = I.node + (size_t)i * kNodeStride;
+    nd[NF_N] = n;
+    nd[NF_U0] = 0;
+    nd[NF_U1] = ut;
+    nd[NF_U2] = 0;
+    nd[NF_T] = T;
+    nd[NF_Q0] = q;
+    nd[NF_P01] = P;
+    full_coeffs<kMaxN>(ut, T, I.N1, nd + NF_C1);
+    full_coeffs<kMaxN>(0.0, T, I.N2, nd + NF_C2);
+}
+
+__global__ void __launch_bounds__(kBlock) k_profile_from_net(const DevInstance* __restrict__ insts,
+                                                             const int32_t* __restrict__ rowoff, int ninst, int r0,
+                                                             int rows, const float* __restrict__ Y, Scale5 sc,
+                                                             const int32_t* __restrict__ mask)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= rows) return;
+    const int row = r0 + t;
+    const int k = row_instance(rowoff, ninst, row);
+    if (!mask[k]) return;
+    const float* y = Y + (size_t)t * 5;
+    double v[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) v[c] = sc.mean[c] + sc.scale[c] * (double)y[c];
+    set_node_profile(insts[k], row - rowoff[k], v[0], v[1], v[2], v[3], v[4]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_profile_from_host(const DevInstance* __restrict__ insts, int inst)
+{
+    const DevInstance& I = insts[inst];
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        const double* p = I.scratch;
+        set_node_profile(I, i, p[i], p[I.nr + i], p[2 * I.nr + i], p[3 * I.nr + i], p[4 * I.nr + i]);
+    }
+}
+
+// Grad 13-moment state of the masked instances from their node blocks (after k_proj):
+//   f_v = n g_r g_1 g_2 [1 + P xi_r xi_1 / (n T^2) + (q xi_r / (n T^2)) (|xi|^2 / (5 T) - 1)],
+// xi = p - (0, u_t1, 0), with the discrete equilibrium factors of the collision term.
+__global__ void __launch_bounds__(kBlock) k_grad13(const DevInstance* __restrict__ insts,
+                                                   const int32_t* __restrict__ mask)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!mask[blockIdx.y]) return;
+    const int i = blockIdx.x;
+    if (i >= I.nr) return;
+    __shared__ double g[3 * kMaxQ * 2];
+    const int n0 = I.n0, n1 = I.n1, n2 = I.n2, ng = n0 + n1 + n2;
+    const double* nd = I.node + (size_t)i * kNodeStride;
+    for (int k = threadIdx.x; k < ng; k += kBlock) {
+        const double *cf, *poly, *wt;
+        int N, kk;
+        if (k < n0) {
+            cf = nd + (I.p0[k] > 0 ? NF_IPLUS : NF_IMINUS);
+            N = I.N0; kk = k; poly = I.poly0; wt = I.w0;
+        } else if (k < n0 + n1) {
+            cf = nd + NF_C1;
+            N = I.N1; kk = k - n0; poly = I.poly1; wt = I.w1;
+        } else {
+            cf = nd + NF_C2;
+            N = I.N2; kk = k - n0 - n1; poly = I.poly2; wt = I.w2;
+        }
+        double acc = 0;
+        for (int l = 0; l <= N; l++) acc += cf[l] * poly[kk * (N + 1) + l];
+        g[k] = wt[kk] * acc;
+    }
+    __syncthreads();
+    const double n = nd[NF_N], ut = nd[NF_U1], T = nd[NF_T], q = nd[NF_Q0], P = nd[NF_P01];
+    const double cP = P / (n * T * T), cq = q / (n * T * T), inv5T = 1 / (5 * T);
+    double* f = I.f[0] + (size_t)i * I.nv;
+    for (int v = threadIdx.x; v < I.nv; v += kBlock) {
+        const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+        const double xr = I.p0[i0], xt = I.p1[i1] - ut, xz = I.p2[i2];
+        const double xi2 = xr * xr + xt * xt + xz * xz;
+        const double fmb = n * g[i0] * g[n0 + i1] * g[n0 + n1 + i2];
+        f[v] = fmb * (1 + cP * xr * xt + cq * xr * (xi2 * inv5T - 1));
+    }
+}
+
+// Rest start (n = 1, u = 0, T = 1) of the instances whose mask is 0.
+__global__ void __launch_bounds__(kBlock) k_rest(const DevInstance* __restrict__ insts,
+                                                 const int32_t* __restrict__ mask)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (mask && mask[blockIdx.y]) return;
+    const int i = blockIdx.x;
+    if (i >= I.nr) return;
+    const int n0 = I.n0, n1 = I.n1;
+    double* f = I.f[0] + (size_t)i * I.nv;
+    for (int v = threadIdx.x; v < I.nv; v += kBlock) {
+        const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+        f[v] = I.rest[i0] * I.rest[n0 + i1] * I.rest[n0 + n1 + i2];
+    }
+}
+
+// Scale the state of each masked instance so that its mass sum_i V_i n_i equals that of the rest
+// start (sum_i V_i); V_i is the cell measure r_i dr (cylinder) or (r_{i+1/2}^3 - r_{i-1/2}^3) / 3
+// (sphere).  Needs the moment sums of f[0] (k_moments).  One workgroup per instance.
+__global__ void __launch_bounds__(kBlock) k_renorm(const DevInstance* __restrict__ insts,
+                                                   const int32_t* __restrict__ mask)
+{
+    const DevInstance& I = insts[blockIdx.x];
+    if (!mask[blockIdx.x]) return;
+    __shared__ double red[2 * 4];
+    double acc[2] = {0, 0};
+    const double dr = I.dr;
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        const double r = I.r[i];
+        const double V = I.geometry == LBE_CYL ? r * dr : r * r * dr + dr * dr * dr / 12;
+        double n = 0;
+        for (int sl = 0; sl < I.nslices; sl++) n += I.mom[((size_t)i * I.nslices + sl) * kMomStride + MF_S0];
+        acc[0] += V * n;
+        acc[1] += V;
+    }
+    block_sum<2>(acc, red);
+    __syncthreads();
+    const double s = red[4] / red[0];
+    double* f = I.f[0];
+    const size_t tot = (size_t)I.nr * I.nv;
+    for (size_t e = threadIdx.x; e < tot; e += kBlock) f[e] *= s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_collect_resid(const DevInstance* __restrict__ insts, int ninst,
+                                                          double* __restrict__ out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < ninst) out[k] = insts[k].resid[0];
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s)
@@ -1225,6 +1406,60 @@ hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s)
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_residual, dim3(1, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_profile_net(const DevInstance* d, const int32_t* rowoff, int ninst, int r0, int rows,
+                                   float* X, const float* Y, const double* mean, const double* scale,
+                                   const int32_t* mask, int features_only, hipStream_t s)
+{
+    const dim3 grid((rows + kBlock - 1) / kBlock);
+    if (features_only) {
+        hipLaunchKernelGGL(k_features, grid, dim3(kBlock), 0, s, d, rowoff, ninst, r0, rows, X);
+        return hipGetLastError();
+    }
+    Scale5 sc;
+    for (int c = 0; c < 5; c++) {
+        sc.mean[c] = mean[c];
+        sc.scale[c] = scale[c];
+    }
+    hipLaunchKernelGGL(k_profile_from_net, grid, dim3(kBlock), 0, s, d, rowoff, ninst, r0, rows, Y, sc, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_from_host(const DevInstance* d, int inst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_profile_from_host, dim3(1), dim3(kBlock), 0, s, d, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad13(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad13, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_rest(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rest, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_renorm(const DevInstance* d, int ninst, const int32_t* mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_renorm, dim3(ninst), dim3(kBlock), 0, s, d, mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_resid(const DevInstance* d, int ninst, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_collect_resid, dim3((ninst + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, ninst, out);
     return hipGetLastError();
 }
 

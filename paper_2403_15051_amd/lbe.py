@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "liblbe.so")
 LBE_OK, LBE_EINVAL, LBE_ENOMEM, LBE_EDEVICE, LBE_ENOTCONV, LBE_ENAN, LBE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 CYL, SPH = 0, 1
 FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
+WARM_FIELDS = ("n", "u_t1", "T", "q_r", "P_rt1")
+GEMM_BF16, GEMM_FP32 = 0, 1
 INFO_KEYS = ("nr", "nv", "n0", "n1", "n2", "chi0", "C", "L", "sigma", "rcl", "rcr", "dr", "dt", "steps", "N0", "N1",
              "N2")
 
@@ -90,6 +92,28 @@ def load() -> ctypes.CDLL:
     lib.lbe_tables.argtypes = [P, i32, _D, _D, i64, _I64]
     lib.lbe_timing.argtypes = [vp, i32, _D, i64]
     lib.lbe_autotune.argtypes = [vp, i32, _D, i64, ctypes.POINTER(i32)]
+    F = ctypes.POINTER(ctypes.c_float)
+    u64 = ctypes.c_uint64
+    lib.lbe_features.argtypes = [vp, vp, i64, _I64]
+    lib.lbe_targets.argtypes = [vp, vp, i64]
+    lib.lbe_set_init_moments.argtypes = [vp, i32, _D, i64]
+    lib.lbe_warm_start.argtypes = [vp, vp, i32, ctypes.POINTER(i32), _D]
+    lib.lbe_mlp_query.argtypes = [i32, ctypes.POINTER(sz), _I64]
+    lib.lbe_mlp_init.argtypes = [i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.lbe_mlp_init_params.argtypes = [vp, u64]
+    lib.lbe_mlp_set_params.argtypes = [vp, F, i64]
+    lib.lbe_mlp_get_params.argtypes = [vp, F, i64]
+    lib.lbe_mlp_set_scaling.argtypes = [vp, _D, _D]
+    lib.lbe_mlp_get_scaling.argtypes = [vp, _D, _D]
+    lib.lbe_mlp_forward.argtypes = [vp, vp, i32, vp]
+    lib.lbe_mlp_loss_grad.argtypes = [vp, vp, vp, i32, _D, F, i64]
+    lib.lbe_mlp_set_grads.argtypes = [vp, F, i64]
+    lib.lbe_mlp_adam_step.argtypes = [vp, ctypes.c_float]
+    lib.lbe_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, u64, _D]
+    lib.lbe_mlp_last_error.argtypes = [vp]
+    lib.lbe_mlp_last_error.restype = ctypes.c_char_p
+    lib.lbe_mlp_free.argtypes = [vp]
+    lib.lbe_mlp_free.restype = None
     lib.lbe_last_error.argtypes = [vp]
     lib.lbe_last_error.restype = ctypes.c_char_p
     lib.lbe_status_string.argtypes = [ctypes.c_int]
@@ -98,7 +122,10 @@ def load() -> ctypes.CDLL:
     lib.lbe_free.restype = None
     for name in ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
                  "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune",
-                 "lbe_status_string"):
+                 "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start", "lbe_mlp_query",
+                 "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
+                 "lbe_mlp_set_scaling", "lbe_mlp_get_scaling", "lbe_mlp_forward", "lbe_mlp_loss_grad",
+                 "lbe_mlp_set_grads", "lbe_mlp_adam_step", "lbe_mlp_train", "lbe_status_string"):
         if name != "lbe_status_string":
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -107,7 +134,10 @@ def load() -> ctypes.CDLL:
 
 EXPORTS = ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
            "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune", "lbe_last_error",
-           "lbe_status_string", "lbe_free")
+           "lbe_status_string", "lbe_free", "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start",
+           "lbe_mlp_query", "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
+           "lbe_mlp_set_scaling", "lbe_mlp_get_scaling", "lbe_mlp_forward", "lbe_mlp_loss_grad", "lbe_mlp_set_grads",
+           "lbe_mlp_adam_step", "lbe_mlp_train", "lbe_mlp_last_error", "lbe_mlp_free")
 
 
 def _ptr(a: np.ndarray):
@@ -233,8 +263,128 @@ class Solver:
         return [{"nv": int(out[4 * q]), "tile_nodes": int(out[4 * q + 1]), "ms": out[4 * q + 2],
                  "ms_before": out[4 * q + 3]} for q in range(ng.value)]
 
+    def rows(self) -> int:
+        return int(sum(int(i["nr"]) for i in self._infos))
+
+    def features(self):
+        """Network inputs of every node (torch float32 tensor [rows][6] on the device)."""
+        import torch
+
+        x = torch.empty((self.rows(), 6), dtype=torch.float32, device="cuda")
+        self._check(self._lib.lbe_features(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0], None), "lbe_features")
+        return x
+
+    def targets(self):
+        """Profiles (n, u_t1, T, q_r, P_rt1) of every node (torch float32 tensor [rows][5])."""
+        import torch
+
+        t = torch.empty((self.rows(), 5), dtype=torch.float32, device="cuda")
+        self._check(self._lib.lbe_targets(self._h, ctypes.c_void_p(t.data_ptr()), t.shape[0]), "lbe_targets")
+        return t
+
+    def set_init_moments(self, inst: int, prof: dict) -> None:
+        a = np.ascontiguousarray(np.stack([np.asarray(prof[k], dtype=np.float64) for k in WARM_FIELDS]).reshape(-1))
+        self._check(self._lib.lbe_set_init_moments(self._h, inst, _ptr(a), a.size), "lbe_set_init_moments")
+
+    def warm_start(self, net: "Mlp", judge: bool = True):
+        kept = np.zeros(self.n_inst, dtype=np.int32)
+        rho = np.zeros(2 * self.n_inst)
+        self._check(self._lib.lbe_warm_start(self._h, net._h, int(judge),
+                                             kept.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(rho)),
+                    "lbe_warm_start")
+        return kept, rho.reshape(self.n_inst, 2)
+
     def rhs(self, inst: int = 0) -> np.ndarray:
         nr, nv = int(self._infos[inst]["nr"]), int(self._infos[inst]["nv"])
         out = np.zeros(nr * nv)
         self._check(self._lib.lbe_rhs(self._h, inst, _ptr(out), out.size), "lbe_rhs")
         return out.reshape(nr, nv)
+
+
+class Mlp:
+    """Network of the learned warm start on the current torch device and stream."""
+
+    def __init__(self, max_rows: int = 4096, gemm: int = GEMM_BF16, seed: int | None = None):
+        import torch
+
+        lib = load()
+        self._lib = lib
+        nbytes = ctypes.c_size_t(0)
+        npar = ctypes.c_int64(0)
+        st = lib.lbe_mlp_query(max_rows, ctypes.byref(nbytes), ctypes.byref(npar))
+        if st != LBE_OK:
+            raise LbeError(st, "lbe_mlp_query")
+        self.n_params = npar.value
+        self.max_rows = max_rows
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self._ws.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p(0)
+        st = lib.lbe_mlp_init(max_rows, gemm, ctypes.c_void_p(aligned), nbytes.value,
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+        if st != LBE_OK:
+            raise LbeError(st, "lbe_mlp_init")
+        self._h = h
+        if seed is not None:
+            self._check(lib.lbe_mlp_init_params(h, seed), "lbe_mlp_init_params")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.lbe_mlp_free(h)
+            self._h = None
+
+    def _check(self, st: int, what: str) -> None:
+        if st != LBE_OK:
+            raise LbeError(st, f"{what}: {self._lib.lbe_mlp_last_error(self._h).decode()}")
+
+    def set_params(self, p: np.ndarray) -> None:
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self._lib.lbe_mlp_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+                    "lbe_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self._lib.lbe_mlp_get_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+                    "lbe_mlp_get_params")
+        return a
+
+    def set_scaling(self, mean, scale) -> None:
+        m = np.ascontiguousarray(mean, dtype=np.float64)
+        s = np.ascontiguousarray(scale, dtype=np.float64)
+        self._check(self._lib.lbe_mlp_set_scaling(self._h, _ptr(m), _ptr(s)), "lbe_mlp_set_scaling")
+
+    def get_scaling(self):
+        m = np.zeros(5)
+        s = np.zeros(5)
+        self._check(self._lib.lbe_mlp_get_scaling(self._h, _ptr(m), _ptr(s)), "lbe_mlp_get_scaling")
+        return m, s
+
+    def forward(self, x):
+        import torch
+
+        y = torch.empty((x.shape[0], 5), dtype=torch.float32, device="cuda")
+        self._check(self._lib.lbe_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                              ctypes.c_void_p(y.data_ptr())), "lbe_mlp_forward")
+        return y
+
+    def loss_grad(self, x, t):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = np.zeros(1)
+        self._check(self._lib.lbe_mlp_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                                x.shape[0], _ptr(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                g.size), "lbe_mlp_loss_grad")
+        return float(loss[0]), g
+
+    def set_grads(self, g: np.ndarray) -> None:
+        a = np.ascontiguousarray(g, dtype=np.float32)
+        self._check(self._lib.lbe_mlp_set_grads(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+                    "lbe_mlp_set_grads")
+
+    def adam_step(self, lr: float) -> None:
+        self._check(self._lib.lbe_mlp_adam_step(self._h, lr), "lbe_mlp_adam_step")
+
+    def train(self, x, t, epochs: int, batch: int, lr: float, seed: int) -> np.ndarray:
+        hist = np.zeros(epochs)
+        self._check(self._lib.lbe_mlp_train(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                            x.shape[0], epochs, batch, lr, seed, _ptr(hist)), "lbe_mlp_train")
+        return hist

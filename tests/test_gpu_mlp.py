@@ -1,0 +1,184 @@
+"""The warm start's network and state on the GPU (through the C ABI) against the CPU references.
+
+Network: forward outputs and every parameter's gradient against the FP64 reference, at 1e-5
+normwise with FP32 matrix-core products and at 1e-2 with BF16 products (the reference then rounds
+the same operands to bfloat16); Adam against the reference on a given gradient.  State: the
+Grad-13 reconstruction with mass renormalisation against the reference at 1e-12.  Warm start:
+a network that predicts nonsense is rejected by the judge (the state is then the rest start,
+bitwise), and a network trained on this solver's own steady states shortens the solves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as M
+from oracle import warmstart as WS
+from paper_2403_15051_amd import lbe, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    lbe.load()
+
+
+def dev(a):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def nrel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def layer_slices():
+    out, o = [], 0
+    for fin, fout in M.LAYERS:
+        out.append(slice(o, o + fin * fout))
+        out.append(slice(o + fin * fout, o + fin * fout + fout))
+        o += fin * fout + fout
+    return out
+
+
+@pytest.mark.parametrize("gemm,tol", [(lbe.GEMM_FP32, 1e-5), (lbe.GEMM_BF16, 1e-2)])
+def test_forward_and_gradients_match_reference(gemm, tol):
+    rows = 300  # several 64-row tiles and a ragged tail
+    p = W.mlp_params(21)
+    X, T = W.mlp_batch(22, rows)
+    net = lbe.Mlp(max_rows=512, gemm=gemm)
+    net.set_params(p)
+    bf = gemm == lbe.GEMM_BF16
+    Yo, _ = M.forward(p, X, use_bf16=bf)
+    Yg = net.forward(dev(X)).cpu().numpy()
+    e = nrel(Yg, Yo)
+    print("forward", gemm, e, flush=True)
+    assert e <= tol
+    lo, go = M.loss_grad(p, X, T, use_bf16=bf)
+    lg, gg = net.loss_grad(dev(X), dev(T))
+    assert abs(lg - lo) <= tol * lo
+    for k, sl in enumerate(layer_slices()):
+        e = nrel(gg[sl], go[sl])
+        print("grad block", k, e, flush=True)
+        assert e <= tol, k
+
+
+def test_adam_matches_reference():
+    p = W.mlp_params(31)
+    g1 = W.mlp_grad_vector(32, p.size)
+    g2 = W.mlp_grad_vector(33, p.size)
+    net = lbe.Mlp(max_rows=64, gemm=lbe.GEMM_FP32)
+    net.set_params(p)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    q = p.copy()
+    for t, g in ((1, g1), (2, g2)):
+        net.set_grads(g)
+        net.adam_step(1e-3)
+        q, m, v = M.adam(q, g, m, v, t, 1e-3)
+    got = net.get_params().astype(np.float64)
+    # steps of size ~1e-3 on parameters of size ~0.1: compare the displacement
+    e = np.abs((got - p) - (q - p)).max() / np.abs(q - p).max()
+    print("adam", e, flush=True)
+    assert e <= 1e-4
+
+
+def test_training_reduces_loss_on_a_smooth_map():
+    import torch
+
+    rng = np.random.default_rng(41)
+    X = rng.uniform(-1.7, 1.7, size=(2048, 6))
+    T = np.stack([np.sin(X[:, 0]) + X[:, 5] ** 2, X[:, 1] * X[:, 2], np.cos(X[:, 3] + X[:, 4]),
+                  np.tanh(X[:, 5]), X[:, 0] - X[:, 3]], axis=1)
+    net = lbe.Mlp(max_rows=256, gemm=lbe.GEMM_BF16, seed=5)
+    hist = net.train(dev(X), dev(T), epochs=40, batch=256, lr=2e-3, seed=9)
+    print("loss", hist[0], hist[-1], flush=True)
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.05 * hist[0]
+    # standardisation set from the data
+    mean, scale = net.get_scaling()
+    assert np.allclose(mean, T.mean(axis=0), rtol=1e-5, atol=1e-5)
+    assert np.allclose(scale, T.std(axis=0), rtol=1e-4)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", [dict(W.FOURIER_CYL, nr=20, q_radial=4, q_t1=4, q_t2=4),
+                               dict(W.COUETTE_SMALL, nr=21, q_t2=4),
+                               dict(W.FOURIER_SPH, nr=18, q_radial=4, q_t1=4, q_t2=4)])
+def test_grad13_state_matches_reference(p):
+    prof = W.smooth_profile(p["nr"], 6)
+    prof["n"] = prof["n"] * 1.3
+    if p["geometry"] == lbe.SPH:
+        prof["u_t1"] = np.zeros(p["nr"])
+        prof["P_rt1"] = np.zeros(p["nr"])
+    fo = WS.grad13_state(p, prof)
+    g = lbe.Solver([p, dict(W.COUETTE_SMALL, nr=12)])
+    g.set_init_moments(0, prof)
+    fg = g.get_state(0)
+    e = nrel(fg, fo)
+    print("grad13", e, flush=True)
+    assert e <= 1e-12
+    # the other instance still holds the rest start
+    assert np.array_equal(g.get_state(1), lbe.Solver(dict(W.COUETTE_SMALL, nr=12)).get_state(0))
+
+
+def test_judge_rejects_a_useless_prediction():
+    ps = [dict(W.COUETTE_SMALL, nr=20), dict(W.FOURIER_CYL, nr=24, q_radial=4, q_t1=4, q_t2=4)]
+    net = lbe.Mlp(max_rows=16, gemm=lbe.GEMM_BF16, seed=3)  # untrained; rows processed in chunks
+    net.set_scaling([3.0, 2.0, 5.0, 1.0, 1.0], [2.0, 1.0, 3.0, 1.0, 1.0])
+    g = lbe.Solver(ps)
+    kept, rho = g.warm_start(net, judge=True)
+    print("kept", kept, "rho", rho, flush=True)
+    assert kept.tolist() == [0, 0]
+    assert np.all(rho[:, 0] > rho[:, 1])
+    ref = lbe.Solver(ps)
+    for k in range(2):
+        assert np.array_equal(g.get_state(k), ref.get_state(k))
+    st, steps, _ = g.run_to_steady(1e-5, 20000, 50)
+    st2, steps2, _ = ref.run_to_steady(1e-5, 20000, 50)
+    assert st == st2 == lbe.LBE_OK and np.array_equal(steps, steps2)
+
+
+def test_trained_network_shortens_steady_solves():
+    """Train on steady states of small instances drawn like the sweep, then solve held-out
+    instances from the judged prediction and from rest: fewer steps warm, same steady state."""
+    import torch
+
+    train, _ = W.warm_sweep(48, W.WARM_TRAIN_SEED, nr_range=(16, 24))
+    held, _ = W.warm_sweep(12, W.WARM_HELDOUT_SEED, nr_range=(16, 24))
+    train = [W.solver_params(p) for p in train]
+    held = [W.solver_params(p) for p in held]
+    tol, cap, every = 1e-6, 60000, 50
+    g = lbe.Solver(train)
+    st, steps, _ = g.run_to_steady(tol, cap, every)
+    ok = steps < cap
+    print("training solves converged", int(ok.sum()), "of", len(train), flush=True)
+    X = g.features()
+    T = g.targets()
+    # rows of the converged instances only
+    rows = np.concatenate([np.arange(sum(int(q["nr"]) for q in train[:k]), sum(int(q["nr"]) for q in train[:k + 1]))
+                           for k in range(len(train)) if ok[k]])
+    idx = torch.tensor(rows, device="cuda")
+    Xs, Ts = X[idx].contiguous(), T[idx].contiguous()
+    net = lbe.Mlp(max_rows=512, gemm=lbe.GEMM_BF16, seed=7)
+    hist = net.train(Xs, Ts, epochs=300, batch=256, lr=2e-3, seed=11)
+    print("loss", hist[0], hist[-1], flush=True)
+    cold = lbe.Solver(held)
+    st_c, steps_c, _ = cold.run_to_steady(tol, cap, every)
+    warm = lbe.Solver(held)
+    kept, rho = warm.warm_start(net, judge=True)
+    st_w, steps_w, _ = warm.run_to_steady(tol, cap, every)
+    print("cold", steps_c.tolist(), "warm", steps_w.tolist(), "kept", kept.tolist(), flush=True)
+    assert st_c == st_w == lbe.LBE_OK
+    assert steps_w.sum() < steps_c.sum()
+    for k in range(len(held)):
+        mc, mw = cold.moments(k), warm.moments(k)
+        for f in ("n", "T"):
+            assert nrel(mw[f], mc[f]) <= 1e-4, (k, f)
