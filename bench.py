@@ -5,6 +5,9 @@ of the workload; inputs are resident in HBM before the timed region.  Prints one
 
 Default workload: the seeded parameter sweep of 256 uneven cylindrical Couette/Fourier
 instances (Nr 64..512, half-range orders 4..16), advanced together in one launch per kernel.
+The "steady" object adds steady solves/s at residual 1e-8 on held-out instances of the same
+generator (reduced grid): one at a time from rest, batched from rest, and batched from the
+judged prediction of the trained warm-start network (paper_2403_15051_amd/warmstart_net.npz).
 """
 from __future__ import annotations
 
@@ -111,6 +114,80 @@ def cpu_baseline(params, budget_s: float, threads: int = 0):
             "sample": f"{len(used)} instance(s) of the workload, FP64 oracle timed per step ({desc})"}
 
 
+def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 200000):
+    """Steady solves/s at residual tol on held-out instances of the warm-start generator (seed
+    240315053): (1) plain cold, one instance at a time from rest (a sample of n_plain instances);
+    (2) batched cold, all instances in one context from rest; (3) batched warm: network inference,
+    the judge and the solve.  Rates count converged instances per wall second of the solve (tables
+    built and resident before the clock starts)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_15051_amd import lbe
+    from paper_2403_15051_amd import train_warmstart as TW
+    from paper_2403_15051_amd import workloads as W
+
+    held = TW.instances(n_held, W.WARM_HELDOUT_SEED)
+    every = TW.CHECK_EVERY
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    cold = lbe.Solver(held)
+    (st_c, steps_c, res_c), t_cold = timed(lambda: cold.run_to_steady(tol, cap, every))
+    ok_c = (res_c >= 0) & (res_c <= tol)
+    print(f"[bench] batched cold: {int(ok_c.sum())}/{n_held} in {t_cold:.1f} s", file=sys.stderr, flush=True)
+    net, meta = TW.load()
+    warm = lbe.Solver(held)
+
+    def warm_solve():
+        kept, rho = warm.warm_start(net, judge=True)
+        return kept, warm.run_to_steady(tol, cap, every)
+
+    (kept, (st_w, steps_w, res_w)), t_warm = timed(warm_solve)
+    ok_w = (res_w >= 0) & (res_w <= tol)
+    print(f"[bench] batched warm: {int(ok_w.sum())}/{n_held} in {t_warm:.1f} s", file=sys.stderr, flush=True)
+    # the converged profiles of both starts agree to the residual's reach
+    agree = 0.0
+    for k in range(n_held):
+        if ok_c[k] and ok_w[k]:
+            mc, mw = cold.moments(k), warm.moments(k)
+            for f in ("n", "T"):
+                agree = max(agree, float(np.abs(mw[f] - mc[f]).max() / np.abs(mc[f]).max()))
+    del cold, warm
+    t_plain, n_ok_plain, steps_plain = 0.0, 0, []
+    for p in held[:n_plain]:
+        one = lbe.Solver([p])
+        (st, steps, res), t = timed(lambda: one.run_to_steady(tol, cap, every))
+        t_plain += t
+        n_ok_plain += int(res[0] >= 0 and res[0] <= tol)
+        steps_plain.append(int(steps[0]))
+        del one
+    print(f"[bench] plain cold: {n_ok_plain}/{n_plain} in {t_plain:.1f} s", file=sys.stderr, flush=True)
+    r1 = n_ok_plain / t_plain
+    r2 = int(ok_c.sum()) / t_cold
+    r3 = int(ok_w.sum()) / t_warm
+    return {
+        "metric": "steady solves/s at residual 1e-8",
+        "workload": (f"{n_held} held-out instances of the sweep generator (seed {W.WARM_HELDOUT_SEED}): Couette/Fourier, "
+                     f"eta0 U(0.01,0.3), Kn 10^U(-2,1), u_w U(0,0.5), T2/T1 U(1,2); reduced grid Nr U{{32..64}}, "
+                     f"half-range order in {{4,8}}"),
+        "plain_cold": {"solves_per_s": r1, "sample": n_plain, "mean_steps": float(np.mean(steps_plain))},
+        "batched_cold": {"solves_per_s": r2, "converged": int(ok_c.sum()), "seconds": t_cold,
+                         "mean_steps": float(steps_c.mean()), "max_steps": int(steps_c.max())},
+        "batched_warm": {"solves_per_s": r3, "converged": int(ok_w.sum()), "seconds": t_warm,
+                         "mean_steps": float(steps_w.mean()), "max_steps": int(steps_w.max()),
+                         "fallback_rate": float(1 - kept.mean())},
+        "warm_over_plain_cold": r3 / r1, "batched_cold_over_plain_cold": r2 / r1, "warm_over_batched_cold": r3 / r2,
+        "profile_agreement_warm_vs_cold": agree,
+        "network": {k: meta[k] for k in ("instances", "rows", "epochs", "loss_last", "nr_range", "orders")},
+    }
+
+
 def host_cpu() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -131,6 +208,9 @@ def main():
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--steady-instances", type=int, default=512, help="held-out instances of the steady-solve metric")
+    ap.add_argument("--steady-plain", type=int, default=8, help="of which solved one at a time")
+    ap.add_argument("--no-steady", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run a plain copy of this size (calibration)")
     args = ap.parse_args()
     if args.copy_bytes:
@@ -182,7 +262,7 @@ def main():
     stage_avg_s = tm["stage_ms"] / tm["stage_launches"] / 1e3
     achieved = bytes_per_launch / stage_avg_s / 1e9
     line = {
-        "metric": "site-velocity updates/s",
+        "metric": "site-velocity updates/s; steady solves/s at 1e-8 residual, warm vs cold start",
         "value": value,
         "unit": "site-velocity updates/s",
         "n_gpus": 1,
@@ -202,6 +282,9 @@ def main():
                      "stage_share_of_step": tm["stage_ms"] / ((t3 - t2) * 1e3),
                      "ms_per_step_eager_timed": (t3 - t2) * 1e3 / args.steps},
     }
+    del solver
+    if not args.no_steady:
+        line["steady"] = steady_metrics(args.steady_instances, args.steady_plain)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
         one = cpu_baseline(params, args.cpu_seconds / 3, threads=1)
