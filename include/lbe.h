@@ -54,7 +54,7 @@ typedef enum {
 } lbe_status;
 
 enum { LBE_CYL = 0, LBE_SPH = 1 };
-enum { LBE_FP64 = 0 };
+enum { LBE_FP64 = 0, LBE_FP32_STORE = 1 }; /* storage of f (lbe_params.precision) */
 enum { LBE_GEMM_BF16 = 0, LBE_GEMM_FP32 = 1 }; /* matrix-core operand type of the network */
 
 /* Problem statement of one instance (Sec. IV set-up of the paper). */
@@ -73,6 +73,10 @@ typedef struct {
     int32_t q_t2;
     int32_t n_expand[3];  /* equilibrium expansion orders N_a; 0 -> min(7, Q_a - 1); N_a < Q_a */
     double cfl;           /* dt = cfl * dr / max|p_r|  (> 0)                                  */
+    int32_t precision;    /* LBE_FP64: f stored in FP64.  LBE_FP32_STORE: f stored as FP32
+                           * deviations from the discrete equilibrium of per-node FP64 moments
+                           * (all arithmetic, moment sums, node coefficients and the residual
+                           * stay FP64); the warm-start calls reject such instances.        */
 } lbe_params;
 
 /* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),

@@ -15,14 +15,20 @@
 #include "lbe_internal.h"
 
 namespace lbe {
-hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s);
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s);
+hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, int tab, int from_scratch, int only,
+                          hipStream_t s);
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int bsrc, hipStream_t s);
+hipError_t launch_base_copy(const DevInstance* d, int ninst, int maxnr, int maxng, hipStream_t s);
+hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s);
+hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s);
+hipError_t launch_mass_fix(const DevInstance* d, int ninst, int maxnr, const double* target, hipStream_t s);
+hipError_t launch_rebase(const DevInstance* d, int inst, int nr, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chunk, int judge, double* st,
                            hipStream_t s);
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
-                        int dst, double an, double bs, int rhs, hipStream_t s);
+                        int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst, hipStream_t s);
 hipError_t set_stage_smem_limit();
 hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s);
 hipError_t launch_warm_profile_net(const DevInstance* d, const int32_t* rowoff, int ninst, int r0, int rows,
@@ -42,6 +48,8 @@ static constexpr int kMaxPlane = 20000;
 // Tile heights (nodes per stage work item) lbe_autotune tries.
 static constexpr int kTileCandidates[] = {4, 8, 16, 32, 64};
 static constexpr int kMinTileNodes = 4;
+// FP32 storage: steps between mass fixes in lbe_step (lbe_run_to_steady fixes once per interval)
+static constexpr int kMassFixEvery = 50;
 
 struct lbe_ctx {
     std::vector<InstanceTables> tabs;
@@ -50,7 +58,8 @@ struct lbe_ctx {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    int ninst = 0, maxnr = 0, maxnv = 0;
+    int ninst = 0, maxnr = 0, maxnv = 0, maxng = 0;
+    bool any_f32 = false;
     std::vector<int64_t> steps;
     std::vector<int32_t> active;
     std::string err;
@@ -73,6 +82,9 @@ struct lbe_ctx {
     int32_t* dev_rowoff = nullptr;
     int32_t* dev_mask = nullptr;
     double* dev_vec = nullptr;
+    // FP32 storage: target mass of every instance; steps since the last mass fix (lbe_step)
+    double* dev_mass = nullptr;
+    int64_t since_fix = 0;
     std::vector<int32_t> rowoff;
     // captured launch sequences: one RK3 step, and one steady-state chunk (chunk steps, the
     // residual and the freeze test), replayed on `stream`; captured on a private stream
@@ -90,7 +102,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Byte layout of one instance inside the workspace.
 struct Layout {
     size_t f[3], mom, node, snap, resid, flags, nw, scratch;
-    size_t rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
+    size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
     size_t total;
 };
 
@@ -106,8 +118,11 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t base)
     const size_t D = sizeof(double);
     const size_t plane = (size_t)t.nr * t.nv * D;
     // state buffers: nr rows plus two ghost rows on each side (filled by the node kernel);
-    // L.f points at row 0
-    for (int k = 0; k < 3; k++) L.f[k] = take(plane + 4 * t.nv * D) + 2 * t.nv * D;
+    // L.f points at row 0; FP64 or FP32 values
+    const size_t E = t.prm.precision == LBE_FP32_STORE ? sizeof(float) : D;
+    for (int k = 0; k < 3; k++) L.f[k] = take((size_t)(t.nr + 4) * t.nv * E) + 2 * t.nv * E;
+    const size_t ng = (size_t)(t.n0 + t.n1 + t.n2);
+    for (int k = 0; k < 4; k++) L.base[k] = t.prm.precision == LBE_FP32_STORE ? take((size_t)t.nr * ng * D) : 0;
     L.mom = take((size_t)t.nr * nslices * kMomStride * D);
     L.node = take((size_t)t.nr * kNodeStride * D);
     L.snap = take((size_t)t.nr * 5 * D);
@@ -157,6 +172,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     b += 2 * align256(M * D) + align256(M * N * D);
     b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
     b += align256(nr * n2 * sizeof(WorkItem));
+    b += 4 * align256(nr * (size_t)(n0 + n1 + n2) * D);
     return b + 4096;
 }
 
@@ -274,6 +290,12 @@ bool layout_group(StageGroup* G, int nt0)
         o += NT * ng;
         G->off_part = o;
         o += NT * nTm * 36;
+        // FP32 storage: base factors of the window rows and of the own rows of f^n
+        G->bstride = n0 + G->plane_cols;
+        G->off_sb = o;
+        o += G->f32 ? (NT + 6) * G->bstride : 0;
+        G->off_fb = o;
+        o += G->f32 ? NT * G->bstride : 0;
         G->lds_doubles = o;
         if (o <= kLdsDoubles) return true;
     }
@@ -316,7 +338,9 @@ lbe_status plan_groups(lbe_ctx* c)
         int g = -1;
         for (size_t q = 0; q < c->groups.size(); q++) {
             const StageGroup& G = c->groups[q];
-            if (G.n0 == t.n0 && G.n1 == t.n1 && G.n2 == t.n2 && G.geometry == t.prm.geometry) g = (int)q;
+            if (G.n0 == t.n0 && G.n1 == t.n1 && G.n2 == t.n2 && G.geometry == t.prm.geometry &&
+                G.f32 == (t.prm.precision == LBE_FP32_STORE))
+                g = (int)q;
         }
         if (g < 0) {
             StageGroup G;
@@ -326,6 +350,7 @@ lbe_status plan_groups(lbe_ctx* c)
             G.n2 = t.n2;
             G.nv = t.nv;
             G.geometry = t.prm.geometry;
+            G.f32 = t.prm.precision == LBE_FP32_STORE;
             G.S = 1;
             c->groups.push_back(G);
             g = (int)c->groups.size() - 1;
@@ -423,12 +448,14 @@ hipEvent_t next_event(lbe_ctx* c, int* idx)
 }
 
 // Node kernel then stage kernel of one RK stage, with events around each when timing.
-hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int rhs)
+// FP32-storage instances read src and f^n through base tables bsrc, bfn and write the output's
+// base table bdst (ignored by FP64 instances).
+hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst)
 {
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, c->stream);
+    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, bsrc, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
@@ -437,7 +464,7 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
     }
     for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
         e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an, bs,
-                         rhs, c->stream);
+                         rhs, bsrc, bfn, bdst, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &y), c->stream);
@@ -450,9 +477,10 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
 //   f1 = f + dt L(f);  f2 = 3/4 f + 1/4 (f1 + dt L(f1));  f <- 1/3 f + 2/3 (f2 + dt L(f2)).
 hipError_t launch_step(lbe_ctx* c)
 {
-    hipError_t e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0);
-    if (e == hipSuccess) e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0);
-    if (e == hipSuccess) e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0);
+    hipError_t e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0, 0, 0, 1);
+    if (e == hipSuccess) e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0, 1, 0, 2);
+    if (e == hipSuccess) e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0, 2, 0, 3);
+    if (e == hipSuccess && c->any_f32) e = launch_base_copy(c->dev_desc, c->ninst, c->maxnr, c->maxng, c->stream);
     return e;
 }
 
@@ -461,6 +489,7 @@ hipError_t launch_step(lbe_ctx* c)
 hipError_t launch_chunk(lbe_ctx* c, int chunk, double tol, int judge)
 {
     hipError_t e = hipSuccess;
+    if (c->any_f32) e = launch_mass_fix(c->dev_desc, c->ninst, c->maxnr, c->dev_mass, c->stream);
     for (int s = 0; s < chunk && e == hipSuccess; s++) {
         if (s == chunk - 1) e = launch_snapshot(c->dev_desc, c->ninst, c->stream);
         if (e == hipSuccess) e = launch_step(c);
@@ -566,7 +595,7 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
     if (!p || n_inst < 1) return LBE_EINVAL;
     size_t total = align256(sizeof(DevInstance) * n_inst) + align256(4 * sizeof(double) * (size_t)n_inst) +
                    align256(sizeof(int32_t) * (size_t)(n_inst + 1)) + align256(sizeof(int32_t) * (size_t)n_inst) +
-                   align256(2 * sizeof(double) * (size_t)n_inst);
+                   align256(2 * sizeof(double) * (size_t)n_inst) + align256(sizeof(double) * (size_t)n_inst);
     size_t host = sizeof(lbe_ctx);
     for (int k = 0; k < n_inst; k++) {
         lbe_params q;
@@ -623,6 +652,8 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
             }
             c->maxnr = std::max(c->maxnr, c->tabs[k].nr);
             c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
+            c->maxng = std::max(c->maxng, c->tabs[k].n0 + c->tabs[k].n1 + c->tabs[k].n2);
+            if (c->tabs[k].prm.precision == LBE_FP32_STORE) c->any_f32 = true;
         }
     }
     st = plan_groups(c);
@@ -642,6 +673,8 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     off = align256(off + sizeof(int32_t) * (size_t)n_inst);
     c->dev_vec = (double*)(c->ws + off);
     off = align256(off + 2 * sizeof(double) * (size_t)n_inst);
+    c->dev_mass = (double*)(c->ws + off);
+    off = align256(off + sizeof(double) * (size_t)n_inst);
     c->rowoff.assign(n_inst + 1, 0);
     for (int k = 0; k < n_inst; k++) c->rowoff[k + 1] = c->rowoff[k] + c->tabs[k].nr;
     if (off > ws_bytes) {
@@ -670,6 +703,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.n1 = t.n1;
         d.n2 = t.n2;
         d.geometry = t.prm.geometry;
+        d.f32 = t.prm.precision == LBE_FP32_STORE;
         d.N0 = t.ax[0].N;
         d.N1 = t.ax[1].N;
         d.N2 = t.ax[2].N;
@@ -696,6 +730,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.nw = (double*)(ws + L.nw);
         d.scratch = (double*)(ws + L.scratch);
         d.rest = (const double*)(ws + L.rest);
+        for (int b = 0; b < 4; b++) d.base[b] = d.f32 ? (double*)(ws + L.base[b]) : nullptr;
         d.p0 = (const double*)(ws + L.p0);
         d.p1 = (const double*)(ws + L.p1);
         d.p2 = (const double*)(ws + L.p2);
@@ -755,7 +790,16 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
                 const double val = g0[i0] * g1[i1] * g2[i2];
                 for (int i = 0; i < t.nr; i++) f[(size_t)i * t.nv + v] = val;
             }
-            if (e == hipSuccess) e = hipMemcpy(d.f[0], f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (d.f32) {
+                // FP32 storage: the rest start is its own base (n = 1), deviations zero
+                std::vector<double> b0;
+                for (int i = 0; i < t.nr; i++) b0.insert(b0.end(), rest.begin(), rest.end());
+                if (e == hipSuccess)
+                    e = hipMemcpy(d.base[0], b0.data(), b0.size() * sizeof(double), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemset(d.f[0], 0, (size_t)t.nr * t.nv * sizeof(float));
+            } else if (e == hipSuccess) {
+                e = hipMemcpy(d.f[0], f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice);
+            }
         }
     }
     if (e == hipSuccess)
@@ -769,7 +813,8 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         return st;
     }
     st = upload_flags(c);
-    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, n_inst, c->maxnr, 0, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, n_inst, c->maxnr, 0, 0, 0, -1, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, launch_mass(c->dev_desc, n_inst, -1, c->dev_mass, c->stream), "mass");
     if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "lbe_init sync");
     if (st != LBE_OK) {
         delete c;
@@ -784,6 +829,12 @@ lbe_status lbe_step(lbe_ctx* c, int64_t nsteps)
     if (!c || nsteps < 0) return LBE_EINVAL;
     if (c->nan_latched) return LBE_ENAN;
     for (int64_t s = 0; s < nsteps; s++) {
+        if (c->any_f32 && ++c->since_fix >= kMassFixEvery) {
+            lbe_status st = dev_err(c, launch_mass_fix(c->dev_desc, c->ninst, c->maxnr, c->dev_mass, c->stream),
+                                    "mass fix");
+            if (st != LBE_OK) return st;
+            c->since_fix = 0;
+        }
         lbe_status st = enqueue_step(c);
         if (st != LBE_OK) return st;
     }
@@ -813,7 +864,7 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     c->active[inst] = 1;
     st = upload_flags(c);
     if (st == LBE_OK)
-        st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments pass");
+        st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "moments pass");
     std::vector<double> node((size_t)d.nr * kNodeStride);
     if (st == LBE_OK)
         st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -842,7 +893,7 @@ lbe_status lbe_rhs(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     c->active[inst] = 1;
     st = upload_flags(c);
     if (st == LBE_OK)
-        st = dev_err(c, run_stage(c, 0, 0, 0, 0, 0, 1), "rhs");
+        st = dev_err(c, run_stage(c, 0, 0, 0, 0, 0, 1, 0, 0, 1), "rhs");
     if (st == LBE_OK)
         st = dev_err(c, hipMemcpyAsync(host_out, d.scratch, (size_t)d.nr * d.nv * sizeof(double),
                                        hipMemcpyDeviceToHost, c->stream),
@@ -915,7 +966,15 @@ lbe_status lbe_get_state(lbe_ctx* c, int32_t inst, double* host_f, int64_t cap)
     if (cap < (int64_t)d.nr * d.nv) return LBE_EINVAL;
     lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
-    return dev_err(c, hipMemcpy(host_f, d.f[0], (size_t)d.nr * d.nv * sizeof(double), hipMemcpyDeviceToHost),
+    const double* from = d.f[0];
+    if (d.f32) {
+        // FP32 storage: deviations plus their base, in FP64, through the scratch
+        st = dev_err(c, launch_expand(c->dev_desc, inst, d.nr, c->stream), "expand");
+        if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+        if (st != LBE_OK) return st;
+        from = d.scratch;
+    }
+    return dev_err(c, hipMemcpy(host_f, from, (size_t)d.nr * d.nv * sizeof(double), hipMemcpyDeviceToHost),
                    "state read");
 }
 
@@ -926,14 +985,36 @@ lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t
     if (len != (int64_t)d.nr * d.nv) return LBE_EINVAL;
     lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
-    st = dev_err(c, hipMemcpy(d.f[0], host_f, (size_t)len * sizeof(double), hipMemcpyHostToDevice), "state write");
+    st = dev_err(c, hipMemcpy(d.f32 ? d.scratch : d.f[0], host_f, (size_t)len * sizeof(double), hipMemcpyHostToDevice),
+                 "state write");
     if (st != LBE_OK) return st;
     c->nan_latched = false;
+    if (!d.f32) {
+        st = upload_flags(c);
+        if (st == LBE_OK)
+            st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, inst, c->stream), "moments");
+        if (st != LBE_OK) return st;
+        return dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    // FP32 storage: moments of the FP64 state, its node coefficients and equilibrium projections,
+    // then the base table and the deviations, and the moment sums of the stored state
+    std::fill(c->active.begin(), c->active.end(), 0);
+    c->active[inst] = 1;
     st = upload_flags(c);
+    if (st == LBE_OK)
+        st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 1, inst, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node");
+    if (st == LBE_OK) st = dev_err(c, launch_rebase(c->dev_desc, inst, d.nr, c->stream), "rebase");
+    if (st == LBE_OK)
+        st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, inst, c->stream), "moments");
+    // the state's own mass becomes the mass kept from now on
+    if (st == LBE_OK) st = dev_err(c, launch_mass(c->dev_desc, c->ninst, inst, c->dev_mass, c->stream), "mass");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    std::fill(c->active.begin(), c->active.end(), 1);
+    lbe_status st2 = upload_flags(c);
     if (st != LBE_OK) return st;
-    st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
-    if (st != LBE_OK) return st;
-    return dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st2 != LBE_OK) return st2;
+    return check_nan(c);
 }
 
 lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap)
@@ -1026,7 +1107,7 @@ lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows)
     std::vector<int32_t> saved = c->active;
     std::fill(c->active.begin(), c->active.end(), 1);
     st = upload_flags(c);
-    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "node pass");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node pass");
     std::vector<float> out((size_t)rows * 5);
     const int fields[5] = {NF_N, NF_U1, NF_T, NF_Q0, NF_P01};
     for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
@@ -1066,9 +1147,9 @@ hipError_t build_warm_state(lbe_ctx* c)
 {
     hipError_t e = launch_proj(c->dev_desc, c->ninst, c->maxnr, c->stream);
     if (e == hipSuccess) e = launch_grad13(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream);
-    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
     if (e == hipSuccess) e = launch_renorm(c->dev_desc, c->ninst, c->dev_mask, c->stream);
-    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
     return e;
 }
 
@@ -1115,6 +1196,10 @@ lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in,
 {
     if (!c || inst < 0 || inst >= c->ninst || !host_in) return LBE_EINVAL;
     const DevInstance& d = c->host_desc[inst];
+    if (d.f32) {
+        c->err = "the warm start needs FP64 storage";
+        return LBE_ESTATE;
+    }
     if (len != 5 * (int64_t)d.nr) return LBE_EINVAL;
     for (int i = 0; i < d.nr; i++)
         if (!(host_in[i] > 0) || !(host_in[2 * d.nr + i] > 0)) return LBE_EINVAL;
@@ -1141,6 +1226,10 @@ lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in,
 lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, double* rho)
 {
     if (!c || !m) return LBE_EINVAL;
+    if (c->any_f32) {
+        c->err = "the warm start needs FP64 storage";
+        return LBE_ESTATE;
+    }
     if (c->nan_latched) return LBE_ENAN;
     lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
@@ -1152,7 +1241,7 @@ lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, 
     if (judge) {
         // one step from the rest start and one from the predicted state
         st = dev_err(c, launch_rest(c->dev_desc, c->ninst, c->maxnr, nullptr, c->stream), "rest");
-        if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
+        if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream), "moments");
         if (st == LBE_OK) st = one_step_residual(c, r_rest);
         if (st == LBE_OK) st = upload_mask(c, keep);
         if (st == LBE_OK) st = dev_err(c, predict_warm_state(c, m), "prediction");
@@ -1164,7 +1253,7 @@ lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, 
     st = upload_mask(c, keep);
     if (st == LBE_OK) st = dev_err(c, predict_warm_state(c, m), "prediction");
     if (st == LBE_OK) st = dev_err(c, launch_rest(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream), "rest");
-    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream), "moments");
     if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
     // a judged state that went non-finite has been replaced: clear the device flags
@@ -1198,7 +1287,7 @@ lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int3
     }
     if (st != LBE_OK) return st;
     // coefficients of the state, so that the timed launches see the real data
-    st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, c->stream), "node");
+    st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e0), "event");
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e1), "event");
@@ -1209,7 +1298,7 @@ lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int3
                                       hipMemcpyHostToDevice, c->stream);
         auto one = [&]() {
             return launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], 0, 0, 1,
-                                0.0, 1.0, 0, c->stream);
+                                0.0, 1.0, 0, 0, 0, 1, c->stream);
         };
         if (e == hipSuccess) e = one();  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);

@@ -67,10 +67,16 @@ struct InstanceTables {
 // Device descriptor of one instance (lives in device memory; pointers into the workspace).
 struct DevInstance {
     int32_t nr, nv, n0, n1, n2, geometry;
+    int32_t f32, pad_;  // 1: state buffers hold FP32 deviations from base[] (LBE_FP32_STORE)
     int32_t N0, N1, N2, wband;
     double dt, dr, eta0, kn, chi0, L, gin_l, gin_r;
     double rcl, rcr, uw, tratio;  // computational walls, inner wall speed, T_outer / T_inner
-    double* f[3];           // state buffers [nr][nv]; f[0] holds the state between steps
+    double* f[3];           // state buffers [nr][nv] (FP64, or FP32 when f32; two ghost rows on each
+                            // side); f[0] holds the state between steps
+    double* base[4];        // f32: per node (n g_0[n0], g_1[n1], g_2[n2]), the discrete equilibrium a
+                            // buffer's deviations are taken from: f = dev + B0[i0] (B1[i1] B2[i2]).
+                            // Tables 0, 1, 2 belong to buffers 0, 1, 2; the third stage writes
+                            // buffer 0's new table into 3, copied to 0 after the step
     double* mom;            // [nr][nslices][kMomStride] moment sums of the last written buffer (per slice)
     double* node;           // [nr][kNodeStride] node coefficients of the current stage
     const double* p0; const double* p1; const double* p2;
@@ -103,7 +109,7 @@ constexpr int kTileDescStride = 16;  // ints per MFMA tile descriptor of the sta
 // Launch group of the stage kernel: instances sharing one velocity set (n0, n1, n2, geometry).
 // All sizes are uniform over the group; LDS offsets are in doubles.
 struct StageGroup {
-    int32_t n0, n1, n2, nv, geometry;
+    int32_t n0, n1, n2, nv, geometry, f32;
     int32_t S, ns2, nvs, ncols_s, ncols16, plane_cols;  // slices, i2 / velocities / columns per slice
     int32_t ncp16;                                       // d2 columns (n0 n1, sphere) padded to 16
     int32_t plane_sz, op_sz, ib_sz;                      // doubles per plane / output / term buffer
@@ -114,6 +120,7 @@ struct StageGroup {
     int16_t perm[kMaxTilePerm];                          // logical tile of each launch slot
     int32_t off_plane, off_op, off_ibuf, off_K1, off_K2a, off_K2b, off_colfac, off_cpinfo, off_tdesc, off_y0p,
         off_psi, off_coef, off_geq, off_part, lds_doubles;
+    int32_t off_sb, off_fb, bstride;  // f32: base factors of the window rows / own rows (stride bstride)
 };
 
 constexpr int kCoefStride = 18;  // doubles per node of the stage kernel's coefficient block

@@ -179,22 +179,59 @@ __device__ inline double reduce_scatter16(const double* v, int lane)
     return w;
 }
 
+// ------------------------------------------------------------------ state access
+
+// Base factors of row `row` of base table `tab` (FP32 storage): (n g_0[n0], g_1[n1], g_2[n2]) of the
+// node, ghost rows taking the base of their wall's node.
+__device__ inline const double* base_row(const DevInstance& I, int tab, int row)
+{
+    const int rb = min(max(row, 0), I.nr - 1);
+    return I.base[tab] + (size_t)rb * (I.n0 + I.n1 + I.n2);
+}
+
+// f of buffer `buf` at row `row` (-2 .. nr + 1) and velocity v; FP32 storage reconstructs the
+// deviation on top of base table `tab`: f = dev + B0[i0] (B1[i1] B2[i2]).
+__device__ inline double f_at(const DevInstance& I, int buf, int tab, int row, int v)
+{
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
+    if (!I.f32) return I.f[buf][e];
+    const double* b = base_row(I, tab, row);
+    const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
+    return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
+}
+
+__device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, int v, double val)
+{
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
+    if (!I.f32) {
+        I.f[buf][e] = val;
+        return;
+    }
+    const double* b = base_row(I, tab, row);
+    const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
+    ((float*)I.f[buf])[e] = (float)(val - b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]));
+}
+
 // ------------------------------------------------------------------ moments of a state
 
-// Moment sums of buffer `buf` with shift 0 (used at start-up and after lbe_set_state).
-__global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restrict__ insts, int buf)
+// Moment sums of buffer `buf` (base table `tab`) with shift 0 (start-up, lbe_set_state, the warm
+// start); from_scratch reads the FP64 copy in the instance's scratch instead.
+__global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restrict__ insts, int buf, int tab,
+                                                    int from_scratch, int only)
 {
+    if (only >= 0 && (int)blockIdx.y != only) return;
     const DevInstance& I = insts[blockIdx.y];
+    if (only == -2 && (!I.f32 || !I.flags[1])) return;  // FP32-storage instances that are active
     const int i = blockIdx.x;
     if (i >= I.nr) return;
     __shared__ double red[16 * 4];
-    const double* fi = I.f[buf] + (size_t)i * I.nv;
     double acc[13];
 #pragma unroll
     for (int k = 0; k < 13; k++) acc[k] = 0;
     for (int v = threadIdx.x; v < I.nv; v += kBlock) {
         const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
-        const double x = I.p0[i0], y = I.p1[i1], z = I.p2[i2], fv = fi[v];
+        const double x = I.p0[i0], y = I.p1[i1], z = I.p2[i2];
+        const double fv = from_scratch ? I.scratch[(size_t)i * I.nv + v] : f_at(I, buf, tab, i, v);
         const double x2 = x * x + y * y + z * z;
         acc[MF_S0] += fv;
         acc[MF_S1X] += fv * x;
@@ -217,7 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
 
 // ------------------------------------------------------------------ node kernel
 
-__global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, int src)
+__global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, int src, int bsrc)
 {
     const DevInstance& I = insts[blockIdx.y];
     if (!I.flags[1]) return;
@@ -226,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     const int bx = blockIdx.x;
     __shared__ double red[16 * 4];
     if (bx >= nchunks + 2) return;
-    const double* f = I.f[src];
+    auto F = [&](int row, int v) { return f_at(I, src, bsrc, row, v); };
 
     if (bx >= nchunks) {
         // Wall density of diffuse reflection: n_w = - sum_{leaving} p_r f_hat / sum_{entering} p_r g_w.
@@ -235,12 +272,11 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         for (int v = threadIdx.x; v < I.nv; v += kBlock) {
             const double pr = I.p0[v % I.n0];
             if (left && pr < 0) {
-                const double f0 = f[v], f1 = f[I.nv + v], f2 = f[2 * (size_t)I.nv + v];
+                const double f0 = F(0, v), f1 = F(1, v), f2 = F(2, v);
                 const double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
                 acc[0] += pr * weno5(f2, f1, f0, gm1, gm2);
             } else if (!left && pr > 0) {
-                const double* fl = f + (size_t)(nr - 1) * I.nv;
-                const double a = fl[v], b = fl[v - I.nv], c = fl[v - 2 * (size_t)I.nv];
+                const double a = F(nr - 1, v), b = F(nr - 2, v), c = F(nr - 3, v);
                 const double gp1 = 3 * a - 3 * b + c, gp2 = 6 * a - 8 * b + 3 * c;
                 acc[0] += pr * weno5(c, b, a, gp1, gp2);
             }
@@ -251,8 +287,6 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // ghost cells of this wall (cells -1, -2, or nr, nr + 1, stored in the two rows the
         // state buffers hold on each side): n_w g_w for entering velocities, the quadratic
         // extrapolation of the three nearest cells for leaving ones
-        double* fw = I.f[src];
-        const size_t nv = I.nv;
         for (int v = threadIdx.x; v < I.nv; v += kBlock) {
             const double pr = I.p0[v % I.n0];
             if (left) {
@@ -260,24 +294,23 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
                 if (pr > 0) {
                     g1 = g2 = nw * I.gwl[v];
                 } else {
-                    const double f0 = f[v], f1 = f[nv + v], f2 = f[2 * nv + v];
+                    const double f0 = F(0, v), f1 = F(1, v), f2 = F(2, v);
                     g1 = 3 * f0 - 3 * f1 + f2;
                     g2 = 6 * f0 - 8 * f1 + 3 * f2;
                 }
-                fw[v - nv] = g1;
-                fw[v - 2 * nv] = g2;
+                f_put(I, src, bsrc, -1, v, g1);
+                f_put(I, src, bsrc, -2, v, g2);
             } else {
-                const double* fl = f + (size_t)(nr - 1) * nv;
                 double g1, g2;
                 if (pr < 0) {
                     g1 = g2 = nw * I.gwr[v];
                 } else {
-                    const double a = fl[v], b = fl[v - nv], c = fl[v - 2 * nv];
+                    const double a = F(nr - 1, v), b = F(nr - 2, v), c = F(nr - 3, v);
                     g1 = 3 * a - 3 * b + c;
                     g2 = 6 * a - 8 * b + 3 * c;
                 }
-                fw[(size_t)nr * nv + v] = g1;
-                fw[(size_t)(nr + 1) * nv + v] = g2;
+                f_put(I, src, bsrc, nr, v, g1);
+                f_put(I, src, bsrc, nr + 1, v, g2);
             }
         }
         return;
@@ -615,10 +648,16 @@ __device__ inline void stage_coefs(const double* nd, const double* geo4, const d
 //      store to HBM and to O, and the staging of node i+1's plane and prefetches.
 // The moment sums are taken about the tile shift c and written per slice (no atomics; fixed
 // order, so runs are bitwise reproducible).
-template <int VPT>
+// FP32 storage (F32): the buffers hold deviations from the per-node discrete equilibrium of
+// base tables bsrc (src), bfn (f^n); the output is stored as its deviation from this stage's own
+// equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
+// completed one node after their load (the ring slot of cell i + 4), so no load is waited for
+// earlier than in the FP64 path.
+template <int VPT, bool F32>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
-                                                 int fn, int dst, double an, double bs, int rhs)
+                                                 int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn,
+                                                 int bdst)
 {
     extern __shared__ double lds[];
     const WorkItem it = items[blockIdx.x];
@@ -655,12 +694,25 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     int* tdesc = (int*)(lds + G.off_tdesc);
     double* y0p = lds + G.off_y0p;
     double* psi = lds + G.off_psi;
-    const int rowb = nv * (int)sizeof(double);
+    constexpr int esz = F32 ? 4 : 8;  // bytes per stored value
+    const int rowb = nv * esz;
     // f_src with its two ghost rows on each side: cell c at byte row offset (c + 2) rowb
-    const rsrc_t rf = make_rsrc(I.f[src] - 2 * (size_t)nv, (size_t)(nr + 4) * rowb);
+    const rsrc_t rf = make_rsrc((const char*)I.f[src] - 2 * (size_t)rowb, (size_t)(nr + 4) * rowb);
     const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
-    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * rowb);
-    auto cell = [&](int c, unsigned vo) { return bload(rf, vo, (min(c, nr + 1) + 2) * rowb); };
+    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * (rhs ? nv * 8 : rowb));
+    // stored value of cell c (F32: the deviation only; its base is added separately)
+    auto cell = [&](int c, unsigned vo) {
+        if constexpr (F32)
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0));
+        else
+            return bload(rf, vo, (min(c, nr + 1) + 2) * rowb);
+    };
+    auto fn_load = [&](int row, unsigned vo) {
+        if constexpr (F32)
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0));
+        else
+            return bload(rfn, vo, row * rowb);
+    };
     const int ng = n0 + n1 + n2;
     // velocity shift of the tile: the velocity of its first node (common to all its slices)
     const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
@@ -846,10 +898,44 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         sgeq[t * ng + k] = wt[kk] * acc;
     }
 
+    // FP32 storage: base factors of the window rows (cells i0-3 .. i0+nt+2) of the src buffer
+    // and of the own rows of f^n, as B0[i0] and C[col] = B1[i1] B2[i2] per plane column; the
+    // equilibrium of this stage's src moments becomes the output's base table
+    double* sbase = lds + G.off_sb;
+    double* fbase = lds + G.off_fb;
+    const int bst = G.bstride;
+    if constexpr (F32) {
+        auto fill = [&](double* dstb, int nrows, int row0, int tab) {
+            for (int e = tid; e < nrows * bst; e += B) {
+                const int wr = e / bst, k = e % bst;
+                const int row = min(max(row0 + wr, 0), nr - 1);
+                const double* b = I.base[tab] + (size_t)row * ng;
+                double val;
+                if (k < n0) {
+                    val = b[k];
+                } else {
+                    const int gc = cp0 + (k - n0);
+                    val = b[n0 + gc % n1] * b[n0 + n1 + gc / n1];
+                }
+                dstb[e] = val;
+            }
+        };
+        fill(sbase, it.nt + 6, it.i0 - 3, bsrc);
+        if (need_fn) fill(fbase, it.nt, it.i0, bfn);
+        if (!rhs && it.slice == 0)
+            for (int e = tid; e < it.nt * ng; e += B) {
+                const int t = e / ng, k = e % ng;
+                const double g = sgeq[t * ng + k];
+                I.base[bdst][(size_t)(it.i0 + t) * ng + k] =
+                    k < n0 ? I.node[(size_t)(it.i0 + t) * kNodeStride + NF_N] * g : g;
+            }
+        __syncthreads();
+    }
+
     // ---- per-lane velocities
     const int nh = hq * ncol;
     unsigned voff[VPT];
-    int ibx[VPT], gx0[VPT], gx1[VPT], gx2[VPT];
+    int ibx[VPT], gx0[VPT], gx1[VPT], gx2[VPT], bcol[VPT];
     bool valid[VPT];
     double prv[VPT], y0[VPT], y1[VPT], y2[VPT], yy[VPT];
 #pragma unroll
@@ -860,7 +946,8 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         const int i0h = e % hq, col = e / hq;
         const int i0 = pos ? i0h : hq + i0h;
         const int cg = c_s0 + col, i1 = cg % n1, i2 = cg / n1;
-        voff[j] = (unsigned)(i0 + n0 * cg) * 8u;
+        voff[j] = (unsigned)(i0 + n0 * cg) * (unsigned)esz;
+        bcol[j] = n0 + (cg - cp0);
         ibx[j] = i0 + cs * col;
         gx0[j] = i0;
         gx1[j] = n0 + i1;
@@ -880,18 +967,26 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     // so the ring never moves data and no load has to complete before the next node.
     // At a wall the face flux of the entering velocities is p_r times the ghost value (n_w g_w).
     // The planes of nodes 0 and 1 of the tile are staged into plane buffers 0 and 1.
+    // base of window row wr (cell i0 - 3 + wr) at the lane's velocity j (FP32 storage)
+    auto wbase = [&](int wr, int j) { return sbase[wr * bst + gx0[j]] * sbase[wr * bst + bcol[j]]; };
     double sl[VPT][7], fnv[VPT], Fl[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
 #pragma unroll
         for (int k = 0; k < 7; k++) sl[j][k] = cell(it.i0 - 2 + k, voff[j]);
-        fnv[j] = need_fn ? bload(rfn, voff[j], it.i0 * rowb) : 0.0;
+        if constexpr (F32) {
+            // cells i0-2 .. i0+3 now; cell i0+4 (slot 6) is completed at node 0
+#pragma unroll
+            for (int k = 0; k < 6; k++) sl[j][k] += wbase(k + 1, j);
+        }
+        fnv[j] = need_fn ? fn_load(it.i0, voff[j]) : 0.0;
         const double pr6 = prv[j] * (1.0 / 6);
         if (pos) {
             if (it.i0 == 0) {
                 Fl[j] = prv[j] * sl[j][1];
             } else {
-                const double cm3 = cell(it.i0 - 3, voff[j]);
+                double cm3 = cell(it.i0 - 3, voff[j]);
+                if constexpr (F32) cm3 += wbase(0, j);
                 Fl[j] = weno_flux(cm3, sl[j][0], sl[j][1], sl[j][2], sl[j][3], prv[j], pr6);
             }
         } else {
@@ -906,7 +1001,14 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     auto fill_other_slices = [&](int t, int buf) {
         double* pl = plane + buf * G.plane_sz;
         for (int v = tid; v < nv; v += B)
-            if (v < vs0 || v >= vs1) pl[(v % n0) + cs * (v / n0)] = bload(rf, 8u * v, (it.i0 + t + 2) * rowb);
+            if (v < vs0 || v >= vs1) {
+                double x = cell(it.i0 + t, (unsigned)(esz * v));
+                if constexpr (F32) {
+                    const int wr = t + 3;  // cell i0 + t
+                    x += sbase[wr * bst + v % n0] * sbase[wr * bst + n0 + v / n0];  // sphere: cp0 = 0
+                }
+                pl[(v % n0) + cs * (v / n0)] = x;
+            }
     };
     if (sph && G.S > 1) {
         fill_other_slices(0, 0);
@@ -1019,11 +1121,13 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             const double* cf = scoef + t * kCoefStride;
             const double* gq = sgeq + t * ng;
             const double* ib0 = lds + G.off_ibuf + buf * G.ib_sz;
+            const double nnode = F32 ? I.node[(size_t)i * kNodeStride + NF_N] : 0.0;
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
                 double Iv = ib0[ibx[j]] + ib0[ibx[j] + cs * ncol];
                 if (sph) Iv += ib0[ibx[j] + 2 * cs * ncol];
-                const double fmb = gq[gx0[j]] * gq[gx1[j]] * gq[gx2[j]];
+                const double g0 = gq[gx0[j]], g1 = gq[gx1[j]], g2 = gq[gx2[j]];
+                const double fmb = g0 * g1 * g2;
                 const double Y0 = y0[j], Y1 = y1[j], Y2 = y2[j];
                 const double a0 = fma(cf[SC_E02], Y2, fma(cf[SC_E01], Y1, fma(cf[SC_E00], Y0, cf[SC_G0])));
                 const double a1 = fma(cf[SC_E12], Y2, fma(cf[SC_E11], Y1, cf[SC_G1]));
@@ -1033,18 +1137,34 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 const double A = fma(cf[SC_AR], Fr[j], -cf[SC_AL] * Fl[j]);
                 double o = fma(fmb, Pc, -(A + Iv));
                 o = fma(cf[SC_CF], sl[j][(P + 2) % 7], o);
-                if (need_fn) o = fma(an, fnv[j], o);
+                if (need_fn) {
+                    double fv = fnv[j];
+                    if constexpr (F32) fv += fbase[t * bst + gx0[j]] * fbase[t * bst + bcol[j]];
+                    o = fma(an, fv, o);
+                }
                 if (valid[j]) {
-                    bstore(ro, voff[j], i * rowb, o);
+                    if constexpr (F32) {
+                        if (rhs) {
+                            bstore(ro, voff[j] * 2u, i * nv * 8, o);
+                        } else {
+                            const double dev = o - (nnode * g0) * (g1 * g2);
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)dev), ro, voff[j],
+                                                                  i * rowb, 0);
+                        }
+                    } else {
+                        bstore(ro, voff[j], i * rowb, o);
+                    }
                     if (!rhs) op[buf * G.op_sz + ibx[j]] = o;
                 }
             }
             if (t + 1 < it.nt) {
 #pragma unroll
                 for (int j = 0; j < VPT; j++) {
+                    // FP32 storage: complete cell i + 4 (loaded during the previous node)
+                    if constexpr (F32) sl[j][(P + 6) % 7] += wbase(t + 7, j);
                     Fl[j] = Fr[j];
                     sl[j][P % 7] = cell(i + 5, voff[j]);
-                    fnv[j] = need_fn ? bload(rfn, voff[j], (i + 1) * rowb) : 0.0;
+                    fnv[j] = need_fn ? fn_load(i + 1, voff[j]) : 0.0;
                 }
             }
         }
@@ -1352,39 +1472,191 @@ __global__ void __launch_bounds__(kBlock) k_collect_resid(const DevInstance* __r
     if (k < ninst) out[k] = insts[k].resid[0];
 }
 
+// ------------------------------------------------------------------ FP32 storage helpers
+
+// Base table 3 (written by the third stage for the new state) becomes buffer 0's table 0.
+__global__ void __launch_bounds__(kBlock) k_base_copy(const DevInstance* __restrict__ insts)
+{
+    const DevInstance& I = insts[blockIdx.y];
+    if (!I.f32 || !I.flags[1]) return;
+    const size_t n = (size_t)I.nr * (I.n0 + I.n1 + I.n2);
+    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < n) I.base[0][e] = I.base[3][e];
+}
+
+// Cell measure V_i: r_i dr (cylinder) or (r_{i+1/2}^3 - r_{i-1/2}^3) / 3 (sphere).
+__device__ inline double cell_volume(const DevInstance& I, int i)
+{
+    const double r = I.r[i], dr = I.dr;
+    return I.geometry == LBE_CYL ? r * dr : r * r * dr + dr * dr * dr / 12;
+}
+
+// Total mass sum_i V_i n_i of every instance (or only instance `only`) from its moment sums.
+__global__ void __launch_bounds__(kBlock) k_mass(const DevInstance* __restrict__ insts, int only,
+                                                 double* __restrict__ mass)
+{
+    const int k = blockIdx.x;
+    if (only >= 0 && k != only) return;
+    const DevInstance& I = insts[k];
+    __shared__ double red[4];
+    double acc[1] = {0};
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        double n = 0;
+        for (int sl = 0; sl < I.nslices; sl++) n += I.mom[((size_t)i * I.nslices + sl) * kMomStride + MF_S0];
+        acc[0] += cell_volume(I, i) * n;
+    }
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) mass[k] = red[0];
+}
+
+// FP32 storage keeps the total mass: every stage rounds the stored deviations, which moves the
+// mass by a random walk of ~1e-10 per stage, and the closed system's steady state depends on its
+// mass.  With the moment sums of the stored state (k_moments), the base density of every node is
+// scaled by one factor s per instance so that sum_i V_i (s nb_i + d_i) equals the target mass
+// (nb_i: density of the base, d_i: of the deviations); the deviations are left as stored.
+__global__ void __launch_bounds__(kBlock) k_mass_fix(const DevInstance* __restrict__ insts,
+                                                     const double* __restrict__ target)
+{
+    const DevInstance& I = insts[blockIdx.x];
+    if (!I.f32 || !I.flags[1]) return;
+    const int n0 = I.n0, n1 = I.n1, n2 = I.n2, ng = n0 + n1 + n2;
+    __shared__ double red[8];
+    double acc[2] = {0, 0};  // sum V nb, sum V d
+    for (int i = threadIdx.x; i < I.nr; i += kBlock) {
+        const double* b = I.base[0] + (size_t)i * ng;
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int k = 0; k < n0; k++) s0 += b[k];
+        for (int k = 0; k < n1; k++) s1 += b[n0 + k];
+        for (int k = 0; k < n2; k++) s2 += b[n0 + n1 + k];
+        const double nb = s0 * (s1 * s2);
+        double n = 0;
+        for (int sl = 0; sl < I.nslices; sl++) n += I.mom[((size_t)i * I.nslices + sl) * kMomStride + MF_S0];
+        const double V = cell_volume(I, i);
+        acc[0] += V * nb;
+        acc[1] += V * (n - nb);
+    }
+    block_sum<2>(acc, red);
+    const double s = (target[blockIdx.x] - red[4]) / red[0];
+    for (size_t e = threadIdx.x; e < (size_t)I.nr * ng; e += kBlock)
+        if ((int)(e % ng) < n0) I.base[0][e] *= s;
+}
+
+// FP64 state of instance inst (buffer 0) into its scratch.
+__global__ void __launch_bounds__(kBlock) k_expand(const DevInstance* __restrict__ insts, int inst)
+{
+    const DevInstance& I = insts[inst];
+    const int i = blockIdx.x;
+    if (i >= I.nr) return;
+    for (int v = threadIdx.x; v < I.nv; v += kBlock) I.scratch[(size_t)i * I.nv + v] = f_at(I, 0, 0, i, v);
+}
+
+// FP32 storage of the FP64 state in instance inst's scratch: base table 0 from the node block
+// (n and the equilibrium factors at the state's u, T; k_node and k_proj ran on its moment sums),
+// buffer 0 = the deviations.
+__global__ void __launch_bounds__(kBlock) k_rebase(const DevInstance* __restrict__ insts, int inst)
+{
+    const DevInstance& I = insts[inst];
+    const int i = blockIdx.x;
+    if (i >= I.nr) return;
+    const int n0 = I.n0, n1 = I.n1, n2 = I.n2, ng = n0 + n1 + n2;
+    const double* nd = I.node + (size_t)i * kNodeStride;
+    double* b = I.base[0] + (size_t)i * ng;
+    for (int k = threadIdx.x; k < ng; k += kBlock) {
+        const double *cf, *poly, *wt;
+        int N, kk;
+        if (k < n0) {
+            cf = nd + (I.p0[k] > 0 ? NF_IPLUS : NF_IMINUS);
+            N = I.N0; kk = k; poly = I.poly0; wt = I.w0;
+        } else if (k < n0 + n1) {
+            cf = nd + NF_C1;
+            N = I.N1; kk = k - n0; poly = I.poly1; wt = I.w1;
+        } else {
+            cf = nd + NF_C2;
+            N = I.N2; kk = k - n0 - n1; poly = I.poly2; wt = I.w2;
+        }
+        double acc = 0;
+        for (int l = 0; l <= N; l++) acc += cf[l] * poly[kk * (N + 1) + l];
+        b[k] = k < n0 ? nd[NF_N] * (wt[kk] * acc) : wt[kk] * acc;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < I.nv; v += kBlock) f_put(I, 0, 0, i, v, I.scratch[(size_t)i * I.nv + v]);
+}
+
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, hipStream_t s)
+hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, int tab, int from_scratch, int only,
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_moments, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, buf);
+    hipLaunchKernelGGL(k_moments, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, buf, tab, from_scratch, only);
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, hipStream_t s)
+hipError_t launch_base_copy(const DevInstance* d, int ninst, int maxnr, int maxng, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_base_copy, dim3((maxnr * maxng + kBlock - 1) / kBlock, ninst), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mass, dim3(ninst), dim3(kBlock), 0, s, d, only, mass);
+    return hipGetLastError();
+}
+
+// Moment sums of the stored FP32 states, the mass fix, and the moment sums again.
+hipError_t launch_mass_fix(const DevInstance* d, int ninst, int maxnr, const double* target, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_moments, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, 0, 0, 0, -2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mass_fix, dim3(ninst), dim3(kBlock), 0, s, d, target);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moments, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, 0, 0, 0, -2);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_expand, dim3(nr), dim3(kBlock), 0, s, d, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebase(const DevInstance* d, int inst, int nr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rebase, dim3(nr), dim3(kBlock), 0, s, d, inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int bsrc, hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
-    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src);
+    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src, bsrc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
     return hipGetLastError();
 }
 
-template <int VPT>
+template <int VPT, bool F32>
 static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
-                                 int fn, int dst, double an, double bs, int rhs, hipStream_t s)
+                                 int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst,
+                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stage<VPT>, dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d, items,
-                       G, src, fn, dst, an, bs, rhs);
+    hipLaunchKernelGGL((k_stage<VPT, F32>), dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d,
+                       items, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst);
     return hipGetLastError();
 }
 
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
-                        int dst, double an, double bs, int rhs, hipStream_t s)
+                        int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst, hipStream_t s)
 {
-    switch (G.vpt) {
-        case 1: return launch_stage_t<1>(d, items, nitems, G, src, fn, dst, an, bs, rhs, s);
-        case 2: return launch_stage_t<2>(d, items, nitems, G, src, fn, dst, an, bs, rhs, s);
+    const int key = G.vpt * 2 + (G.f32 ? 1 : 0);
+    switch (key) {
+        case 2: return launch_stage_t<1, false>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
+        case 3: return launch_stage_t<1, true>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
+        case 4: return launch_stage_t<2, false>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
+        case 5: return launch_stage_t<2, true>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1392,8 +1664,13 @@ hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems,
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-    hipError_t e = hipFuncSetAttribute((const void*)k_stage<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_stage<2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_stage<1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_stage<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_stage<1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_stage<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 

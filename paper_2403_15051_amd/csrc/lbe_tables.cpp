@@ -513,6 +513,7 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
     if (!std::isfinite(p.u_wall_inner)) return bad("u_wall_inner must be finite");
     if (p.geometry == LBE_SPH && p.u_wall_inner != 0) return bad("a spherical instance cannot have a wall velocity");
     if (p.nr < 8 || p.nr > 1024) return bad("nr must lie in [8, 1024]");
+    if (p.precision != LBE_FP64 && p.precision != LBE_FP32_STORE) return bad("precision must be LBE_FP64 or LBE_FP32_STORE");
     const int Q[3] = {p.q_radial, p.q_t1, p.q_t2};
     for (int a = 0; a < 3; a++) {
         if (Q[a] < 2 || Q[a] > kMaxQ) return bad("quadrature orders must lie in [2, 64]");

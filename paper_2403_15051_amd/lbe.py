@@ -20,6 +20,7 @@ CYL, SPH = 0, 1
 FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
 WARM_FIELDS = ("n", "u_t1", "T", "q_r", "P_rt1")
 GEMM_BF16, GEMM_FP32 = 0, 1
+FP64, FP32_STORE = 0, 1
 INFO_KEYS = ("nr", "nv", "n0", "n1", "n2", "chi0", "C", "L", "sigma", "rcl", "rcr", "dr", "dt", "steps", "N0", "N1",
              "N2")
 
@@ -48,6 +49,7 @@ class Params(ctypes.Structure):
         ("q_t2", ctypes.c_int32),
         ("n_expand", ctypes.c_int32 * 3),
         ("cfl", ctypes.c_double),
+        ("precision", ctypes.c_int32),
     ]
 
 
@@ -59,6 +61,7 @@ def make_params(d: dict) -> Params:
     p = Params()
     for k in PARAM_KEYS:
         setattr(p, k, d[k])
+    p.precision = int(d.get("precision", FP64))
     ne = d.get("n_expand", (0, 0, 0))
     for a in range(3):
         p.n_expand[a] = int(ne[a])

