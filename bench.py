@@ -25,7 +25,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 # HBM traffic of the stage kernel measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE, each
 # scaled by the same counter on a plain copy of known size); valid only for the kernel source it
 # was measured on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_stage_sweep256_fp64.json")
+TRAFFIC_FILES = {"fp64": os.path.join(ROOT, "profiles", "traffic_k_stage_sweep256_fp64.json"),
+                 "fp32": os.path.join(ROOT, "profiles", "traffic_k_stage_sweep256_fp32.json")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_15051_amd", "csrc", "lbe_kernels.hip")
 
 
@@ -34,11 +35,11 @@ def kernel_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(precision: str):
     """Bytes per stage launch from the committed counter measurement, or None when the kernel
     source has changed since (or no measurement exists)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[precision]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -60,14 +61,16 @@ def copy_calibration(nbytes: int, reps: int) -> None:
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def workload(name: str, n_inst: int):
+def workload(name: str, n_inst: int, precision: str = "fp64"):
     from paper_2403_15051_amd import workloads as W
 
     if name == "sweep":
         ps, acc = W.sweep(n_inst)
         desc = (f"parameter sweep: {n_inst} cylindrical Couette/Fourier instances, Nr U{{64..512}}, "
-                f"eta0 U(0.01,0.3), Kn 10^U(-2,1), Q in {{4,8,12,16}}, seed {W.SWEEP_SEED}")
-        return [W.solver_params(p) for p in ps], desc
+                f"eta0 U(0.01,0.3), Kn 10^U(-2,1), Q in {{4,8,12,16}}, seed {W.SWEEP_SEED}, "
+                f"{'FP32 f / FP64 moments' if precision == 'fp32' else 'FP64'}")
+        prec = 1 if precision == "fp32" else 0
+        return [dict(W.solver_params(p), precision=prec) for p in ps], desc
     if name == "fourier_sph":
         return [W.FOURIER_SPH] * n_inst, f"spherical Fourier (Nr 256, 32x12x12 velocities) x {n_inst}"
     if name == "fourier_cyl":
@@ -211,6 +214,10 @@ def main():
     ap.add_argument("--steady-instances", type=int, default=512, help="held-out instances of the steady-solve metric")
     ap.add_argument("--steady-plain", type=int, default=8, help="of which solved one at a time")
     ap.add_argument("--no-steady", action="store_true")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="storage of f (the sweep is specified with FP32 f and FP64 moments)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-alt", action="store_true", help="skip the FP64-storage comparison run")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run a plain copy of this size (calibration)")
     args = ap.parse_args()
     if args.copy_bytes:
@@ -226,7 +233,8 @@ def main():
     from paper_2403_15051_amd import lbe
 
     torch.cuda.set_device(0)
-    params, desc = workload(args.workload, args.instances if args.workload == "sweep" else max(1, args.instances))
+    params, desc = workload(args.workload, args.instances if args.workload == "sweep" else max(1, args.instances),
+                            args.precision)
     print(f"[bench] workload: {desc}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     solver = lbe.Solver(params)
@@ -235,6 +243,12 @@ def main():
     sv = sum(int(i["nr"]) * int(i["nv"]) for i in infos)
     print(f"[bench] init {t_init:.1f} s, {solver.n_inst} instances, {sv / 1e6:.2f} M site-velocities", file=sys.stderr,
           flush=True)
+    tuned = None
+    if not args.no_autotune:
+        tuned = solver.autotune(reps=3)
+        print("[bench] autotuned tiles: " + ", ".join(f"Nv {r['nv']}: {r['tile_nodes']} nodes "
+                                                      f"({r['ms_before']:.3f} -> {r['ms']:.3f} ms)" for r in tuned),
+              file=sys.stderr, flush=True)
     solver.step(args.warmup)
     solver.sync()
     print("[bench] warmup done", file=sys.stderr, flush=True)
@@ -256,9 +270,11 @@ def main():
     solver.sync()
     t3 = time.perf_counter()
     tm = solver.timing_stop()
-    # algorithmic HBM bytes of one stage launch: stage 1 reads f^n and writes f1 (16 B per
-    # site-velocity in FP64), stages 2 and 3 read f_s and f^n and write (24 B): 64 B per step
-    bytes_per_launch = sv * 64.0 / 3
+    # algorithmic HBM bytes of one stage launch: stage 1 reads f^n and writes f1, stages 2 and 3
+    # read f_s and f^n and write: 8 f-accesses per site-velocity per step, 64 B in FP64 and 32 B
+    # with FP32 storage, a third of it per stage launch on average
+    fbytes = 4 if args.precision == "fp32" else 8
+    bytes_per_launch = sv * 8.0 * fbytes / 3
     stage_avg_s = tm["stage_ms"] / tm["stage_launches"] / 1e3
     achieved = bytes_per_launch / stage_avg_s / 1e9
     line = {
@@ -272,17 +288,36 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64",  # arithmetic; the storage of f is config.precision
         "data": "synthetic",
-        "config": {"workload": desc, "instances": solver.n_inst, "site_velocities": sv, "precision": "fp64",
+        "config": {"workload": desc, "instances": solver.n_inst, "site_velocities": sv,
+                   "precision": "fp32 storage, fp64 arithmetic" if args.precision == "fp32" else "fp64",
+                   "tiles": ([{"nv": r["nv"], "tile_nodes": r["tile_nodes"]} for r in tuned] if tuned else "default"),
                    "parallelism": "single GPU, instances batched per launch"},
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
                      "stage_ms_avg": stage_avg_s * 1e3, "node_ms_avg": tm["node_ms"] / max(1, tm["node_launches"]),
                      "stage_share_of_step": tm["stage_ms"] / ((t3 - t2) * 1e3),
                      "ms_per_step_eager_timed": (t3 - t2) * 1e3 / args.steps},
     }
     del solver
+    if args.precision == "fp32" and args.workload == "sweep" and not args.no_alt:
+        # the same workload with FP64 storage, for comparison (same tiles procedure, graph replay)
+        p64 = [dict(p, precision=0) for p in params]
+        s64 = lbe.Solver(p64)
+        if not args.no_autotune:
+            s64.autotune(reps=3)
+        s64.step(args.warmup)
+        s64.sync()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        s64.step(args.steps)
+        s64.sync()
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        line["fp64_storage"] = {"value": sv * args.steps / (t5 - t4), "ms_per_step": (t5 - t4) * 1e3 / args.steps}
+        print(f"[bench] fp64 storage: {(t5 - t4) * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        del s64
     if not args.no_steady:
         line["steady"] = steady_metrics(args.steady_instances, args.steady_plain)
     if not args.no_cpu:

@@ -1,13 +1,16 @@
 """Summarise rocprofv3 output as short markdown tables.
 
 usage:
-  python -m paper_2403_15051_amd.prof_summary trace <results.db> [title]
+  python -m paper_2403_15051_amd.prof_summary trace <results.db> [title] [--last N]
       per kernel and workgroup size (the stage kernel has one launch per velocity-set group):
       calls, total and average duration, share of GPU time, grid/workgroup sizes and the
       register/LDS footprint recorded by the profiler;
-  python -m paper_2403_15051_amd.prof_summary pmc <counter_collection.csv> <kernel substring>
+  python -m paper_2403_15051_amd.prof_summary pmc <counter_collection.csv> <kernel substring> [--last N]
       per-dispatch average of each counter over the matching dispatches, and the per-stage
       total (sum over the workgroup-size groups of one stage).
+  --last N keeps only the last N dispatches of every (kernel, workgroup size) group, e.g. the
+  3 K stage launches of bench.py's final timed pass of K steps (earlier dispatches include the
+  tile autotuner's trial launches).
 """
 from __future__ import annotations
 
@@ -17,14 +20,25 @@ import sqlite3
 import sys
 
 
-def summarise_trace(db_path: str, title: str = "") -> str:
+def summarise_trace(db_path: str, title: str = "", last: int = 0) -> str:
     db = sqlite3.connect(db_path)
     cur = db.cursor()
-    total = list(cur.execute("select sum(duration) from kernels"))[0][0] or 1
-    rows = list(cur.execute(
-        "select name, workgroup_x, count(*), sum(duration), avg(duration), max(grid_x), max(grid_y), "
-        "max(lds_size), max(vgpr_count), max(accum_vgpr_count), max(sgpr_count), max(scratch_size) "
-        "from kernels group by name, workgroup_x order by sum(duration) desc"))
+    recs = list(cur.execute(
+        "select name, workgroup_x, start, duration, grid_x, grid_y, lds_size, vgpr_count, accum_vgpr_count, "
+        "sgpr_count, scratch_size from kernels order by start"))
+    groups = collections.defaultdict(list)
+    for r in recs:
+        groups[(r[0], r[1])].append(r)
+    rows = []
+    for (name, wg), rs in groups.items():
+        if last:
+            rs = rs[-last:]
+        durs = [r[3] for r in rs]
+        rows.append((name, wg, len(rs), sum(durs), sum(durs) / len(rs), max(r[4] for r in rs), max(r[5] for r in rs),
+                     max(r[6] for r in rs), max(r[7] for r in rs), max(r[8] for r in rs), max(r[9] for r in rs),
+                     max(r[10] for r in rs)))
+    rows.sort(key=lambda r: -r[3])
+    total = sum(r[3] for r in rows) or 1
     out = []
     if title:
         out.append(f"### {title}\n")
@@ -32,19 +46,21 @@ def summarise_trace(db_path: str, title: str = "") -> str:
                "SGPR | scratch |")
     out.append("|---|---|---|---|---|---|---|---|---|---|---|---|")
     for name, wg, calls, tot, avg, gx, gy, lds, vg, ag, sg, sc in rows:
-        short = name.split("(")[0].replace("void ", "")
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
         out.append(f"| {short} | {wg} | {calls} | {tot / 1e6:.2f} | {avg / 1e6:.3f} | {100 * tot / total:.1f} | "
                    f"{gx}*{gy} | {lds} | {vg} | {ag} | {sg} | {sc} |")
     return "\n".join(out)
 
 
-def summarise_pmc(csv_path: str, kernel: str) -> str:
+def summarise_pmc(csv_path: str, kernel: str, last: int = 0) -> str:
     rows = list(csv.DictReader(open(csv_path)))
     per = collections.defaultdict(list)
-    for r in rows:
+    for r in sorted(rows, key=lambda r: int(r.get("Dispatch_Id", 0))):
         if kernel in r["Kernel_Name"]:
             wg = r.get("Workgroup_Size", r.get("Workgroup_Size_X", ""))
             per[(r["Counter_Name"], wg)].append(float(r["Counter_Value"]))
+    if last:
+        per = {k: v[-last:] for k, v in per.items()}
     out = ["| counter | wg | dispatches | average per dispatch |", "|---|---|---|---|"]
     totals = collections.defaultdict(float)
     for (cname, wg), v in sorted(per.items()):
@@ -57,9 +73,15 @@ def summarise_pmc(csv_path: str, kernel: str) -> str:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) < 3 or sys.argv[1] not in ("trace", "pmc"):
+    args = sys.argv[1:]
+    last = 0
+    if "--last" in args:
+        i = args.index("--last")
+        last = int(args[i + 1])
+        args = args[:i] + args[i + 2:]
+    if len(args) < 2 or args[0] not in ("trace", "pmc"):
         raise SystemExit(__doc__)
-    if sys.argv[1] == "trace":
-        print(summarise_trace(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""))
+    if args[0] == "trace":
+        print(summarise_trace(args[1], args[2] if len(args) > 2 else "", last))
     else:
-        print(summarise_pmc(sys.argv[2], sys.argv[3]))
+        print(summarise_pmc(args[1], args[2], last))
