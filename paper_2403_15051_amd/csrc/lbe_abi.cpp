@@ -747,6 +747,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.qlam0 = (const double*)(ws + L.qlam0);
         d.qh0 = (const double*)(ws + L.qh0);
         d.M0 = (int32_t)t.ax[0].qy.size();
+        d.qpw = t.ax[0].qpanel;
         d.nslices = nsl;
         d.geo = (const double*)(ws + L.geo);
         d.r = (const double*)(ws + L.r);

@@ -44,6 +44,7 @@ struct AxisTables {
     std::vector<double> p, w;    // nodes, weights
     std::vector<double> poly;    // nq x (N+1): h_l(|p_k|) (half) or He_l(p_k) (full)
     std::vector<double> qy, qlam;  // half-range: projection rule on [0, Y] (nodes, weights)
+    double qpanel = 0.75;          // half-range: panel width of that rule (16 nodes per panel)
     std::vector<double> qh;        // half-range: h_l(qy_m), M x (N+1)
 };
 
@@ -85,6 +86,7 @@ struct DevInstance {
     const double* poly0; const double* poly1; const double* poly2;
     const double* qy0; const double* qlam0; const double* qh0;  // projection rule, M0 nodes
     int32_t M0, nslices;    // equilibrium projection nodes; velocity slices of the stage kernel
+    double qpw;             // panel width of the projection rule
     const double* geo;      // [nr][4]
     const double* r;        // [nr]
     const int32_t* wlo;     // [nr]

@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__
     for (int k = 0; k < 32; k++) acc[k] = 0;
     for (int side = 0; side < 2; side++) {
         const double uu = side ? -u : u;
-        int p0 = (int)floor((uu - reach) / 0.75), p1 = (int)ceil((uu + reach) / 0.75);
+        int p0 = (int)floor((uu - reach) / I.qpw), p1 = (int)ceil((uu + reach) / I.qpw);
         p0 = max(0, min(p0, npan));
         p1 = max(p0, min(p1, npan));
         for (int m = 16 * p0 + lane; m < 16 * p1; m += 64) {

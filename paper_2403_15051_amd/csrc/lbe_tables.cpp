@@ -169,7 +169,8 @@ static void herm_eval(int n, ld x, ld* psi)
 
 // Half-range rule of order Q (Golub-Welsch on the Jacobi matrix, Newton-polished zeros,
 // Christoffel weights), with the derivative-projection force matrices of eq. (force1)/(force2).
-static void build_half_axis(int Q, int N, double Y, AxisTables* ax, std::vector<double>* K1, std::vector<double>* K2)
+static void build_half_axis(int Q, int N, double Y, double hwidth, AxisTables* ax, std::vector<double>* K1,
+                            std::vector<double>* K2)
 {
     std::vector<ld> a, b;
     half_recurrence(Q + 1, a, b);
@@ -210,11 +211,12 @@ static void build_half_axis(int Q, int N, double Y, AxisTables* ax, std::vector<
         for (int l = 0; l <= N; l++) ax->poly[k * (N + 1) + l] = (double)h[l];
     }
     // projection rule of the equilibrium: composite 16-point Gauss-Legendre on [0, Y], panels
-    // of width 3/4, with h_l at its nodes
+    // of width hwidth, with h_l at its nodes
     {
         std::vector<ld> gx, gw;
         gauss_legendre(16, gx, gw);
-        const ld hw = 0.75L;
+        const ld hw = hwidth;
+        ax->qpanel = hwidth;
         const int npan = (int)ceill(Y / hw);
         ax->qy.clear();
         ax->qlam.clear();
@@ -537,7 +539,13 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
     // the equilibrium projection rule covers Gaussians up to 1.5 times the hottest wall
     const double Tmax = std::max(1.0, std::max(p.t_wall_inner, p.t_wall_outer));
     const double Y = 3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner);
-    build_half_axis(p.q_radial, p.n_expand[0], Y, &t->ax[0], &t->K1, &t->K2r);
+    // panel width of the projection rule: 16-point Gauss-Legendre integrates the Gaussian of
+    // temperature T times h_l (l <= 7) to rounding (measured against 30-digit quadrature: 3e-16
+    // at 3.35 sqrt(T), 2e-14 at 4.7 sqrt(T)); the width is sized for half the colder wall's
+    // temperature and kept within [0.1875, 1.5]
+    const double Tlow = 0.5 * std::min(p.t_wall_inner, p.t_wall_outer);
+    const double hwidth = std::min(1.5, std::max(0.1875, 3.35 * std::sqrt(Tlow)));
+    build_half_axis(p.q_radial, p.n_expand[0], Y, hwidth, &t->ax[0], &t->K1, &t->K2r);
     build_full_axis(p.q_t1, p.n_expand[1], &t->ax[1], &t->K2a);
     build_full_axis(p.q_t2, p.n_expand[2], &t->ax[2], &t->K2b);
     t->n0 = t->ax[0].nq;
