@@ -905,19 +905,24 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     double* fbase = lds + G.off_fb;
     const int bst = G.bstride;
     if constexpr (F32) {
+        // threads over (entry k of a row, row group): the column index math is done once per
+        // entry, the rows are strided by the number of row groups
+        const int kw = min(bst, B), ngrp = B / kw;
+        const int k0 = tid % kw, grp = tid / kw;
         auto fill = [&](double* dstb, int nrows, int row0, int tab) {
-            for (int e = tid; e < nrows * bst; e += B) {
-                const int wr = e / bst, k = e % bst;
-                const int row = min(max(row0 + wr, 0), nr - 1);
-                const double* b = I.base[tab] + (size_t)row * ng;
-                double val;
-                if (k < n0) {
-                    val = b[k];
-                } else {
-                    const int gc = cp0 + (k - n0);
-                    val = b[n0 + gc % n1] * b[n0 + n1 + gc / n1];
+            if (grp >= ngrp) return;
+            for (int kk = k0; kk < bst; kk += kw) {
+                int o1 = kk, o2 = -1;
+                if (kk >= n0) {
+                    const int gc = cp0 + (kk - n0);
+                    o1 = n0 + gc % n1;
+                    o2 = n0 + n1 + gc / n1;
                 }
-                dstb[e] = val;
+                for (int wr = grp; wr < nrows; wr += ngrp) {
+                    const int row = min(max(row0 + wr, 0), nr - 1);
+                    const double* b = I.base[tab] + (size_t)row * ng;
+                    dstb[wr * bst + kk] = o2 < 0 ? b[o1] : b[o1] * b[o2];
+                }
             }
         };
         fill(sbase, it.nt + 6, it.i0 - 3, bsrc);
