@@ -17,8 +17,9 @@
 namespace lbe {
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, int tab, int from_scratch, int only,
                           hipStream_t s);
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int bsrc, hipStream_t s);
-hipError_t launch_base_copy(const DevInstance* d, int ninst, int maxnr, int maxng, hipStream_t s);
+hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int src, int bsrc,
+                       hipStream_t s);
+hipError_t launch_base_copy(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxng, hipStream_t s);
 hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s);
 hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s);
 hipError_t launch_mass_fix(const DevInstance* d, int ninst, int maxnr, const double* target, hipStream_t s);
@@ -86,6 +87,14 @@ struct lbe_ctx {
     double* dev_mass = nullptr;
     int64_t since_fix = 0;
     std::vector<int32_t> rowoff;
+    // instances ordered by launch group (device), and per group: offset, count, largest nr and
+    // velocity-factor count, FP32 storage; streams and events that fork a step into one chain of
+    // launches per group and join them again (independent groups overlap on the device)
+    int32_t* dev_glist = nullptr;
+    std::vector<int> gl_off, gl_cnt, gl_maxnr, gl_maxng;
+    std::vector<char> gl_f32;
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> gevents;
     // captured launch sequences: one RK3 step, and one steady-state chunk (chunk steps, the
     // residual and the freeze test), replayed on `stream`; captured on a private stream
     bool use_graph = true;
@@ -455,7 +464,7 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, c->ninst, c->maxnr, src, bsrc, c->stream);
+    e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, src, bsrc, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
@@ -475,14 +484,78 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
 
 // One TVD-RK3 step (Shu-Osher) of every active instance:
 //   f1 = f + dt L(f);  f2 = 3/4 f + 1/4 (f1 + dt L(f1));  f <- 1/3 f + 2/3 (f2 + dt L(f2)).
-hipError_t launch_step(lbe_ctx* c)
+// Whole batch, one launch per kernel (and per group for the stage kernel): the per-launch timing
+// path and single-group contexts.
+hipError_t launch_step_serial(lbe_ctx* c)
 {
     hipError_t e = run_stage(c, 0, 0, 1, 0.0, 1.0, 0, 0, 0, 1);
     if (e == hipSuccess) e = run_stage(c, 1, 0, 2, 0.75, 0.25, 0, 1, 0, 2);
     if (e == hipSuccess) e = run_stage(c, 2, 0, 0, 1.0 / 3, 2.0 / 3, 0, 2, 0, 3);
-    if (e == hipSuccess && c->any_f32) e = launch_base_copy(c->dev_desc, c->ninst, c->maxnr, c->maxng, c->stream);
+    if (e == hipSuccess && c->any_f32)
+        e = launch_base_copy(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxng, c->stream);
     return e;
 }
+
+// nsteps RK3 steps of launch group q only, on stream s.
+hipError_t launch_steps_group(lbe_ctx* c, int q, int nsteps, hipStream_t s)
+{
+    const int32_t* il = c->dev_glist + c->gl_off[q];
+    const int cnt = c->gl_cnt[q], mnr = c->gl_maxnr[q];
+    // (src, fn, dst, an, bs, src table, f^n table, output table) of the three stages
+    struct St {
+        int src, fn, dst;
+        double an, bs;
+        int bsrc, bfn, bdst;
+    };
+    const St st[3] = {{0, 0, 1, 0.0, 1.0, 0, 0, 1}, {1, 0, 2, 0.75, 0.25, 1, 0, 2}, {2, 0, 0, 1.0 / 3, 2.0 / 3, 2, 0, 3}};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nsteps && e == hipSuccess; k++) {
+        for (int j = 0; j < 3 && e == hipSuccess; j++) {
+            e = launch_node(c->dev_desc, il, cnt, mnr, st[j].src, st[j].bsrc, s);
+            if (e == hipSuccess)
+                e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], st[j].src,
+                                 st[j].fn, st[j].dst, st[j].an, st[j].bs, 0, st[j].bsrc, st[j].bfn, st[j].bdst, s);
+        }
+        if (e == hipSuccess && c->gl_f32[q]) e = launch_base_copy(c->dev_desc, il, cnt, mnr, c->gl_maxng[q], s);
+    }
+    return e;
+}
+
+// nsteps steps of every group, each group a chain of launches on its own stream (forked from and
+// joined back into the context's stream, default priorities); instances of different groups share
+// no data within a step, so the chains overlap on the device.
+hipError_t launch_steps_forked(lbe_ctx* c, int nsteps)
+{
+    const int ng = (int)c->groups.size();
+    if (c->timing || ng == 1) {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < nsteps && e == hipSuccess; k++) e = launch_step_serial(c);
+        return e;
+    }
+    hipError_t e = hipSuccess;
+    while ((int)c->gstreams.size() < ng && e == hipSuccess) {
+        hipStream_t t = nullptr;
+        e = hipStreamCreateWithFlags(&t, hipStreamNonBlocking);
+        if (e == hipSuccess) c->gstreams.push_back(t);
+    }
+    while ((int)c->gevents.size() < ng + 1 && e == hipSuccess) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) c->gevents.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->gevents[ng], c->stream);
+    for (int q = 1; q < ng && e == hipSuccess; q++) e = hipStreamWaitEvent(c->gstreams[q], c->gevents[ng], 0);
+    for (int q = 0; q < ng && e == hipSuccess; q++) e = launch_steps_group(c, q, nsteps, q == 0 ? c->stream : c->gstreams[q]);
+    // join (also after an error, so that no stream is left forked)
+    for (int q = 1; q < ng; q++) {
+        hipError_t ej = hipEventRecord(c->gevents[q], c->gstreams[q]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(c->stream, c->gevents[q], 0);
+        if (e == hipSuccess) e = ej;
+    }
+    return e;
+}
+
+hipError_t launch_step(lbe_ctx* c) { return launch_steps_forked(c, 1); }
 
 // `chunk` steps with the moment snapshot taken before the last one, then the residual of that
 // step and the freeze test of every instance (lbe_run_to_steady).
@@ -490,10 +563,9 @@ hipError_t launch_chunk(lbe_ctx* c, int chunk, double tol, int judge)
 {
     hipError_t e = hipSuccess;
     if (c->any_f32) e = launch_mass_fix(c->dev_desc, c->ninst, c->maxnr, c->dev_mass, c->stream);
-    for (int s = 0; s < chunk && e == hipSuccess; s++) {
-        if (s == chunk - 1) e = launch_snapshot(c->dev_desc, c->ninst, c->stream);
-        if (e == hipSuccess) e = launch_step(c);
-    }
+    if (e == hipSuccess && chunk > 1) e = launch_steps_forked(c, chunk - 1);
+    if (e == hipSuccess) e = launch_snapshot(c->dev_desc, c->ninst, c->stream);
+    if (e == hipSuccess) e = launch_steps_forked(c, 1);
     if (e == hipSuccess) e = launch_residual(c->dev_desc, c->ninst, c->stream);
     if (e == hipSuccess) e = launch_converge(c->dev_desc, c->ninst, tol, chunk, judge, c->dev_status, c->stream);
     return e;
@@ -595,7 +667,8 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
     if (!p || n_inst < 1) return LBE_EINVAL;
     size_t total = align256(sizeof(DevInstance) * n_inst) + align256(4 * sizeof(double) * (size_t)n_inst) +
                    align256(sizeof(int32_t) * (size_t)(n_inst + 1)) + align256(sizeof(int32_t) * (size_t)n_inst) +
-                   align256(2 * sizeof(double) * (size_t)n_inst) + align256(sizeof(double) * (size_t)n_inst);
+                   align256(2 * sizeof(double) * (size_t)n_inst) + align256(sizeof(double) * (size_t)n_inst) +
+                   align256(sizeof(int32_t) * (size_t)n_inst);
     size_t host = sizeof(lbe_ctx);
     for (int k = 0; k < n_inst; k++) {
         lbe_params q;
@@ -675,14 +748,33 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     off = align256(off + 2 * sizeof(double) * (size_t)n_inst);
     c->dev_mass = (double*)(c->ws + off);
     off = align256(off + sizeof(double) * (size_t)n_inst);
+    c->dev_glist = (int32_t*)(c->ws + off);
+    off = align256(off + sizeof(int32_t) * (size_t)n_inst);
     c->rowoff.assign(n_inst + 1, 0);
     for (int k = 0; k < n_inst; k++) c->rowoff[k + 1] = c->rowoff[k] + c->tabs[k].nr;
+    std::vector<int32_t> glist;
+    for (size_t q = 0; q < c->groups.size(); q++) {
+        c->gl_off.push_back((int)glist.size());
+        int mnr = 0, mng = 0;
+        for (int k = 0; k < n_inst; k++)
+            if (c->group_of[k] == (int)q) {
+                glist.push_back(k);
+                mnr = std::max(mnr, c->tabs[k].nr);
+                mng = std::max(mng, c->tabs[k].n0 + c->tabs[k].n1 + c->tabs[k].n2);
+            }
+        c->gl_cnt.push_back((int)glist.size() - c->gl_off[q]);
+        c->gl_maxnr.push_back(mnr);
+        c->gl_maxng.push_back(mng);
+        c->gl_f32.push_back(c->groups[q].f32 ? 1 : 0);
+    }
     if (off > ws_bytes) {
         delete c;
         return LBE_ENOMEM;
     }
     hipError_t e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
                                   hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->dev_glist, glist.data(), glist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dev_rowoff, c->rowoff.data(), c->rowoff.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream);
@@ -865,7 +957,7 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     c->active[inst] = 1;
     st = upload_flags(c);
     if (st == LBE_OK)
-        st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "moments pass");
+        st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "moments pass");
     std::vector<double> node((size_t)d.nr * kNodeStride);
     if (st == LBE_OK)
         st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -1004,7 +1096,7 @@ lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t
     st = upload_flags(c);
     if (st == LBE_OK)
         st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 1, inst, c->stream), "moments");
-    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node");
     if (st == LBE_OK) st = dev_err(c, launch_rebase(c->dev_desc, inst, d.nr, c->stream), "rebase");
     if (st == LBE_OK)
         st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, inst, c->stream), "moments");
@@ -1108,7 +1200,7 @@ lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows)
     std::vector<int32_t> saved = c->active;
     std::fill(c->active.begin(), c->active.end(), 1);
     st = upload_flags(c);
-    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node pass");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node pass");
     std::vector<float> out((size_t)rows * 5);
     const int fields[5] = {NF_N, NF_U1, NF_T, NF_Q0, NF_P01};
     for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
@@ -1288,7 +1380,7 @@ lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int3
     }
     if (st != LBE_OK) return st;
     // coefficients of the state, so that the timed launches see the real data
-    st = dev_err(c, launch_node(c->dev_desc, c->ninst, c->maxnr, 0, 0, c->stream), "node");
+    st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e0), "event");
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e1), "event");
@@ -1392,6 +1484,8 @@ void lbe_free(lbe_ctx* c)
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipStream_t t : c->gstreams) (void)hipStreamDestroy(t);
+    for (hipEvent_t ev : c->gevents) (void)hipEventDestroy(ev);
     delete c;
 }
 

@@ -254,9 +254,11 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
 
 // ------------------------------------------------------------------ node kernel
 
-__global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, int src, int bsrc)
+// ilist (may be null): the instances of grid row y are ilist[y] (one launch group's instances).
+__global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist,
+                                                 int src, int bsrc)
 {
-    const DevInstance& I = insts[blockIdx.y];
+    const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
     if (!I.flags[1]) return;
     const int nr = I.nr;
     const int nchunks = (nr + kNodeChunk - 1) / kNodeChunk;
@@ -450,9 +452,9 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 // the 64 lanes share the quadrature nodes of the panels within 9.6 sqrt(T) of +-u (farther
 // panels contribute below 1e-20 of the peak), and the 2 (N0+1) <= 32 sums are reduced with
 // the register reduce-scatter.  Runs after k_node (needs u_r and T of the node).
-__global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts)
+__global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist)
 {
-    const DevInstance& I = insts[blockIdx.y];
+    const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
     if (!I.flags[1]) return;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -1480,9 +1482,10 @@ __global__ void __launch_bounds__(kBlock) k_collect_resid(const DevInstance* __r
 // ------------------------------------------------------------------ FP32 storage helpers
 
 // Base table 3 (written by the third stage for the new state) becomes buffer 0's table 0.
-__global__ void __launch_bounds__(kBlock) k_base_copy(const DevInstance* __restrict__ insts)
+__global__ void __launch_bounds__(kBlock) k_base_copy(const DevInstance* __restrict__ insts,
+                                                      const int32_t* __restrict__ ilist)
 {
-    const DevInstance& I = insts[blockIdx.y];
+    const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
     if (!I.f32 || !I.flags[1]) return;
     const size_t n = (size_t)I.nr * (I.n0 + I.n1 + I.n2);
     const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1596,9 +1599,9 @@ hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, i
     return hipGetLastError();
 }
 
-hipError_t launch_base_copy(const DevInstance* d, int ninst, int maxnr, int maxng, hipStream_t s)
+hipError_t launch_base_copy(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxng, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_base_copy, dim3((maxnr * maxng + kBlock - 1) / kBlock, ninst), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_base_copy, dim3((maxnr * maxng + kBlock - 1) / kBlock, ninst), dim3(kBlock), 0, s, d, ilist);
     return hipGetLastError();
 }
 
@@ -1633,13 +1636,14 @@ hipError_t launch_rebase(const DevInstance* d, int inst, int nr, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, int ninst, int maxnr, int src, int bsrc, hipStream_t s)
+hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int src, int bsrc,
+                       hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
-    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, src, bsrc);
+    hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, ilist, src, bsrc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, ilist);
     return hipGetLastError();
 }
 
@@ -1693,7 +1697,7 @@ hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
 
 hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, nullptr);
     return hipGetLastError();
 }
 
