@@ -366,6 +366,29 @@ lbe_status plan_groups(lbe_ctx* c)
         }
         c->group_of[k] = g;
     }
+    // a velocity set holding more than a third of the batch's site-velocities is split into two
+    // launch groups (alternate instances), so that the node and projection kernels of one half
+    // overlap the stage kernel of the other
+    {
+        std::vector<double> work(c->groups.size(), 0.0);
+        double total = 0;
+        for (int k = 0; k < c->ninst; k++) {
+            const double w = (double)c->tabs[k].nr * c->tabs[k].nv;
+            work[c->group_of[k]] += w;
+            total += w;
+        }
+        const size_t ng0 = c->groups.size();
+        for (size_t q = 0; q < ng0; q++) {
+            int members = 0;
+            for (int k = 0; k < c->ninst; k++) members += c->group_of[k] == (int)q;
+            if (work[q] <= total / 3 || members < 2) continue;
+            c->groups.push_back(c->groups[q]);
+            const int g2 = (int)c->groups.size() - 1;
+            int idx = 0;
+            for (int k = 0; k < c->ninst; k++)
+                if (c->group_of[k] == (int)q && (idx++ & 1)) c->group_of[k] = g2;
+        }
+    }
     auto total_items = [&]() {
         long tot = 0;
         for (int k = 0; k < c->ninst; k++) {

@@ -63,7 +63,7 @@ def test_autotune_keeps_results_to_rounding():
     b.step(3)
     rep = a.autotune(reps=2)
     print("autotune", rep, flush=True)
-    assert len(rep) == 3
+    assert 3 <= len(rep) <= 6  # three velocity sets; a large one is split in two
     for r in rep:
         assert r["tile_nodes"] in (4, 8, 16, 32, 64) and r["ms"] > 0 and r["ms"] <= r["ms_before"]
     a.step(20)
