@@ -71,12 +71,14 @@ def workload(name: str, n_inst: int, precision: str = "fp64"):
                 f"{'FP32 f / FP64 moments' if precision == 'fp32' else 'FP64'}")
         prec = 1 if precision == "fp32" else 0
         return [dict(W.solver_params(p), precision=prec) for p in ps], desc
+    prec = 1 if precision == "fp32" else 0
+    tag = ", FP32 f / FP64 moments" if precision == "fp32" else ", FP64"
     if name == "fourier_sph":
-        return [W.FOURIER_SPH] * n_inst, f"spherical Fourier (Nr 256, 32x12x12 velocities) x {n_inst}"
+        return [dict(W.FOURIER_SPH, precision=prec)] * n_inst, f"spherical Fourier (Nr 256, 32x12x12 velocities) x {n_inst}{tag}"
     if name == "fourier_cyl":
-        return [W.FOURIER_CYL] * n_inst, f"cylindrical Fourier (Nr 128, 16x8x4 velocities) x {n_inst}"
+        return [dict(W.FOURIER_CYL, precision=prec)] * n_inst, f"cylindrical Fourier (Nr 128, 16x8x4 velocities) x {n_inst}{tag}"
     if name == "couette":
-        return [W.COUETTE_SMALL] * n_inst, f"cylindrical Couette (Nr 32, 8x4x2 velocities) x {n_inst}"
+        return [dict(W.COUETTE_SMALL, precision=prec)] * n_inst, f"cylindrical Couette (Nr 32, 8x4x2 velocities) x {n_inst}{tag}"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -98,7 +100,7 @@ def cpu_baseline(params, budget_s: float, threads: int = 0):
         for p in params:
             if time.perf_counter() - t_start > budget_s:
                 break
-            s = oracle.Solver(p)
+            s = oracle.Solver({k: v for k, v in p.items() if k != "precision"})  # the oracle is FP64
             nv = s.nv
             steps = 0
             t0 = time.perf_counter()
@@ -191,6 +193,50 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
     }
 
 
+def solve_only(args) -> None:
+    """Cold steady solve (rest start, residual 1e-8 checked every 50 steps) of the workload; with
+    FP32 storage the solve stops at its residual floor and is continued with FP64 storage (the
+    polish); prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2403_15051_amd import lbe
+
+    params, desc = workload(args.workload, max(1, args.instances), args.precision)
+    s = lbe.Solver(params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if args.precision == "fp32":
+        # rounds of 5000 steps until 1e-8 or until the residual stops falling (its FP32 floor)
+        steps = np.zeros(len(params), dtype=np.int64)
+        hist = []
+        while steps.max() < 400000:
+            st, taken, res = s.run_to_steady(1e-8, 5000, 50)
+            steps += taken
+            hist.append(float(res.max()))
+            print(f"[bench] fp32 solve: {int(steps.max())} steps, residual {hist[-1]:.3e}", file=sys.stderr, flush=True)
+            if st == lbe.LBE_OK or (len(hist) > 4 and hist[-1] > 0.8 * hist[-5]):
+                break
+    else:
+        st, steps, res = s.run_to_steady(1e-8, 400000, 50)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = {"workload": desc, "precision": args.precision, "converged": int(((res >= 0) & (res <= 1e-8)).sum()),
+           "steps": steps.tolist(), "residual": res.tolist(), "seconds": t1 - t0}
+    if args.precision == "fp32":
+        # FP64 polish from the FP32 state
+        p64 = [dict(p, precision=0) for p in params]
+        pol = lbe.Solver(p64)
+        for k in range(len(p64)):
+            pol.set_state(k, s.get_state(k))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st2, steps2, res2 = pol.run_to_steady(1e-8, 400000, 50)
+        torch.cuda.synchronize()
+        out["polish"] = {"steps": steps2.tolist(), "residual": res2.tolist(), "seconds": time.perf_counter() - t2}
+    print(json.dumps(out), flush=True)
+
+
 def host_cpu() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -218,6 +264,8 @@ def main():
                     help="storage of f (the sweep is specified with FP32 f and FP64 moments)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-alt", action="store_true", help="skip the FP64-storage comparison run")
+    ap.add_argument("--solve", action="store_true",
+                    help="only time a cold steady solve (residual 1e-8) of the workload and print its steps")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run a plain copy of this size (calibration)")
     args = ap.parse_args()
     if args.copy_bytes:
@@ -233,6 +281,9 @@ def main():
     from paper_2403_15051_amd import lbe
 
     torch.cuda.set_device(0)
+    if args.solve:
+        solve_only(args)
+        return
     params, desc = workload(args.workload, args.instances if args.workload == "sweep" else max(1, args.instances),
                             args.precision)
     print(f"[bench] workload: {desc}", file=sys.stderr, flush=True)
