@@ -320,7 +320,8 @@ int default_tile_nodes()
 }
 
 // Work items of every group: tiles of G.NT consecutive nodes x velocity slices, grouped by launch.
-void build_items(lbe_ctx* c)
+// (only: the instances to include, all when null)
+void build_items(lbe_ctx* c, const std::vector<int32_t>* only = nullptr)
 {
     c->items.clear();
     c->item_off.assign(c->groups.size(), 0);
@@ -329,7 +330,7 @@ void build_items(lbe_ctx* c)
         const StageGroup& G = c->groups[q];
         c->item_off[q] = (int)c->items.size();
         for (int k = 0; k < c->ninst; k++) {
-            if (c->group_of[k] != (int)q) continue;
+            if (c->group_of[k] != (int)q || (only && !(*only)[k])) continue;
             const int nr = c->tabs[k].nr;
             for (int i0 = 0; i0 < nr; i0 += G.NT)
                 for (int sl = 0; sl < G.S; sl++) c->items.push_back({k, i0, std::min(G.NT, nr - i0), sl});
@@ -480,6 +481,45 @@ hipEvent_t next_event(lbe_ctx* c, int* idx)
 }
 
 // Node kernel then stage kernel of one RK stage, with events around each when timing.
+void drop_graphs(lbe_ctx* c);
+
+// Launch plan of the given instances (all when null): stage work items and per-group instance
+// lists, uploaded to the device; the captured graphs are dropped (they hold the old plan).
+hipError_t upload_plan(lbe_ctx* c, const std::vector<int32_t>* only)
+{
+    build_items(c, only);
+    std::vector<int32_t> glist;
+    c->gl_off.clear();
+    c->gl_cnt.clear();
+    c->gl_maxnr.clear();
+    c->gl_maxng.clear();
+    c->gl_f32.clear();
+    for (size_t q = 0; q < c->groups.size(); q++) {
+        c->gl_off.push_back((int)glist.size());
+        int mnr = 0, mng = 0;
+        for (int k = 0; k < c->ninst; k++)
+            if (c->group_of[k] == (int)q && (!only || (*only)[k])) {
+                glist.push_back(k);
+                mnr = std::max(mnr, c->tabs[k].nr);
+                mng = std::max(mng, c->tabs[k].n0 + c->tabs[k].n1 + c->tabs[k].n2);
+            }
+        c->gl_cnt.push_back((int)glist.size() - c->gl_off[q]);
+        c->gl_maxnr.push_back(mnr);
+        c->gl_maxng.push_back(mng);
+        c->gl_f32.push_back(c->groups[q].f32 ? 1 : 0);
+    }
+    drop_graphs(c);
+    hipError_t e = hipSuccess;
+    if (!c->items.empty())
+        e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess && !glist.empty())
+        e = hipMemcpyAsync(c->dev_glist, glist.data(), glist.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
 // FP32-storage instances read src and f^n through base tables bsrc, bfn and write the output's
 // base table bdst (ignored by FP64 instances).
 hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst)
@@ -495,8 +535,9 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
         (void)hipEventRecord(next_event(c, &x), c->stream);
     }
     for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
-        e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an, bs,
-                         rhs, bsrc, bfn, bdst, c->stream);
+        if (c->item_cnt[q] > 0)
+            e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], src, fn, dst, an,
+                             bs, rhs, bsrc, bfn, bdst, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &y), c->stream);
@@ -524,6 +565,7 @@ hipError_t launch_steps_group(lbe_ctx* c, int q, int nsteps, hipStream_t s)
 {
     const int32_t* il = c->dev_glist + c->gl_off[q];
     const int cnt = c->gl_cnt[q], mnr = c->gl_maxnr[q];
+    if (cnt == 0 || c->item_cnt[q] == 0) return hipSuccess;
     // (src, fn, dst, an, bs, src table, f^n table, output table) of the three stages
     struct St {
         int src, fn, dst;
@@ -775,29 +817,11 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     off = align256(off + sizeof(int32_t) * (size_t)n_inst);
     c->rowoff.assign(n_inst + 1, 0);
     for (int k = 0; k < n_inst; k++) c->rowoff[k + 1] = c->rowoff[k] + c->tabs[k].nr;
-    std::vector<int32_t> glist;
-    for (size_t q = 0; q < c->groups.size(); q++) {
-        c->gl_off.push_back((int)glist.size());
-        int mnr = 0, mng = 0;
-        for (int k = 0; k < n_inst; k++)
-            if (c->group_of[k] == (int)q) {
-                glist.push_back(k);
-                mnr = std::max(mnr, c->tabs[k].nr);
-                mng = std::max(mng, c->tabs[k].n0 + c->tabs[k].n1 + c->tabs[k].n2);
-            }
-        c->gl_cnt.push_back((int)glist.size() - c->gl_off[q]);
-        c->gl_maxnr.push_back(mnr);
-        c->gl_maxng.push_back(mng);
-        c->gl_f32.push_back(c->groups[q].f32 ? 1 : 0);
-    }
     if (off > ws_bytes) {
         delete c;
         return LBE_ENOMEM;
     }
-    hipError_t e = hipMemcpyAsync(c->dev_items, c->items.data(), c->items.size() * sizeof(WorkItem),
-                                  hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpy(c->dev_glist, glist.data(), glist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    hipError_t e = upload_plan(c, nullptr);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->dev_rowoff, c->rowoff.data(), c->rowoff.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream);
@@ -1040,10 +1064,12 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
     if (st != LBE_OK) return st;
     int64_t taken = 0;
     bool all = false;
+    int planned = c->ninst;  // instances in the launch plan
+    std::vector<int32_t> act(c->ninst, 1);
     while (taken < max_steps && !all) {
         const int chunk = (int)std::min<int64_t>(check_every, max_steps - taken);
         st = enqueue_chunk(c, chunk, tol, chunk == check_every);
-        if (st != LBE_OK) return st;
+        if (st != LBE_OK) break;
         st = dev_err(c, hipMemcpyAsync(stv.data(), c->dev_status, stv.size() * sizeof(double),
                                        hipMemcpyDeviceToHost, c->stream),
                      "status read");
@@ -1051,15 +1077,30 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
         if (st != LBE_OK) return st;
         taken += chunk;
         all = true;
+        int nact = 0;
         for (int k = 0; k < c->ninst; k++) {
             if (stv[4 * k + 2] != 0) {
                 c->nan_latched = true;
                 c->err = "non-finite state or non-positive density/temperature in instance " + std::to_string(k);
-                return LBE_ENAN;
+                st = LBE_ENAN;
             }
-            if (stv[4 * k + 3] != 0) all = false;
+            act[k] = stv[4 * k + 3] != 0;
+            nact += act[k];
+            if (act[k]) all = false;
+        }
+        if (st != LBE_OK) break;
+        // once half of the planned instances have converged, launch only the others
+        if (nact > 0 && 2 * nact <= planned) {
+            st = dev_err(c, upload_plan(c, &act), "plan");
+            if (st != LBE_OK) break;
+            planned = nact;
         }
     }
+    if (planned < c->ninst) {
+        lbe_status stp = dev_err(c, upload_plan(c, nullptr), "plan");
+        if (st == LBE_OK) st = stp;
+    }
+    if (st != LBE_OK) return st;
     std::fill(c->active.begin(), c->active.end(), 1);
     st = upload_flags(c);
     if (st != LBE_OK) return st;
