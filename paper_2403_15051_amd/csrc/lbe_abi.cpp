@@ -1066,6 +1066,32 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
     bool all = false;
     int planned = c->ninst;  // instances in the launch plan
     std::vector<int32_t> act(c->ninst, 1);
+    // plans with shorter tiles while few work items remain: a tile's nodes are processed in
+    // sequence, so with fewer items than two per compute unit the tile height sets the latency
+    const std::vector<StageGroup> saved = c->groups;
+    bool replanned = false;
+    auto adapt_tiles = [&](const std::vector<int32_t>* only) {
+        for (size_t q = 0; q < c->groups.size(); q++) {
+            auto items_at = [&](int nt) {
+                long n = 0;
+                for (int k = 0; k < c->ninst; k++)
+                    if (c->group_of[k] == (int)q && (!only || (*only)[k]))
+                        n += (long)((c->tabs[k].nr + nt - 1) / nt) * saved[q].S;
+                return n;
+            };
+            int nt = saved[q].NT;
+            while (nt > kMinTileNodes && items_at(nt) < 512) nt /= 2;
+            StageGroup G = saved[q];
+            if (nt != saved[q].NT && layout_group(&G, nt) && G.NT == nt)
+                c->groups[q] = G;
+            else
+                c->groups[q] = saved[q];
+        }
+        replanned = true;
+        return upload_plan(c, only);
+    };
+    st = dev_err(c, adapt_tiles(nullptr), "plan");
+    if (st != LBE_OK) return st;
     while (taken < max_steps && !all) {
         const int chunk = (int)std::min<int64_t>(check_every, max_steps - taken);
         st = enqueue_chunk(c, chunk, tol, chunk == check_every);
@@ -1091,12 +1117,13 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
         if (st != LBE_OK) break;
         // once half of the planned instances have converged, launch only the others
         if (nact > 0 && 2 * nact <= planned) {
-            st = dev_err(c, upload_plan(c, &act), "plan");
+            st = dev_err(c, adapt_tiles(&act), "plan");
             if (st != LBE_OK) break;
             planned = nact;
         }
     }
-    if (planned < c->ninst) {
+    if (replanned) {
+        c->groups = saved;
         lbe_status stp = dev_err(c, upload_plan(c, nullptr), "plan");
         if (st == LBE_OK) st = stp;
     }
