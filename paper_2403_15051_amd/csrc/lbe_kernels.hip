@@ -715,6 +715,13 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         else
             return bload(rfn, vo, row * rowb);
     };
+    // FP32 storage, loads ahead: the raw bits stay in a register until the value is needed (a
+    // conversion right after the load would wait for it there)
+    auto cell_raw = [&](int c, unsigned vo) {
+        return __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0);
+    };
+    auto fn_raw = [&](int row, unsigned vo) { return __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0); };
+    auto as_f64 = [](unsigned bits) { return (double)__builtin_bit_cast(float, bits); };
     const int ng = n0 + n1 + n2;
     // velocity shift of the tile: the velocity of its first node (common to all its slices)
     const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
@@ -977,16 +984,22 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     // base of window row wr (cell i0 - 3 + wr) at the lane's velocity j (FP32 storage)
     auto wbase = [&](int wr, int j) { return sbase[wr * bst + gx0[j]] * sbase[wr * bst + bcol[j]]; };
     double sl[VPT][7], fnv[VPT], Fl[VPT];
+    unsigned rawc[VPT], rawf[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
-#pragma unroll
-        for (int k = 0; k < 7; k++) sl[j][k] = cell(it.i0 - 2 + k, voff[j]);
         if constexpr (F32) {
             // cells i0-2 .. i0+3 now; cell i0+4 (slot 6) is completed at node 0
 #pragma unroll
-            for (int k = 0; k < 6; k++) sl[j][k] += wbase(k + 1, j);
+            for (int k = 0; k < 6; k++) sl[j][k] = cell(it.i0 - 2 + k, voff[j]) + wbase(k + 1, j);
+            sl[j][6] = 0.0;
+            rawc[j] = cell_raw(it.i0 + 4, voff[j]);
+            rawf[j] = need_fn ? fn_raw(it.i0, voff[j]) : 0u;
+            fnv[j] = 0.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 7; k++) sl[j][k] = cell(it.i0 - 2 + k, voff[j]);
+            fnv[j] = need_fn ? fn_load(it.i0, voff[j]) : 0.0;
         }
-        fnv[j] = need_fn ? fn_load(it.i0, voff[j]) : 0.0;
         const double pr6 = prv[j] * (1.0 / 6);
         if (pos) {
             if (it.i0 == 0) {
@@ -1145,8 +1158,11 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 double o = fma(fmb, Pc, -(A + Iv));
                 o = fma(cf[SC_CF], sl[j][(P + 2) % 7], o);
                 if (need_fn) {
-                    double fv = fnv[j];
-                    if constexpr (F32) fv += fbase[t * bst + gx0[j]] * fbase[t * bst + bcol[j]];
+                    double fv;
+                    if constexpr (F32)
+                        fv = as_f64(rawf[j]) + fbase[t * bst + gx0[j]] * fbase[t * bst + bcol[j]];
+                    else
+                        fv = fnv[j];
                     o = fma(an, fv, o);
                 }
                 if (valid[j]) {
@@ -1167,11 +1183,16 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             if (t + 1 < it.nt) {
 #pragma unroll
                 for (int j = 0; j < VPT; j++) {
-                    // FP32 storage: complete cell i + 4 (loaded during the previous node)
-                    if constexpr (F32) sl[j][(P + 6) % 7] += wbase(t + 7, j);
                     Fl[j] = Fr[j];
-                    sl[j][P % 7] = cell(i + 5, voff[j]);
-                    fnv[j] = need_fn ? fn_load(i + 1, voff[j]) : 0.0;
+                    if constexpr (F32) {
+                        // complete cell i + 4 (loaded during the previous node), load cell i + 5
+                        sl[j][(P + 6) % 7] = as_f64(rawc[j]) + wbase(t + 7, j);
+                        rawc[j] = cell_raw(i + 5, voff[j]);
+                        rawf[j] = need_fn ? fn_raw(i + 1, voff[j]) : 0u;
+                    } else {
+                        sl[j][P % 7] = cell(i + 5, voff[j]);
+                        fnv[j] = need_fn ? fn_load(i + 1, voff[j]) : 0.0;
+                    }
                 }
             }
         }
