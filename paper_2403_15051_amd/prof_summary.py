@@ -8,9 +8,9 @@ usage:
   python -m paper_2403_15051_amd.prof_summary pmc <counter_collection.csv> <kernel substring> [--last N]
       per-dispatch average of each counter over the matching dispatches, and the per-stage
       total (sum over the workgroup-size groups of one stage).
-  --last N keeps only the last N dispatches of every (kernel, workgroup size) group, e.g. the
-  3 K stage launches of bench.py's final timed pass of K steps (earlier dispatches include the
-  tile autotuner's trial launches).
+  --last N keeps only the last N dispatches of every kernel (by name), e.g. the 3 K G launches of
+  the node, projection and stage kernels in bench.py's final timed pass of K steps over G launch
+  groups (earlier dispatches include the tile autotuner's trial launches).
 """
 from __future__ import annotations
 
@@ -26,13 +26,16 @@ def summarise_trace(db_path: str, title: str = "", last: int = 0) -> str:
     recs = list(cur.execute(
         "select name, workgroup_x, start, duration, grid_x, grid_y, lds_size, vgpr_count, accum_vgpr_count, "
         "sgpr_count, scratch_size from kernels order by start"))
+    if last:
+        by_name = collections.defaultdict(list)
+        for r in recs:
+            by_name[r[0]].append(r)
+        recs = sorted((r for rs in by_name.values() for r in rs[-last:]), key=lambda r: r[2])
     groups = collections.defaultdict(list)
     for r in recs:
         groups[(r[0], r[1])].append(r)
     rows = []
     for (name, wg), rs in groups.items():
-        if last:
-            rs = rs[-last:]
         durs = [r[3] for r in rs]
         rows.append((name, wg, len(rs), sum(durs), sum(durs) / len(rs), max(r[4] for r in rs), max(r[5] for r in rs),
                      max(r[6] for r in rs), max(r[7] for r in rs), max(r[8] for r in rs), max(r[9] for r in rs),
@@ -53,14 +56,17 @@ def summarise_trace(db_path: str, title: str = "", last: int = 0) -> str:
 
 
 def summarise_pmc(csv_path: str, kernel: str, last: int = 0) -> str:
-    rows = list(csv.DictReader(open(csv_path)))
-    per = collections.defaultdict(list)
-    for r in sorted(rows, key=lambda r: int(r.get("Dispatch_Id", 0))):
-        if kernel in r["Kernel_Name"]:
-            wg = r.get("Workgroup_Size", r.get("Workgroup_Size_X", ""))
-            per[(r["Counter_Name"], wg)].append(float(r["Counter_Value"]))
+    rows = [r for r in csv.DictReader(open(csv_path)) if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
     if last:
-        per = {k: v[-last:] for k, v in per.items()}
+        by = collections.defaultdict(list)
+        for r in rows:
+            by[(r["Kernel_Name"], r["Counter_Name"])].append(r)
+        rows = [r for rs in by.values() for r in rs[-last:]]
+    per = collections.defaultdict(list)
+    for r in rows:
+        wg = r.get("Workgroup_Size", r.get("Workgroup_Size_X", ""))
+        per[(r["Counter_Name"], wg)].append(float(r["Counter_Value"]))
     out = ["| counter | wg | dispatches | average per dispatch |", "|---|---|---|---|"]
     totals = collections.defaultdict(float)
     for (cname, wg), v in sorted(per.items()):
