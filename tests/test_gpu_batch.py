@@ -112,3 +112,32 @@ def test_run_to_steady_reports_not_converged_and_partial_chunk():
     assert st == lbe.LBE_ENOTCONV
     assert steps[0] == 130 and res[0] > 1e-14
     assert g.info()["steps"] == 130
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_full_sweep_sampled_instances_match_oracle(precision, tol):
+    """The 256-instance sweep at its full size, in the configuration bench.py times (autotuned
+    tiles, captured steps, forked group chains): after 3 steps, the smallest, the largest and the
+    first instance match the oracle run on their own (FP64 1e-12 normwise on f; FP32 storage 1e-5
+    on the profiles)."""
+    ps, _ = workloads.sweep(256)
+    ps = [dict(workloads.solver_params(p), precision=precision) for p in ps]
+    g = lbe.Solver(ps)
+    g.autotune(reps=1)
+    g.step(3)
+    g.sync()
+    size = [p["nr"] * (2 * p["q_radial"]) * p["q_t1"] * p["q_t2"] for p in ps]
+    for k in sorted({0, int(np.argmin(size)), int(np.argmax(size))}):
+        p = {kk: v for kk, v in ps[k].items() if kk != "precision"}
+        o = oracle.Solver(p)
+        o.step(3)
+        if precision == 0:
+            f_o = o.get_f()
+            e = nrel(g.get_state(k), f_o)
+            print("sweep instance", k, size[k], "f", e, flush=True)
+            assert e <= tol, k
+        mg, mo = g.moments(k), o.moments()
+        for f in ("n", "T"):
+            e = nrel(mg[f], mo[f])
+            print("sweep instance", k, f, e, flush=True)
+            assert e <= tol, (k, f)
