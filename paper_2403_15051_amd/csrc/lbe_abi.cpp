@@ -171,8 +171,9 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
-    size_t b = align256((size_t)(n0 + n1 + n2) * D) + 3 * align256((nr + 4) * nv * D) + align256(nr * nv * D) + align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) +
-               align256(nr * 5 * D) + 3 * 256;
+    const size_t E = p.precision == LBE_FP32_STORE ? sizeof(float) : D;  // stored value of f
+    size_t b = align256((size_t)(n0 + n1 + n2) * D) + 3 * align256((nr + 4) * nv * E) + align256(nr * nv * D) +
+               align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) + align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
     b += 3 * align256((size_t)std::max(n0, std::max(n1, n2)) * N * D);
