@@ -1101,7 +1101,7 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
                                        hipMemcpyDeviceToHost, c->stream),
                      "status read");
         if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
-        if (st != LBE_OK) return st;
+        if (st != LBE_OK) break;
         taken += chunk;
         all = true;
         int nact = 0;
