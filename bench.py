@@ -123,7 +123,7 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
     """Steady solves/s at residual tol on held-out instances of the warm-start generator (seed
     240315053): (1) plain cold, one instance at a time from rest (a sample of n_plain instances);
     (2) batched cold, all instances in one context from rest; (3) batched warm: network inference,
-    the judge and the solve.  Rates count converged instances per wall second of the solve (tables
+    the one-step residual test of the prediction against the rest start, and the solve.  Rates count converged instances per wall second of the solve (tables
     built and resident before the clock starts)."""
     import numpy as np
     import torch
