@@ -200,6 +200,27 @@ __device__ inline double f_at(const DevInstance& I, int buf, int tab, int row, i
     return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
 }
 
+// The same with the velocity's axis indices already known.
+__device__ inline double f_at3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2)
+{
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
+    if (!I.f32) return I.f[buf][e];
+    const double* b = base_row(I, tab, row);
+    return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
+}
+
+__device__ inline void f_put3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2,
+                              double val)
+{
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
+    if (!I.f32) {
+        I.f[buf][e] = val;
+        return;
+    }
+    const double* b = base_row(I, tab, row);
+    ((float*)I.f[buf])[e] = (float)(val - b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]));
+}
+
 __device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, int v, double val)
 {
     const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
@@ -265,20 +286,22 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     const int bx = blockIdx.x;
     __shared__ double red[16 * 4];
     if (bx >= nchunks + 2) return;
-    auto F = [&](int row, int v) { return f_at(I, src, bsrc, row, v); };
+    const int n0 = I.n0, n1 = I.n1;
 
     if (bx >= nchunks) {
         // Wall density of diffuse reflection: n_w = - sum_{leaving} p_r f_hat / sum_{entering} p_r g_w.
         const int left = bx == nchunks;
         double acc[1] = {0};
         for (int v = threadIdx.x; v < I.nv; v += kBlock) {
-            const double pr = I.p0[v % I.n0];
+            const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+            auto F = [&](int row) { return f_at3(I, src, bsrc, row, v, i0, i1, i2); };
+            const double pr = I.p0[i0];
             if (left && pr < 0) {
-                const double f0 = F(0, v), f1 = F(1, v), f2 = F(2, v);
+                const double f0 = F(0), f1 = F(1), f2 = F(2);
                 const double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
                 acc[0] += pr * weno5(f2, f1, f0, gm1, gm2);
             } else if (!left && pr > 0) {
-                const double a = F(nr - 1, v), b = F(nr - 2, v), c = F(nr - 3, v);
+                const double a = F(nr - 1), b = F(nr - 2), c = F(nr - 3);
                 const double gp1 = 3 * a - 3 * b + c, gp2 = 6 * a - 8 * b + 3 * c;
                 acc[0] += pr * weno5(c, b, a, gp1, gp2);
             }
@@ -290,29 +313,31 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // state buffers hold on each side): n_w g_w for entering velocities, the quadratic
         // extrapolation of the three nearest cells for leaving ones
         for (int v = threadIdx.x; v < I.nv; v += kBlock) {
-            const double pr = I.p0[v % I.n0];
+            const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+            auto F = [&](int row) { return f_at3(I, src, bsrc, row, v, i0, i1, i2); };
+            const double pr = I.p0[i0];
             if (left) {
                 double g1, g2;
                 if (pr > 0) {
                     g1 = g2 = nw * I.gwl[v];
                 } else {
-                    const double f0 = F(0, v), f1 = F(1, v), f2 = F(2, v);
+                    const double f0 = F(0), f1 = F(1), f2 = F(2);
                     g1 = 3 * f0 - 3 * f1 + f2;
                     g2 = 6 * f0 - 8 * f1 + 3 * f2;
                 }
-                f_put(I, src, bsrc, -1, v, g1);
-                f_put(I, src, bsrc, -2, v, g2);
+                f_put3(I, src, bsrc, -1, v, i0, i1, i2, g1);
+                f_put3(I, src, bsrc, -2, v, i0, i1, i2, g2);
             } else {
                 double g1, g2;
                 if (pr < 0) {
                     g1 = g2 = nw * I.gwr[v];
                 } else {
-                    const double a = F(nr - 1, v), b = F(nr - 2, v), c = F(nr - 3, v);
+                    const double a = F(nr - 1), b = F(nr - 2), c = F(nr - 3);
                     g1 = 3 * a - 3 * b + c;
                     g2 = 6 * a - 8 * b + 3 * c;
                 }
-                f_put(I, src, bsrc, nr, v, g1);
-                f_put(I, src, bsrc, nr + 1, v, g2);
+                f_put3(I, src, bsrc, nr, v, i0, i1, i2, g1);
+                f_put3(I, src, bsrc, nr + 1, v, i0, i1, i2, g2);
             }
         }
         return;
