@@ -151,3 +151,33 @@ def test_nan_state_is_detected_and_latched():
     g.set_state(0, oracle.Solver(p).get_f())  # a finite state clears the latch
     g.step(2)
     g.sync()
+
+
+def kn_for_confinement(eta0: float, C: float) -> float:
+    chi = (2 - eta0) / (2 * (1 - eta0) ** 3)
+    return 1.0 / (6 * np.sqrt(2.0) * eta0 * chi * C)
+
+
+@pytest.mark.parametrize("name,p,steps", [
+    # the largest grid with a large velocity set (2 x 16 x 16 x 8 = 4096 velocities, Nr 1024)
+    ("max size", dict(workloads.FOURIER_CYL, nr=1024, q_radial=16, q_t1=16, q_t2=8), 2),
+    # sigma close to L: the averaged-density band spans the whole domain
+    ("C = 1.1", dict(workloads.COUETTE_SMALL, nr=40, q_t2=4, eta0=0.2, kn=kn_for_confinement(0.2, 1.1)), 20),
+    # nearly dilute gas
+    ("eta0 = 1e-4", dict(workloads.FOURIER_CYL, nr=24, q_radial=4, q_t1=4, q_t2=4, eta0=1e-4, kn=0.1), 20),
+    # nearly free-molecular gas, sphere
+    ("Kn = 10", dict(workloads.FOURIER_SPH, nr=20, q_radial=6, q_t1=6, q_t2=6, eta0=0.01, kn=10.0), 20),
+    # smallest grid, order-2 transverse axes
+    ("nr = 8", dict(workloads.COUETTE_SMALL, nr=8, q_radial=2, q_t1=2, q_t2=2, n_expand=(1, 1, 1)), 50),
+])
+def test_edge_cases_match_oracle(name, p, steps):
+    print("case", name, flush=True)
+    o = oracle.Solver(p)
+    g = lbe.Solver(p)
+    o.step(steps)
+    g.step(steps)
+    g.sync()
+    e = nrel(g.get_state(), o.get_f())
+    print(name, "f", e, flush=True)
+    assert e <= TOL
+    compare_profiles(g.moments(), o.moments(), ctx=name)
