@@ -1,4 +1,4 @@
-// Device kernels of liblbe (gfx950, FP64 state).
+// Device kernels of liblbe (gfx950; FP64 arithmetic, f stored in FP64 or as FP32 deviations).
 //
 // One RK stage of every instance is three launches:
 //   k_node  - per-node coefficients from the moment sums of the stage input (eqs. (macro_def),
