@@ -45,6 +45,8 @@ __device__ inline float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
 // B(k, n) = B[k sbk + n sbn].  Tile 64 x 64 per workgroup of four waves, each wave 32 x 32 as
 // 2 x 2 MFMA tiles of 16 x 16; K staged in LDS 32 at a time (zero-filled past M, N, K).
 // Epilogues: store; + bias then SiLU (pre-activation to Zout); + bias; times SiLU'(Zin).
+// With gridDim.z > 1 (plain store only) workgroup z sums the z-th of gridDim.z K ranges into
+// C + z M ldc, to be summed by k_splitk_sum.
 template <bool BF16, int EPI>
 __global__ void __launch_bounds__(256)
     k_gemm(int M, int N, int K, const float* __restrict__ A, long sam, long sak, const float* __restrict__ B,
@@ -62,16 +64,19 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     const bool a_kfast = sak == 1, b_kfast = sbk == 1;
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kper = ((K + gridDim.z - 1) / gridDim.z + BK - 1) / BK * BK;
+    const int kbeg = blockIdx.z * kper, kend = min(K, kbeg + kper);
+    if (gridDim.z > 1) C += (long)blockIdx.z * M * ldc;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
         for (int e = tid; e < BM * BK; e += 256) {
             // walk the staged tile along whichever index is contiguous in memory
             int r, kk;
             if (a_kfast) { r = e / BK; kk = e % BK; } else { kk = e / BM; r = e % BM; }
             const int m = m0 + r, k = k0 + kk;
-            As[r][kk] = (m < M && k < K) ? A[(long)m * sam + (long)k * sak] : 0.f;
+            As[r][kk] = (m < M && k < kend) ? A[(long)m * sam + (long)k * sak] : 0.f;
             if (b_kfast) { r = e / BK; kk = e % BK; } else { kk = e / BN; r = e % BN; }
             const int n = n0 + r, k2 = k0 + kk;
-            Bs[r][kk] = (n < N && k2 < K) ? B[(long)k2 * sbk + (long)n * sbn] : 0.f;
+            Bs[r][kk] = (n < N && k2 < kend) ? B[(long)k2 * sbk + (long)n * sbn] : 0.f;
         }
         __syncthreads();
         if constexpr (BF16) {
@@ -132,6 +137,17 @@ __global__ void __launch_bounds__(256)
                 }
                 C[o] = v;
             }
+}
+
+// C[m][n] = sum over z < nz of P[z][m][n] (fixed order), P of row stride N.
+__global__ void __launch_bounds__(256) k_splitk_sum(int M, int N, int nz, const float* __restrict__ P,
+                                                    float* __restrict__ C, int ldc)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= M * N) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; z++) s += P[(long)z * M * N + e];
+    C[(long)(e / N) * ldc + e % N] = s;
 }
 
 // out[n] = sum over rows of D[m][n] (fixed order: four interleaved row groups, then their sum).
@@ -210,6 +226,8 @@ __global__ void __launch_bounds__(256) k_gather(int64_t N, uint64_t a, uint64_t 
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int kMaxSplit = 8;
+
 uint64_t splitmix64(uint64_t& s)
 {
     uint64_t z = (s += 0x9E3779B97F4A7C15ull);
@@ -237,6 +255,7 @@ struct lbe_mlp {
     float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
     float *Z[4] = {}, *H[4] = {};
     float *Y = nullptr, *dY = nullptr, *dA = nullptr, *dB = nullptr, *Xb = nullptr, *Tb = nullptr;
+    float* split = nullptr;  // partial sums of split-K products [kMaxSplit][256][256]
     double* loss = nullptr;
     double out_mean[kOut] = {0, 0, 0, 0, 0};
     double out_scale[kOut] = {1, 1, 1, 1, 1};
@@ -250,7 +269,8 @@ size_t mlp_bytes(int rows)
 {
     const size_t F = sizeof(float), R = (size_t)rows;
     return 4 * a256(kParams * F) + 8 * a256(R * kHid * F) + 2 * a256(R * kOut * F) + 2 * a256(R * kHid * F) +
-           a256(R * kIn * F) + a256(R * kOut * F) + a256(2 * sizeof(double));
+           a256(R * kIn * F) + a256(R * kOut * F) + a256(2 * sizeof(double)) +
+           a256((size_t)kMaxSplit * kHid * kHid * F);
 }
 
 lbe_status merr(lbe_mlp* m, hipError_t e, const char* what)
@@ -262,9 +282,9 @@ lbe_status merr(lbe_mlp* m, hipError_t e, const char* what)
 
 template <bool BF16, int EPI>
 hipError_t gemm_t(hipStream_t s, int M, int N, int K, const float* A, long sam, long sak, const float* B, long sbk,
-                  long sbn, float* C, int ldc, const float* bias, float* Zout, const float* Zin)
+                  long sbn, float* C, int ldc, const float* bias, float* Zout, const float* Zin, int nz = 1)
 {
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz);
     hipLaunchKernelGGL((k_gemm<BF16, EPI>), grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias,
                        Zout, Zin);
     return hipGetLastError();
@@ -276,6 +296,20 @@ hipError_t gemm(const lbe_mlp* m, hipStream_t s, int epi, int M, int N, int K, c
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const bool bf = m->gemm == LBE_GEMM_BF16;
+    // long-K products with few output tiles (the weight gradients) are split over K
+    const int tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+    int nz = 1;
+    if (epi == EPI_STORE && tiles < 64 && (size_t)M * N <= (size_t)kHid * kHid)
+        nz = std::max(1, std::min(kMaxSplit, K / 256));
+    if (nz > 1) {
+        hipError_t e = bf ? gemm_t<true, EPI_STORE>(s, M, N, K, A, sam, sak, B, sbk, sbn, m->split, N, nullptr,
+                                                     nullptr, nullptr, nz)
+                          : gemm_t<false, EPI_STORE>(s, M, N, K, A, sam, sak, B, sbk, sbn, m->split, N, nullptr,
+                                                      nullptr, nullptr, nz);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_splitk_sum, dim3((M * N + 255) / 256), dim3(256), 0, s, M, N, nz, m->split, C, ldc);
+        return hipGetLastError();
+    }
 #define LBE_GEMM_CASE(E)                                                                                   \
     case E:                                                                                                \
         return bf ? gemm_t<true, E>(s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, Zout, Zin)         \
@@ -418,6 +452,7 @@ lbe_status lbe_mlp_init(int32_t max_rows, int32_t gemm_kind, void* device_ws, si
     m->Xb = (float*)take(R * kIn * F);
     m->Tb = (float*)take(R * kOut * F);
     m->loss = (double*)take(2 * sizeof(double));
+    m->split = (float*)take((size_t)kMaxSplit * kHid * kHid * F);
     hipError_t e = hipMemsetAsync(device_ws, 0, mlp_bytes(max_rows), m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) {

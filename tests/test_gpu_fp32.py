@@ -173,3 +173,17 @@ def test_steady_state_fp32_vs_oracle(name, p):
     st64, steps64, _ = g64.run_to_steady(1e-8, 400000, 50)
     assert st64 == lbe.LBE_OK and steps64[0] == steps_o
     check(g64.moments(), mo, name + " fp64", tol=1e-12)
+
+
+def test_warm_start_rejects_fp32_storage():
+    g = lbe.Solver(f32(dict(W.COUETTE_SMALL, nr=12)))
+    net = lbe.Mlp(max_rows=64, gemm=lbe.GEMM_BF16, seed=1)
+    with pytest.raises(lbe.LbeError) as e:
+        g.warm_start(net)
+    assert e.value.status == lbe.LBE_ESTATE
+    prof = W.smooth_profile(12, 1)
+    with pytest.raises(lbe.LbeError) as e:
+        g.set_init_moments(0, prof)
+    assert e.value.status == lbe.LBE_ESTATE
+    g.step(5)  # the context is still usable
+    g.sync()

@@ -48,12 +48,14 @@ def layer_slices():
     return out
 
 
-@pytest.mark.parametrize("gemm,tol", [(lbe.GEMM_FP32, 1e-5), (lbe.GEMM_BF16, 1e-2)])
-def test_forward_and_gradients_match_reference(gemm, tol):
-    rows = 300  # several 64-row tiles and a ragged tail
+@pytest.mark.parametrize("gemm,tol,rows", [(lbe.GEMM_FP32, 1e-5, 300), (lbe.GEMM_BF16, 1e-2, 300),
+                                           (lbe.GEMM_FP32, 1e-5, 1030)])
+def test_forward_and_gradients_match_reference(gemm, tol, rows):
+    """300 rows: several 64-row tiles and a ragged tail; 1030 rows: the weight gradients are split
+    over four K ranges (the last one ragged) and summed in a fixed order."""
     p = W.mlp_params(21)
     X, T = W.mlp_batch(22, rows)
-    net = lbe.Mlp(max_rows=512, gemm=gemm)
+    net = lbe.Mlp(max_rows=2048, gemm=gemm)
     net.set_params(p)
     bf = gemm == lbe.GEMM_BF16
     Yo, _ = M.forward(p, X, use_bf16=bf)
