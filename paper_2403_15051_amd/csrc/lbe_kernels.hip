@@ -961,6 +961,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         };
         fill(sbase, it.nt + 6, it.i0 - 3, bsrc);
         if (need_fn) fill(fbase, it.nt, it.i0, bfn);
+        // (each thread reads the factors it computed itself above, so no barrier is needed here)
         if (!rhs && it.slice == 0)
             for (int e = tid; e < it.nt * ng; e += B) {
                 const int t = e / ng, k = e % ng;
