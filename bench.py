@@ -51,18 +51,22 @@ def measured_traffic(precision: str):
 
 
 def copy_calibration(nbytes: int, reps: int) -> None:
-    """A plain device-to-device copy of nbytes (reads nbytes, writes nbytes), for scaling the
-    HBM counters."""
+    """A plain device-to-device copy of nbytes (reads nbytes, writes nbytes), for scaling the HBM
+    counters; also reports its bandwidth (read + write bytes per second), the achievable HBM rate."""
     import torch
 
     torch.cuda.set_device(0)
     x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
+    y.copy_(x)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for _ in range(reps):
         y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps, "seconds_per_copy": dt,
+                      "read_plus_write_GBps": 2 * nbytes / dt / 1e9}), flush=True)
 
 
 def workload(name: str, n_inst: int, precision: str = "fp64"):
