@@ -93,7 +93,9 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
 
 /* Enqueue nsteps full TVD-RK3 steps of every instance on the context's stream (async).  The
  * launches of one step are captured once into a HIP graph and replayed (set LBE_GRAPH=0 in the
- * environment before lbe_init to launch them one by one). */
+ * environment before lbe_init to launch them one by one); instances sharing a velocity set form a
+ * launch group, and the groups' launch chains run on forked streams joined back into the
+ * context's stream.  FP32-storage instances get their total mass restored every 50 steps. */
 lbe_status lbe_step(lbe_ctx* c, int64_t nsteps);
 
 /* Wait for the stream; returns LBE_ENAN if the device flagged a non-finite state. */
@@ -111,7 +113,10 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
  * (n_inst each, may be NULL) receive per-instance steps taken and the last residual.
  * Returns LBE_OK when all converged, LBE_ENOTCONV otherwise.  One check interval (the steps,
  * the residual and the freeze test, all on the device) is one captured HIP graph; the host reads
- * one status array per interval. */
+ * one status array per interval.  Once half of the instances still advancing have converged, the
+ * launches cover only the others, with shorter tiles while few work items remain; results agree
+ * with lbe_step to rounding.  FP32-storage instances get their total mass restored at the start
+ * of every interval. */
 lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t check_every, int64_t* steps_out,
                              double* resid_out);
 
