@@ -236,7 +236,8 @@ __device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, in
 // ------------------------------------------------------------------ moments of a state
 
 // Moment sums of buffer `buf` (base table `tab`) with shift 0 (start-up, lbe_set_state, the warm
-// start); from_scratch reads the FP64 copy in the instance's scratch instead.
+// start, the FP32 mass fix); from_scratch reads the FP64 copy in the instance's scratch instead.
+// only: -1 every instance, k >= 0 instance k alone, -2 the active FP32-storage instances.
 __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restrict__ insts, int buf, int tab,
                                                     int from_scratch, int only)
 {
