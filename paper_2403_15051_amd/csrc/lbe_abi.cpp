@@ -31,6 +31,7 @@ hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chun
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
                         int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst, hipStream_t s);
 hipError_t set_stage_smem_limit();
+hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ninst, const StageGroup& G, hipStream_t s);
 hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s);
 hipError_t launch_warm_profile_net(const DevInstance* d, const int32_t* rowoff, int ninst, int r0, int rows,
                                    float* X, const float* Y, const double* mean, const double* scale,
@@ -112,10 +113,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t f[3], mom, node, snap, resid, flags, nw, scratch;
     size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
+    size_t simg;
     size_t total;
 };
 
-Layout make_layout(const InstanceTables& t, int nslices, size_t base)
+Layout make_layout(const InstanceTables& t, int nslices, size_t img_doubles, size_t base)
 {
     Layout L;
     size_t o = base;
@@ -161,8 +163,25 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t base)
     L.wb = take(t.wb.size() * D);
     L.gwl = take(t.nv * D);
     L.gwr = take(t.nv * D);
+    L.simg = take(img_doubles * D);
     L.total = o;
     return L;
+}
+
+// Doubles of the stage kernel's image of one slice when the velocity set is not sliced
+// (layout_group's regions K1 .. p values, then the polynomials and weights at the largest
+// order); every region shrinks or stays as the slices grow, so nslices times the sliced size
+// never exceeds n2 times this.
+size_t stage_image_bound(int n0, int n1, int n2, bool sph)
+{
+    auto r4 = [](int x) { return (size_t)(x + 3) / 4 * 4; };
+    auto r16 = [](int x) { return (size_t)(x + 15) / 16 * 16; };
+    const size_t n0p = r16(n0), n1p = r16(n1), n2p = r16(n2), nc16 = r16(n1 * n2), ncp16 = sph ? r16(n0 * n1) : 0;
+    const size_t nTall = nc16 / 16 + (n0p / 16) * (nc16 / 16) + (size_t)n2 * (n1p / 16) * (n0p / 16) +
+                         (sph ? (n2p / 16) * (ncp16 / 16) : 0);
+    return n0p * (r4(n0) + 1) + n1p * (r4(n1) + 1) + (sph ? n2p * (r4(n2) + 1) : 0) + nc16 + n0p + ncp16 +
+           (ncp16 + 1) / 2 + (nTall * kTileDescStride + 1) / 2 + n0p + 2 * nc16 + 1 +
+           (size_t)(n0 + n1 + n2) * (kMaxN + 3) + 1;
 }
 
 // Sizes of a layout without building the tables (for lbe_query).
@@ -183,6 +202,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
     b += align256(nr * n2 * sizeof(WorkItem));
     b += 4 * align256(nr * (size_t)(n0 + n1 + n2) * D);
+    b += align256((size_t)n2 * stage_image_bound(n0, n1, n2, p.geometry == LBE_SPH) * D);
     return b + 4096;
 }
 
@@ -231,6 +251,7 @@ bool layout_group(StageGroup* G, int nt0)
     const int nTm = G->ncols16 / 16;
     const int nTall = nTm + (G->n0p / 16) * (G->ncols16 / 16) + G->ns2 * (G->n1p / 16) * (G->n0p / 16) +
                       (sph ? (G->ns2p / 16) * (G->ncp16 / 16) : 0);
+    G->ntiles = nTall;
     // slot order of the MFMA tiles: heaviest first, each into the free slot whose SIMD (slot is
     // run by wave slot % W, on SIMD wave % 4) has the least MFMA work so far
     {
@@ -290,6 +311,13 @@ bool layout_group(StageGroup* G, int nt0)
         o += (G->ncp16 + 1) / 2;
         G->off_tdesc = o;   // ints
         o += (nTall * kTileDescStride + 1) / 2;
+        G->off_pv = o;      // p_r per radial node, p_1 and p_2 per column of the slice
+        o += G->n0p + 2 * G->ncols16;
+        o += (o - G->off_K1) & 1;  // the image is copied two doubles at a time
+        G->img_lds = o - G->off_K1;
+        G->poly_sz = ng * G->pstride + ng;
+        G->poly_sz += G->poly_sz & 1;
+        G->img_sz = G->img_lds + G->poly_sz;
         G->off_y0p = o;
         o += G->n0k * 16;
         G->off_psi = o;
@@ -306,6 +334,13 @@ bool layout_group(StageGroup* G, int nt0)
         o += G->f32 ? (NT + 6) * G->bstride : 0;
         G->off_fb = o;
         o += G->f32 ? NT * G->bstride : 0;
+        if (G->poly_sz <= 2 * G->ib_sz) {
+            G->off_poly = G->off_ibuf;
+        } else {
+            o += o & 1;
+            G->off_poly = o;
+            o += G->poly_sz;
+        }
         G->lds_doubles = o;
         if (o <= kLdsDoubles) return true;
     }
@@ -363,10 +398,15 @@ lbe_status plan_groups(lbe_ctx* c)
             G.geometry = t.prm.geometry;
             G.f32 = t.prm.precision == LBE_FP32_STORE;
             G.S = 1;
+            G.pstride = 1;
             c->groups.push_back(G);
             g = (int)c->groups.size() - 1;
         }
         c->group_of[k] = g;
+        // row stride of the expansion polynomials in the stage kernel's LDS: the largest order
+        // of the group plus one, odd
+        const int nmax = std::max(t.ax[0].N, std::max(t.ax[1].N, t.ax[2].N)) + 1;
+        c->groups[g].pstride = std::max(c->groups[g].pstride, nmax | 1);
     }
     // a velocity set holding more than a third of the batch's site-velocities is split into two
     // launch groups (alternate instances), so that the node and projection kernels of one half
@@ -828,8 +868,13 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
                            c->stream);
     for (int k = 0; k < n_inst && e == hipSuccess; k++) {
         const InstanceTables& t = c->tabs[k];
-        const int nsl = c->groups[c->group_of[k]].S;
-        Layout L = make_layout(t, nsl, off);
+        const StageGroup& Gk = c->groups[c->group_of[k]];
+        const int nsl = Gk.S;
+        if ((size_t)nsl * Gk.img_sz > (size_t)t.n2 * stage_image_bound(t.n0, t.n1, t.n2, t.prm.geometry == LBE_SPH)) {
+            delete c;
+            return LBE_ENOMEM;
+        }
+        Layout L = make_layout(t, nsl, (size_t)nsl * Gk.img_sz, off);
         if (L.total > ws_bytes) {
             delete c;
             return LBE_ENOMEM;
@@ -895,6 +940,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.wb = (const double*)(ws + L.wb);
         d.gwl = (const double*)(ws + L.gwl);
         d.gwr = (const double*)(ws + L.gwr);
+        d.simg = (double*)(ws + L.simg);
         if (e == hipSuccess) e = put(ws, L.p0, t.ax[0].p, c->stream);
         if (e == hipSuccess) e = put(ws, L.p1, t.ax[1].p, c->stream);
         if (e == hipSuccess) e = put(ws, L.p2, t.ax[2].p, c->stream);
@@ -947,6 +993,11 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         e = hipMemcpyAsync(c->dev_desc, c->host_desc.data(), sizeof(DevInstance) * n_inst, hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = set_stage_smem_limit();
+    // constant LDS images of the stage kernel (tables and tile descriptors per slice); the tile
+    // height never moves them, so they are built once
+    for (size_t q = 0; q < c->groups.size() && e == hipSuccess; q++)
+        if (c->gl_cnt[q] > 0)
+            e = launch_stage_image(c->dev_desc, c->dev_glist + c->gl_off[q], c->gl_cnt[q], c->groups[q], c->stream);
 
     if (e != hipSuccess) {
         st = dev_err(c, e, "lbe_init upload");

@@ -98,6 +98,7 @@ struct DevInstance {
     double* nw;             // [2] wall densities of the current stage
     double* scratch;        // [nr][nv] rhs output (lbe_rhs); staging of lbe_set_init_moments
     const double* rest;     // [n0 + n1 + n2] equilibrium factors at rest (n = 1, u = 0, T = 1)
+    double* simg;           // [nslices][img_sz] constant part of the stage kernel's LDS per slice
 };
 
 // One unit of stage-kernel work: a tile of consecutive nodes of one instance, one velocity slice.
@@ -120,8 +121,14 @@ struct StageGroup {
                                                          // waves per sign of the radial momentum
     int32_t nperm;                                       // MFMA tiles when perm is used, else 0
     int16_t perm[kMaxTilePerm];                          // logical tile of each launch slot
-    int32_t off_plane, off_op, off_ibuf, off_K1, off_K2a, off_K2b, off_colfac, off_cpinfo, off_tdesc, off_y0p,
-        off_psi, off_coef, off_geq, off_part, lds_doubles;
+    int32_t off_plane, off_op, off_ibuf, off_K1, off_K2a, off_K2b, off_colfac, off_cpinfo, off_tdesc, off_pv,
+        off_y0p, off_psi, off_coef, off_geq, off_part, lds_doubles;
+    int32_t img_sz;    // doubles of the stage image per slice: img_lds, then poly_sz
+    int32_t img_lds;   // its constant LDS part, copied to [off_K1, off_y0p) (even)
+    int32_t poly_sz;   // its set-up part, copied to off_poly: expansion polynomials (stride pstride)
+    int32_t pstride;   // and weights of every factor (even); off_poly is the term buffers when they
+    int32_t off_poly;  // have room (they are written before they are read), else a region of its own
+    int32_t ntiles;    // MFMA tiles per node (moment, d0, d1, d2 tiles)
     int32_t off_sb, off_fb, bstride;  // f32: base factors of the window rows / own rows (stride bstride)
 };
 

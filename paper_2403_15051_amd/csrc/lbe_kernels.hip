@@ -655,106 +655,37 @@ __device__ inline void stage_coefs(const double* nd, const double* geo4, const d
     out[SC_FFAC] = sigma * geo4[2];
 }
 
-// One RK stage (or the bare right-hand side, rhs != 0) for a tile of consecutive nodes x one
-// velocity slice of one instance.
-//
-// Lanes: the first wh waves take the velocities with p_r > 0, the next wh those with p_r < 0
-// (element e of a half: radial index e % Q, column e / Q of the slice), so the upwind
-// direction is uniform per wave.  Each lane keeps, per velocity, a register window of the
-// cells i-2 .. i+3 around the current node i plus one prefetched cell, so every face flux is
-// computed once and every value of f_src is read once (plus a halo per tile).
-//
-// Per node, two phases separated by barriers:
-//   A: FP64 MFMA 16x16x4 tiles over the node's LDS plane P (column stride n0 + 1)
-//        d0 = K1 P (n0 x n0 times n0 x columns), d1 = K2a P_i2 (per i2), d2 = K2b P' (sphere),
-//      each times its momentum and geometry factor into its own plane; the moment sums of the
-//      previous node's output plane O as two chained MFMAs, D1 = O^T Y0 (Y0: powers 0..3 of
-//      y_r per radial node) and D2 = Psi^T D1 (Psi: the transverse factors 1, y1, y2, y1^2,
-//      y2^2, y1 y2, rho, y1 rho, y2 rho with rho = y1^2 + y2^2, per column); the WENO face
-//      flux at i + 1/2;
-//   B: the update of every velocity (one cubic per lane, coefficients from the set-up), the
-//      store to HBM and to O, and the staging of node i+1's plane and prefetches.
-// The moment sums are taken about the tile shift c and written per slice (no atomics; fixed
-// order, so runs are bitwise reproducible).
-// FP32 storage (F32): the buffers hold deviations from the per-node discrete equilibrium of
-// base tables bsrc (src), bfn (f^n); the output is stored as its deviation from this stage's own
-// equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
-// completed one node after their load (the ring slot of cell i + 4), so no load is waited for
-// earlier than in the FP64 path.
-template <int VPT, bool F32>
-__global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
-                                                 const WorkItem* __restrict__ items, const StageGroup G, int src,
-                                                 int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn,
-                                                 int bdst)
+// Stage image of one instance and velocity slice, written to R: the tables the stage kernel
+// copies into LDS.  Its constant part (img_lds doubles) is the image of LDS offsets
+// [off_K1, off_y0p): K1, K2a and (sphere) the slice's rows of K2b padded to the MFMA tiles;
+// lane factors of the contraction tiles: p_1^2 [+ p_2^2] per d0 column, -p_r per radial node
+// (d1) and per d2 column; plane offsets of the d2 columns (i0 + cs i1); the tile descriptors;
+// p_r per radial node and p_1, p_2 per column of the slice.  Its set-up part (poly_sz doubles,
+// read only before the first node) holds the expansion polynomials and weights of the
+// equilibrium factors.  It depends on the tables and the slice only, not on the state or the
+// tile height.
+__device__ void stage_image(const DevInstance& I, const StageGroup& G, int slice, double* R, int tid, int B)
 {
-    extern __shared__ double lds[];
-    const WorkItem it = items[blockIdx.x];
-    const DevInstance& I = insts[it.inst];
-    if (!I.flags[1]) return;
-    const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2, hq = n0 >> 1;
-    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, W = B >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wh = G.wh;
-    const bool pos = wave < wh;
-    const int cs = n0 + 1;  // LDS column stride of the planes
+    const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
     const bool sph = G.geometry == LBE_SPH;
-    const bool need_fn = an != 0.0;
-    const double sigma = rhs ? 1.0 : bs * I.dt, bsv = rhs ? 0.0 : bs;
-    const int k1s = G.n0k + 1, k2as = G.n1k + 1, k2bs = G.n2k + 1;  // odd LDS row strides of K
-    const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
+    const int cs = n0 + 1;
+    const int k1s = G.n0k + 1, k2as = G.n1k + 1, k2bs = G.n2k + 1;
     const int ncol = G.ncols_s;
-    const int c_s0 = it.slice * ncol;  // first global column (i1 + n1 i2) of the slice
-    const int cp0 = sph ? 0 : c_s0;    // first global column held in the plane
-    const int i2s0 = it.slice * G.ns2;
-    const int nTm = G.ncols16 / 16;  // moment tiles (skipped for the bare right-hand side)
-    double* plane = lds + G.off_plane;
-    double* op = lds + G.off_op;
-    double* K1s = lds + G.off_K1;
-    double* K2as = lds + G.off_K2a;
-    double* K2bs = lds + G.off_K2b;
-    double* scoef = lds + G.off_coef;
-    double* sgeq = lds + G.off_geq;
-    double* spart = lds + G.off_part;
-    double* colfac = lds + G.off_colfac;   // d0 column factors, then -p_r per radial node (d1)
+    const int c_s0 = slice * ncol;
+    const int cp0 = sph ? 0 : c_s0;
+    const int i2s0 = slice * G.ns2;
+    const int nTm = G.ncols16 / 16;
+    double* K1s = R;
+    double* K2as = R + (G.off_K2a - G.off_K1);
+    double* K2bs = R + (G.off_K2b - G.off_K1);
+    double* colfac = R + (G.off_colfac - G.off_K1);
     double* nsp = colfac + G.ncols16;
-    double* cpfac = nsp + G.n0p;           // -p_r per d2 column (sphere)
-    int* cpoff = (int*)(lds + G.off_cpinfo);
-    int* tdesc = (int*)(lds + G.off_tdesc);
-    double* y0p = lds + G.off_y0p;
-    double* psi = lds + G.off_psi;
-    constexpr int esz = F32 ? 4 : 8;  // bytes per stored value
-    const int rowb = nv * esz;
-    // f_src with its two ghost rows on each side: cell c at byte row offset (c + 2) rowb
-    const rsrc_t rf = make_rsrc((const char*)I.f[src] - 2 * (size_t)rowb, (size_t)(nr + 4) * rowb);
-    const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
-    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * (rhs ? nv * 8 : rowb));
-    // stored value of cell c (F32: the deviation only; its base is added separately)
-    auto cell = [&](int c, unsigned vo) {
-        if constexpr (F32)
-            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0));
-        else
-            return bload(rf, vo, (min(c, nr + 1) + 2) * rowb);
-    };
-    auto fn_load = [&](int row, unsigned vo) {
-        if constexpr (F32)
-            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0));
-        else
-            return bload(rfn, vo, row * rowb);
-    };
-    // FP32 storage, loads ahead: the raw bits stay in a register until the value is needed (a
-    // conversion right after the load would wait for it there)
-    auto cell_raw = [&](int c, unsigned vo) {
-        return __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0);
-    };
-    auto fn_raw = [&](int row, unsigned vo) { return __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0); };
-    auto as_f64 = [](unsigned bits) { return (double)__builtin_bit_cast(float, bits); };
-    const int ng = n0 + n1 + n2;
-    // velocity shift of the tile: the velocity of its first node (common to all its slices)
-    const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
-    const double csh[3] = {ndc[NF_U0], ndc[NF_U1], ndc[NF_U2]};
-
-    // ---- set-up.  The planes are zeroed first: the MFMA tiles read their padding.
-    for (int e = tid; e < G.off_ibuf - G.off_plane; e += B) plane[e] = 0.0;
+    double* cpfac = nsp + G.n0p;
+    int* cpoff = (int*)(R + (G.off_cpinfo - G.off_K1));
+    int* tdesc = (int*)(R + (G.off_tdesc - G.off_K1));
+    double* pv0 = R + (G.off_pv - G.off_K1);
+    double* pc1 = pv0 + G.n0p;
+    double* pc2 = pc1 + G.ncols16;
     for (int e = tid; e < G.n0p * k1s; e += B) {
         const int r = e / k1s, k = e % k1s;
         K1s[e] = (r < n0 && k < n0) ? I.K1[r * n0 + k] : 0.0;
@@ -790,41 +721,6 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             cpoff[e] = ok ? (e % n0) + cs * (e / n0) : 0;
             cpfac[e] = ok ? -I.p0[e % n0] : 0.0;
         }
-    for (int t = tid; t < it.nt; t += B) {
-        const int i = it.i0 + t;
-        stage_coefs(I.node + (size_t)i * kNodeStride, I.geo + 4 * i, csh, sph, sigma, bsv, scoef + t * kCoefStride);
-    }
-    // moment-sum operands: powers of y_r per radial node, transverse factors per column
-    for (int e = tid; e < G.n0k * 16; e += B) {
-        const int r = e >> 4, a = e & 15;
-        double val = 0.0;
-        if (r < n0 && a < 4) {
-            const double y = I.p0[r] - csh[0];
-            val = a == 0 ? 1.0 : a == 1 ? y : a == 2 ? y * y : y * y * y;
-        }
-        y0p[e] = val;
-    }
-    for (int e = tid; e < G.ncols16 * 16; e += B) {
-        const int col = e >> 4, m = e & 15;
-        double val = 0.0;
-        if (col < ncol && m < 9) {
-            const int cg = c_s0 + col;
-            const double y1 = I.p1[cg % n1] - csh[1], y2 = I.p2[cg / n1] - csh[2];
-            const double rho = y1 * y1 + y2 * y2;
-            switch (m) {
-                case 0: val = 1.0; break;
-                case 1: val = y1; break;
-                case 2: val = y2; break;
-                case 3: val = y1 * y1; break;
-                case 4: val = y2 * y2; break;
-                case 5: val = y1 * y2; break;
-                case 6: val = rho; break;
-                case 7: val = y1 * rho; break;
-                default: val = y2 * rho; break;
-            }
-        }
-        psi[e] = val;
-    }
     // tile descriptors: logical tiles are the moment tiles, then d0, d1, d2 tiles; slot s (run
     // by wave s mod W) holds logical tile perm[s], which balances the MFMA work over the SIMDs
     const int nM1 = G.n0p / 16, nN1 = G.ncols16 / 16;
@@ -895,47 +791,148 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             d[TD_OUT] = G.off_ibuf + 2 * cs * ncol;
         }
     }
-    // equilibrium factors of the tile's nodes from their projection coefficients
-    for (int e = tid; e < it.nt * ng; e += B) {
-        const int t = e / ng, k = e % ng;
-        const double* nd = I.node + (size_t)(it.i0 + t) * kNodeStride;
-        const double *cf, *poly, *wt;
-        int N, kk;
-        if (k < n0) {
-            cf = nd + (I.p0[k] > 0 ? NF_IPLUS : NF_IMINUS);
-            N = I.N0;
-            kk = k;
-            poly = I.poly0;
-            wt = I.w0;
-        } else if (k < n0 + n1) {
-            cf = nd + NF_C1;
-            N = I.N1;
-            kk = k - n0;
-            poly = I.poly1;
-            wt = I.w1;
-        } else {
-            cf = nd + NF_C2;
-            N = I.N2;
-            kk = k - n0 - n1;
-            poly = I.poly2;
-            wt = I.w2;
-        }
-        // the l sums are unrolled to the largest order so that their loads issue together
-        double cv[kMaxN + 1], pv[kMaxN + 1];
-#pragma unroll
-        for (int l = 0; l <= kMaxN; l++) {
-            cv[l] = l <= N ? cf[l] : 0.0;
-            pv[l] = l <= N ? poly[kk * (N + 1) + l] : 0.0;
-        }
-        double acc = 0;
-#pragma unroll
-        for (int l = 0; l <= kMaxN; l++) acc += cv[l] * pv[l];
-        sgeq[t * ng + k] = wt[kk] * acc;
+    for (int e = tid; e < G.n0p; e += B) pv0[e] = e < n0 ? I.p0[e] : 0.0;
+    for (int e = tid; e < G.ncols16; e += B) {
+        const int cg = c_s0 + e;
+        pc1[e] = e < ncol ? I.p1[cg % n1] : 0.0;
+        pc2[e] = e < ncol ? I.p2[cg / n1] : 0.0;
     }
+    for (int e = (G.off_pv - G.off_K1) + G.n0p + 2 * G.ncols16 + tid; e < G.img_lds; e += B) R[e] = 0.0;
+    // set-up part: the expansion polynomials of every factor (rows of pstride, zero past the
+    // instance's order), then the quadrature weights
+    const int ng = n0 + n1 + n2, pst = G.pstride;
+    double* P = R + G.img_lds;
+    for (int e = tid; e < G.poly_sz; e += B) {
+        double v = 0.0;
+        const int k = e < ng * pst ? e / pst : e - ng * pst, l = e < ng * pst ? e % pst : -1;
+        if (k < ng) {
+            const int ax = k < n0 ? 0 : k < n0 + n1 ? 1 : 2;
+            const int kk = k - (ax == 0 ? 0 : ax == 1 ? n0 : n0 + n1);
+            const int N = ax == 0 ? I.N0 : ax == 1 ? I.N1 : I.N2;
+            const double* poly = ax == 0 ? I.poly0 : ax == 1 ? I.poly1 : I.poly2;
+            const double* wt = ax == 0 ? I.w0 : ax == 1 ? I.w1 : I.w2;
+            if (l < 0) v = wt[kk];
+            else if (l <= N) v = poly[kk * (N + 1) + l];
+        }
+        P[e] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __restrict__ insts,
+                                                         const int32_t* __restrict__ ilist, const StageGroup G)
+{
+    const DevInstance& I = insts[ilist[blockIdx.y]];
+    stage_image(I, G, blockIdx.x, I.simg + (size_t)blockIdx.x * G.img_sz, threadIdx.x, blockDim.x);
+}
+
+// One RK stage (or the bare right-hand side, rhs != 0) for a tile of consecutive nodes x one
+// velocity slice of one instance.
+//
+// Lanes: the first wh waves take the velocities with p_r > 0, the next wh those with p_r < 0
+// (element e of a half: radial index e % Q, column e / Q of the slice), so the upwind
+// direction is uniform per wave.  Each lane keeps, per velocity, a register window of the
+// cells i-2 .. i+3 around the current node i plus one prefetched cell, so every face flux is
+// computed once and every value of f_src is read once (plus a halo per tile).
+//
+// Per node, two phases separated by barriers:
+//   A: FP64 MFMA 16x16x4 tiles over the node's LDS plane P (column stride n0 + 1)
+//        d0 = K1 P (n0 x n0 times n0 x columns), d1 = K2a P_i2 (per i2), d2 = K2b P' (sphere),
+//      each times its momentum and geometry factor into its own plane; the moment sums of the
+//      previous node's output plane O as two chained MFMAs, D1 = O^T Y0 (Y0: powers 0..3 of
+//      y_r per radial node) and D2 = Psi^T D1 (Psi: the transverse factors 1, y1, y2, y1^2,
+//      y2^2, y1 y2, rho, y1 rho, y2 rho with rho = y1^2 + y2^2, per column); the WENO face
+//      flux at i + 1/2;
+//   B: the update of every velocity (one cubic per lane, coefficients from the set-up), the
+//      store to HBM and to O, and the staging of node i+1's plane and prefetches.
+// The moment sums are taken about the tile shift c and written per slice (no atomics; fixed
+// order, so runs are bitwise reproducible).
+// FP32 storage (F32): the buffers hold deviations from the per-node discrete equilibrium of
+// base tables bsrc (src), bfn (f^n); the output is stored as its deviation from this stage's own
+// equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
+// completed one node after their load (the ring slot of cell i + 4), so no load is waited for
+// earlier than in the FP64 path.
+template <int VPT, bool F32>
+__global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
+                                                 const WorkItem* __restrict__ items, const StageGroup G, int src,
+                                                 int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn,
+                                                 int bdst)
+{
+    extern __shared__ double lds[];
+    const WorkItem it = items[blockIdx.x];
+    const DevInstance& I = insts[it.inst];
+    if (!I.flags[1]) return;
+    const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2, hq = n0 >> 1;
+    const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, W = B >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wh = G.wh;
+    const bool pos = wave < wh;
+    const int cs = n0 + 1;  // LDS column stride of the planes
+    const bool sph = G.geometry == LBE_SPH;
+    const bool need_fn = an != 0.0;
+    const double sigma = rhs ? 1.0 : bs * I.dt, bsv = rhs ? 0.0 : bs;
+    const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
+    const int ncol = G.ncols_s;
+    const int c_s0 = it.slice * ncol;  // first global column (i1 + n1 i2) of the slice
+    const int cp0 = sph ? 0 : c_s0;    // first global column held in the plane
+    const int nTm = G.ncols16 / 16;  // moment tiles (skipped for the bare right-hand side)
+    const int nTall = G.ntiles;
+    double* plane = lds + G.off_plane;
+    double* op = lds + G.off_op;
+    double* scoef = lds + G.off_coef;
+    double* sgeq = lds + G.off_geq;
+    double* spart = lds + G.off_part;
+    int* tdesc = (int*)(lds + G.off_tdesc);
+    double* y0p = lds + G.off_y0p;
+    double* psi = lds + G.off_psi;
+    constexpr int esz = F32 ? 4 : 8;  // bytes per stored value
+    const int rowb = nv * esz;
+    // f_src with its two ghost rows on each side: cell c at byte row offset (c + 2) rowb
+    const rsrc_t rf = make_rsrc((const char*)I.f[src] - 2 * (size_t)rowb, (size_t)(nr + 4) * rowb);
+    const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
+    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * (rhs ? nv * 8 : rowb));
+    // stored value of cell c (F32: the deviation only; its base is added separately)
+    auto cell = [&](int c, unsigned vo) {
+        if constexpr (F32)
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0));
+        else
+            return bload(rf, vo, (min(c, nr + 1) + 2) * rowb);
+    };
+    auto fn_load = [&](int row, unsigned vo) {
+        if constexpr (F32)
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0));
+        else
+            return bload(rfn, vo, row * rowb);
+    };
+    // FP32 storage, loads ahead: the raw bits stay in a register until the value is needed (a
+    // conversion right after the load would wait for it there)
+    auto cell_raw = [&](int c, unsigned vo) {
+        return __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0);
+    };
+    auto fn_raw = [&](int row, unsigned vo) { return __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0); };
+    auto as_f64 = [](unsigned bits) { return (double)__builtin_bit_cast(float, bits); };
+    const int ng = n0 + n1 + n2;
+    // velocity shift of the tile: the velocity of its first node (common to all its slices)
+    const double* ndc = I.node + (size_t)it.i0 * kNodeStride;
+    const double csh[3] = {ndc[NF_U0], ndc[NF_U1], ndc[NF_U2]};
+
+    // ---- set-up, in two passes.  The first reads no LDS: the stage image of the slice (tables
+    // and tile descriptors, built once per instance) is copied in, the planes are zeroed (the MFMA
+    // tiles read their padding) and, with FP32 storage, the base factors are gathered.  The
+    // second computes the node coefficients (last wave) beside the equilibrium factors (the
+    // other waves), then the moment-sum operands and the lane velocities.
+    const double2* img2 = (const double2*)(I.simg + (size_t)it.slice * G.img_sz);
+    const int nimg2 = G.img_sz >> 1, nlds2 = G.img_lds >> 1;
+    auto img_dst = [&](int e) {  // constant part to off_K1, set-up part to off_poly
+        return e < nlds2 ? (double2*)(lds + G.off_K1) + e : (double2*)(lds + G.off_poly) + (e - nlds2);
+    };
+    const double2 img_first = tid < nimg2 ? img2[tid] : double2{0.0, 0.0};
+    const double* pv0 = lds + G.off_pv;  // p_r per radial node
+    const double* pc1 = pv0 + G.n0p;     // p_1, p_2 per column of the slice
+    const double* pc2 = pc1 + G.ncols16;
+    const double* spoly = lds + G.off_poly;  // [ng][pstride] expansion polynomials, then weights [ng]
 
     // FP32 storage: base factors of the window rows (cells i0-3 .. i0+nt+2) of the src buffer
-    // and of the own rows of f^n, as B0[i0] and C[col] = B1[i1] B2[i2] per plane column; the
-    // equilibrium of this stage's src moments becomes the output's base table
+    // and of the own rows of f^n, as B0[i0] and C[col] = B1[i1] B2[i2] per plane column
     double* sbase = lds + G.off_sb;
     double* fbase = lds + G.off_fb;
     const int bst = G.bstride;
@@ -962,15 +959,75 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         };
         fill(sbase, it.nt + 6, it.i0 - 3, bsrc);
         if (need_fn) fill(fbase, it.nt, it.i0, bfn);
-        // (each thread reads the factors it computed itself above, so no barrier is needed here)
-        if (!rhs && it.slice == 0)
-            for (int e = tid; e < it.nt * ng; e += B) {
-                const int t = e / ng, k = e % ng;
-                const double g = sgeq[t * ng + k];
-                I.base[bdst][(size_t)(it.i0 + t) * ng + k] =
-                    k < n0 ? I.node[(size_t)(it.i0 + t) * kNodeStride + NF_N] * g : g;
+    }
+    if (tid < nimg2) *img_dst(tid) = img_first;
+    for (int e = tid + B; e < nimg2; e += B) *img_dst(e) = img2[e];
+    for (int e = tid; e < G.off_ibuf - G.off_plane; e += B) plane[e] = 0.0;
+    __syncthreads();
+
+    if (wave == W - 1) {
+        for (int t = lane; t < it.nt; t += 64) {
+            const int i = it.i0 + t;
+            stage_coefs(I.node + (size_t)i * kNodeStride, I.geo + 4 * i, csh, sph, sigma, bsv,
+                        scoef + t * kCoefStride);
+        }
+    } else {
+        // equilibrium factors of the tile's nodes from their projection coefficients; with FP32
+        // storage the equilibrium of this stage's src moments becomes the output's base table
+        const int pst = G.pstride;
+        for (int e = tid; e < it.nt * ng; e += B - 64) {
+            const int t = e / ng, k = e % ng;
+            const double* nd = I.node + (size_t)(it.i0 + t) * kNodeStride;
+            const int ax = k < n0 ? 0 : k < n0 + n1 ? 1 : 2;
+            // radial index < n0/2: p_r > 0
+            const double* cf = nd + (ax == 0 ? (k < hq ? NF_IPLUS : NF_IMINUS) : ax == 1 ? NF_C1 : NF_C2);
+            const int N = ax == 0 ? I.N0 : ax == 1 ? I.N1 : I.N2;
+            const double* pk = spoly + k * pst;
+            // the l sums are unrolled to the largest order so that their loads issue together
+            double cv[kMaxN + 1], pv[kMaxN + 1];
+#pragma unroll
+            for (int l = 0; l <= kMaxN; l++) {
+                cv[l] = l <= N ? cf[l] : 0.0;
+                pv[l] = l <= N ? pk[l] : 0.0;
             }
-        __syncthreads();
+            double acc = 0;
+#pragma unroll
+            for (int l = 0; l <= kMaxN; l++) acc += cv[l] * pv[l];
+            const double g = spoly[ng * pst + k] * acc;
+            sgeq[t * ng + k] = g;
+            if (F32 && !rhs && it.slice == 0) I.base[bdst][(size_t)(it.i0 + t) * ng + k] = k < n0 ? nd[NF_N] * g : g;
+        }
+    }
+
+    // moment-sum operands: powers of y_r per radial node, transverse factors per column
+    for (int e = tid; e < G.n0k * 16; e += B) {
+        const int r = e >> 4, a = e & 15;
+        double val = 0.0;
+        if (r < n0 && a < 4) {
+            const double y = pv0[r] - csh[0];
+            val = a == 0 ? 1.0 : a == 1 ? y : a == 2 ? y * y : y * y * y;
+        }
+        y0p[e] = val;
+    }
+    for (int e = tid; e < G.ncols16 * 16; e += B) {
+        const int col = e >> 4, m = e & 15;
+        double val = 0.0;
+        if (col < ncol && m < 9) {
+            const double y1 = pc1[col] - csh[1], y2 = pc2[col] - csh[2];
+            const double rho = y1 * y1 + y2 * y2;
+            switch (m) {
+                case 0: val = 1.0; break;
+                case 1: val = y1; break;
+                case 2: val = y2; break;
+                case 3: val = y1 * y1; break;
+                case 4: val = y2 * y2; break;
+                case 5: val = y1 * y2; break;
+                case 6: val = rho; break;
+                case 7: val = y1 * rho; break;
+                default: val = y2 * rho; break;
+            }
+        }
+        psi[e] = val;
     }
 
     // ---- per-lane velocities
@@ -993,10 +1050,10 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         gx0[j] = i0;
         gx1[j] = n0 + i1;
         gx2[j] = n0 + n1 + i2;
-        prv[j] = I.p0[i0];
+        prv[j] = pv0[i0];
         y0[j] = prv[j] - csh[0];
-        y1[j] = I.p1[i1] - csh[1];
-        y2[j] = I.p2[i2] - csh[2];
+        y1[j] = pc1[col] - csh[1];
+        y2[j] = pc2[col] - csh[2];
         yy[j] = y0[j] * y0[j] + y1[j] * y1[j] + y2[j] * y2[j];
     }
     const int pshift = cs * (c_s0 - cp0);  // plane index = ibx + pshift
@@ -1716,6 +1773,12 @@ hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems,
         case 5: return launch_stage_t<2, true>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ninst, const StageGroup& G, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_image, dim3(G.S, ninst), dim3(kBlock), 0, s, d, ilist, G);
+    return hipGetLastError();
 }
 
 hipError_t set_stage_smem_limit()
