@@ -582,7 +582,7 @@ enum TileDesc {
 //          + |y|^2 (H0 y0 + H1 y1 + H2 y2).
 enum StageCoef {
     SC_C0 = 0, SC_G0, SC_G1, SC_G2, SC_E00, SC_E01, SC_E02, SC_E11, SC_E12, SC_E22, SC_H0, SC_H1, SC_H2,
-    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_COUNT
+    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_N, SC_COUNT
 };
 static_assert(SC_COUNT <= kCoefStride, "stage coefficient block");
 
@@ -653,6 +653,7 @@ __device__ inline void stage_coefs(const double* nd, const double* geo4, const d
     out[SC_AL] = sigma * geo4[0];
     out[SC_AR] = sigma * geo4[1];
     out[SC_FFAC] = sigma * geo4[2];
+    out[SC_N] = n;
 }
 
 // Stage image of one instance and velocity slice, written to R: the tables the stage kernel
@@ -1225,7 +1226,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             const double* cf = scoef + t * kCoefStride;
             const double* gq = sgeq + t * ng;
             const double* ib0 = lds + G.off_ibuf + buf * G.ib_sz;
-            const double nnode = F32 ? I.node[(size_t)i * kNodeStride + NF_N] : 0.0;
+            const double nnode = cf[SC_N];
 #pragma unroll
             for (int j = 0; j < VPT; j++) {
                 double Iv = ib0[ibx[j]] + ib0[ibx[j] + cs * ncol];
@@ -1264,19 +1265,21 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                     if (!rhs) op[buf * G.op_sz + ibx[j]] = o;
                 }
             }
-            if (t + 1 < it.nt) {
+            // the loads ahead are issued unconditionally (after the tile's last node they read
+            // clamped cells and the zero row past f^n, unused): with no branch around them the
+            // compiler can count them exactly and wait only for the load each use needs
+            const int fnrow = need_fn ? i + 1 : nr;
 #pragma unroll
-                for (int j = 0; j < VPT; j++) {
-                    Fl[j] = Fr[j];
-                    if constexpr (F32) {
-                        // complete cell i + 4 (loaded during the previous node), load cell i + 5
-                        sl[j][(P + 6) % 7] = as_f64(rawc[j]) + wbase(t + 7, j);
-                        rawc[j] = cell_raw(i + 5, voff[j]);
-                        rawf[j] = need_fn ? fn_raw(i + 1, voff[j]) : 0u;
-                    } else {
-                        sl[j][P % 7] = cell(i + 5, voff[j]);
-                        fnv[j] = need_fn ? fn_load(i + 1, voff[j]) : 0.0;
-                    }
+            for (int j = 0; j < VPT; j++) {
+                Fl[j] = Fr[j];
+                if constexpr (F32) {
+                    // complete cell i + 4 (loaded during the previous node), load cell i + 5
+                    if (t + 1 < it.nt) sl[j][(P + 6) % 7] = as_f64(rawc[j]) + wbase(t + 7, j);
+                    rawc[j] = cell_raw(i + 5, voff[j]);
+                    rawf[j] = fn_raw(fnrow, voff[j]);
+                } else {
+                    sl[j][P % 7] = cell(i + 5, voff[j]);
+                    fnv[j] = fn_load(fnrow, voff[j]);
                 }
             }
         }
@@ -1286,15 +1289,23 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     __syncthreads();
     run_tiles(0, -1);  // contractions of node 0
     __syncthreads();
-    for (int t0 = 0; t0 < it.nt; t0 += 7) {
+    // whole rounds of the ring's seven phases, then the remaining nodes (no branch inside a round)
+    int t0 = 0;
+    for (; t0 + 7 <= it.nt; t0 += 7) {
         node_step(t0, std::integral_constant<int, 0>{});
-        if (t0 + 1 < it.nt) node_step(t0 + 1, std::integral_constant<int, 1>{});
-        if (t0 + 2 < it.nt) node_step(t0 + 2, std::integral_constant<int, 2>{});
-        if (t0 + 3 < it.nt) node_step(t0 + 3, std::integral_constant<int, 3>{});
-        if (t0 + 4 < it.nt) node_step(t0 + 4, std::integral_constant<int, 4>{});
-        if (t0 + 5 < it.nt) node_step(t0 + 5, std::integral_constant<int, 5>{});
-        if (t0 + 6 < it.nt) node_step(t0 + 6, std::integral_constant<int, 6>{});
+        node_step(t0 + 1, std::integral_constant<int, 1>{});
+        node_step(t0 + 2, std::integral_constant<int, 2>{});
+        node_step(t0 + 3, std::integral_constant<int, 3>{});
+        node_step(t0 + 4, std::integral_constant<int, 4>{});
+        node_step(t0 + 5, std::integral_constant<int, 5>{});
+        node_step(t0 + 6, std::integral_constant<int, 6>{});
     }
+    if (t0 < it.nt) node_step(t0, std::integral_constant<int, 0>{});
+    if (t0 + 1 < it.nt) node_step(t0 + 1, std::integral_constant<int, 1>{});
+    if (t0 + 2 < it.nt) node_step(t0 + 2, std::integral_constant<int, 2>{});
+    if (t0 + 3 < it.nt) node_step(t0 + 3, std::integral_constant<int, 3>{});
+    if (t0 + 4 < it.nt) node_step(t0 + 4, std::integral_constant<int, 4>{});
+    if (t0 + 5 < it.nt) node_step(t0 + 5, std::integral_constant<int, 5>{});
     if (rhs) return;
     // ---- moment sums of the last node, then per node and slice: combine the column tiles and
     // map the (transverse factor, power of y_r) products to the moment block
