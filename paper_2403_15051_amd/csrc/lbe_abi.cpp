@@ -257,13 +257,14 @@ bool layout_group(StageGroup* G, int nt0)
     {
         const int W = G->block / 64;
         const int nT1 = (G->n0p / 16) * (G->ncols16 / 16), nT2 = G->ns2 * (G->n1p / 16) * (G->n0p / 16);
-        std::vector<std::pair<int, int>> tiles;  // (weight in MFMAs, logical tile)
+        std::vector<std::pair<int, int>> tiles;  // (weight, logical tile)
         for (int k = 0; k < nTall; k++) {
             int wgt;
-            if (k < nTm) wgt = G->n0k / 4 + 4;
-            else if (k < nTm + nT1) wgt = G->n0k / 4;
-            else if (k < nTm + nT1 + nT2) wgt = G->n1k / 4;
-            else wgt = G->n2k / 4;
+            // in cycles of the matrix core / 16: a 16x16x4 FP64 MFMA is 4, a 4x4x4 one is 1
+            if (k < nTm) wgt = G->n0k / 4 + 3;
+            else if (k < nTm + nT1) wgt = G->n0k;
+            else if (k < nTm + nT1 + nT2) wgt = G->n1k;
+            else wgt = G->n2k;
             tiles.push_back({wgt, k});
         }
         std::stable_sort(tiles.begin(), tiles.end(), [](auto& a, auto& b) { return a.first > b.first; });
@@ -318,8 +319,8 @@ bool layout_group(StageGroup* G, int nt0)
         G->poly_sz = ng * G->pstride + ng;
         G->poly_sz += G->poly_sz & 1;
         G->img_sz = G->img_lds + G->poly_sz;
-        G->off_y0p = o;
-        o += G->n0k * 16;
+        G->off_y0p = o;  // powers 0..3 of y_r per radial node
+        o += G->n0k * 4;
         G->off_psi = o;
         o += G->ncols16 * 16;
         G->off_coef = o;

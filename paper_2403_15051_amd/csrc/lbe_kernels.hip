@@ -568,7 +568,7 @@ __device__ inline double weno_flux(double a, double b, double c, double d, doubl
 //   A: abase + q16 * arow + q4 + k,   B: bbase + col + (q4 + k) * bk,
 // where col = q16 * bcol, or the table ctab[q16] when bcol = 0.  Contraction tiles then write
 // fac * D[q4 + 4r][q16] (fac = ffac * lftab[q16], lanes q16 < okl, rows q4 + 4r < rowlim) to
-// out + obase + col + (q4 + 4r) * orow.  Moment tiles (type 1) chain a second MFMA instead.
+// out + obase + col + (q4 + 4r) * orow.  Moment tiles (type 1) only name their column tile (ct).
 enum TileDesc {
     TD_TYPE = 0, TD_ABASE, TD_AROW, TD_BBASE, TD_BK, TD_NK, TD_BCOL, TD_CTAB, TD_LFTAB, TD_OKL, TD_OBASE, TD_OROW,
     TD_ROWLIM, TD_OUT, TD_CT, TD_COUNT
@@ -733,14 +733,8 @@ __device__ void stage_image(const DevInstance& I, const StageGroup& G, int slice
         const int tile = G.nperm ? G.perm[slot] : slot;
         int* d = tdesc + slot * kTileDescStride;
         for (int k = 0; k < kTileDescStride; k++) d[k] = 0;
-        if (tile < nTm) {
+        if (tile < nTm) {  // moment tile: columns 16 tile .. 16 tile + 15 of the output plane
             d[TD_TYPE] = 1;
-            d[TD_ABASE] = G.off_op + cs * 16 * tile;
-            d[TD_AROW] = cs;
-            d[TD_BBASE] = G.off_y0p;
-            d[TD_BK] = 16;
-            d[TD_NK] = G.n0k;
-            d[TD_BCOL] = 1;
             d[TD_CT] = tile;
             continue;
         }
@@ -1001,10 +995,10 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     }
 
     // moment-sum operands: powers of y_r per radial node, transverse factors per column
-    for (int e = tid; e < G.n0k * 16; e += B) {
-        const int r = e >> 4, a = e & 15;
+    for (int e = tid; e < G.n0k * 4; e += B) {
+        const int r = e >> 2, a = e & 3;
         double val = 0.0;
-        if (r < n0 && a < 4) {
+        if (r < n0) {
             const double y = pv0[r] - csh[0];
             val = a == 0 ? 1.0 : a == 1 ? y : a == 2 ? y * y : y * y * y;
         }
@@ -1123,15 +1117,63 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     const int q16 = lane & 15, q4 = lane >> 4;
     const int* ctabs = (const int*)lds;
 
+    // Moment sums of node t over the 16 output-plane columns 16 ct .. 16 ct + 15 (output buffer
+    // t mod 2), with the 4-block FP64 MFMA 4x4x4, whose lane layout on gfx950 is A[b][i][k] at
+    // lane i + 4b + 16k, B[b][k][j] at j + 4b + 16k and D[b][i][j] at j + 4b + 16i.  Block b
+    // takes columns 4b .. 4b + 3 of the tile:
+    //   D1[b][c][a] = sum_r O[r][4b + c] y_r^a                  (a < 4, four radial nodes a step)
+    //   D2[b][m][a] = sum_c Psi[4b + c][4g + m] D1[b][c][a]      (transverse factors 4g .. 4g + 3)
+    // D1 is the second product's B operand as it stands (its row index is the contraction
+    // index); the four blocks' partial D2 are then summed across lanes by row rotations.
+    auto moment_tile = [&](int ct, int t) {
+        const int i4 = lane & 3, b4 = (lane >> 2) & 3, k4 = lane >> 4;
+        const double* ap = op + (t & 1) * G.op_sz + (16 * ct + 4 * b4 + i4) * cs + k4;
+        const double* bp = y0p + 4 * k4 + i4;
+        const int nk = G.n0k;
+        double d1 = 0.0;
+        for (int ks = 0; ks < nk; ks += 16) {
+            double a[4], b[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const bool ok = ks + 4 * m < nk;
+                a[m] = ok ? ap[ks + 4 * m] : 0.0;
+                b[m] = ok ? bp[4 * (ks + 4 * m)] : 0.0;
+            }
+            d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[0], b[0], d1, 0, 0, 0);
+#pragma unroll
+            for (int m = 1; m < 4; m++)
+                if (ks + 4 * m < nk) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[m], b[m], d1, 0, 0, 0);
+        }
+        const double* pp = psi + (16 * ct + 4 * b4 + k4) * 16 + i4;
+        double d2[3];
+#pragma unroll
+        for (int g = 0; g < 3; g++) {
+            double v = __builtin_amdgcn_mfma_f64_4x4x4f64(pp[4 * g], d1, 0.0, 0, 0, 0);
+            v += dpp_or_old<0x128, 0xf>(0.0, v);  // row_ror:8: blocks b, b - 2
+            v += dpp_or_old<0x124, 0xf>(0.0, v);  // row_ror:4: all four blocks
+            d2[g] = v;
+        }
+        // lane (a, b = 0, m): D2[4g + m][a], written as the tile's [m][a] block of 9 x 4
+        if (b4 == 0) {
+            double* dst = spart + (t * nTm + ct) * 36 + i4;
+            dst[4 * k4] = d2[0];
+            dst[4 * (4 + k4)] = d2[1];
+            if (k4 == 0) dst[32] = d2[2];
+        }
+    };
     // One MFMA tile (descriptor slot): a contraction of node t (plane and term buffers t mod 2)
-    // or the moment sums of node t (output buffer t mod 2).
+    // or the moment sums of node t.
     auto run_tile = [&](int tile, int t) {
         const int* td = tdesc + tile * kTileDescStride;
         const int type = __builtin_amdgcn_readfirstlane(td[TD_TYPE]);
+        if (type == 1) {
+            moment_tile(__builtin_amdgcn_readfirstlane(td[TD_CT]), t);
+            return;
+        }
         const int buf = t & 1;
-        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]) + (type == 1 ? buf * G.op_sz : 0);
+        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]);
         const int arow = __builtin_amdgcn_readfirstlane(td[TD_AROW]);
-        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]) + (type == 0 ? buf * G.plane_sz : 0);
+        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]) + buf * G.plane_sz;
         const int bk = __builtin_amdgcn_readfirstlane(td[TD_BK]);
         const int nk = __builtin_amdgcn_readfirstlane(td[TD_NK]);
         const int bcol = __builtin_amdgcn_readfirstlane(td[TD_BCOL]);
@@ -1153,35 +1195,18 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             for (int m = 1; m < 4; m++)
                 if (ks + 4 * m < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
         }
-        if (type == 0) {
-            const int okl = __builtin_amdgcn_readfirstlane(td[TD_OKL]);
-            if (q16 < okl) {
-                const int lftab = __builtin_amdgcn_readfirstlane(td[TD_LFTAB]);
-                const int obase = __builtin_amdgcn_readfirstlane(td[TD_OBASE]);
-                const int orow = __builtin_amdgcn_readfirstlane(td[TD_OROW]);
-                const int rowlim = __builtin_amdgcn_readfirstlane(td[TD_ROWLIM]);
-                const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]) + buf * G.ib_sz;
-                const double fac = scoef[t * kCoefStride + SC_FFAC] * lds[lftab + q16];
-                double* o = lds + out + obase + col + q4 * orow;
+        const int okl = __builtin_amdgcn_readfirstlane(td[TD_OKL]);
+        if (q16 < okl) {
+            const int lftab = __builtin_amdgcn_readfirstlane(td[TD_LFTAB]);
+            const int obase = __builtin_amdgcn_readfirstlane(td[TD_OBASE]);
+            const int orow = __builtin_amdgcn_readfirstlane(td[TD_OROW]);
+            const int rowlim = __builtin_amdgcn_readfirstlane(td[TD_ROWLIM]);
+            const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]) + buf * G.ib_sz;
+            const double fac = scoef[t * kCoefStride + SC_FFAC] * lds[lftab + q16];
+            double* o = lds + out + obase + col + q4 * orow;
 #pragma unroll
-                for (int r = 0; r < 4; r++)
-                    if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
-            }
-        } else {
-            // D2 = Psi^T D1 over the tile's 16 columns; lane holds D2[m = q4 + 4r][a = q16]
-            const int ct = __builtin_amdgcn_readfirstlane(td[TD_CT]);
-            v4d d2 = {0, 0, 0, 0};
-            const double* pp = psi + (ct * 16 + q4) * 16 + q16;
-            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[0], acc[0], d2, 0, 0, 0);
-            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[64], acc[1], d2, 0, 0, 0);
-            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[128], acc[2], d2, 0, 0, 0);
-            d2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pp[192], acc[3], d2, 0, 0, 0);
-            if (q16 < 4) {
-                double* dst4 = spart + (t * nTm + ct) * 36 + q16;
-                dst4[q4 * 4] = d2[0];
-                dst4[(4 + q4) * 4] = d2[1];
-                if (q4 == 0) dst4[32] = d2[2];
-            }
+            for (int r = 0; r < 4; r++)
+                if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
         }
     };
     // the wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0)
