@@ -1161,25 +1161,46 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             if (k4 == 0) dst[32] = d2[2];
         }
     };
-    // One MFMA tile (descriptor slot): a contraction of node t (plane and term buffers t mod 2)
-    // or the moment sums of node t.
-    auto run_tile = [&](int tile, int t) {
-        const int* td = tdesc + tile * kTileDescStride;
-        const int type = __builtin_amdgcn_readfirstlane(td[TD_TYPE]);
-        if (type == 1) {
-            moment_tile(__builtin_amdgcn_readfirstlane(td[TD_CT]), t);
+    // A tile descriptor in scalar registers, read with four 16-byte LDS loads and one wait.
+    struct Tile {
+        int type, abase, arow, bbase, bk, nk, bcol, ctab, lftab, okl, obase, orow, rowlim, out, ct;
+    };
+    auto load_tile = [&](int slot) {
+        const int4* q = (const int4*)(tdesc + slot * kTileDescStride);
+        const int4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        Tile T;
+        T.type = __builtin_amdgcn_readfirstlane(q0.x);
+        T.abase = __builtin_amdgcn_readfirstlane(q0.y);
+        T.arow = __builtin_amdgcn_readfirstlane(q0.z);
+        T.bbase = __builtin_amdgcn_readfirstlane(q0.w);
+        T.bk = __builtin_amdgcn_readfirstlane(q1.x);
+        T.nk = __builtin_amdgcn_readfirstlane(q1.y);
+        T.bcol = __builtin_amdgcn_readfirstlane(q1.z);
+        T.ctab = __builtin_amdgcn_readfirstlane(q1.w);
+        T.lftab = __builtin_amdgcn_readfirstlane(q2.x);
+        T.okl = __builtin_amdgcn_readfirstlane(q2.y);
+        T.obase = __builtin_amdgcn_readfirstlane(q2.z);
+        T.orow = __builtin_amdgcn_readfirstlane(q2.w);
+        T.rowlim = __builtin_amdgcn_readfirstlane(q3.x);
+        T.out = __builtin_amdgcn_readfirstlane(q3.y);
+        T.ct = __builtin_amdgcn_readfirstlane(q3.z);
+        return T;
+    };
+    static_assert(TD_CT == 14 && kTileDescStride == 16, "tile descriptor layout");
+
+    // One MFMA tile: a contraction of node t (plane and term buffers t mod 2) or the moment sums
+    // of node t.
+    auto run_tile = [&](const Tile& T, int t) {
+        if (T.type == 1) {
+            moment_tile(T.ct, t);
             return;
         }
         const int buf = t & 1;
-        const int abase = __builtin_amdgcn_readfirstlane(td[TD_ABASE]);
-        const int arow = __builtin_amdgcn_readfirstlane(td[TD_AROW]);
-        const int bbase = __builtin_amdgcn_readfirstlane(td[TD_BBASE]) + buf * G.plane_sz;
-        const int bk = __builtin_amdgcn_readfirstlane(td[TD_BK]);
-        const int nk = __builtin_amdgcn_readfirstlane(td[TD_NK]);
-        const int bcol = __builtin_amdgcn_readfirstlane(td[TD_BCOL]);
-        const int col = bcol ? q16 * bcol : ctabs[__builtin_amdgcn_readfirstlane(td[TD_CTAB]) + q16];
-        const double* ap = lds + abase + q16 * arow + q4;
-        const double* bp = lds + bbase + col + q4 * bk;
+        const int col = T.bcol ? q16 * T.bcol : ctabs[T.ctab + q16];
+        const double lf = lds[T.lftab + q16];
+        const double* ap = lds + T.abase + q16 * T.arow + q4;
+        const double* bp = lds + T.bbase + buf * G.plane_sz + col + q4 * T.bk;
+        const int nk = T.nk, bk = T.bk;
         // operands of four k-steps are read together, then their MFMAs issue back to back
         v4d acc = {0, 0, 0, 0};
         for (int ks = 0; ks < nk; ks += 16) {
@@ -1195,25 +1216,20 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             for (int m = 1; m < 4; m++)
                 if (ks + 4 * m < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
         }
-        const int okl = __builtin_amdgcn_readfirstlane(td[TD_OKL]);
-        if (q16 < okl) {
-            const int lftab = __builtin_amdgcn_readfirstlane(td[TD_LFTAB]);
-            const int obase = __builtin_amdgcn_readfirstlane(td[TD_OBASE]);
-            const int orow = __builtin_amdgcn_readfirstlane(td[TD_OROW]);
-            const int rowlim = __builtin_amdgcn_readfirstlane(td[TD_ROWLIM]);
-            const int out = __builtin_amdgcn_readfirstlane(td[TD_OUT]) + buf * G.ib_sz;
-            const double fac = scoef[t * kCoefStride + SC_FFAC] * lds[lftab + q16];
-            double* o = lds + out + obase + col + q4 * orow;
+        if (q16 < T.okl) {
+            const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
+            double* o = lds + T.out + buf * G.ib_sz + T.obase + col + q4 * T.orow;
 #pragma unroll
             for (int r = 0; r < 4; r++)
-                if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
+                if (q4 + 4 * r < T.rowlim) o[4 * r * T.orow] = fac * acc[r];
         }
     };
-    // the wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0)
+    // The wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0).
     auto run_tiles = [&](int tc, int tm) {
         for (int slot = wave; slot < nTall; slot += W) {
-            const bool mom = __builtin_amdgcn_readfirstlane(tdesc[slot * kTileDescStride + TD_TYPE]) == 1;
-            if (mom ? (tm >= 0 && !rhs) : (tc >= 0 && tc < it.nt)) run_tile(slot, mom ? tm : tc);
+            const Tile T = load_tile(slot);
+            const bool mom = T.type == 1;
+            if (mom ? (tm >= 0 && !rhs) : (tc >= 0 && tc < it.nt)) run_tile(T, mom ? tm : tc);
         }
     };
 
