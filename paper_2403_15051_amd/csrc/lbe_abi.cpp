@@ -112,7 +112,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Byte layout of one instance inside the workspace.
 struct Layout {
     size_t f[3], mom, node, snap, resid, flags, nw, scratch;
-    size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qh0, geo, r, wlo, wb, gwl, gwr;
+    size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qrec0, geo, r, wlo, wb, gwl, gwr;
     size_t simg;
     size_t total;
 };
@@ -156,7 +156,7 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t img_doubles, siz
     L.poly2 = take(t.ax[2].poly.size() * D);
     L.qy0 = take(t.ax[0].qy.size() * D);
     L.qlam0 = take(t.ax[0].qlam.size() * D);
-    L.qh0 = take(t.ax[0].qh.size() * D);
+    L.qrec0 = take(t.ax[0].qrec.size() * D);
     L.geo = take(t.geo.size() * D);
     L.r = take(t.r.size() * D);
     L.wlo = take(t.wlo.size() * sizeof(int32_t));
@@ -196,9 +196,12 @@ size_t instance_bytes_estimate(const lbe_params& p)
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
     b += 3 * align256((size_t)std::max(n0, std::max(n1, n2)) * N * D);
+    // projection rule: as build_instance sizes it (panels of 16 nodes, width from the colder wall)
     const double Tmax = std::max(1.0, std::max(p.t_wall_inner, p.t_wall_outer));
-    const size_t M = (size_t)(16 * (std::ceil((3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner)) / 0.75) + 1));
-    b += 2 * align256(M * D) + align256(M * N * D);
+    const double Tlow = 0.5 * std::min(p.t_wall_inner, p.t_wall_outer);
+    const double hwidth = std::min(1.5, std::max(0.1875, 3.35 * std::sqrt(std::max(Tlow, 0.0))));
+    const size_t M = (size_t)(16 * (std::ceil((3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner)) / hwidth) + 1));
+    b += 2 * align256(M * D) + align256((size_t)(3 * N + 1) * D);
     b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
     b += align256(nr * n2 * sizeof(WorkItem));
     b += 4 * align256(nr * (size_t)(n0 + n1 + n2) * D);
@@ -931,7 +934,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.poly2 = (const double*)(ws + L.poly2);
         d.qy0 = (const double*)(ws + L.qy0);
         d.qlam0 = (const double*)(ws + L.qlam0);
-        d.qh0 = (const double*)(ws + L.qh0);
+        d.qrec0 = (const double*)(ws + L.qrec0);
         d.M0 = (int32_t)t.ax[0].qy.size();
         d.qpw = t.ax[0].qpanel;
         d.nslices = nsl;
@@ -956,7 +959,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         if (e == hipSuccess) e = put(ws, L.poly2, t.ax[2].poly, c->stream);
         if (e == hipSuccess) e = put(ws, L.qy0, t.ax[0].qy, c->stream);
         if (e == hipSuccess) e = put(ws, L.qlam0, t.ax[0].qlam, c->stream);
-        if (e == hipSuccess) e = put(ws, L.qh0, t.ax[0].qh, c->stream);
+        if (e == hipSuccess) e = put(ws, L.qrec0, t.ax[0].qrec, c->stream);
         if (e == hipSuccess) e = put(ws, L.geo, t.geo, c->stream);
         if (e == hipSuccess) e = put(ws, L.r, t.r, c->stream);
         if (e == hipSuccess) e = put(ws, L.wlo, t.wlo, c->stream);

@@ -46,6 +46,8 @@ struct AxisTables {
     std::vector<double> qy, qlam;  // half-range: projection rule on [0, Y] (nodes, weights)
     double qpanel = 0.75;          // half-range: panel width of that rule (16 nodes per panel)
     std::vector<double> qh;        // half-range: h_l(qy_m), M x (N+1)
+    std::vector<double> qrec;      // half-range, from x h_l = b_{l+1} h_{l+1} + a_l h_l + b_l h_{l-1}:
+                                   // (a_l, b_l^2) for l < N, then h_0 / (b_1 ... b_l) for l <= N
 };
 
 // Everything the host precomputes for one instance.
@@ -84,7 +86,8 @@ struct DevInstance {
     const double* K1; const double* K2a; const double* K2b;
     const double* w0; const double* w1; const double* w2;
     const double* poly0; const double* poly1; const double* poly2;
-    const double* qy0; const double* qlam0; const double* qh0;  // projection rule, M0 nodes
+    const double* qy0; const double* qlam0;  // projection rule, M0 nodes
+    const double* qrec0;    // recurrence of the half-range polynomials (AxisTables::qrec)
     int32_t M0, nslices;    // equilibrium projection nodes; velocity slices of the stage kernel
     double qpw;             // panel width of the projection rule
     const double* geo;      // [nr][4]

@@ -474,10 +474,65 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     }
 }
 
-// Half-range projection coefficients I_l^+- (Sec. III.C) of every node: one wave per node,
-// the 64 lanes share the quadrature nodes of the panels within 9.6 sqrt(T) of +-u (farther
-// panels contribute below 1e-20 of the peak), and the 2 (N0+1) <= 32 sums are reduced with
-// the register reduce-scatter.  Runs after k_node (needs u_r and T of the node).
+// Half-range projection coefficients I_l^+- (Sec. III.C) of one node by one wave: the 64 lanes
+// share the quadrature nodes of the panels within 9.6 sqrt(T) of +-u (farther panels contribute
+// below 1e-20 of the peak) and the 2 (N0+1) sums are reduced with the register reduce-scatter.
+// h_l at a quadrature node comes from the monic form of its three-term recurrence,
+// p_{l+1} = (x - a_l) p_l - b_l^2 p_{l-1}, h_l = p_l n_l with n_l = h_0 / (b_1 ... b_l) applied to
+// the reduced sums: cheaper than reading a table row per node, which made the kernel L2-bound.
+// NH bounds N0 + 1; with NH <= 8 the recurrence coefficients stay in scalar registers.
+typedef const __attribute__((address_space(4))) double* cdptr;
+template <int NH>
+__device__ inline void proj_node(const DevInstance& I, double* nd, int lane)
+{
+    const double u = nd[NF_U0], T = nd[NF_T];
+    const int N0 = I.N0, M = I.M0, npan = M / 16;
+    const double reach = 9.6 * sqrt(T), c = kInvSqrt2Pi / sqrt(T), inv2T = 1 / (2 * T);
+    const cdptr q = (cdptr)I.qrec0;  // read-only in the kernel: scalar loads
+    constexpr bool REG = NH <= 8;
+    constexpr int NR = REG ? NH - 1 : 1;
+    double ra[NR], rb[NR];
+#pragma unroll
+    for (int l = 0; l < NR; l++) {
+        ra[l] = REG && l < N0 ? q[2 * l] : 0.0;
+        rb[l] = REG && l < N0 ? q[2 * l + 1] : 0.0;
+    }
+    const int which = (lane >> 2) & 15;
+    for (int side = 0; side < 2; side++) {
+        double acc[NH];
+#pragma unroll
+        for (int k = 0; k < NH; k++) acc[k] = 0;
+        const double uu = side ? -u : u;
+        int p0 = (int)floor((uu - reach) / I.qpw), p1 = (int)ceil((uu + reach) / I.qpw);
+        p0 = max(0, min(p0, npan));
+        p1 = max(p0, min(p1, npan));
+        for (int m = 16 * p0 + lane; m < 16 * p1; m += 64) {
+            const double x = I.qy0[m], d = x - uu;
+            const double gw = I.qlam0[m] * c * exp(-d * d * inv2T);
+            double pm = 0.0, p = 1.0;
+#pragma unroll
+            for (int l = 0; l < NH; l++) {
+                if (l <= N0) acc[l] += gw * p;
+                if (l + 1 < NH && l < N0) {
+                    const double ca = REG ? ra[l < NR ? l : 0] : q[2 * l];
+                    const double cb = REG ? rb[l < NR ? l : 0] : q[2 * l + 1];
+                    const double pn = fma(x - ca, p, -cb * pm);
+                    pm = p;
+                    p = pn;
+                }
+            }
+        }
+        // reduce-scatter of the 16 sums: lanes with (lane >> 2) & 15 = l hold the total of l
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = k < NH ? acc[k < NH ? k : 0] : 0.0;
+        const double tot = reduce_scatter16(v, lane);
+        if ((lane & 3) == 0 && which <= N0) nd[(side ? NF_IMINUS : NF_IPLUS) + which] = tot * q[2 * N0 + which];
+    }
+}
+
+// Projection coefficients of every node (one wave per node).  Runs after k_node (needs u_r and
+// T of the node).
 __global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist)
 {
     const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
@@ -486,34 +541,10 @@ __global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__
     const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (i >= I.nr) return;
     double* nd = I.node + (size_t)i * kNodeStride;
-    const double u = nd[NF_U0], T = nd[NF_T];
-    const int N0 = I.N0, M = I.M0, npan = M / 16;
-    const double reach = 9.6 * sqrt(T), c = kInvSqrt2Pi / sqrt(T), inv2T = 1 / (2 * T);
-    double acc[32];
-#pragma unroll
-    for (int k = 0; k < 32; k++) acc[k] = 0;
-    for (int side = 0; side < 2; side++) {
-        const double uu = side ? -u : u;
-        int p0 = (int)floor((uu - reach) / I.qpw), p1 = (int)ceil((uu + reach) / I.qpw);
-        p0 = max(0, min(p0, npan));
-        p1 = max(p0, min(p1, npan));
-        for (int m = 16 * p0 + lane; m < 16 * p1; m += 64) {
-            const double d = I.qy0[m] - uu;
-            const double gw = I.qlam0[m] * c * exp(-d * d * inv2T);
-            const double* h = I.qh0 + (size_t)m * (N0 + 1);
-#pragma unroll
-            for (int l = 0; l < 16; l++)
-                if (l <= N0) acc[side * 16 + l] += gw * h[l];
-        }
-    }
-    // two reduce-scatters of 16 values: lanes (l >> 2) & 15 = l-index hold the totals
-    const double totp = reduce_scatter16(acc, lane);
-    const double totm = reduce_scatter16(acc + 16, lane);
-    const int which = (lane >> 2) & 15;
-    if ((lane & 3) == 0 && which <= N0) {
-        nd[NF_IPLUS + which] = totp;
-        nd[NF_IMINUS + which] = totm;
-    }
+    if (I.N0 < 8)
+        proj_node<8>(I, nd, lane);
+    else
+        proj_node<kMaxN + 1>(I, nd, lane);
 }
 
 // ------------------------------------------------------------------ stage kernel

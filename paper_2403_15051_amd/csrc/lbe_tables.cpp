@@ -230,6 +230,18 @@ static void build_half_axis(int Q, int N, double Y, double hwidth, AxisTables* a
                 for (int l = 0; l <= N; l++) ax->qh.push_back((double)h[l]);
             }
     }
+    // the same polynomials in monic form for the device: p_{l+1} = (x - a_l) p_l - b_l^2 p_{l-1},
+    // p_0 = 1, h_l = p_l h_0 / (b_1 ... b_l); qrec = (a_l, b_l^2) for l < N, then the N + 1 norms
+    ax->qrec.clear();
+    for (int l = 0; l < N; l++) {
+        ax->qrec.push_back((double)a[l]);
+        ax->qrec.push_back((double)(b[l] * b[l]));
+    }
+    ld nrm = 1 / sqrtl(b[0]);
+    for (int l = 0; l <= N; l++) {
+        if (l > 0) nrm /= b[l];
+        ax->qrec.push_back((double)nrm);
+    }
     half_eval(Q, a, b, 0, h.data(), nullptr);
     std::vector<ld> hzero(h.begin(), h.begin() + Q);
 

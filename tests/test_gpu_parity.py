@@ -32,10 +32,18 @@ def _setup():
 def compare_profiles(mg, mo, fields=("n", "u_r", "u_t1", "T", "q_r", "P_rt1", "nbar", "chi"), tol=TOL, ctx=""):
     """Normwise relative error per field; the velocity components are one vector field, so
     each is measured against the largest velocity component (a radial velocity that is only
-    truncation-small in a steady state is not amplified by its own tiny norm)."""
+    truncation-small in a steady state is not amplified by its own tiny norm).  Likewise the heat
+    flux and the shear stress are what is left of third and second moments of size n T^(3/2) and
+    n T after cancellation, so their rounding is measured against that size when they are
+    smaller than it."""
     uscale = max(np.abs(mo[k]).max() for k in ("u_r", "u_t1", "u_t2"))
+    nmax, tmax = np.abs(mo["n"]).max(), np.abs(mo["T"]).max()
     for k in fields:
         scale = uscale if k.startswith("u_") else np.abs(mo[k]).max()
+        if k.startswith("q_"):
+            scale = max(scale, nmax * tmax ** 1.5)
+        elif k.startswith("P_"):
+            scale = max(scale, nmax * tmax)
         if scale < 1e-13:  # a field that vanishes by symmetry: compare absolutely
             assert np.abs(mg[k]).max() < 1e-12, (ctx, k)
             continue
@@ -169,6 +177,9 @@ def kn_for_confinement(eta0: float, C: float) -> float:
     ("Kn = 10", dict(workloads.FOURIER_SPH, nr=20, q_radial=6, q_t1=6, q_t2=6, eta0=0.01, kn=10.0), 20),
     # smallest grid, order-2 transverse axes
     ("nr = 8", dict(workloads.COUETTE_SMALL, nr=8, q_radial=2, q_t1=2, q_t2=2, n_expand=(1, 1, 1)), 50),
+    # cold walls: the projection rule's panels shrink with the colder wall's temperature
+    ("cold walls", dict(workloads.FOURIER_CYL, nr=24, q_radial=6, q_t1=6, q_t2=4, t_wall_inner=0.1,
+                        t_wall_outer=0.3, kn=0.2), 20),
 ])
 def test_edge_cases_match_oracle(name, p, steps):
     print("case", name, flush=True)
