@@ -75,7 +75,10 @@ def test_state_roundtrip_and_rest_start():
 
 
 @pytest.mark.parametrize("p", [dict(W.COUETTE_SMALL, nr=16), dict(W.FOURIER_SPH, nr=24, q_radial=4, q_t1=4, q_t2=4),
-                               dict(W.FOURIER_CYL, nr=24)])
+                               dict(W.FOURIER_CYL, nr=24),
+                               # two velocities per lane (a 1536-velocity slice; CFL 0.1, stable at
+                               # this transverse order)
+                               dict(W.FOURIER_CYL, nr=12, q_radial=16, q_t1=48, q_t2=2, cfl=0.1)])
 def test_rhs_of_an_oracle_state(p):
     o = oracle.Solver(p)
     o.step(30)
