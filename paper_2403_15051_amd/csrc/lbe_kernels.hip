@@ -877,12 +877,12 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
 // completed one node after their load (the ring slot of cell i + 4), so no load is waited for
 // earlier than in the FP64 path.
-template <int VPT, bool F32>
+template <int VPT, bool F32, bool RHS>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
-                                                 int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn,
-                                                 int bdst)
+                                                 int fn, int dst, double an, double bs, int bsrc, int bfn, int bdst)
 {
+    constexpr int rhs = RHS ? 1 : 0;
     extern __shared__ double lds[];
     const WorkItem it = items[blockIdx.x];
     const DevInstance& I = insts[it.inst];
@@ -912,29 +912,34 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     double* psi = lds + G.off_psi;
     constexpr int esz = F32 ? 4 : 8;  // bytes per stored value
     const int rowb = nv * esz;
-    // f_src with its two ghost rows on each side: cell c at byte row offset (c + 2) rowb
-    const rsrc_t rf = make_rsrc((const char*)I.f[src] - 2 * (size_t)rowb, (size_t)(nr + 4) * rowb);
-    const rsrc_t rfn = make_rsrc(I.f[fn], (size_t)nr * rowb);
-    const rsrc_t ro = make_rsrc(rhs ? I.scratch : I.f[dst], (size_t)nr * (rhs ? nv * 8 : rowb));
+    // The instance's three state buffers lie in order in one allocation, each with two ghost rows
+    // on either side: one buffer resource spans them all and each is addressed by its byte offset
+    // (fewer scalar registers than a resource per buffer).  Row r of buffer k is at ok + r rowb.
+    const char* fall = (const char*)I.f[0] - 2 * (size_t)rowb;
+    const rsrc_t rs = make_rsrc(fall, (size_t)((const char*)I.f[2] - fall) + (size_t)(nr + 2) * rowb);
+    const int osrc = (int)((const char*)I.f[src] - fall), ofn = (int)((const char*)I.f[fn] - fall);
+    // output: the dst buffer, or the right-hand side in the instance's scratch (FP64)
+    const rsrc_t ro = RHS ? make_rsrc(I.scratch, (size_t)nr * nv * 8) : rs;
+    const int oout = RHS ? 0 : (int)((const char*)I.f[dst] - fall);
     // stored value of cell c (F32: the deviation only; its base is added separately)
     auto cell = [&](int c, unsigned vo) {
         if constexpr (F32)
-            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0));
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, osrc + min(c, nr + 1) * rowb, 0));
         else
-            return bload(rf, vo, (min(c, nr + 1) + 2) * rowb);
+            return bload(rs, vo, osrc + min(c, nr + 1) * rowb);
     };
     auto fn_load = [&](int row, unsigned vo) {
         if constexpr (F32)
-            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0));
+            return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, ofn + row * rowb, 0));
         else
-            return bload(rfn, vo, row * rowb);
+            return bload(rs, vo, ofn + row * rowb);
     };
     // FP32 storage, loads ahead: the raw bits stay in a register until the value is needed (a
     // conversion right after the load would wait for it there)
     auto cell_raw = [&](int c, unsigned vo) {
-        return __builtin_amdgcn_raw_buffer_load_b32(rf, vo, (min(c, nr + 1) + 2) * rowb, 0);
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, osrc + min(c, nr + 1) * rowb, 0);
     };
-    auto fn_raw = [&](int row, unsigned vo) { return __builtin_amdgcn_raw_buffer_load_b32(rfn, vo, row * rowb, 0); };
+    auto fn_raw = [&](int row, unsigned vo) { return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, ofn + row * rowb, 0); };
     auto as_f64 = [](unsigned bits) { return (double)__builtin_bit_cast(float, bits); };
     const int ng = n0 + n1 + n2;
     // velocity shift of the tile: the velocity of its first node (common to all its slices)
@@ -1329,10 +1334,10 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                         } else {
                             const double dev = o - (nnode * g0) * (g1 * g2);
                             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)dev), ro, voff[j],
-                                                                  i * rowb, 0);
+                                                                  oout + i * rowb, 0);
                         }
                     } else {
-                        bstore(ro, voff[j], i * rowb, o);
+                        bstore(ro, voff[j], oout + i * rowb, o);
                     }
                     if (!rhs) op[buf * G.op_sz + ibx[j]] = o;
                 }
@@ -1840,8 +1845,13 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
                                  int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst,
                                  hipStream_t s)
 {
-    hipLaunchKernelGGL((k_stage<VPT, F32>), dim3(nitems), dim3(G.block), (size_t)G.lds_doubles * sizeof(double), s, d,
-                       items, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst);
+    const size_t lds = (size_t)G.lds_doubles * sizeof(double);
+    if (rhs)
+        hipLaunchKernelGGL((k_stage<VPT, F32, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn, dst, an,
+                           bs, bsrc, bfn, bdst);
+    else
+        hipLaunchKernelGGL((k_stage<VPT, F32, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn, dst,
+                           an, bs, bsrc, bfn, bdst);
     return hipGetLastError();
 }
 
@@ -1867,13 +1877,13 @@ hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ni
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-    hipError_t e = hipFuncSetAttribute((const void*)k_stage<1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_stage<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_stage<1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_stage<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* fns[8] = {(const void*)k_stage<1, false, false>, (const void*)k_stage<2, false, false>,
+                          (const void*)k_stage<1, true, false>,  (const void*)k_stage<2, true, false>,
+                          (const void*)k_stage<1, false, true>,  (const void*)k_stage<2, false, true>,
+                          (const void*)k_stage<1, true, true>,   (const void*)k_stage<2, true, true>};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 8 && e == hipSuccess; k++)
+        e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
 
