@@ -1343,7 +1343,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 }
             }
             // the loads ahead are issued unconditionally (after the tile's last node they read
-            // clamped cells and the zero row past f^n, unused): with no branch around them the
+            // clamped cells and f^n's ghost row nr, unused): with no branch around them the
             // compiler can count them exactly and wait only for the load each use needs
             const int fnrow = need_fn ? i + 1 : nr;
 #pragma unroll
