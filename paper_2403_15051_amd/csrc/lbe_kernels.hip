@@ -1165,21 +1165,20 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         const int i4 = lane & 3, b4 = (lane >> 2) & 3, k4 = lane >> 4;
         const double* ap = op + (t & 1) * G.op_sz + (16 * ct + 4 * b4 + i4) * cs + k4;
         const double* bp = y0p + 4 * k4 + i4;
-        const int nk = G.n0k;
+        const int nk = G.n0k;  // a multiple of 4
         double d1 = 0.0;
-        for (int ks = 0; ks < nk; ks += 16) {
+        int ks = 0;
+        for (; ks + 16 <= nk; ks += 16) {
             double a[4], b[4];
 #pragma unroll
             for (int m = 0; m < 4; m++) {
-                const bool ok = ks + 4 * m < nk;
-                a[m] = ok ? ap[ks + 4 * m] : 0.0;
-                b[m] = ok ? bp[4 * (ks + 4 * m)] : 0.0;
+                a[m] = ap[ks + 4 * m];
+                b[m] = bp[4 * (ks + 4 * m)];
             }
-            d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[0], b[0], d1, 0, 0, 0);
 #pragma unroll
-            for (int m = 1; m < 4; m++)
-                if (ks + 4 * m < nk) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[m], b[m], d1, 0, 0, 0);
+            for (int m = 0; m < 4; m++) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[m], b[m], d1, 0, 0, 0);
         }
+        for (; ks < nk; ks += 4) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(ap[ks], bp[4 * ks], d1, 0, 0, 0);
         const double* pp = psi + (16 * ct + 4 * b4 + k4) * 16 + i4;
         double d2[3];
 #pragma unroll
@@ -1236,22 +1235,22 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         const double lf = lds[T.lftab + q16];
         const double* ap = lds + T.abase + q16 * T.arow + q4;
         const double* bp = lds + T.bbase + buf * G.plane_sz + col + q4 * T.bk;
-        const int nk = T.nk, bk = T.bk;
-        // operands of four k-steps are read together, then their MFMAs issue back to back
+        const int nk = T.nk, bk = T.bk;  // nk: a multiple of 4
+        // operands of four k-steps are read together, then their MFMAs issue back to back; the
+        // k-steps beyond the last whole group of four follow one by one (same order)
         v4d acc = {0, 0, 0, 0};
-        for (int ks = 0; ks < nk; ks += 16) {
+        int ks = 0;
+        for (; ks + 16 <= nk; ks += 16) {
             double a[4], b[4];
 #pragma unroll
             for (int m = 0; m < 4; m++) {
-                const bool ok = ks + 4 * m < nk;
-                a[m] = ok ? ap[ks + 4 * m] : 0.0;
-                b[m] = ok ? bp[(ks + 4 * m) * bk] : 0.0;
+                a[m] = ap[ks + 4 * m];
+                b[m] = bp[(ks + 4 * m) * bk];
             }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
 #pragma unroll
-            for (int m = 1; m < 4; m++)
-                if (ks + 4 * m < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
+            for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
         }
+        for (; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
         if (q16 < T.okl) {
             const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
             double* o = lds + T.out + buf * G.ib_sz + T.obase + col + q4 * T.orow;
