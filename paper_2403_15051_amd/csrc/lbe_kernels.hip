@@ -1238,8 +1238,25 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         const int nk = T.nk, bk = T.bk;  // nk: a multiple of 4
         // operands of four k-steps are read together, then their MFMAs issue back to back; the
         // k-steps beyond the last whole group of four follow one by one (same order)
-        v4d acc = {0, 0, 0, 0};
-        int ks = 0;
+        // (the first step takes a zero accumulator as a constant)
+        const v4d zero = {0, 0, 0, 0};
+        v4d acc;
+        int ks;
+        if (nk >= 16) {
+            double a[4], b[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                a[m] = ap[4 * m];
+                b[m] = bp[4 * m * bk];
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], zero, 0, 0, 0);
+#pragma unroll
+            for (int m = 1; m < 4; m++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
+            ks = 16;
+        } else {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[0], bp[0], zero, 0, 0, 0);
+            ks = 4;
+        }
         for (; ks + 16 <= nk; ks += 16) {
             double a[4], b[4];
 #pragma unroll
@@ -1251,9 +1268,12 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
         }
         for (; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
-        if (q16 < T.okl) {
-            const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
-            double* o = lds + T.out + buf * G.ib_sz + T.obase + col + q4 * T.orow;
+        const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
+        double* o = lds + T.out + buf * G.ib_sz + T.obase + col + q4 * T.orow;
+        if (T.okl >= 16 && T.rowlim >= 16) {  // a whole tile: no lane or row guard
+#pragma unroll
+            for (int r = 0; r < 4; r++) o[4 * r * T.orow] = fac * acc[r];
+        } else if (q16 < T.okl) {
 #pragma unroll
             for (int r = 0; r < 4; r++)
                 if (q4 + 4 * r < T.rowlim) o[4 * r * T.orow] = fac * acc[r];
