@@ -86,8 +86,9 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
 /* Build the tables of every instance on the host (quadratures Sec. III, force matrices
  * Sec. III.B, averaged-density weights eq. (fm) / Appendix A, wall Maxwellians), upload
  * them into device_ws (>= lbe_query's device_bytes, 256-byte aligned) on hip_stream
- * (a hipStream_t, or NULL for the default stream), set every instance to the rest start
- * (n = 1, u = 0, T = 1) and compute its moments.  *out receives the context. */
+ * (a hipStream_t, or NULL for the default stream), derive on the device the stage kernel's
+ * per-slice table images (its constant LDS contents, written once), set every instance to the
+ * rest start (n = 1, u = 0, T = 1) and compute its moments.  *out receives the context. */
 lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t ws_bytes, void* hip_stream,
                     lbe_ctx** out);
 
