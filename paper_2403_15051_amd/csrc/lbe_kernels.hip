@@ -599,10 +599,12 @@ __device__ inline double weno_flux(double a, double b, double c, double d, doubl
 //   A: abase + q16 * arow + q4 + k,   B: bbase + col + (q4 + k) * bk,
 // where col = q16 * bcol, or the table ctab[q16] when bcol = 0.  Contraction tiles then write
 // fac * D[q4 + 4r][q16] (fac = ffac * lftab[q16], lanes q16 < okl, rows q4 + 4r < rowlim) to
-// out + obase + col + (q4 + 4r) * orow.  Moment tiles (type 1) only name their column tile (ct).
+// out + obase + col + (q4 + 4r) * orow.  Type: 0 a contraction tile with a ragged edge, 2 a whole
+// one (okl and rowlim >= 16), 1 moment sums (over column tile ct, nk = n0k).  The first four
+// fields are the ones a wave reads at every node; the rest fix its per-lane offsets.
 enum TileDesc {
-    TD_TYPE = 0, TD_ABASE, TD_AROW, TD_BBASE, TD_BK, TD_NK, TD_BCOL, TD_CTAB, TD_LFTAB, TD_OKL, TD_OBASE, TD_OROW,
-    TD_ROWLIM, TD_OUT, TD_CT, TD_COUNT
+    TD_TYPE = 0, TD_NK, TD_BK, TD_OROW, TD_OKL, TD_ROWLIM, TD_ABASE, TD_AROW, TD_BBASE, TD_BCOL, TD_CTAB, TD_LFTAB,
+    TD_OBASE, TD_OUT, TD_CT, TD_COUNT
 };
 
 // Per-node coefficients of the stage update, written by the workgroup set-up:
@@ -766,6 +768,7 @@ __device__ void stage_image(const DevInstance& I, const StageGroup& G, int slice
         for (int k = 0; k < kTileDescStride; k++) d[k] = 0;
         if (tile < nTm) {  // moment tile: columns 16 tile .. 16 tile + 15 of the output plane
             d[TD_TYPE] = 1;
+            d[TD_NK] = G.n0k;
             d[TD_CT] = tile;
             continue;
         }
@@ -816,6 +819,7 @@ __device__ void stage_image(const DevInstance& I, const StageGroup& G, int slice
             d[TD_ROWLIM] = G.ns2 - 16 * mt;
             d[TD_OUT] = G.off_ibuf + 2 * cs * ncol;
         }
+        d[TD_TYPE] = d[TD_OKL] >= 16 && d[TD_ROWLIM] >= 16 ? 2 : 0;
     }
     for (int e = tid; e < G.n0p; e += B) pv0[e] = e < n0 ? I.p0[e] : 0.0;
     for (int e = tid; e < G.ncols16; e += B) {
@@ -877,7 +881,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
 // completed one node after their load (the ring slot of cell i + 4), so no load is waited for
 // earlier than in the FP64 path.
-template <int VPT, bool F32, bool RHS>
+template <int VPT, bool F32, bool RHS, bool ONE>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
                                                  int fn, int dst, double an, double bs, int bsrc, int bfn, int bdst)
@@ -1161,10 +1165,24 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     //   D2[b][m][a] = sum_c Psi[4b + c][4g + m] D1[b][c][a]      (transverse factors 4g .. 4g + 3)
     // D1 is the second product's B operand as it stands (its row index is the contraction
     // index); the four blocks' partial D2 are then summed across lanes by row rotations.
-    auto moment_tile = [&](int ct, int t) {
+    // Per-lane offsets of a moment tile over column tile ct: A operand in the output plane, B
+    // operand in the y_r power table, transverse factors in psi, destination in the partial sums.
+    struct TileOffs {
+        int a, b, o, l;
+    };
+    auto moment_offs = [&](int ct) {
         const int i4 = lane & 3, b4 = (lane >> 2) & 3, k4 = lane >> 4;
-        const double* ap = op + (t & 1) * G.op_sz + (16 * ct + 4 * b4 + i4) * cs + k4;
-        const double* bp = y0p + 4 * k4 + i4;
+        TileOffs f;
+        f.a = (16 * ct + 4 * b4 + i4) * cs + k4;
+        f.b = 4 * k4 + i4;
+        f.l = (16 * ct + 4 * b4 + k4) * 16 + i4;
+        f.o = ct * 36 + i4;
+        return f;
+    };
+    auto moment_tile = [&](const TileOffs& f, int t) {
+        const int i4 = lane & 3, b4 = (lane >> 2) & 3, k4 = lane >> 4;
+        const double* ap = op + (t & 1) * G.op_sz + f.a;
+        const double* bp = y0p + f.b;
         const int nk = G.n0k;  // a multiple of 4
         double d1 = 0.0;
         int ks = 0;
@@ -1179,7 +1197,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             for (int m = 0; m < 4; m++) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[m], b[m], d1, 0, 0, 0);
         }
         for (; ks < nk; ks += 4) d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(ap[ks], bp[4 * ks], d1, 0, 0, 0);
-        const double* pp = psi + (16 * ct + 4 * b4 + k4) * 16 + i4;
+        const double* pp = psi + f.l;
         double d2[3];
 #pragma unroll
         for (int g = 0; g < 3; g++) {
@@ -1190,7 +1208,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         }
         // lane (a, b = 0, m): D2[4g + m][a], written as the tile's [m][a] block of 9 x 4
         if (b4 == 0) {
-            double* dst = spart + (t * nTm + ct) * 36 + i4;
+            double* dst = spart + t * nTm * 36 + f.o;
             dst[4 * k4] = d2[0];
             dst[4 * (4 + k4)] = d2[1];
             if (k4 == 0) dst[32] = d2[2];
@@ -1198,47 +1216,54 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     };
     // A tile descriptor in scalar registers, read with four 16-byte LDS loads and one wait.
     struct Tile {
-        int type, abase, arow, bbase, bk, nk, bcol, ctab, lftab, okl, obase, orow, rowlim, out, ct;
+        int type, nk, bk, orow, okl, rowlim, abase, arow, bbase, bcol, ctab, lftab, obase, out, ct;
     };
     auto load_tile = [&](int slot) {
         const int4* q = (const int4*)(tdesc + slot * kTileDescStride);
         const int4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        const int w[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                           q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
         Tile T;
-        T.type = __builtin_amdgcn_readfirstlane(q0.x);
-        T.abase = __builtin_amdgcn_readfirstlane(q0.y);
-        T.arow = __builtin_amdgcn_readfirstlane(q0.z);
-        T.bbase = __builtin_amdgcn_readfirstlane(q0.w);
-        T.bk = __builtin_amdgcn_readfirstlane(q1.x);
-        T.nk = __builtin_amdgcn_readfirstlane(q1.y);
-        T.bcol = __builtin_amdgcn_readfirstlane(q1.z);
-        T.ctab = __builtin_amdgcn_readfirstlane(q1.w);
-        T.lftab = __builtin_amdgcn_readfirstlane(q2.x);
-        T.okl = __builtin_amdgcn_readfirstlane(q2.y);
-        T.obase = __builtin_amdgcn_readfirstlane(q2.z);
-        T.orow = __builtin_amdgcn_readfirstlane(q2.w);
-        T.rowlim = __builtin_amdgcn_readfirstlane(q3.x);
-        T.out = __builtin_amdgcn_readfirstlane(q3.y);
-        T.ct = __builtin_amdgcn_readfirstlane(q3.z);
+        T.type = __builtin_amdgcn_readfirstlane(w[TD_TYPE]);
+        T.nk = __builtin_amdgcn_readfirstlane(w[TD_NK]);
+        T.bk = __builtin_amdgcn_readfirstlane(w[TD_BK]);
+        T.orow = __builtin_amdgcn_readfirstlane(w[TD_OROW]);
+        T.okl = __builtin_amdgcn_readfirstlane(w[TD_OKL]);
+        T.rowlim = __builtin_amdgcn_readfirstlane(w[TD_ROWLIM]);
+        T.abase = __builtin_amdgcn_readfirstlane(w[TD_ABASE]);
+        T.arow = __builtin_amdgcn_readfirstlane(w[TD_AROW]);
+        T.bbase = __builtin_amdgcn_readfirstlane(w[TD_BBASE]);
+        T.bcol = __builtin_amdgcn_readfirstlane(w[TD_BCOL]);
+        T.ctab = __builtin_amdgcn_readfirstlane(w[TD_CTAB]);
+        T.lftab = __builtin_amdgcn_readfirstlane(w[TD_LFTAB]);
+        T.obase = __builtin_amdgcn_readfirstlane(w[TD_OBASE]);
+        T.out = __builtin_amdgcn_readfirstlane(w[TD_OUT]);
+        T.ct = __builtin_amdgcn_readfirstlane(w[TD_CT]);
         return T;
     };
-    static_assert(TD_CT == 14 && kTileDescStride == 16, "tile descriptor layout");
-
-    // One MFMA tile: a contraction of node t (plane and term buffers t mod 2) or the moment sums
-    // of node t.
-    auto run_tile = [&](const Tile& T, int t) {
-        if (T.type == 1) {
-            moment_tile(T.ct, t);
-            return;
-        }
-        const int buf = t & 1;
+    static_assert(TD_CT == 14 && TD_OKL == 4 && TD_ROWLIM == 5 && kTileDescStride == 16, "tile descriptor layout");
+    // per-lane offsets of a contraction tile (A, B, output without the buffer, lane factor)
+    auto contraction_offs = [&](const Tile& T) {
         const int col = T.bcol ? q16 * T.bcol : ctabs[T.ctab + q16];
-        const double lf = lds[T.lftab + q16];
-        const double* ap = lds + T.abase + q16 * T.arow + q4;
-        const double* bp = lds + T.bbase + buf * G.plane_sz + col + q4 * T.bk;
-        const int nk = T.nk, bk = T.bk;  // nk: a multiple of 4
-        // operands of four k-steps are read together, then their MFMAs issue back to back; the
-        // k-steps beyond the last whole group of four follow one by one (same order)
-        // (the first step takes a zero accumulator as a constant)
+        TileOffs f;
+        f.a = T.abase + q16 * T.arow + q4;
+        f.b = T.bbase + col + q4 * T.bk;
+        f.o = T.out + T.obase + col + q4 * T.orow;
+        f.l = T.lftab + q16;
+        return f;
+    };
+
+    // One contraction tile of node t (plane and term buffers t mod 2).  whole: no lane or row
+    // guard; otherwise lanes q16 < okl and rows q4 + 4r < rowlim are written.
+    auto contraction_tile = [&](const TileOffs& f, int t, int nk, int bk, int orow, bool whole, int okl,
+                                int rowlim) {
+        const int buf = t & 1;
+        const double lf = lds[f.l];
+        const double* ap = lds + f.a;
+        const double* bp = lds + f.b + buf * G.plane_sz;
+        // nk is a multiple of 4: operands of four k-steps are read together, then their MFMAs
+        // issue back to back; the k-steps beyond the last whole group of four follow one by one
+        // (same order; the first step takes a zero accumulator as a constant)
         const v4d zero = {0, 0, 0, 0};
         v4d acc;
         int ks;
@@ -1269,22 +1294,53 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         }
         for (; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
         const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
-        double* o = lds + T.out + buf * G.ib_sz + T.obase + col + q4 * T.orow;
-        if (T.okl >= 16 && T.rowlim >= 16) {  // a whole tile: no lane or row guard
+        double* o = lds + f.o + buf * G.ib_sz;
+        if (whole) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) o[4 * r * T.orow] = fac * acc[r];
-        } else if (q16 < T.okl) {
+            for (int r = 0; r < 4; r++) o[4 * r * orow] = fac * acc[r];
+        } else if (q16 < okl) {
 #pragma unroll
             for (int r = 0; r < 4; r++)
-                if (q4 + 4 * r < T.rowlim) o[4 * r * T.orow] = fac * acc[r];
+                if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
         }
     };
+    // ONE (no more tiles than waves): the wave's tile (slot = wave) keeps its per-lane offsets in
+    // registers over the node loop and reads only the descriptor's first four fields per node.
+    // Otherwise (small workgroups) a wave runs slots wave, wave + W, ... and reads each whole
+    // descriptor every time.
+    TileOffs f1 = {0, 0, 0, 0};
+    if (ONE && wave < nTall) {
+        const Tile T = load_tile(wave);
+        f1 = T.type == 1 ? moment_offs(T.ct) : contraction_offs(T);
+    }
     // The wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0).
     auto run_tiles = [&](int tc, int tm) {
+        const bool cok = tc >= 0 && tc < it.nt, mok = tm >= 0 && !rhs;
+        if (ONE && wave < nTall) {
+            const int4 h = *(const int4*)(tdesc + wave * kTileDescStride);
+            const int type = __builtin_amdgcn_readfirstlane(h.x);
+            if (type == 1) {
+                if (mok) moment_tile(f1, tm);
+            } else if (cok) {
+                const int nk = __builtin_amdgcn_readfirstlane(h.y), bk = __builtin_amdgcn_readfirstlane(h.z);
+                const int orow = __builtin_amdgcn_readfirstlane(h.w);
+                if (type == 2) {
+                    contraction_tile(f1, tc, nk, bk, orow, true, 16, 16);
+                } else {
+                    const int2 g = *(const int2*)(tdesc + wave * kTileDescStride + TD_OKL);
+                    contraction_tile(f1, tc, nk, bk, orow, false, __builtin_amdgcn_readfirstlane(g.x),
+                                     __builtin_amdgcn_readfirstlane(g.y));
+                }
+            }
+        }
+        if (ONE) return;
         for (int slot = wave; slot < nTall; slot += W) {
             const Tile T = load_tile(slot);
-            const bool mom = T.type == 1;
-            if (mom ? (tm >= 0 && !rhs) : (tc >= 0 && tc < it.nt)) run_tile(T, mom ? tm : tc);
+            if (T.type == 1) {
+                if (mok) moment_tile(moment_offs(T.ct), tm);
+            } else if (cok) {
+                contraction_tile(contraction_offs(T), tc, T.nk, T.bk, T.orow, T.type == 2, T.okl, T.rowlim);
+            }
         }
     };
 
@@ -1865,12 +1921,19 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
                                  hipStream_t s)
 {
     const size_t lds = (size_t)G.lds_doubles * sizeof(double);
-    if (rhs)
-        hipLaunchKernelGGL((k_stage<VPT, F32, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn, dst, an,
-                           bs, bsrc, bfn, bdst);
+    const bool one = G.ntiles <= G.block / 64;
+    if (rhs && one)
+        hipLaunchKernelGGL((k_stage<VPT, F32, true, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
+                           dst, an, bs, bsrc, bfn, bdst);
+    else if (rhs)
+        hipLaunchKernelGGL((k_stage<VPT, F32, true, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
+                           dst, an, bs, bsrc, bfn, bdst);
+    else if (one)
+        hipLaunchKernelGGL((k_stage<VPT, F32, false, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
+                           dst, an, bs, bsrc, bfn, bdst);
     else
-        hipLaunchKernelGGL((k_stage<VPT, F32, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn, dst,
-                           an, bs, bsrc, bfn, bdst);
+        hipLaunchKernelGGL((k_stage<VPT, F32, false, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
+                           dst, an, bs, bsrc, bfn, bdst);
     return hipGetLastError();
 }
 
@@ -1896,12 +1959,17 @@ hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ni
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-    const void* fns[8] = {(const void*)k_stage<1, false, false>, (const void*)k_stage<2, false, false>,
-                          (const void*)k_stage<1, true, false>,  (const void*)k_stage<2, true, false>,
-                          (const void*)k_stage<1, false, true>,  (const void*)k_stage<2, false, true>,
-                          (const void*)k_stage<1, true, true>,   (const void*)k_stage<2, true, true>};
+    const void* fns[16] = {
+        (const void*)k_stage<1, false, false, false>, (const void*)k_stage<2, false, false, false>,
+        (const void*)k_stage<1, true, false, false>,  (const void*)k_stage<2, true, false, false>,
+        (const void*)k_stage<1, false, true, false>,  (const void*)k_stage<2, false, true, false>,
+        (const void*)k_stage<1, true, true, false>,   (const void*)k_stage<2, true, true, false>,
+        (const void*)k_stage<1, false, false, true>,  (const void*)k_stage<2, false, false, true>,
+        (const void*)k_stage<1, true, false, true>,   (const void*)k_stage<2, true, false, true>,
+        (const void*)k_stage<1, false, true, true>,   (const void*)k_stage<2, false, true, true>,
+        (const void*)k_stage<1, true, true, true>,    (const void*)k_stage<2, true, true, true>};
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 8 && e == hipSuccess; k++)
+    for (int k = 0; k < 16 && e == hipSuccess; k++)
         e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
