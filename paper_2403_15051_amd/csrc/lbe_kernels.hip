@@ -881,7 +881,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
 // completed one node after their load (the ring slot of cell i + 4), so no load is waited for
 // earlier than in the FP64 path.
-template <int VPT, bool F32, bool RHS, bool ONE>
+template <int VPT, bool F32, bool RHS, int MT>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
                                                  int fn, int dst, double an, double bs, int bsrc, int bfn, int bdst)
@@ -1304,36 +1304,53 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 if (q4 + 4 * r < rowlim) o[4 * r * orow] = fac * acc[r];
         }
     };
-    // ONE (no more tiles than waves): the wave's tile (slot = wave) keeps its per-lane offsets in
-    // registers over the node loop and reads only the descriptor's first four fields per node.
-    // Otherwise (small workgroups) a wave runs slots wave, wave + W, ... and reads each whole
-    // descriptor every time.
-    TileOffs f1 = {0, 0, 0, 0};
-    if (ONE && wave < nTall) {
+    // MT = 1 or 2 (at most that many tiles per wave): the wave's tiles (slots wave, wave + W) keep
+    // their per-lane offsets in registers over the node loop and read only the descriptor's first
+    // four fields per node.  MT = 0 (small workgroups, more tiles): a wave runs slots wave,
+    // wave + W, ... and reads each whole descriptor every time.
+    TileOffs f1 = {0, 0, 0, 0}, f2 = {0, 0, 0, 0};
+    if (MT >= 1 && wave < nTall) {
         const Tile T = load_tile(wave);
         f1 = T.type == 1 ? moment_offs(T.ct) : contraction_offs(T);
     }
+    if (MT == 2 && wave + W < nTall) {
+        const Tile T = load_tile(wave + W);
+        f2 = T.type == 1 ? moment_offs(T.ct) : contraction_offs(T);
+    }
+    // tile in slot `slot` with offsets f: contractions of node tc (if cok), moments of tm (if mok)
+    auto held_tile = [&](const TileOffs& f, int slot, int tc, int tm, bool cok, bool mok) {
+        const int4 h = *(const int4*)(tdesc + slot * kTileDescStride);
+        const int type = __builtin_amdgcn_readfirstlane(h.x);
+        if (type == 1) {
+            if (mok) moment_tile(f, tm);
+        } else if (cok) {
+            const int nk = __builtin_amdgcn_readfirstlane(h.y), bk = __builtin_amdgcn_readfirstlane(h.z);
+            const int orow = __builtin_amdgcn_readfirstlane(h.w);
+            if (type == 2) {
+                contraction_tile(f, tc, nk, bk, orow, true, 16, 16);
+            } else {
+                const int2 g = *(const int2*)(tdesc + slot * kTileDescStride + TD_OKL);
+                contraction_tile(f, tc, nk, bk, orow, false, __builtin_amdgcn_readfirstlane(g.x),
+                                 __builtin_amdgcn_readfirstlane(g.y));
+            }
+        }
+    };
     // The wave's tiles: contractions of node tc (if 0 <= tc < nt), moments of node tm (if >= 0).
     auto run_tiles = [&](int tc, int tm) {
         const bool cok = tc >= 0 && tc < it.nt, mok = tm >= 0 && !rhs;
-        if (ONE && wave < nTall) {
-            const int4 h = *(const int4*)(tdesc + wave * kTileDescStride);
-            const int type = __builtin_amdgcn_readfirstlane(h.x);
-            if (type == 1) {
-                if (mok) moment_tile(f1, tm);
-            } else if (cok) {
-                const int nk = __builtin_amdgcn_readfirstlane(h.y), bk = __builtin_amdgcn_readfirstlane(h.z);
-                const int orow = __builtin_amdgcn_readfirstlane(h.w);
-                if (type == 2) {
-                    contraction_tile(f1, tc, nk, bk, orow, true, 16, 16);
-                } else {
-                    const int2 g = *(const int2*)(tdesc + wave * kTileDescStride + TD_OKL);
-                    contraction_tile(f1, tc, nk, bk, orow, false, __builtin_amdgcn_readfirstlane(g.x),
-                                     __builtin_amdgcn_readfirstlane(g.y));
-                }
+        if (MT == 1 && wave < nTall) held_tile(f1, wave, tc, tm, cok, mok);
+        if (MT == 2) {  // one copy of the tile code for both slots
+#pragma unroll 1
+            for (int k = 0; k < 2 && wave + k * W < nTall; k++) {
+                TileOffs f;
+                f.a = k ? f2.a : f1.a;
+                f.b = k ? f2.b : f1.b;
+                f.o = k ? f2.o : f1.o;
+                f.l = k ? f2.l : f1.l;
+                held_tile(f, wave + k * W, tc, tm, cok, mok);
             }
         }
-        if (ONE) return;
+        if (MT) return;
         for (int slot = wave; slot < nTall; slot += W) {
             const Tile T = load_tile(slot);
             if (T.type == 1) {
@@ -1921,19 +1938,21 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
                                  hipStream_t s)
 {
     const size_t lds = (size_t)G.lds_doubles * sizeof(double);
-    const bool one = G.ntiles <= G.block / 64;
-    if (rhs && one)
-        hipLaunchKernelGGL((k_stage<VPT, F32, true, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
-                           dst, an, bs, bsrc, bfn, bdst);
-    else if (rhs)
-        hipLaunchKernelGGL((k_stage<VPT, F32, true, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
-                           dst, an, bs, bsrc, bfn, bdst);
-    else if (one)
-        hipLaunchKernelGGL((k_stage<VPT, F32, false, true>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
-                           dst, an, bs, bsrc, bfn, bdst);
-    else
-        hipLaunchKernelGGL((k_stage<VPT, F32, false, false>), dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn,
-                           dst, an, bs, bsrc, bfn, bdst);
+    const int W = G.block / 64;
+    const int mt = G.ntiles <= W ? 1 : G.ntiles <= 2 * W ? 2 : 0;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nitems), dim3(G.block), lds, s, d, items, G, src, fn, dst, an, bs, bsrc, bfn,
+                           bdst);
+    };
+    if (rhs) {
+        if (mt == 1) go(k_stage<VPT, F32, true, 1>);
+        else if (mt == 2) go(k_stage<VPT, F32, true, 2>);
+        else go(k_stage<VPT, F32, true, 0>);
+    } else {
+        if (mt == 1) go(k_stage<VPT, F32, false, 1>);
+        else if (mt == 2) go(k_stage<VPT, F32, false, 2>);
+        else go(k_stage<VPT, F32, false, 0>);
+    }
     return hipGetLastError();
 }
 
@@ -1959,17 +1978,15 @@ hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ni
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-    const void* fns[16] = {
-        (const void*)k_stage<1, false, false, false>, (const void*)k_stage<2, false, false, false>,
-        (const void*)k_stage<1, true, false, false>,  (const void*)k_stage<2, true, false, false>,
-        (const void*)k_stage<1, false, true, false>,  (const void*)k_stage<2, false, true, false>,
-        (const void*)k_stage<1, true, true, false>,   (const void*)k_stage<2, true, true, false>,
-        (const void*)k_stage<1, false, false, true>,  (const void*)k_stage<2, false, false, true>,
-        (const void*)k_stage<1, true, false, true>,   (const void*)k_stage<2, true, false, true>,
-        (const void*)k_stage<1, false, true, true>,   (const void*)k_stage<2, false, true, true>,
-        (const void*)k_stage<1, true, true, true>,    (const void*)k_stage<2, true, true, true>};
+#define LBE_STAGE_FNS(MT)                                                                                   \
+    (const void*)k_stage<1, false, false, MT>, (const void*)k_stage<2, false, false, MT>,                   \
+        (const void*)k_stage<1, true, false, MT>, (const void*)k_stage<2, true, false, MT>,                 \
+        (const void*)k_stage<1, false, true, MT>, (const void*)k_stage<2, false, true, MT>,                 \
+        (const void*)k_stage<1, true, true, MT>, (const void*)k_stage<2, true, true, MT>
+    const void* fns[24] = {LBE_STAGE_FNS(0), LBE_STAGE_FNS(1), LBE_STAGE_FNS(2)};
+#undef LBE_STAGE_FNS
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 16 && e == hipSuccess; k++)
+    for (int k = 0; k < 24 && e == hipSuccess; k++)
         e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
