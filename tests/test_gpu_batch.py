@@ -117,9 +117,10 @@ def test_run_to_steady_reports_not_converged_and_partial_chunk():
 @pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
 def test_full_sweep_sampled_instances_match_oracle(precision, tol):
     """The 256-instance sweep at its full size, in the configuration bench.py times (autotuned
-    tiles, captured steps, forked group chains): after 3 steps, the smallest, the largest and the
-    first instance match the oracle run on their own (FP64 1e-12 normwise on f; FP32 storage 1e-5
-    on the profiles)."""
+    tiles, captured steps, forked group chains): after 3 steps, the smallest, the largest, the
+    first instance and the first of each velocity order (so every launch group, with its own
+    workgroup size and tile mode, is checked) match the oracle run on their own (FP64 1e-12
+    normwise on f; FP32 storage 1e-5 on the profiles)."""
     ps, _ = workloads.sweep(256)
     ps = [dict(workloads.solver_params(p), precision=precision) for p in ps]
     g = lbe.Solver(ps)
@@ -127,7 +128,8 @@ def test_full_sweep_sampled_instances_match_oracle(precision, tol):
     g.step(3)
     g.sync()
     size = [p["nr"] * (2 * p["q_radial"]) * p["q_t1"] * p["q_t2"] for p in ps]
-    for k in sorted({0, int(np.argmin(size)), int(np.argmax(size))}):
+    first_of_order = {next(k for k, p in enumerate(ps) if p["q_radial"] == q) for q in workloads.SWEEP_ORDERS}
+    for k in sorted({0, int(np.argmin(size)), int(np.argmax(size))} | first_of_order):
         p = {kk: v for kk, v in ps[k].items() if kk != "precision"}
         o = oracle.Solver(p)
         o.step(3)
