@@ -255,10 +255,12 @@ bool layout_group(StageGroup* G, int nt0)
     const int nTall = nTm + (G->n0p / 16) * (G->ncols16 / 16) + G->ns2 * (G->n1p / 16) * (G->n0p / 16) +
                       (sph ? (G->ns2p / 16) * (G->ncp16 / 16) : 0);
     G->ntiles = nTall;
-    // a few more MFMA tiles than waves (the 12^3 set's slices: 16 tiles over 14 waves): add the
-    // waves that give each tile a wave of its own (their lanes hold no velocity); the tile waves
-    // set the node interval, so two tiles on one wave cost more than the idle lanes
-    if (G->vpt == 1 && nTall > 2 * G->wh && nTall <= 2 * G->wh + 4 && (nTall + 1) / 2 * 128 <= 1024) {
+    // a few more MFMA tiles than waves (the 12^3 set's slices: 15 tiles over 14 waves): add the
+    // waves that give each tile a wave of its own (their lanes hold no velocity) when that adds at
+    // most a quarter to the workgroup; the tile waves set the node interval, so two tiles on one
+    // wave cost more than a few idle lanes (not more than tripling a small workgroup's lanes)
+    if (G->vpt == 1 && nTall > 2 * G->wh && 4 * ((nTall + 1) / 2 - G->wh) <= G->wh &&
+        (nTall + 1) / 2 * 128 <= 1024) {
         G->wh = (nTall + 1) / 2;
         G->block = 128 * G->wh;
     }
