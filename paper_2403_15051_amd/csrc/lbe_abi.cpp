@@ -664,7 +664,14 @@ hipError_t launch_steps_forked(lbe_ctx* c, int nsteps)
     }
     if (e == hipSuccess) e = hipEventRecord(c->gevents[ng], c->stream);
     for (int q = 1; q < ng && e == hipSuccess; q++) e = hipStreamWaitEvent(c->gstreams[q], c->gevents[ng], 0);
-    for (int q = 0; q < ng && e == hipSuccess; q++) e = launch_steps_group(c, q, nsteps, q == 0 ? c->stream : c->gstreams[q]);
+    // chains in order of increasing work (site-velocities of the group's work items), whatever the
+    // order of the instances: on the sweep, the heaviest first made the step 2.5 % slower
+    std::vector<int> ord(ng);
+    for (int q = 0; q < ng; q++) ord[q] = q;
+    auto work = [&](int q) { return (double)c->item_cnt[q] * c->groups[q].nvs * c->groups[q].NT; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) < work(b); });
+    for (int k = 0; k < ng && e == hipSuccess; k++)
+        e = launch_steps_group(c, ord[k], nsteps, k == 0 ? c->stream : c->gstreams[k]);
     // join (also after an error, so that no stream is left forked)
     for (int q = 1; q < ng; q++) {
         hipError_t ej = hipEventRecord(c->gevents[q], c->gstreams[q]);
