@@ -881,6 +881,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // equilibrium n g_0 g_1 g_2 of the src moments, whose factors go to base table bdst.  Reads are
 // completed one node after their load (the ring slot of cell i + 4), so no load is waited for
 // earlier than in the FP64 path.
+// VPT: velocities per lane (1 or 2); RHS: write the right-hand side L(f) to the instance's
+// scratch instead of the RK combination (lbe_rhs); MT: MFMA tiles a wave holds over the node loop, 1 or 2 (the
+// launch requires ntiles <= MT * waves), or 0 for workgroups with more tiles (descriptors reread).
 template <int VPT, bool F32, bool RHS, int MT>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
