@@ -3,6 +3,7 @@
 // Appendix A).  Everything here runs once per lbe_init, in long double where accuracy
 // matters, and is uploaded to the device.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -23,29 +24,91 @@ double chi_cs(double eta) { return (2 - eta) / (2 * (1 - eta) * (1 - eta) * (1 -
 
 // ------------------------------------------------------------------ quadratures (Sec. III)
 
-// Gauss-Legendre rule on [-1, 1] in long double (Newton on P_n).
+// Eigenvalues of the symmetric tridiagonal matrix with diagonal d[0..n-1] and off-diagonal e[1..n-1]
+// (e[i] couples rows i-1 and i), in increasing order, by bisection on Sturm counts: the number of
+// eigenvalues below x equals the number of negative pivots in the LDL^T factorisation of T - x I
+// (Sylvester's law of inertia).  Each eigenvalue is bracketed to a few units in the last place of
+// long double; the callers polish the zeros by Newton's method on the polynomial.
+static int pivots_below(const std::vector<ld>& d, const std::vector<ld>& e, ld x)
+{
+    int neg = 0;
+    ld piv = 1;
+    for (size_t i = 0; i < d.size(); i++) {
+        piv = (d[i] - x) - (i > 0 ? e[i] * e[i] / piv : 0);
+        if (piv == 0) piv = -LDBL_EPSILON * (fabsl(d[i]) + fabsl(x) + (i > 0 ? fabsl(e[i]) : 0) + LDBL_MIN);
+        if (piv < 0) neg++;
+    }
+    return neg;
+}
+
+static void tridiag_eigenvalues(const std::vector<ld>& d, const std::vector<ld>& e, std::vector<ld>& ev)
+{
+    const int n = (int)d.size();
+    ld lo = 0, hi = 0;  // Gershgorin bounds
+    for (int i = 0; i < n; i++) {
+        const ld r = (i > 0 ? fabsl(e[i]) : 0) + (i + 1 < n ? fabsl(e[i + 1]) : 0);
+        lo = i ? std::min(lo, d[i] - r) : d[i] - r;
+        hi = i ? std::max(hi, d[i] + r) : d[i] + r;
+    }
+    ev.assign(n, 0);
+    for (int k = 0; k < n; k++) {
+        // the k-th eigenvalue lies where the count of eigenvalues below x steps from k to k + 1
+        ld a = k > 0 ? ev[k - 1] : lo, b = hi;
+        for (int it = 0; it < 256; it++) {
+            const ld mid = a + (b - a) / 2;
+            if (mid <= a || mid >= b) break;
+            if (pivots_below(d, e, mid) > k)
+                b = mid;
+            else
+                a = mid;
+        }
+        ev[k] = a + (b - a) / 2;
+    }
+}
+
+// Gauss-Legendre rule on [-1, 1] in long double: the nodes are the eigenvalues of the Legendre
+// Jacobi matrix (zero diagonal, off-diagonal l / sqrt(4 l^2 - 1)), polished by Newton's method
+// on the orthonormal P_n; the weights are the Christoffel numbers 1 / sum_{l<n} p_l(x)^2 of the
+// orthonormal Legendre polynomials p_l = sqrt(l + 1/2) P_l.
+static void legendre_orthonormal(int n, ld x, ld* p, ld* dp)
+{
+    // p_{l+1} = (x p_l - beta_l p_{l-1}) / beta_{l+1}, beta_l = l / sqrt(4 l^2 - 1), p_0 = 1/sqrt 2
+    p[0] = 1 / sqrtl(2.0L);
+    dp[0] = 0;
+    ld bprev = 0;
+    for (int l = 0; l < n; l++) {
+        const ld bnext = (l + 1) / sqrtl((ld)(4 * (l + 1) * (l + 1) - 1));
+        const ld pm = l > 0 ? p[l - 1] : 0, dpm = l > 0 ? dp[l - 1] : 0;
+        p[l + 1] = (x * p[l] - bprev * pm) / bnext;
+        dp[l + 1] = (p[l] + x * dp[l] - bprev * dpm) / bnext;
+        bprev = bnext;
+    }
+}
+
 static void gauss_legendre(int n, std::vector<ld>& x, std::vector<ld>& w)
 {
-    x.assign(n, 0);
+    std::vector<ld> d(n, 0), e(n, 0);
+    for (int l = 1; l < n; l++) e[l] = l / sqrtl((ld)(4 * l * l - 1));
+    tridiag_eigenvalues(d, e, x);
+    std::vector<ld> p(n + 1), dp(n + 1);
     w.assign(n, 0);
-    for (int i = 0; i < (n + 1) / 2; i++) {
-        ld z = cosl(kPi * (i + 0.75L) / (n + 0.5L)), dp = 0;
-        for (int it = 0; it < 100; it++) {
-            ld p0 = 1, p1 = z;
-            for (int k = 2; k <= n; k++) {
-                ld p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = n * (z * p1 - p0) / (z * z - 1);
-            ld dz = p1 / dp;
-            z -= dz;
-            if (fabsl(dz) < 1e-19L) break;
+    for (int i = 0; i < n; i++) {
+        for (int it = 0; it < 2; it++) {
+            legendre_orthonormal(n, x[i], p.data(), dp.data());
+            x[i] -= p[n] / dp[n];
         }
-        x[i] = -z;
-        x[n - 1 - i] = z;
-        w[i] = w[n - 1 - i] = 2 / ((1 - z * z) * dp * dp);
+        legendre_orthonormal(n, x[i], p.data(), dp.data());
+        ld s = 0;
+        for (int l = 0; l < n; l++) s += p[l] * p[l];
+        w[i] = 1 / s;
     }
+    for (int i = 0; i < n / 2; i++) {  // exact mirror symmetry
+        const ld m = (x[n - 1 - i] - x[i]) / 2, wm = (w[i] + w[n - 1 - i]) / 2;
+        x[i] = -m;
+        x[n - 1 - i] = m;
+        w[i] = w[n - 1 - i] = wm;
+    }
+    if (n % 2) x[n / 2] = 0;
 }
 
 // Recurrence x h_l = b_{l+1} h_{l+1} + a_l h_l + b_l h_{l-1} of the polynomials orthonormal on
@@ -93,55 +156,6 @@ static void half_recurrence(int n, std::vector<ld>& a, std::vector<ld>& b)
             cur[m] = nxt[m] / bk;
         }
     }
-}
-
-// Eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e[1..n-1]) by the
-// implicit QL algorithm with Wilkinson shifts.
-static void tridiag_eigenvalues(std::vector<ld> d, std::vector<ld> e, std::vector<ld>& ev)
-{
-    const int n = (int)d.size();
-    e.push_back(0);
-    for (int i = 0; i < n - 1; i++) e[i] = e[i + 1];
-    e[n - 1] = 0;
-    for (int l = 0; l < n; l++) {
-        for (int iter = 0; iter < 200; iter++) {
-            int m;
-            for (m = l; m < n - 1; m++) {
-                volatile ld dd = fabsl(d[m]) + fabsl(d[m + 1]);
-                volatile ld sum = fabsl(e[m]) + dd;
-                if (sum == dd) break;
-            }
-            if (m == l) break;
-            ld g = (d[l + 1] - d[l]) / (2 * e[l]);
-            ld r = hypotl(g, 1.0L);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? fabsl(r) : -fabsl(r)));
-            ld s = 1, c = 1, p = 0;
-            int i;
-            for (i = m - 1; i >= l; i--) {
-                ld f = s * e[i], bb = c * e[i];
-                r = hypotl(f, g);
-                e[i + 1] = r;
-                if (r == 0) {
-                    d[i + 1] -= p;
-                    e[m] = 0;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2 * c * bb;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - bb;
-            }
-            if (r == 0 && i >= l) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0;
-        }
-    }
-    ev = d;
-    std::sort(ev.begin(), ev.end());
 }
 
 // Values of the orthonormal half-range polynomials h_0..h_n at x and their derivatives.
@@ -379,92 +393,42 @@ void equilibrium_axis(const AxisTables& ax, double u, double T, double* g)
 
 // ------------------------------------------------------------------ volumes (Appendix A)
 
-// Carlson's symmetric elliptic integrals R_F, R_D, R_C, R_J by the duplication theorem with
-// the fifth-order Taylor tails (B. C. Carlson, Numer. Algorithms 10 (1995) 13-26).
-static ld carlson_rf(ld x, ld y, ld z)
-{
-    for (int it = 0; it < 100; it++) {
-        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
-        ld lam = sx * (sy + sz) + sy * sz;
-        x = (x + lam) / 4;
-        y = (y + lam) / 4;
-        z = (z + lam) / 4;
-        ld mu = (x + y + z) / 3;
-        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu;
-        if (std::max(fabsl(dx), std::max(fabsl(dy), fabsl(dz))) < 2e-4L) {
-            ld e2 = dx * dy - dz * dz, e3 = dx * dy * dz;
-            return (1 - e2 / 10 + e3 / 14 + e2 * e2 / 24 - 3 * e2 * e3 / 44) / sqrtl(mu);
-        }
-    }
-    return NAN;
-}
+// Complete elliptic integrals by Gauss's arithmetic-geometric mean (DLMF 19.8.6-19.8.8), with
+// k2 = k^2 and the characteristic alpha2 < 1 of the third kind
+//   Pi(alpha2, k) = int_0^{pi/2} dt / ((1 - alpha2 sin^2 t) sqrt(1 - k2 sin^2 t)).
+// With a_0 = 1, b_0 = sqrt(1 - k2), a_{n+1} = (a_n + b_n)/2, b_{n+1} = sqrt(a_n b_n), c_0 = k,
+// c_{n+1} = (a_n - b_n)/2 and the common limit M:  K = pi/(2M),  E = K (1 - sum_n 2^(n-1) c_n^2);
+// with g_0 = sqrt(1 - alpha2), z_0 = 1, g_{n+1} = (g_n^2 + a_n b_n)/(2 g_n) and
+// z_{n+1} = z_n (g_n^2 - a_n b_n) / (2 (g_n^2 + a_n b_n)):  Pi = pi/(4M) (2 + alpha2/(1 - alpha2) sum_n z_n).
+// The iteration converges quadratically; a few steps reach long double rounding.
+struct CompleteElliptic {
+    ld K, E, Pi;
+};
 
-static ld carlson_rd(ld x, ld y, ld z)
+static CompleteElliptic complete_elliptic(ld k2, ld alpha2)
 {
-    ld sum = 0, fac = 1;
-    for (int it = 0; it < 100; it++) {
-        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
-        ld lam = sx * (sy + sz) + sy * sz;
-        sum += fac / (sz * (z + lam));
-        fac /= 4;
-        x = (x + lam) / 4;
-        y = (y + lam) / 4;
-        z = (z + lam) / 4;
-        ld mu = (x + y + 3 * z) / 5;
-        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu;
-        if (std::max(fabsl(dx), std::max(fabsl(dy), fabsl(dz))) < 2e-4L) {
-            ld ea = dx * dy, eb = dz * dz, ec = ea - eb, ed = ea - 6 * eb, ee = ed + ec + ec;
-            ld tail = 1 + ed * (-3.0L / 14 + 9.0L / 88 * ed - 9.0L / 52 * dz * ee) +
-                      dz * (ee / 6 + dz * (-9.0L / 22 * ec + 3.0L / 26 * dz * ea));
-            return 3 * sum + fac * tail / (mu * sqrtl(mu));
-        }
+    ld a = 1, b = sqrtl(1 - k2), g = sqrtl(1 - alpha2), z = 1;
+    ld csum = k2 / 2, zsum = 1, pow2 = 1;  // pow2 = 2^(n-1) for the next c_n
+    for (int it = 0; it < 64; it++) {
+        const ld ab = a * b, g2 = g * g;
+        const ld znext = z * (g2 - ab) / (2 * (g2 + ab));
+        const ld gnext = (g2 + ab) / (2 * g);
+        const ld c = (a - b) / 2;
+        const ld an = (a + b) / 2, bn = sqrtl(ab);
+        csum += pow2 * c * c;
+        zsum += znext;
+        pow2 *= 2;
+        a = an;
+        b = bn;
+        g = gnext;
+        z = znext;
+        if (fabsl(c) <= 1e-21L * a && fabsl(z) <= 1e-21L) break;
     }
-    return NAN;
-}
-
-static ld carlson_rc(ld x, ld y)
-{
-    for (int it = 0; it < 100; it++) {
-        ld lam = 2 * sqrtl(x) * sqrtl(y) + y;
-        x = (x + lam) / 4;
-        y = (y + lam) / 4;
-        ld mu = (x + y + y) / 3;
-        ld s = (y - mu) / mu;
-        if (fabsl(s) < 2e-4L)
-            return (1 + s * s * (0.3L + s * (1.0L / 7 + s * (0.375L + s * 9.0L / 22)))) / sqrtl(mu);
-    }
-    return NAN;
-}
-
-static ld carlson_rj(ld x, ld y, ld z, ld p)
-{
-    ld sum = 0, fac = 1;
-    for (int it = 0; it < 100; it++) {
-        ld sx = sqrtl(x), sy = sqrtl(y), sz = sqrtl(z);
-        ld lam = sx * (sy + sz) + sy * sz;
-        ld alpha = p * (sx + sy + sz) + sx * sy * sz;
-        alpha *= alpha;
-        ld beta = p * (p + lam) * (p + lam);
-        sum += fac * carlson_rc(alpha, beta);
-        fac /= 4;
-        x = (x + lam) / 4;
-        y = (y + lam) / 4;
-        z = (z + lam) / 4;
-        p = (p + lam) / 4;
-        ld mu = (x + y + z + p + p) / 5;
-        ld dx = (mu - x) / mu, dy = (mu - y) / mu, dz = (mu - z) / mu, dp = (mu - p) / mu;
-        ld m = std::max(std::max(fabsl(dx), fabsl(dy)), std::max(fabsl(dz), fabsl(dp)));
-        if (m < 2e-4L) {
-            ld ea = dx * (dy + dz) + dy * dz, eb = dx * dy * dz, ec = dp * dp, ed = ea - 3 * ec;
-            ld ee = eb + 2 * dp * (ea - ec);
-            const ld C1 = 3.0L / 14, C2 = 1.0L / 3, C3 = 3.0L / 22, C4 = 3.0L / 26;
-            const ld C5 = 0.75L * C3, C6 = 1.5L * C4, C7 = 0.5L * C2, C8 = C3 + C3;
-            ld tail = 1 + ed * (-C1 + C5 * ed - C6 * ee) + eb * (C7 + dp * (-C8 + dp * C4)) +
-                      dp * ea * (C2 - dp * C3) - C2 * dp * ec;
-            return 3 * sum + fac * tail / (mu * sqrtl(mu));
-        }
-    }
-    return NAN;
+    CompleteElliptic out;
+    out.K = kPi / (2 * a);
+    out.E = out.K * (1 - csum);
+    out.Pi = kPi / (4 * a) * (2 + alpha2 / (1 - alpha2) * zsum);
+    return out;
 }
 
 // Volume of the ball of radius s centred at distance b from the axis inside the cylinder of
@@ -483,11 +447,9 @@ double ball_in_cylinder(double s_, double R_, double b_)
     const ld k2 = (B - C) / (A - C);
     const ld m = (B - C) / C;  // the paper's -alpha^2
     const ld sg = (b + R) * (b - R);
-    const ld kc2 = 1 - k2;
-    const ld RF = carlson_rf(0, kc2, 1);
-    const ld Kk = RF;
-    const ld Ek = RF - k2 / 3 * carlson_rd(0, kc2, 1);
-    const ld Pk = RF - m / 3 * carlson_rj(0, kc2, 1, 1 + m);  // int dz/((1 + m z^2) sqrt..)
+    // K(k), E(k) and the third kind with alpha^2 = -m: int dz / ((1 + m z^2) sqrt((1 - z^2)(1 - k^2 z^2)))
+    const CompleteElliptic ell = complete_elliptic(k2, -m);
+    const ld Kk = ell.K, Ek = ell.E, Pk = ell.Pi;
     ld V = (R > b) ? ball : 0;
     V += 4 / (3 * sqrtl(A - C)) *
          (Pk * B * B * sg / C + Kk * (sg * (A - 2 * B) + (A - B) * (3 * B - C - 2 * A) / 3) +
