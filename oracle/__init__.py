@@ -63,7 +63,30 @@ def _load():
         return _lib
     if not os.path.exists(_LIB):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    _lib = _setup(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def load_variant(substitutions, workdir: str):
+    """Compile a copy of the oracle with textual substitutions [(old, new), ...] applied (each
+    ``old`` must occur exactly once) into ``workdir`` and load it.  Used only by the tests that
+    plant a deliberate mistake in the oracle to show that a pin catches it."""
+    src = open(_SRC).read()
+    for old, new in substitutions:
+        if src.count(old) != 1:
+            raise ValueError(f"substitution target must occur exactly once: {old!r}")
+        src = src.replace(old, new)
+    tag = str(abs(hash(tuple(substitutions))))
+    c = os.path.join(workdir, f"oracle_variant_{tag}.c")
+    so = os.path.join(workdir, f"oracle_variant_{tag}.so")
+    with open(c, "w") as fh:
+        fh.write(src)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11", "-o", so, c, "-lquadmath", "-lm"],
+                   check=True)
+    return _setup(ctypes.CDLL(so))
+
+
+def _setup(lib):
     vp = ctypes.c_void_p
     lib.orc_quad_half.argtypes = [ctypes.c_int, _D, _D]
     lib.orc_quad_full.argtypes = [ctypes.c_int, _D, _D]
@@ -96,7 +119,8 @@ def _load():
     lib.orc_step.argtypes = [vp, ctypes.c_int64]
     lib.orc_run_to_steady.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int64), _D]
-    for name in ("orc_moments", "orc_node_coeffs", "orc_rhs", "orc_get_f", "orc_set_f", "orc_get_W", "orc_info"):
+    for name in ("orc_moments", "orc_node_coeffs", "orc_node_grads", "orc_rhs", "orc_get_f", "orc_set_f",
+                 "orc_get_W", "orc_info"):
         getattr(lib, name).argtypes = [vp, _D]
     lib.orc_grid.argtypes = [vp, _D, _D, _D, _D]
     lib.orc_rhs_terms.argtypes = [vp, _D, _D, _D, _D]
@@ -104,7 +128,6 @@ def _load():
     lib.orc_mass.restype = ctypes.c_double
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_get_threads.restype = ctypes.c_int
-    _lib = lib
     return lib
 
 
@@ -234,8 +257,8 @@ def make_params(geometry, r_inner, r_outer, u_wall_inner, t_wall_inner, t_wall_o
 class Solver:
     """One FDLB solve on the CPU (FP64)."""
 
-    def __init__(self, params: Params | dict):
-        lib = _load()
+    def __init__(self, params: Params | dict, lib=None):
+        lib = lib if lib is not None else _load()
         if isinstance(params, dict):
             params = make_params(**params)
         st = ctypes.c_int(0)
@@ -293,6 +316,13 @@ class Solver:
         self._lib.orc_node_coeffs(self._h, _ptr(out))
         out = out.reshape(5, self.nr)
         return {k: out[i].copy() for i, k in enumerate(("tau", "Pr", "brhochi", "q_t1", "q_t2"))}
+
+    def node_grads(self) -> dict:
+        """Radial gradients entering J1: d ln(n^2 chi T), d ln T and du of the three components."""
+        out = np.zeros(5 * self.nr)
+        self._lib.orc_node_grads(self._h, _ptr(out))
+        out = out.reshape(5, self.nr)
+        return {k: out[i].copy() for i, k in enumerate(("dlog_nnchiT", "dlogT", "du_r", "du_t1", "du_t2"))}
 
     def rhs(self) -> np.ndarray:
         out = np.zeros(self.nr * self.nv)

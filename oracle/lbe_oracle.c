@@ -838,6 +838,7 @@ typedef struct {
 typedef struct {
     double n, u[3], T, q[3], P[3][3];
     double nbar, chi, tau, Pr, brhochi;
+    double dlog_nnchiT, dlogT, du[3]; /* radial gradients used by J1 */
 } node_t;
 
 static inline void vel_of(const orc_solver* s, int v, double p[3])
@@ -1134,6 +1135,9 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
         dg1[i] = fd4(g1, i, nr, s->dr);
         dg2[i] = fd4(g2, i, nr, s->dr);
         for (int a = 0; a < 3; a++) du[a * nr + i] = fd4(ua + a * nr, i, nr, s->dr);
+        nd[i].dlog_nnchiT = dg1[i];
+        nd[i].dlogT = dg2[i];
+        for (int a = 0; a < 3; a++) nd[i].du[a] = du[a * nr + i];
     }
 
     /* (5) wall densities.  Reading (diffuse reflection): two ghost cells per side; for
@@ -1434,6 +1438,21 @@ int orc_node_coeffs(orc_solver* s, double* out)
         out[2 * nr + i] = nd[i].brhochi;
         out[3 * nr + i] = nd[i].q[1];
         out[4 * nr + i] = nd[i].q[2];
+    }
+    free(nd);
+    return ORC_OK;
+}
+
+/* Radial gradients [field][nr] entering J1 (for pins): d ln(n^2 chi T), d ln T, du_r, du_t1, du_t2. */
+int orc_node_grads(orc_solver* s, double* out)
+{
+    const int nr = s->nr;
+    node_t* nd = malloc(sizeof(node_t) * nr);
+    compute_rhs(s, s->f, s->Lbuf, nd);
+    for (int i = 0; i < nr; i++) {
+        out[0 * nr + i] = nd[i].dlog_nnchiT;
+        out[1 * nr + i] = nd[i].dlogT;
+        for (int a = 0; a < 3; a++) out[(2 + a) * nr + i] = nd[i].du[a];
     }
     free(nd);
     return ORC_OK;
