@@ -92,6 +92,18 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
 lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t ws_bytes, void* hip_stream,
                     lbe_ctx** out);
 
+/* lbe_init without a caller workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the context
+ * lives in a device array inside the library, 64 MiB, one copy per GPU, held by each GPU the
+ * library runs on until the process ends.  The call itself allocates no device memory.  Same
+ * arguments and effect as lbe_init otherwise.  Returns LBE_ENOMEM when lbe_query's device_bytes
+ * exceed 64 MiB, LBE_ESTATE when a context made by this call on the current device has not been
+ * freed yet (there is one such workspace per GPU: contexts on it would overwrite each other), and
+ * LBE_EDEVICE when the array's address cannot be obtained.  lbe_free releases the workspace for
+ * the next call after waiting for the context's stream.  The workspace keeps the previous
+ * context's contents; lbe_init writes everything it later reads. */
+lbe_status lbe_init_static(const lbe_params* p, int32_t n_inst, void* hip_stream, lbe_ctx** out);
+
 /* Enqueue nsteps full TVD-RK3 steps of every instance on the context's stream (async).  The
  * launches of one step are captured once into a HIP graph and replayed (set LBE_GRAPH=0 in the
  * environment before lbe_init to launch them one by one); instances sharing a velocity set form a

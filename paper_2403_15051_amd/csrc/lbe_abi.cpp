@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <atomic>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -103,6 +104,8 @@ struct lbe_ctx {
     hipGraphExec_t g_step = nullptr, g_chunk = nullptr;
     int g_chunk_n = 0;
     double g_chunk_tol = 0;
+    // device whose static workspace this context occupies (lbe_init_static), -1 otherwise
+    int static_dev = -1;
 };
 
 namespace {
@@ -770,6 +773,23 @@ lbe_status check_nan(lbe_ctx* c)
 
 }  // namespace
 
+static __device__ __align__(256) char scratch[size_t(64) << 20];
+
+namespace {
+
+// Workspace of lbe_init_static: a file-scope device array, one copy per GPU, held by every GPU
+// the library runs on until the process ends.  Host code never passes the array's name to the
+// device (on the host it is only a stand-in symbol): the device address of each GPU's copy is
+// looked up once per device with hipGetSymbolAddress and kept in static_ws_addr.
+constexpr size_t kStaticWsBytes = size_t(64) << 20;
+constexpr int kStaticMaxDevices = 64;
+std::mutex static_ws_mu;
+void* static_ws_addr[kStaticMaxDevices] = {};
+bool static_ws_busy[kStaticMaxDevices] = {};
+static_assert(sizeof(scratch) == kStaticWsBytes, "static workspace size");
+
+}  // namespace
+
 extern "C" {
 
 const char* lbe_status_string(lbe_status s)
@@ -1032,6 +1052,32 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         delete c;
         return st;
     }
+    *out = c;
+    return LBE_OK;
+}
+
+lbe_status lbe_init_static(const lbe_params* p, int32_t n_inst, void* hip_stream, lbe_ctx** out)
+{
+    if (!p || n_inst < 1 || !out) return LBE_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    lbe_status st = lbe_query(p, n_inst, &need, nullptr);
+    if (st != LBE_OK) return st;
+    if (need > kStaticWsBytes) return LBE_ENOMEM;  // beyond the static workspace's fixed size
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStaticMaxDevices) return LBE_EDEVICE;
+    std::lock_guard<std::mutex> lock(static_ws_mu);
+    if (static_ws_busy[dev]) return LBE_ESTATE;  // one static-workspace context per device at a time
+    if (!static_ws_addr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBE_EDEVICE;
+        static_ws_addr[dev] = ptr;
+    }
+    lbe_ctx* c = nullptr;
+    st = lbe_init(p, n_inst, static_ws_addr[dev], kStaticWsBytes, hip_stream, &c);
+    if (st != LBE_OK) return st;
+    c->static_dev = dev;
+    static_ws_busy[dev] = true;
     *out = c;
     return LBE_OK;
 }
@@ -1644,6 +1690,12 @@ lbe_status lbe_timing(lbe_ctx* c, int32_t enable, double* out, int64_t cap)
 void lbe_free(lbe_ctx* c)
 {
     if (!c) return;
+    if (c->static_dev >= 0) {
+        // the static workspace is free for the next lbe_init_static once this context's work is done
+        (void)hipStreamSynchronize(c->stream);
+        std::lock_guard<std::mutex> lock(static_ws_mu);
+        static_ws_busy[c->static_dev] = false;
+    }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
     P = ctypes.POINTER(Params)
     lib.lbe_query.argtypes = [P, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.lbe_init.argtypes = [P, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.lbe_init_static.argtypes = [P, i32, vp, ctypes.POINTER(vp)]
     lib.lbe_step.argtypes = [vp, i64]
     lib.lbe_sync.argtypes = [vp]
     lib.lbe_moments.argtypes = [vp, i32, _D, i64]
@@ -123,7 +124,7 @@ def load() -> ctypes.CDLL:
     lib.lbe_status_string.restype = ctypes.c_char_p
     lib.lbe_free.argtypes = [vp]
     lib.lbe_free.restype = None
-    for name in ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
+    for name in ("lbe_query", "lbe_init", "lbe_init_static", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
                  "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune",
                  "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start", "lbe_mlp_query",
                  "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
@@ -135,7 +136,7 @@ def load() -> ctypes.CDLL:
     return lib
 
 
-EXPORTS = ("lbe_query", "lbe_init", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
+EXPORTS = ("lbe_query", "lbe_init", "lbe_init_static", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
            "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune", "lbe_last_error",
            "lbe_status_string", "lbe_free", "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start",
            "lbe_mlp_query", "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
@@ -178,7 +179,9 @@ def tables(params: dict, which: int, extra: Iterable[float] | None = None) -> np
 class Solver:
     """A batch of FDLB instances on one GPU (the current torch device and stream)."""
 
-    def __init__(self, params: dict | Sequence[dict]):
+    def __init__(self, params: dict | Sequence[dict], static_ws: bool = False):
+        """static_ws: take the library's own device workspace (lbe_init_static) instead of a
+        torch tensor; at most one such solver per GPU at a time, up to 64 MiB."""
         import torch
 
         if isinstance(params, dict):
@@ -186,22 +189,29 @@ class Solver:
         self.params = [dict(p) for p in params]
         lib = load()
         self._lib = lib
-        dev_bytes, _ = query(self.params)
-        self._ws = torch.empty(dev_bytes + 256, dtype=torch.uint8, device="cuda")
-        base = self._ws.data_ptr()
-        aligned = (base + 255) & ~255
         arr = (Params * len(self.params))(*[make_params(p) for p in self.params])
         stream = torch.cuda.current_stream().cuda_stream
         h = ctypes.c_void_p(0)
-        st = lib.lbe_init(arr, len(self.params), ctypes.c_void_p(aligned), dev_bytes, ctypes.c_void_p(stream),
-                          ctypes.byref(h))
-        if st != LBE_OK:
-            raise LbeError(st, "lbe_init failed")
+        if static_ws:
+            self._ws = None
+            st = lib.lbe_init_static(arr, len(self.params), ctypes.c_void_p(stream), ctypes.byref(h))
+            if st != LBE_OK:
+                raise LbeError(st, "lbe_init_static failed")
+        else:
+            dev_bytes, _ = query(self.params)
+            self._ws = torch.empty(dev_bytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            aligned = (base + 255) & ~255
+            st = lib.lbe_init(arr, len(self.params), ctypes.c_void_p(aligned), dev_bytes, ctypes.c_void_p(stream),
+                              ctypes.byref(h))
+            if st != LBE_OK:
+                raise LbeError(st, "lbe_init failed")
         self._h = h
         self.n_inst = len(self.params)
         self._infos = [self.info(k) for k in range(self.n_inst)]
 
-    def __del__(self):
+    def close(self) -> None:
+        """Free the context now (waits for its stream); the workspace tensor goes with the object."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             try:
@@ -209,6 +219,9 @@ class Solver:
             finally:
                 self._lib.lbe_free(h)
             self._h = None
+
+    def __del__(self):
+        self.close()
 
     def _check(self, st: int, what: str) -> int:
         if st not in (LBE_OK, LBE_ENOTCONV):
