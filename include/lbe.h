@@ -76,7 +76,9 @@ typedef struct {
     int32_t precision;    /* LBE_FP64: f stored in FP64.  LBE_FP32_STORE: f stored as FP32
                            * deviations from the discrete equilibrium of per-node FP64 moments
                            * (all arithmetic, moment sums, node coefficients and the residual
-                           * stay FP64); the warm-start calls reject such instances.        */
+                           * stay FP64).  The state buffers are laid out at FP64 size so that
+                           * lbe_run_to_steady can switch such an instance to FP64 storage in
+                           * place (the bytes streamed per step are those of FP32 storage).   */
 } lbe_params;
 
 /* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),
@@ -129,7 +131,13 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
  * one status array per interval.  Once half of the instances still advancing have converged, the
  * launches cover only the others, with shorter tiles while few work items remain; results agree
  * with lbe_step to rounding.  FP32-storage instances get their total mass restored at the start
- * of every interval. */
+ * of every interval.  The rounding of FP32 storage leaves a residual floor of order 1e-6 on hard
+ * cases: when every still-advancing instance of an FP32-storage launch group has stopped
+ * improving (the smallest residual of its last ~2000 steps is not below 0.8 times the smallest of
+ * the ~2000 steps before), above tol, the group is switched to FP64 storage in place (state =
+ * stored deviations plus base, in FP64) and continues to tol; the instances stay FP64-storage
+ * afterwards (lbe_info reports it).  LBE_FP32_PROMOTE=0 in the environment before lbe_init turns
+ * the switch off. */
 lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t check_every, int64_t* steps_out,
                              double* resid_out);
 
@@ -138,12 +146,25 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
 lbe_status lbe_get_state(lbe_ctx* c, int32_t inst, double* host_f, int64_t cap);
 lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t len);
 
+/* Checkpoint / resume of the whole context: the exact device state one step reads from the
+ * previous one (the stored state buffer in its stored precision, the FP32 base tables, the moment
+ * sums, the FP32 mass targets), the step counters, each instance's storage precision and the
+ * launch plan's tile heights.  lbe_checkpoint_size gives the bytes; lbe_checkpoint_save fills a
+ * host buffer of at least that size (synchronises); lbe_checkpoint_load restores it into a
+ * context made by lbe_init with the same problem statements (checked by a fingerprint, else
+ * LBE_EINVAL), switching instances that were switched to FP64 storage, after which stepping
+ * continues bitwise as the saved context would (the kernels use no atomics and fixed orders). */
+lbe_status lbe_checkpoint_size(lbe_ctx* c, size_t* bytes);
+lbe_status lbe_checkpoint_save(lbe_ctx* c, void* host_buf, size_t cap);
+lbe_status lbe_checkpoint_load(lbe_ctx* c, const void* host_buf, size_t len);
+
 /* Right-hand side L(f)[nr][nv] of the current state of instance inst (one evaluation of
  * every term of one RK stage, without updating the state); synchronises. */
 lbe_status lbe_rhs(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
 
 /* Derived scalars of instance inst: [nr, nv, n0, n1, n2, chi0, C, L, sigma, rcl, rcr, dr,
- * dt, steps, N0, N1, N2]; cap >= 17. */
+ * dt, steps, N0, N1, N2]; cap >= 17.  With cap >= 19 also [fp32_storage_now, step at which the
+ * instance was switched from FP32 to FP64 storage or -1]. */
 lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap);
 
 /* Host-only access to the tables lbe_init builds for one instance (no device needed):
@@ -240,13 +261,16 @@ lbe_status lbe_features(lbe_ctx* c, float* dev_x, int64_t cap_rows, int64_t* row
 lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows);
 /* Start instance inst from a given profile host_in[field * nr + i], fields n, u_t1, T, q_r,
  * P_r,t1 (n, T > 0; u_r = u_t2 = 0): Grad-13 state, scaled to the rest start's total mass
- * sum_i V_i n_i = sum_i V_i.  Synchronises; clears a latched LBE_ENAN. */
+ * sum_i V_i n_i = sum_i V_i.  An FP32-storage instance gets the FP64 state re-based into
+ * deviations from the discrete equilibrium of its own moments, and keeps that state's mass.
+ * Synchronises; clears a latched LBE_ENAN. */
 lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in, int64_t len);
 /* Start every instance from the network's prediction (n, T kept within [0.05, 20]).  With judge
  * set, one step is taken from the rest start and one from the predicted state, and an instance
  * keeps the prediction only if its residual (as in lbe_run_to_steady) is the smaller; the others
  * get the rest start.  kept[k] (may be NULL) receives 1 / 0; rho[2k], rho[2k+1] (may be NULL)
- * the two residuals (-1 without judge).  Step counters are unchanged.  Synchronises. */
+ * the two residuals (-1 without judge).  Step counters are unchanged.  FP32-storage instances are
+ * handled as in lbe_set_init_moments (the rest start as lbe_init sets it).  Synchronises. */
 lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, double* rho);
 
 const char* lbe_last_error(const lbe_ctx* c);

@@ -17,20 +17,26 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbe_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("LBE_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP over radial nodes)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11", "-o", tmp, _SRC,
-               "-lquadmath", "-lm"]
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP over radial nodes).  sanitize: the
+    AddressSanitizer + UndefinedBehaviorSanitizer build SAN_LIB (load it with LBE_ORACLE_LIB and
+    gcc's libasan / libubsan preloaded)."""
+    lib = SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined",
+                        "-g"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class Params(ctypes.Structure):

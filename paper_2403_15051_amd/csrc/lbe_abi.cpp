@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -22,9 +23,11 @@ hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, in
                        hipStream_t s);
 hipError_t launch_base_copy(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxng, hipStream_t s);
 hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s);
-hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s);
+hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s,
+                       const int32_t* mask = nullptr);
 hipError_t launch_mass_fix(const DevInstance* d, int ninst, int maxnr, const double* target, hipStream_t s);
 hipError_t launch_rebase(const DevInstance* d, int inst, int nr, hipStream_t s);
+hipError_t launch_rebase_masked(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s);
 hipError_t launch_snapshot(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s);
 hipError_t launch_converge(const DevInstance* d, int ninst, double tol, int chunk, int judge, double* st,
@@ -106,6 +109,12 @@ struct lbe_ctx {
     double g_chunk_tol = 0;
     // device whose static workspace this context occupies (lbe_init_static), -1 otherwise
     int static_dev = -1;
+    // FP32 storage: start of each state buffer's allocation (laid out at FP64 size, so that an
+    // instance can switch to FP64 storage in place), and the step at which each instance did
+    // (-1: never); the steady driver switches a launch group whose solves have stopped improving
+    std::vector<std::array<char*, 3>> fraw;
+    std::vector<int64_t> promoted_at;
+    bool promote = true;
 };
 
 namespace {
@@ -114,7 +123,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte layout of one instance inside the workspace.
 struct Layout {
-    size_t f[3], mom, node, snap, resid, flags, nw, scratch;
+    size_t fraw[3], f[3], mom, node, snap, resid, flags, nw, scratch;
     size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qrec0, geo, r, wlo, wb, gwl, gwr;
     size_t simg;
     size_t total;
@@ -132,9 +141,14 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t img_doubles, siz
     const size_t D = sizeof(double);
     const size_t plane = (size_t)t.nr * t.nv * D;
     // state buffers: nr rows plus two ghost rows on each side (filled by the node kernel);
-    // L.f points at row 0; FP64 or FP32 values
+    // L.f points at row 0; FP64 or FP32 values.  Each buffer is sized for FP64 values, so that an
+    // FP32-storage instance can be switched to FP64 storage in place (the FP32 values use the
+    // first half; the bytes streamed per step are those of the stored precision)
     const size_t E = t.prm.precision == LBE_FP32_STORE ? sizeof(float) : D;
-    for (int k = 0; k < 3; k++) L.f[k] = take((size_t)(t.nr + 4) * t.nv * E) + 2 * t.nv * E;
+    for (int k = 0; k < 3; k++) {
+        L.fraw[k] = take((size_t)(t.nr + 4) * t.nv * D);
+        L.f[k] = L.fraw[k] + 2 * t.nv * E;
+    }
     const size_t ng = (size_t)(t.n0 + t.n1 + t.n2);
     for (int k = 0; k < 4; k++) L.base[k] = t.prm.precision == LBE_FP32_STORE ? take((size_t)t.nr * ng * D) : 0;
     L.mom = take((size_t)t.nr * nslices * kMomStride * D);
@@ -193,8 +207,8 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const int n0 = 2 * p.q_radial, n1 = p.q_t1, n2 = p.q_t2;
     const size_t nv = (size_t)n0 * n1 * n2, nr = p.nr, D = sizeof(double);
     const int N = kMaxN + 2;
-    const size_t E = p.precision == LBE_FP32_STORE ? sizeof(float) : D;  // stored value of f
-    size_t b = align256((size_t)(n0 + n1 + n2) * D) + 3 * align256((nr + 4) * nv * E) + align256(nr * nv * D) +
+    // state buffers at FP64 size whatever the storage (an FP32 instance can switch in place)
+    size_t b = align256((size_t)(n0 + n1 + n2) * D) + 3 * align256((nr + 4) * nv * D) + align256(nr * nv * D) +
                align256(nr * n2 * kMomStride * D) + align256(nr * kNodeStride * D) + align256(nr * 5 * D) + 3 * 256;
     b += 3 * align256(n0 * D) + align256((size_t)n0 * n0 * D) + align256((size_t)n1 * n1 * D) +
          align256((size_t)n2 * n2 * D) + 3 * align256(std::max(n0, std::max(n1, n2)) * D);
@@ -757,6 +771,53 @@ lbe_status enqueue_chunk(lbe_ctx* c, int chunk, double tol, int judge)
     return dev_err(c, hipGraphLaunch(c->g_chunk, c->stream), "chunk launch");
 }
 
+// Switch every instance of launch group q from FP32 to FP64 storage, in place: buffer 0 becomes
+// the FP64 state (the stored deviations plus their base, as lbe_get_state returns it), the
+// instances' descriptors point at FP64 buffers (their allocations are FP64-sized) and the group's
+// stage kernel takes its FP64 form.  The stage image does not depend on the storage, so it is
+// kept.  `also`: another copy of the groups to keep in step (the steady driver's saved plan).
+// The caller re-uploads the launch plan.
+lbe_status promote_group(lbe_ctx* c, int q, int64_t at_step, std::vector<StageGroup>* also)
+{
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
+        if (c->group_of[k] != q || !c->host_desc[k].f32) continue;
+        DevInstance& d = c->host_desc[k];
+        const size_t plane = (size_t)d.nr * d.nv * sizeof(double);
+        char* row0 = c->fraw[k][0] + 2 * (size_t)d.nv * sizeof(double);
+        st = dev_err(c, launch_expand(c->dev_desc, k, d.nr, c->stream), "expand");
+        if (st == LBE_OK)
+            st = dev_err(c, hipMemcpyAsync(row0, d.scratch, plane, hipMemcpyDeviceToDevice, c->stream), "promote");
+        if (st != LBE_OK) break;
+        d.f32 = 0;
+        for (int b = 0; b < 3; b++) d.f[b] = (double*)(c->fraw[k][b] + 2 * (size_t)d.nv * sizeof(double));
+        c->tabs[k].prm.precision = LBE_FP64;
+        c->promoted_at[k] = c->steps[k] + at_step;
+    }
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpyAsync(c->dev_desc, c->host_desc.data(), sizeof(DevInstance) * c->ninst,
+                                       hipMemcpyHostToDevice, c->stream),
+                     "descriptor upload");
+    // moment sums of the FP64 states (the next stage's node kernel reads them)
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++)
+        if (c->group_of[k] == q)
+            st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, k, c->stream), "moments");
+    if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    auto relayout = [&](StageGroup& G) {
+        G.f32 = 0;
+        return layout_group(&G, G.NT);
+    };
+    if (!relayout(c->groups[q]) || (also && !relayout((*also)[q]))) {
+        c->err = "stage kernel layout of the promoted group";
+        return LBE_EINVAL;
+    }
+    c->any_f32 = false;
+    for (int k = 0; k < c->ninst; k++) c->any_f32 = c->any_f32 || c->host_desc[k].f32;
+    drop_graphs(c);
+    return LBE_OK;
+}
+
 lbe_status check_nan(lbe_ctx* c)
 {
     for (int k = 0; k < c->ninst; k++) {
@@ -849,7 +910,10 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
     c->host_desc.resize(n_inst);
     c->steps.assign(n_inst, 0);
     c->active.assign(n_inst, 1);
+    c->fraw.resize(n_inst);
+    c->promoted_at.assign(n_inst, -1);
     if (const char* g = std::getenv("LBE_GRAPH")) c->use_graph = std::atoi(g) != 0;
+    if (const char* g = std::getenv("LBE_FP32_PROMOTE")) c->promote = std::atoi(g) != 0;
     // host tables of the instances, built by a small pool of host threads
     {
         std::vector<lbe_status> sts(n_inst, LBE_OK);
@@ -946,7 +1010,10 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.uw = t.prm.u_wall_inner;
         d.tratio = t.prm.t_wall_outer / t.prm.t_wall_inner;
         char* ws = c->ws;
-        for (int b = 0; b < 3; b++) d.f[b] = (double*)(ws + L.f[b]);
+        for (int b = 0; b < 3; b++) {
+            d.f[b] = (double*)(ws + L.f[b]);
+            c->fraw[k][b] = ws + L.fraw[b];
+        }
         d.mom = (double*)(ws + L.mom);
         d.node = (double*)(ws + L.node);
         d.snap = (double*)(ws + L.snap);
@@ -1186,7 +1253,7 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
     std::vector<int32_t> act(c->ninst, 1);
     // plans with shorter tiles while few work items remain: a tile's nodes are processed in
     // sequence, so with fewer items than two per compute unit the tile height sets the latency
-    const std::vector<StageGroup> saved = c->groups;
+    std::vector<StageGroup> saved = c->groups;
     bool replanned = false;
     auto adapt_tiles = [&](const std::vector<int32_t>* only) {
         for (size_t q = 0; q < c->groups.size(); q++) {
@@ -1210,6 +1277,13 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
     };
     st = dev_err(c, adapt_tiles(nullptr), "plan");
     if (st != LBE_OK) return st;
+    // FP32 storage leaves a residual floor (the rounding of the stored deviations); an instance has
+    // stopped improving when the smallest residual of its last `win` check intervals (about 2000
+    // steps) is not below 0.8 times the smallest of the `win` intervals before.  A launch group of
+    // FP32-storage instances that all stopped improving above tol is switched to FP64 storage in
+    // place and the solve continues (LBE_FP32_PROMOTE=0 in the environment turns this off).
+    const int win = std::max(2, (int)((2000 + check_every - 1) / check_every));
+    std::vector<std::vector<double>> hist(c->ninst);
     while (taken < max_steps && !all) {
         const int chunk = (int)std::min<int64_t>(check_every, max_steps - taken);
         st = enqueue_chunk(c, chunk, tol, chunk == check_every);
@@ -1233,8 +1307,32 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
             if (act[k]) all = false;
         }
         if (st != LBE_OK) break;
+        bool promoted = false;
+        if (c->promote && c->any_f32 && chunk == check_every) {
+            std::vector<int> stalled(c->groups.size(), 1), members(c->groups.size(), 0);
+            for (int k = 0; k < c->ninst; k++) {
+                if (!c->host_desc[k].f32 || !act[k]) continue;
+                hist[k].push_back(stv[4 * k]);
+                const int g = c->group_of[k];
+                members[g]++;
+                const size_t h = hist[k].size();
+                bool flat = h >= (size_t)(2 * win);
+                if (flat) {
+                    const double recent = *std::min_element(hist[k].end() - win, hist[k].end());
+                    const double before = *std::min_element(hist[k].end() - 2 * win, hist[k].end() - win);
+                    flat = !(recent < 0.8 * before);
+                }
+                if (!flat) stalled[g] = 0;
+            }
+            for (size_t q = 0; q < c->groups.size() && st == LBE_OK; q++) {
+                if (!c->groups[q].f32 || !members[q] || !stalled[q]) continue;
+                st = promote_group(c, (int)q, taken, &saved);
+                promoted = true;
+            }
+            if (st != LBE_OK) break;
+        }
         // once half of the planned instances have converged, launch only the others
-        if (nact > 0 && 2 * nact <= planned) {
+        if (nact > 0 && (2 * nact <= planned || promoted)) {
             st = dev_err(c, adapt_tiles(&act), "plan");
             if (st != LBE_OK) break;
             planned = nact;
@@ -1259,6 +1357,192 @@ lbe_status lbe_run_to_steady(lbe_ctx* c, double tol, int64_t max_steps, int32_t 
         if (!(r >= 0 && r <= tol)) conv = false;
     }
     return conv ? LBE_OK : LBE_ENOTCONV;
+}
+
+// ---- checkpoint / resume: the exact device state a step reads from one step to the next
+namespace {
+constexpr char kCkptMagic[8] = {'L', 'B', 'E', 'C', 'K', 'P', 'T', '1'};
+
+// FNV-1a over the problem statements, field by field (the struct has padding).
+uint64_t params_fingerprint(const lbe_ctx* c)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    for (const InstanceTables& t : c->tabs) {
+        const lbe_params& q = t.prm;
+        const double dv[8] = {q.r_inner, q.r_outer, q.u_wall_inner, q.t_wall_inner, q.t_wall_outer, q.eta0, q.kn, q.cfl};
+        const int32_t iv[7] = {q.geometry, q.nr, q.q_radial, q.q_t1, q.q_t2, q.n_expand[0], q.n_expand[1]};
+        mix(dv, sizeof(dv));
+        mix(iv, sizeof(iv));
+        mix(&q.n_expand[2], sizeof(int32_t));
+    }
+    return h;
+}
+
+struct CkptInst {
+    int64_t steps, promoted_at;
+    int32_t f32, nr, nv, nslices, ng, pad;
+};
+
+size_t inst_state_bytes(const DevInstance& d)
+{
+    const size_t E = d.f32 ? sizeof(float) : sizeof(double);
+    const size_t ng = (size_t)(d.n0 + d.n1 + d.n2);
+    return (size_t)d.nr * d.nv * E + (d.f32 ? (size_t)d.nr * ng * sizeof(double) : 0) +
+           (size_t)d.nr * d.nslices * kMomStride * sizeof(double) + sizeof(double);
+}
+
+size_t checkpoint_bytes(const lbe_ctx* c)
+{
+    size_t b = sizeof(kCkptMagic) + sizeof(uint64_t) + 3 * sizeof(int64_t) + c->groups.size() * sizeof(int32_t);
+    for (int k = 0; k < c->ninst; k++) b += sizeof(CkptInst) + inst_state_bytes(c->host_desc[k]);
+    return b;
+}
+}  // namespace
+
+lbe_status lbe_checkpoint_size(lbe_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBE_EINVAL;
+    *bytes = checkpoint_bytes(c);
+    return LBE_OK;
+}
+
+lbe_status lbe_checkpoint_save(lbe_ctx* c, void* host_buf, size_t cap)
+{
+    if (!c || !host_buf) return LBE_EINVAL;
+    if (cap < checkpoint_bytes(c)) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    char* o = (char*)host_buf;
+    auto put_h = [&](const void* p, size_t n) {
+        std::memcpy(o, p, n);
+        o += n;
+    };
+    const uint64_t fp = params_fingerprint(c);
+    const int64_t hdr[3] = {c->ninst, (int64_t)c->groups.size(), c->since_fix};
+    put_h(kCkptMagic, sizeof(kCkptMagic));
+    put_h(&fp, sizeof(fp));
+    put_h(hdr, sizeof(hdr));
+    for (const StageGroup& G : c->groups) put_h(&G.NT, sizeof(int32_t));
+    std::vector<double> mass(c->ninst);
+    st = dev_err(c, hipMemcpy(mass.data(), c->dev_mass, mass.size() * sizeof(double), hipMemcpyDeviceToHost), "mass");
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
+        const DevInstance& d = c->host_desc[k];
+        const CkptInst ci = {c->steps[k], c->promoted_at[k], d.f32, d.nr, d.nv, d.nslices, d.n0 + d.n1 + d.n2, 0};
+        put_h(&ci, sizeof(ci));
+        const size_t fb = (size_t)d.nr * d.nv * (d.f32 ? sizeof(float) : sizeof(double));
+        st = dev_err(c, hipMemcpy(o, d.f[0], fb, hipMemcpyDeviceToHost), "state");
+        o += fb;
+        if (st == LBE_OK && d.f32) {
+            const size_t bb = (size_t)d.nr * ci.ng * sizeof(double);
+            st = dev_err(c, hipMemcpy(o, d.base[0], bb, hipMemcpyDeviceToHost), "base table");
+            o += bb;
+        }
+        const size_t mb = (size_t)d.nr * d.nslices * kMomStride * sizeof(double);
+        if (st == LBE_OK) st = dev_err(c, hipMemcpy(o, d.mom, mb, hipMemcpyDeviceToHost), "moment sums");
+        o += mb;
+        put_h(&mass[k], sizeof(double));
+    }
+    if (st != LBE_OK) return st;
+    return check_nan(c);
+}
+
+lbe_status lbe_checkpoint_load(lbe_ctx* c, const void* host_buf, size_t len)
+{
+    if (!c || !host_buf) return LBE_EINVAL;
+    const char* o = (const char*)host_buf;
+    const char* end = o + len;
+    auto get_h = [&](void* p, size_t n) {
+        if (o + n > end) return false;
+        std::memcpy(p, o, n);
+        o += n;
+        return true;
+    };
+    char magic[8];
+    uint64_t fp = 0;
+    int64_t hdr[3];
+    if (!get_h(magic, 8) || std::memcmp(magic, kCkptMagic, 8) != 0 || !get_h(&fp, sizeof(fp)) ||
+        !get_h(hdr, sizeof(hdr))) {
+        c->err = "not a checkpoint of this library";
+        return LBE_EINVAL;
+    }
+    if (fp != params_fingerprint(c) || hdr[0] != c->ninst || hdr[1] != (int64_t)c->groups.size()) {
+        c->err = "checkpoint of different problem statements";
+        return LBE_EINVAL;
+    }
+    std::vector<int32_t> nts(c->groups.size());
+    if (!get_h(nts.data(), nts.size() * sizeof(int32_t))) return LBE_EINVAL;
+    lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
+    if (st != LBE_OK) return st;
+    // the instances' storage as saved (instances switched to FP64 storage are switched here too)
+    {
+        const char* scan = o;
+        std::vector<int32_t> f32s(c->ninst);
+        for (int k = 0; k < c->ninst; k++) {
+            CkptInst ci;
+            if (scan + sizeof(ci) > end) return LBE_EINVAL;
+            std::memcpy(&ci, scan, sizeof(ci));
+            const DevInstance& d = c->host_desc[k];
+            if (ci.nr != d.nr || ci.nv != d.nv || ci.nslices != d.nslices) {
+                c->err = "checkpoint of a different launch plan";
+                return LBE_EINVAL;
+            }
+            f32s[k] = ci.f32;
+            scan += sizeof(ci) + (size_t)ci.nr * ci.nv * (ci.f32 ? 4 : 8) + (ci.f32 ? (size_t)ci.nr * ci.ng * 8 : 0) +
+                    (size_t)ci.nr * ci.nslices * kMomStride * 8 + 8;
+        }
+        for (size_t q = 0; q < c->groups.size() && st == LBE_OK; q++) {
+            if (!c->groups[q].f32) continue;
+            bool promote = false;
+            for (int k = 0; k < c->ninst; k++)
+                if (c->group_of[k] == (int)q && !f32s[k]) promote = true;
+            if (promote) st = promote_group(c, (int)q, 0, nullptr);
+        }
+        if (st != LBE_OK) return st;
+    }
+    for (size_t q = 0; q < c->groups.size(); q++) {
+        StageGroup G = c->groups[q];
+        if (!layout_group(&G, nts[q]) || G.NT != nts[q]) {
+            c->err = "checkpoint tile height does not fit";
+            return LBE_EINVAL;
+        }
+        c->groups[q] = G;
+    }
+    std::vector<double> mass(c->ninst);
+    for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
+        const DevInstance& d = c->host_desc[k];
+        CkptInst ci;
+        if (!get_h(&ci, sizeof(ci)) || ci.f32 != d.f32) return LBE_EINVAL;
+        const size_t fb = (size_t)d.nr * d.nv * (d.f32 ? sizeof(float) : sizeof(double));
+        if (o + fb > end) return LBE_EINVAL;
+        st = dev_err(c, hipMemcpy(d.f[0], o, fb, hipMemcpyHostToDevice), "state");
+        o += fb;
+        if (st == LBE_OK && d.f32) {
+            const size_t bb = (size_t)d.nr * ci.ng * sizeof(double);
+            if (o + bb > end) return LBE_EINVAL;
+            st = dev_err(c, hipMemcpy(d.base[0], o, bb, hipMemcpyHostToDevice), "base table");
+            o += bb;
+        }
+        const size_t mb = (size_t)d.nr * d.nslices * kMomStride * sizeof(double);
+        if (o + mb + sizeof(double) > end) return LBE_EINVAL;
+        if (st == LBE_OK) st = dev_err(c, hipMemcpy(d.mom, o, mb, hipMemcpyHostToDevice), "moment sums");
+        o += mb;
+        get_h(&mass[k], sizeof(double));
+        c->steps[k] = ci.steps;
+        c->promoted_at[k] = ci.promoted_at;
+    }
+    if (st == LBE_OK)
+        st = dev_err(c, hipMemcpy(c->dev_mass, mass.data(), mass.size() * sizeof(double), hipMemcpyHostToDevice), "mass");
+    if (st != LBE_OK) return st;
+    c->since_fix = hdr[2];
+    c->nan_latched = false;
+    std::fill(c->active.begin(), c->active.end(), 1);
+    st = dev_err(c, upload_plan(c, nullptr), "plan");
+    if (st == LBE_OK) st = upload_flags(c);
+    return st;
 }
 
 lbe_status lbe_get_state(lbe_ctx* c, int32_t inst, double* host_f, int64_t cap)
@@ -1323,10 +1607,11 @@ lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap)
 {
     if (!c || inst < 0 || inst >= c->ninst || !out || cap < 17) return LBE_EINVAL;
     const InstanceTables& t = c->tabs[inst];
-    const double v[17] = {(double)t.nr, (double)t.nv, (double)t.n0, (double)t.n1, (double)t.n2, t.chi0, t.C, t.L,
+    const double v[19] = {(double)t.nr, (double)t.nv, (double)t.n0, (double)t.n1, (double)t.n2, t.chi0, t.C, t.L,
                           t.sigma, t.rcl, t.rcr, t.dr, t.dt, (double)c->steps[inst], (double)t.ax[0].N,
-                          (double)t.ax[1].N, (double)t.ax[2].N};
-    std::memcpy(out, v, sizeof(v));
+                          (double)t.ax[1].N, (double)t.ax[2].N, (double)c->host_desc[inst].f32,
+                          (double)c->promoted_at[inst]};
+    std::memcpy(out, v, sizeof(double) * (cap >= 19 ? 19 : 17));
     return LBE_OK;
 }
 
@@ -1444,14 +1729,22 @@ lbe_status upload_mask(lbe_ctx* c, const std::vector<int32_t>& mask)
 }
 
 // Grad-13 state of the masked instances from the profiles in their node blocks, then the mass
-// renormalisation and the moment sums of the new state.
+// renormalisation and the moment sums of the new state.  FP32-storage instances get the FP64
+// state in their scratch first; its mass becomes the mass they keep, and it is then stored as
+// deviations from the discrete equilibrium of its own moments (as lbe_set_state does).
 hipError_t build_warm_state(lbe_ctx* c)
 {
     hipError_t e = launch_proj(c->dev_desc, c->ninst, c->maxnr, c->stream);
     if (e == hipSuccess) e = launch_grad13(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream);
-    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 2, -1, c->stream);
     if (e == hipSuccess) e = launch_renorm(c->dev_desc, c->ninst, c->dev_mask, c->stream);
-    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
+    if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 2, -1, c->stream);
+    if (c->any_f32) {
+        if (e == hipSuccess) e = launch_mass(c->dev_desc, c->ninst, -2, c->dev_mass, c->stream, c->dev_mask);
+        if (e == hipSuccess) e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream);
+        if (e == hipSuccess) e = launch_rebase_masked(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream);
+        if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
+    }
     return e;
 }
 
@@ -1498,10 +1791,6 @@ lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in,
 {
     if (!c || inst < 0 || inst >= c->ninst || !host_in) return LBE_EINVAL;
     const DevInstance& d = c->host_desc[inst];
-    if (d.f32) {
-        c->err = "the warm start needs FP64 storage";
-        return LBE_ESTATE;
-    }
     if (len != 5 * (int64_t)d.nr) return LBE_EINVAL;
     for (int i = 0; i < d.nr; i++)
         if (!(host_in[i] > 0) || !(host_in[2 * d.nr + i] > 0)) return LBE_EINVAL;
@@ -1528,10 +1817,6 @@ lbe_status lbe_set_init_moments(lbe_ctx* c, int32_t inst, const double* host_in,
 lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, double* rho)
 {
     if (!c || !m) return LBE_EINVAL;
-    if (c->any_f32) {
-        c->err = "the warm start needs FP64 storage";
-        return LBE_ESTATE;
-    }
     if (c->nan_latched) return LBE_ENAN;
     lbe_status st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
@@ -1556,6 +1841,14 @@ lbe_status lbe_warm_start(lbe_ctx* c, lbe_mlp* m, int32_t judge, int32_t* kept, 
     if (st == LBE_OK) st = dev_err(c, predict_warm_state(c, m), "prediction");
     if (st == LBE_OK) st = dev_err(c, launch_rest(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream), "rest");
     if (st == LBE_OK) st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream), "moments");
+    if (st == LBE_OK && c->any_f32) {
+        // FP32-storage instances back at the rest start keep the rest start's mass
+        std::vector<int32_t> rest_mask(c->ninst);
+        for (int k = 0; k < c->ninst; k++) rest_mask[k] = !keep[k];
+        st = upload_mask(c, rest_mask);
+        if (st == LBE_OK)
+            st = dev_err(c, launch_mass(c->dev_desc, c->ninst, -2, c->dev_mass, c->stream, c->dev_mask), "mass");
+    }
     if (st == LBE_OK) st = dev_err(c, hipStreamSynchronize(c->stream), "sync");
     if (st != LBE_OK) return st;
     // a judged state that went non-finite has been replaced: clear the device flags

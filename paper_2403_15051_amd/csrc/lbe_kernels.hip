@@ -236,7 +236,8 @@ __device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, in
 // ------------------------------------------------------------------ moments of a state
 
 // Moment sums of buffer `buf` (base table `tab`) with shift 0 (start-up, lbe_set_state, the warm
-// start, the FP32 mass fix); from_scratch reads the FP64 copy in the instance's scratch instead.
+// start, the FP32 mass fix); from_scratch 1 reads the FP64 copy in the instance's scratch instead,
+// 2 does so for the FP32-storage instances only (where the warm start builds their FP64 state).
 // only: -1 every instance, k >= 0 instance k alone, -2 the active FP32-storage instances.
 __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restrict__ insts, int buf, int tab,
                                                     int from_scratch, int only)
@@ -253,7 +254,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
     for (int v = threadIdx.x; v < I.nv; v += kBlock) {
         const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
         const double x = I.p0[i0], y = I.p1[i1], z = I.p2[i2];
-        const double fv = from_scratch ? I.scratch[(size_t)i * I.nv + v] : f_at(I, buf, tab, i, v);
+        const double fv = (from_scratch == 1 || (from_scratch == 2 && I.f32)) ? I.scratch[(size_t)i * I.nv + v]
+                                                                                : f_at(I, buf, tab, i, v);
         const double x2 = x * x + y * y + z * z;
         acc[MF_S0] += fv;
         acc[MF_S1X] += fv * x;
@@ -1676,7 +1678,8 @@ __global__ void __launch_bounds__(kBlock) k_profile_from_host(const DevInstance*
 
 // Grad 13-moment state of the masked instances from their node blocks (after k_proj):
 //   f_v = n g_r g_1 g_2 [1 + P xi_r xi_1 / (n T^2) + (q xi_r / (n T^2)) (|xi|^2 / (5 T) - 1)],
-// xi = p - (0, u_t1, 0), with the discrete equilibrium factors of the collision term.
+// xi = p - (0, u_t1, 0), with the discrete equilibrium factors of the collision term.  FP64 into
+// buffer 0, or into the scratch for FP32-storage instances (re-based into deviations later).
 __global__ void __launch_bounds__(kBlock) k_grad13(const DevInstance* __restrict__ insts,
                                                    const int32_t* __restrict__ mask)
 {
@@ -1707,7 +1710,7 @@ __global__ void __launch_bounds__(kBlock) k_grad13(const DevInstance* __restrict
     __syncthreads();
     const double n = nd[NF_N], ut = nd[NF_U1], T = nd[NF_T], q = nd[NF_Q0], P = nd[NF_P01];
     const double cP = P / (n * T * T), cq = q / (n * T * T), inv5T = 1 / (5 * T);
-    double* f = I.f[0] + (size_t)i * I.nv;
+    double* f = (I.f32 ? I.scratch : I.f[0]) + (size_t)i * I.nv;
     for (int v = threadIdx.x; v < I.nv; v += kBlock) {
         const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
         const double xr = I.p0[i0], xt = I.p1[i1] - ut, xz = I.p2[i2];
@@ -1726,6 +1729,13 @@ __global__ void __launch_bounds__(kBlock) k_rest(const DevInstance* __restrict__
     const int i = blockIdx.x;
     if (i >= I.nr) return;
     const int n0 = I.n0, n1 = I.n1;
+    if (I.f32) {  // FP32 storage: the rest factors are the base, the deviations zero (as lbe_init)
+        const int ng = n0 + n1 + I.n2;
+        for (int k = threadIdx.x; k < ng; k += kBlock) I.base[0][(size_t)i * ng + k] = I.rest[k];
+        float* d = (float*)I.f[0] + (size_t)i * I.nv;
+        for (int v = threadIdx.x; v < I.nv; v += kBlock) d[v] = 0.0f;
+        return;
+    }
     double* f = I.f[0] + (size_t)i * I.nv;
     for (int v = threadIdx.x; v < I.nv; v += kBlock) {
         const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
@@ -1755,7 +1765,7 @@ __global__ void __launch_bounds__(kBlock) k_renorm(const DevInstance* __restrict
     block_sum<2>(acc, red);
     __syncthreads();
     const double s = red[4] / red[0];
-    double* f = I.f[0];
+    double* f = I.f32 ? I.scratch : I.f[0];  // where k_grad13 put the FP64 state
     const size_t tot = (size_t)I.nr * I.nv;
     for (size_t e = threadIdx.x; e < tot; e += kBlock) f[e] *= s;
 }
@@ -1787,12 +1797,14 @@ __device__ inline double cell_volume(const DevInstance& I, int i)
     return I.geometry == LBE_CYL ? r * dr : r * r * dr + dr * dr * dr / 12;
 }
 
-// Total mass sum_i V_i n_i of every instance (or only instance `only`) from its moment sums.
+// Total mass sum_i V_i n_i of every instance (only >= 0: that instance; -2: the FP32-storage
+// instances whose mask is set) from its moment sums.
 __global__ void __launch_bounds__(kBlock) k_mass(const DevInstance* __restrict__ insts, int only,
-                                                 double* __restrict__ mass)
+                                                 const int32_t* __restrict__ mask, double* __restrict__ mass)
 {
     const int k = blockIdx.x;
     if (only >= 0 && k != only) return;
+    if (only == -2 && (!insts[k].f32 || !mask[k])) return;  // masked FP32-storage instances only
     const DevInstance& I = insts[k];
     __shared__ double red[4];
     double acc[1] = {0};
@@ -1849,9 +1861,13 @@ __global__ void __launch_bounds__(kBlock) k_expand(const DevInstance* __restrict
 // FP32 storage of the FP64 state in instance inst's scratch: base table 0 from the node block
 // (n and the equilibrium factors at the state's u, T; k_node and k_proj ran on its moment sums),
 // buffer 0 = the deviations.
-__global__ void __launch_bounds__(kBlock) k_rebase(const DevInstance* __restrict__ insts, int inst)
+__global__ void __launch_bounds__(kBlock) k_rebase(const DevInstance* __restrict__ insts, int inst,
+                                                   const int32_t* __restrict__ mask)
 {
-    const DevInstance& I = insts[inst];
+    // inst >= 0: that instance; else every FP32-storage instance of grid row y whose mask is set
+    const int k = inst >= 0 ? inst : (int)blockIdx.y;
+    const DevInstance& I = insts[k];
+    if (inst < 0 && (!I.f32 || !mask[k])) return;
     const int i = blockIdx.x;
     if (i >= I.nr) return;
     const int n0 = I.n0, n1 = I.n1, n2 = I.n2, ng = n0 + n1 + n2;
@@ -1893,9 +1909,9 @@ hipError_t launch_base_copy(const DevInstance* d, const int32_t* ilist, int nins
     return hipGetLastError();
 }
 
-hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s)
+hipError_t launch_mass(const DevInstance* d, int ninst, int only, double* mass, hipStream_t s, const int32_t* mask)
 {
-    hipLaunchKernelGGL(k_mass, dim3(ninst), dim3(kBlock), 0, s, d, only, mass);
+    hipLaunchKernelGGL(k_mass, dim3(ninst), dim3(kBlock), 0, s, d, only, mask, mass);
     return hipGetLastError();
 }
 
@@ -1920,7 +1936,13 @@ hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s)
 
 hipError_t launch_rebase(const DevInstance* d, int inst, int nr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rebase, dim3(nr), dim3(kBlock), 0, s, d, inst);
+    hipLaunchKernelGGL(k_rebase, dim3(nr), dim3(kBlock), 0, s, d, inst, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebase_masked(const DevInstance* d, int ninst, int maxnr, const int32_t* mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rebase, dim3(maxnr, ninst), dim3(kBlock), 0, s, d, -1, mask);
     return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ from typing import Iterable, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbe.so")
+# LBE_LIB selects another build of the library (the host-sanitized one of build.py --sanitize)
+LIB_PATH = os.environ.get("LBE_LIB") or os.path.join(_HERE, "liblbe.so")
 
 LBE_OK, LBE_EINVAL, LBE_ENOMEM, LBE_EDEVICE, LBE_ENOTCONV, LBE_ENAN, LBE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 CYL, SPH = 0, 1
@@ -22,7 +23,7 @@ WARM_FIELDS = ("n", "u_t1", "T", "q_r", "P_rt1")
 GEMM_BF16, GEMM_FP32 = 0, 1
 FP64, FP32_STORE = 0, 1
 INFO_KEYS = ("nr", "nv", "n0", "n1", "n2", "chi0", "C", "L", "sigma", "rcl", "rcr", "dr", "dt", "steps", "N0", "N1",
-             "N2")
+             "N2", "fp32_now", "promoted_at")
 
 
 class LbeError(RuntimeError):
@@ -92,6 +93,9 @@ def load() -> ctypes.CDLL:
     lib.lbe_get_state.argtypes = [vp, i32, _D, i64]
     lib.lbe_set_state.argtypes = [vp, i32, _D, i64]
     lib.lbe_rhs.argtypes = [vp, i32, _D, i64]
+    lib.lbe_checkpoint_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.lbe_checkpoint_save.argtypes = [vp, vp, sz]
+    lib.lbe_checkpoint_load.argtypes = [vp, vp, sz]
     lib.lbe_info.argtypes = [vp, i32, _D, i64]
     lib.lbe_tables.argtypes = [P, i32, _D, _D, i64, _I64]
     lib.lbe_timing.argtypes = [vp, i32, _D, i64]
@@ -125,7 +129,8 @@ def load() -> ctypes.CDLL:
     lib.lbe_free.argtypes = [vp]
     lib.lbe_free.restype = None
     for name in ("lbe_query", "lbe_init", "lbe_init_static", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
-                 "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune",
+                 "lbe_set_state", "lbe_rhs", "lbe_checkpoint_size", "lbe_checkpoint_save", "lbe_checkpoint_load",
+                 "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune",
                  "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start", "lbe_mlp_query",
                  "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
                  "lbe_mlp_set_scaling", "lbe_mlp_get_scaling", "lbe_mlp_forward", "lbe_mlp_loss_grad",
@@ -137,7 +142,8 @@ def load() -> ctypes.CDLL:
 
 
 EXPORTS = ("lbe_query", "lbe_init", "lbe_init_static", "lbe_step", "lbe_sync", "lbe_moments", "lbe_run_to_steady", "lbe_get_state",
-           "lbe_set_state", "lbe_rhs", "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune", "lbe_last_error",
+           "lbe_set_state", "lbe_rhs", "lbe_checkpoint_size", "lbe_checkpoint_save", "lbe_checkpoint_load",
+           "lbe_info", "lbe_tables", "lbe_timing", "lbe_autotune", "lbe_last_error",
            "lbe_status_string", "lbe_free", "lbe_features", "lbe_targets", "lbe_set_init_moments", "lbe_warm_start",
            "lbe_mlp_query", "lbe_mlp_init", "lbe_mlp_init_params", "lbe_mlp_set_params", "lbe_mlp_get_params",
            "lbe_mlp_set_scaling", "lbe_mlp_get_scaling", "lbe_mlp_forward", "lbe_mlp_loss_grad", "lbe_mlp_set_grads",
@@ -230,8 +236,8 @@ class Solver:
         return st
 
     def info(self, inst: int = 0) -> dict:
-        out = np.zeros(17)
-        self._check(self._lib.lbe_info(self._h, inst, _ptr(out), 17), "lbe_info")
+        out = np.zeros(19)
+        self._check(self._lib.lbe_info(self._h, inst, _ptr(out), 19), "lbe_info")
         return dict(zip(INFO_KEYS, out.tolist()))
 
     def step(self, n: int = 1) -> None:
@@ -309,6 +315,19 @@ class Solver:
                                              kept.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(rho)),
                     "lbe_warm_start")
         return kept, rho.reshape(self.n_inst, 2)
+
+    def checkpoint(self) -> bytes:
+        """Exact device state of the whole context (lbe_checkpoint_save)."""
+        n = ctypes.c_size_t(0)
+        self._check(self._lib.lbe_checkpoint_size(self._h, ctypes.byref(n)), "lbe_checkpoint_size")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._lib.lbe_checkpoint_save(self._h, buf, n.value), "lbe_checkpoint_save")
+        return buf.raw
+
+    def restore(self, blob: bytes) -> None:
+        """Continue from a checkpoint of a context with the same problem statements."""
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self._lib.lbe_checkpoint_load(self._h, buf, len(blob)), "lbe_checkpoint_load")
 
     def rhs(self, inst: int = 0) -> np.ndarray:
         nr, nv = int(self._infos[inst]["nr"]), int(self._infos[inst]["nv"])

@@ -184,3 +184,86 @@ def test_trained_network_shortens_steady_solves():
         mc, mw = cold.moments(k), warm.moments(k)
         for f in ("n", "T"):
             assert nrel(mw[f], mc[f]) <= 1e-4, (k, f)
+
+
+def reference_warm_state(p, X_gpu, Y_gpu, mean, scale):
+    """The warm start's state from the network outputs Y (standardised) by the references:
+    de-standardise, keep n and T within [0.05, 20], u_r = u_t2 = 0, Grad-13 state with the rest
+    start's mass (oracle.warmstart)."""
+    v = mean[None, :] + scale[None, :] * np.asarray(Y_gpu, dtype=np.float64)
+    prof = {"n": np.clip(v[:, 0], 0.05, 20.0), "u_t1": v[:, 1], "T": np.clip(v[:, 2], 0.05, 20.0),
+            "q_r": v[:, 3], "P_rt1": v[:, 4]}
+    return WS.grad13_state(p, prof)
+
+
+@pytest.mark.parametrize("precision", [lbe.FP64, lbe.FP32_STORE])
+def test_warm_start_end_to_end_matches_references(precision):
+    """lbe_features against the reference features, the network's forward pass against the FP64
+    reference, and the state lbe_warm_start (no judge) builds from the network's outputs against the
+    reference Grad-13 state of the de-standardised, clamped prediction: 1e-12 with FP64 storage,
+    FP32 rounding of the deviations (1e-7 of f) with FP32 storage."""
+    ps = [W.solver_params(q) for q in W.warm_sweep(4, 77, nr_range=(16, 28), orders=(4, 8))[0]]
+    ps[1] = dict(ps[1], geometry=1, u_wall_inner=0.0)  # one sphere: the geometry input is 1
+    ps = [dict(q, precision=precision) for q in ps]
+    prm = W.mlp_params(31)
+    net = lbe.Mlp(max_rows=40, gemm=lbe.GEMM_FP32)  # predictions in chunks of 40 rows
+    net.set_params(prm)
+    mean, scale = np.array([1.0, 0.05, 1.2, -0.02, 0.01]), np.array([0.1, 0.03, 0.2, 0.02, 0.01])
+    net.set_scaling(mean, scale)
+    g = lbe.Solver(ps)
+    X = g.features()
+    Xh = X.cpu().numpy().astype(np.float64)
+    row = 0
+    for k, q in enumerate(ps):
+        o = oracle.Solver(W.solver_params({kk: v for kk, v in q.items() if kk != "precision"}))
+        info, r = o.info(), o.grid()["r"]
+        r_hat = (r - info["rcl"]) / (info["rcr"] - info["rcl"])
+        Xr = M.features(q["geometry"], q["eta0"], q["kn"], q["u_wall_inner"], q["t_wall_outer"] / q["t_wall_inner"],
+                        r_hat)
+        assert np.abs(Xh[row:row + o.nr] - Xr).max() <= 1e-6 * max(1.0, np.abs(Xr).max()), k
+        row += o.nr
+    # the same network with room for every row (each row's output depends on that row only)
+    full = lbe.Mlp(max_rows=X.shape[0], gemm=lbe.GEMM_FP32)
+    full.set_params(prm)
+    Y = full.forward(X).cpu().numpy().astype(np.float64)
+    Yr = M.forward(prm, Xh)[0]
+    assert nrel(Y, Yr) <= 1e-5
+    kept, rho = g.warm_start(net, judge=False)
+    assert kept.tolist() == [1] * len(ps)
+    row = 0
+    for k, q in enumerate(ps):
+        nr = int(q["nr"])
+        fr = reference_warm_state({kk: v for kk, v in q.items() if kk != "precision"}, Xh[row:row + nr],
+                                  Y[row:row + nr], mean, scale)
+        e = nrel(g.get_state(k), fr)
+        print("warm state", k, "precision", precision, e, flush=True)
+        assert e <= (1e-12 if precision == lbe.FP64 else 1e-7)
+        row += nr
+
+
+def test_warm_start_on_fp32_storage_matches_fp64_storage():
+    """The judged warm start of the same instances with FP32 and with FP64 storage keeps the same
+    predictions and builds the same states (up to the FP32 rounding of the deviations); a set
+    profile likewise; the solves from them reach the same steady state."""
+    ps = [W.solver_params(q) for q in W.warm_sweep(3, 78, nr_range=(16, 24), orders=(4,))[0]]
+    net = lbe.Mlp(max_rows=64, gemm=lbe.GEMM_BF16, seed=4)
+    net.set_scaling([1.0, 0.05, 1.2, 0.0, 0.0], [0.05, 0.02, 0.1, 0.01, 0.01])
+    g64 = lbe.Solver(ps)
+    g32 = lbe.Solver([dict(q, precision=lbe.FP32_STORE) for q in ps])
+    k64, _ = g64.warm_start(net, judge=True)
+    k32, _ = g32.warm_start(net, judge=True)
+    print("kept", k64.tolist(), k32.tolist(), flush=True)
+    assert k64.tolist() == k32.tolist()
+    for k in range(len(ps)):
+        assert nrel(g32.get_state(k), g64.get_state(k)) <= 1e-7
+    prof = W.smooth_profile(int(ps[0]["nr"]), 9)
+    g64.set_init_moments(0, prof)
+    g32.set_init_moments(0, prof)
+    assert nrel(g32.get_state(0), g64.get_state(0)) <= 1e-7
+    st64, _, _ = g64.run_to_steady(1e-6, 60000, 50)
+    st32, _, _ = g32.run_to_steady(1e-6, 60000, 50)
+    assert st64 == st32 == lbe.LBE_OK
+    for k in range(len(ps)):
+        m64, m32 = g64.moments(k), g32.moments(k)
+        for f in ("n", "T"):
+            assert nrel(m32[f], m64[f]) <= 1e-5, (k, f)
