@@ -53,13 +53,16 @@ typedef enum {
     LBE_ESTATE = -6    /* call not valid in the current state */
 } lbe_status;
 
-enum { LBE_CYL = 0, LBE_SPH = 1 };
+enum { LBE_CYL = 0, LBE_SPH = 1, LBE_PLANAR = 2 }; /* LBE_PLANAR: the Cartesian model equation of
+                                                    * Sec. II between parallel walls at x = r_inner,
+                                                    * r_outer (the R_L -> infinity limit)         */
 enum { LBE_FP64 = 0, LBE_FP32_STORE = 1 }; /* storage of f (lbe_params.precision) */
 enum { LBE_GEMM_BF16 = 0, LBE_GEMM_FP32 = 1 }; /* matrix-core operand type of the network */
 
 /* Problem statement of one instance (Sec. IV set-up of the paper). */
 typedef struct {
-    int32_t geometry;     /* LBE_CYL (coaxial cylinders) | LBE_SPH (concentric spheres)      */
+    int32_t geometry;     /* LBE_CYL (coaxial cylinders) | LBE_SPH (concentric spheres) |
+                           * LBE_PLANAR (parallel plates; u_wall_inner moves along axis 1)    */
     double r_inner;       /* physical wall radii R_L < R_R; L = R_R - R_L                     */
     double r_outer;
     double u_wall_inner;  /* tangential (phi) speed of the inner cylinder; must be 0 for LBE_SPH */
@@ -79,6 +82,10 @@ typedef struct {
                            * stay FP64).  The state buffers are laid out at FP64 size so that
                            * lbe_run_to_steady can switch such an instance to FP64 storage in
                            * place (the bytes streamed per step are those of FP32 storage).   */
+    int32_t reduced;      /* cylinder or plates, 0 or 1: integrate p_z out (Sec. III, "Quadrature
+                           * choice"): the state holds phi = int f dp_z and chi = int p_z^2 f dp_z
+                           * on the (p_R, p_phi) quadrature, as the two planes i2 = 0, 1 of the
+                           * velocity index (q_t2 and n_expand[2] are then ignored; n2 = 2).   */
 } lbe_params;
 
 /* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),
@@ -177,7 +184,9 @@ lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap);
  *           9: cell volume of the ball of radius extra[0] centred at distance extra[2] from
  *              the axis/origin inside radius extra[1] (geometry of p) [1];
  *          10: d(f p)/dp matrix of the radial half-range axis (n0 x n0; not used by the
- *              reduced equations, exported for checks).
+ *              reduced equations, exported for checks);
+ *          11: nodes then weights of the 32-point half-range Gauss rule the equilibrium
+ *              projection uses at moderate u / sqrt(T) [64].
  * len_out receives the number of doubles written (or needed when cap is too small). */
 lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, double* out, int64_t cap,
                       int64_t* len_out);

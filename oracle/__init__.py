@@ -57,6 +57,7 @@ class Params(ctypes.Structure):
         ("q_t2", ctypes.c_int32),
         ("n_expand", ctypes.c_int32 * 3),
         ("cfl", ctypes.c_double),
+        ("reduced", ctypes.c_int32),
     ]
 
 
@@ -113,6 +114,8 @@ def _setup(lib):
     lib.orc_tau.restype = ctypes.c_double
     lib.orc_vol_sph.argtypes = [ctypes.c_double] * 3
     lib.orc_vol_sph.restype = ctypes.c_double
+    lib.orc_vol_slab.argtypes = [ctypes.c_double] * 3
+    lib.orc_vol_slab.restype = ctypes.c_double
     lib.orc_vol_cyl.argtypes = [ctypes.c_double] * 3
     lib.orc_vol_cyl.restype = ctypes.c_double
     lib.orc_fd4.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double]
@@ -214,6 +217,10 @@ def vol_sph(s: float, R: float, b: float) -> float:
     return _load().orc_vol_sph(s, R, b)
 
 
+def vol_slab(s: float, X: float, b: float) -> float:
+    return _load().orc_vol_slab(s, X, b)
+
+
 def vol_cyl(s: float, R: float, b: float) -> float:
     return _load().orc_vol_cyl(s, R, b)
 
@@ -240,7 +247,7 @@ FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
 
 
 def make_params(geometry, r_inner, r_outer, u_wall_inner, t_wall_inner, t_wall_outer, eta0, kn, nr,
-                q_radial, q_t1, q_t2, cfl, n_expand=(0, 0, 0)) -> Params:
+                q_radial, q_t1, q_t2, cfl, n_expand=(0, 0, 0), reduced=0, precision=0) -> Params:
     p = Params()
     p.geometry = geometry
     p.r_inner = r_inner
@@ -257,6 +264,7 @@ def make_params(geometry, r_inner, r_outer, u_wall_inner, t_wall_inner, t_wall_o
     for a in range(3):
         p.n_expand[a] = n_expand[a]
     p.cfl = cfl
+    p.reduced = int(reduced)
     return p
 
 

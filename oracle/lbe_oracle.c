@@ -685,6 +685,17 @@ double orc_vol_sph(double s, double R, double b)
            (12 * d);
 }
 
+/* Planar channel (the Cartesian model equation of Sec. II, the R_L -> infinity limit): volume of the
+ * ball of radius s centred at x = b that lies at x < X, a spherical cap of height h = X - (b - s):
+ * pi h^2 (3 s - h) / 3. */
+double orc_vol_slab(double s, double X, double b)
+{
+    if (X <= b - s) return 0;
+    if (X >= b + s) return 4.0 / 3 * PI * s * s * s;
+    double h = X - (b - s);
+    return PI * h * h * (3 * s - h) / 3;
+}
+
 /* alpha - sin(alpha) cos(alpha), the area of a circular segment of unit radius with half
  * angle alpha; a Taylor series for small alpha avoids the cancellation. */
 static double seg_area(double a)
@@ -806,6 +817,7 @@ typedef struct {
     int32_t nr, q_radial, q_t1, q_t2;
     int32_t n_expand[3];
     double cfl;
+    int32_t reduced; /* cylinder only: p_z integrated out (see "Reduced distributions" below) */
 } orc_params;
 
 typedef struct {
@@ -831,6 +843,7 @@ typedef struct {
     double last_resid;
     int64_t steps;
     int nan_flag;
+    int reduced;
 } orc_solver;
 
 /* Per-node macroscopic block computed from f, eqs. (macro_def) with quadrature sums
@@ -852,8 +865,77 @@ static inline void vel_of(const orc_solver* s, int v, double p[3])
     p[2] = s->ax[2].p[i2];
 }
 
+/* Reduced distributions (cylinder, Sec. III "Quadrature choice": the trivial p_z dependence is
+ * integrated out at the level of the model equation).  Reading: the state holds
+ *   phi(R, p_R, p_phi) = int f dp_z   (velocity index i2 = 0) and
+ *   chi(R, p_R, p_phi) = int p_z^2 f dp_z   (i2 = 1),
+ * on the mixed (p_R, p_phi) quadrature, with u_z = q_z = 0 by the symmetry of the flow.  Both obey
+ * the transport of f itself (radial advection and the (p_R, p_phi) force terms do not involve p_z).
+ * Their collision terms are the p_z-integrals of eqs. (j0), (j1) over the Maxwellian factor in p_z
+ * (mean 0, variance T): a polynomial linear in xi_z^2 integrates to its value at xi_z^2 = T
+ * (weight 1) and, times p_z^2, to T times its value at xi_z^2 = 3T (since int p^4 G = 3T^2). */
+static inline int is_chi(const orc_solver* s, int v) { return s->reduced && v / (s->n0 * s->n1) == 1; }
+
+/* Factors of the third axis of the equilibrium: the discrete projection of Sec. III.C, or for the
+ * reduced distributions the p_z-integrals int G dp_z = 1 and int p_z^2 G dp_z = T. */
+static void zfactors(const orc_solver* s, double u2, double T, double* g2)
+{
+    if (s->reduced) {
+        g2[0] = 1;
+        g2[1] = T;
+    } else {
+        geq_axis(&s->ax[2], u2, T, g2);
+    }
+}
+
+
+static void node_moments_reduced(const orc_solver* s, const double* fi, node_t* m)
+{
+    /* n, momentum from phi; the energy adds sum chi = int xi_z^2 f (u_z = 0). */
+    double n = 0, j[2] = {0, 0};
+    for (int v = 0; v < s->nv; v++) {
+        if (is_chi(s, v)) continue;
+        double p[3];
+        vel_of(s, v, p);
+        n += fi[v];
+        j[0] += fi[v] * p[0];
+        j[1] += fi[v] * p[1];
+    }
+    m->n = n;
+    m->u[0] = j[0] / n;
+    m->u[1] = j[1] / n;
+    m->u[2] = 0;
+    double e2 = 0, q[3] = {0, 0, 0}, P[3][3] = {{0}};
+    for (int v = 0; v < s->nv; v++) {
+        double p[3];
+        vel_of(s, v, p);
+        double xi[2] = {p[0] - m->u[0], p[1] - m->u[1]};
+        if (is_chi(s, v)) {
+            e2 += fi[v];
+            for (int a = 0; a < 2; a++) q[a] += 0.5 * fi[v] * xi[a];
+            P[2][2] += fi[v];
+        } else {
+            double x2 = xi[0] * xi[0] + xi[1] * xi[1];
+            e2 += fi[v] * x2;
+            for (int a = 0; a < 2; a++) {
+                q[a] += 0.5 * fi[v] * x2 * xi[a];
+                for (int b = 0; b < 2; b++) P[a][b] += fi[v] * xi[a] * xi[b];
+            }
+        }
+    }
+    m->T = e2 / (3 * n);
+    for (int a = 0; a < 3; a++) {
+        m->q[a] = q[a];
+        for (int b = 0; b < 3; b++) m->P[a][b] = P[a][b];
+    }
+}
+
 static void node_moments(const orc_solver* s, const double* fi, node_t* m)
 {
+    if (s->reduced) {
+        node_moments_reduced(s, fi, m);
+        return;
+    }
     double n = 0, j[3] = {0, 0, 0};
     for (int v = 0; v < s->nv; v++) {
         double p[3];
@@ -922,7 +1004,7 @@ void orc_free(orc_solver* s);
 static int validate(const orc_params* p)
 {
     if (!p) return ORC_EINVAL;
-    if (p->geometry != 0 && p->geometry != 1) return ORC_EINVAL;
+    if (p->geometry != 0 && p->geometry != 1 && p->geometry != 2) return ORC_EINVAL;
     if (!(p->r_inner > 0) || !(p->r_outer > p->r_inner)) return ORC_EINVAL;
     if (!(p->eta0 > 0 && p->eta0 < 0.5) || !(p->kn > 0)) return ORC_EINVAL;
     if (!(p->t_wall_inner > 0) || !(p->t_wall_outer > 0) || !(p->cfl > 0)) return ORC_EINVAL;
@@ -930,6 +1012,7 @@ static int validate(const orc_params* p)
     if (p->q_radial < 2 || p->q_t1 < 2 || p->q_t2 < 2) return ORC_EINVAL;
     if (p->q_radial > QMAX || p->q_t1 > QMAX || p->q_t2 > QMAX) return ORC_EINVAL;
     if (p->geometry == 1 && p->u_wall_inner != 0) return ORC_EINVAL;
+    if (p->reduced && p->geometry == 1) return ORC_EINVAL;
     double C = orc_confinement(p->eta0, p->kn);
     if (!(C > 1)) return ORC_EINVAL;
     int Q[3] = {p->q_radial, p->q_t1, p->q_t2};
@@ -946,6 +1029,10 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
     build_ptables();
     gl10_init();
     orc_params prm = *prm_in;
+    if (prm.reduced) { /* two planes (phi, chi) in place of the p_z axis */
+        prm.q_t2 = 2;
+        prm.n_expand[2] = 1;
+    }
     int Q[3] = {prm.q_radial, prm.q_t1, prm.q_t2};
     /* Reading: expansion order N_a = min(7, Q_a - 1) when not given (the paper uses 7). */
     for (int a = 0; a < 3; a++)
@@ -957,9 +1044,11 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
     }
     orc_solver* s = calloc(1, sizeof(orc_solver));
     s->prm = prm;
+    s->reduced = prm.reduced != 0;
     axis_build(&s->ax[0], 1, Q[0], prm.n_expand[0]);
     axis_build(&s->ax[1], 0, Q[1], prm.n_expand[1]);
     axis_build(&s->ax[2], 0, Q[2], prm.n_expand[2]);
+    if (s->reduced) s->ax[2].p[0] = s->ax[2].p[1] = 0; /* no p_z node: the planes carry its moments */
     s->n0 = s->ax[0].nq;
     s->n1 = s->ax[1].nq;
     s->n2 = s->ax[2].nq;
@@ -982,7 +1071,9 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
     for (int i = 0; i <= nr; i++) s->ri[i] = s->rcl + i * s->dr;
     for (int i = 0; i < nr; i++) {
         s->r[i] = s->rcl + (i + 0.5) * s->dr;
-        if (prm.geometry == 0)
+        if (prm.geometry == 2)
+            s->vol[i] = s->dr; /* planar: per unit wall area */
+        else if (prm.geometry == 0)
             s->vol[i] = s->r[i] * s->dr;
         else
             s->vol[i] = (s->ri[i + 1] * s->ri[i + 1] * s->ri[i + 1] - s->ri[i] * s->ri[i] * s->ri[i]) / 3;
@@ -1012,8 +1103,9 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
 #pragma omp parallel for schedule(dynamic)
         for (int i = 0; i < nr; i++)
             for (int j = 0; j <= nr; j++)
-                Vtab[i * (nr + 1) + j] = (prm.geometry == 0) ? orc_vol_cyl(s->sigma, s->ri[j], s->r[i])
-                                                              : orc_vol_sph(s->sigma, s->ri[j], s->r[i]);
+                Vtab[i * (nr + 1) + j] = (prm.geometry == 0)   ? orc_vol_cyl(s->sigma, s->ri[j], s->r[i])
+                                         : (prm.geometry == 1) ? orc_vol_sph(s->sigma, s->ri[j], s->r[i])
+                                                               : orc_vol_slab(s->sigma, s->ri[j], s->r[i]);
         for (int i = 0; i < nr; i++)
             for (int j = 0; j < nr; j++)
                 s->W[i * nr + j] = (Vtab[i * (nr + 1) + j + 1] - Vtab[i * (nr + 1) + j]) / ball;
@@ -1030,13 +1122,15 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
             double uw = side == 0 ? prm.u_wall_inner : 0;
             geq_axis(&s->ax[0], 0, Tw, g0);
             geq_axis(&s->ax[1], uw, Tw, g1);
-            geq_axis(&s->ax[2], 0, Tw, g2);
+            zfactors(s, 0, Tw, g2);
             double* gw = side == 0 ? s->gwl : s->gwr;
             double gin = 0;
             for (int v = 0; v < nv; v++) {
                 int i0 = v % s->n0, i1 = (v / s->n0) % s->n1, i2 = v / (s->n0 * s->n1);
                 gw[v] = g0[i0] * g1[i1] * g2[i2];
                 double pr = s->ax[0].p[i0];
+                /* the mass flux of the reduced model is that of phi alone */
+                if (is_chi(s, v)) continue;
                 if ((side == 0 && pr > 0) || (side == 1 && pr < 0)) gin += pr * gw[v];
             }
             if (side == 0)
@@ -1057,7 +1151,7 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
         double g0[2 * QMAX], g1[QMAX], g2[QMAX];
         geq_axis(&s->ax[0], 0, 1, g0);
         geq_axis(&s->ax[1], 0, 1, g1);
-        geq_axis(&s->ax[2], 0, 1, g2);
+        zfactors(s, 0, 1, g2);
         for (int i = 0; i < nr; i++)
             for (int v = 0; v < nv; v++) {
                 int i0 = v % s->n0, i1 = (v / s->n0) % s->n1, i2 = v / (s->n0 * s->n1);
@@ -1099,6 +1193,7 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
     const int nr = s->nr, nv = s->nv, n0 = s->n0, n1 = s->n1, n2 = s->n2;
     const orc_params* P = &s->prm;
     const int sph = P->geometry == 1;
+    const int planar = P->geometry == 2; /* Cartesian model equation: no vielbein force terms */
     node_t* nd = malloc(sizeof(node_t) * nr);
 
     /* (1) moments at every node. */
@@ -1150,6 +1245,7 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
         double outl = 0, outr = 0;
         for (int v = 0; v < nv; v++) {
             double pr = s->ax[0].p[v % n0];
+            if (is_chi(s, v)) continue; /* zero net mass flux: phi alone carries mass */
             if (pr < 0) {
                 double f0 = f[0 * (size_t)nv + v], f1 = f[1 * (size_t)nv + v], f2 = f[2 * (size_t)nv + v];
                 double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
@@ -1213,13 +1309,16 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
         double gR[2 * QMAX], gA[QMAX], gB[QMAX];
         geq_axis(&s->ax[0], m->u[0], m->T, gR);
         geq_axis(&s->ax[1], m->u[1], m->T, gA);
-        geq_axis(&s->ax[2], m->u[2], m->T, gB);
+        zfactors(s, m->u[2], m->T, gB);
         double rl = s->ri[i], rr = s->ri[i + 1];
         /* Reading (flux form of d(fR)/dR^2 and d(fr^2)/dr^3): finite volume with exact
          * shell measures; geometric factor of the force terms 1/r_i (cylinder) and
          * G_i = 3 (rr^2 - rl^2) / (2 (rr^3 - rl^3)) (sphere). */
         double adv_fac, force_fac;
-        if (!sph) {
+        if (planar) {
+            adv_fac = 1 / s->dr;
+            force_fac = 0;
+        } else if (!sph) {
             adv_fac = 1 / (s->r[i] * s->dr);
             force_fac = 1 / s->r[i];
         } else {
@@ -1228,7 +1327,9 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
         }
         double shak = (1 - m->Pr) / (m->n * m->T * m->T);
         double divu, dur = du[0 * nr + i];
-        if (!sph)
+        if (planar)
+            divu = dur;
+        else if (!sph)
             divu = dur + m->u[0] / s->r[i];
         else
             divu = dur + 2 * m->u[0] / s->r[i];
@@ -1238,7 +1339,9 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
             double p[3] = {s->ax[0].p[i0], s->ax[1].p[i1], s->ax[2].p[i2]};
             /* advection */
             double A;
-            if (!sph)
+            if (planar)
+                A = (F[(size_t)(i + 1) * nv + v] - F[(size_t)i * nv + v]) * adv_fac;
+            else if (!sph)
                 A = (rr * F[(size_t)(i + 1) * nv + v] - rl * F[(size_t)i * nv + v]) * adv_fac;
             else
                 A = (rr * rr * F[(size_t)(i + 1) * nv + v] - rl * rl * F[(size_t)i * nv + v]) * adv_fac;
@@ -1249,7 +1352,9 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
             double d1 = 0;
             for (int k = 0; k < n1; k++) d1 += s->K2a[i1 * n1 + k] * fi[i0 + n0 * (k + n1 * i2)];
             double I;
-            if (!sph) {
+            if (planar) {
+                I = 0;
+            } else if (!sph) {
                 I = force_fac * (p[1] * p[1] * d0 - p[0] * d1);
             } else {
                 double d2 = 0;
@@ -1261,13 +1366,22 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
             double fmb = m->n * gR[i0] * gA[i1] * gB[i2];
             double xi[3] = {p[0] - m->u[0], p[1] - m->u[1], p[2] - m->u[2]};
             double xi2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+            /* reduced distributions: the collision polynomials are linear in xi_z^2, which takes
+             * the value T for phi and 3T for chi (whose factor T sits in fmb through gB) */
+            if (s->reduced) {
+                xi[2] = 0;
+                xi2 = xi[0] * xi[0] + xi[1] * xi[1] + (i2 == 0 ? m->T : 3 * m->T);
+            }
             double xq = xi[0] * m->q[0] + xi[1] * m->q[1] + xi[2] * m->q[2];
             double fS = fmb * (1 + shak * (xi2 / (5 * m->T) - 1) * xq);
             double zeta[3] = {xi[0] / s2T, xi[1] / s2T, xi[2] / s2T};
             double z2 = zeta[0] * zeta[0] + zeta[1] * zeta[1] + zeta[2] * zeta[2];
+            if (s->reduced) z2 = xi2 / (2 * m->T); /* with xi_z^2 as above */
             /* Reading: zeta zeta : grad u in the covariant (orthonormal-frame) form. */
             double zzgu;
-            if (!sph)
+            if (planar)
+                zzgu = zeta[0] * zeta[0] * dur + zeta[0] * zeta[1] * du[1 * nr + i] + zeta[0] * zeta[2] * du[2 * nr + i];
+            else if (!sph)
                 zzgu = zeta[0] * zeta[0] * dur + zeta[0] * zeta[1] * (du[1 * nr + i] - m->u[1] / s->r[i]) +
                        zeta[1] * zeta[1] * m->u[0] / s->r[i] + zeta[0] * zeta[2] * du[2 * nr + i];
             else
@@ -1536,7 +1650,8 @@ double orc_mass(orc_solver* s)
     double m = 0;
     for (int i = 0; i < s->nr; i++) {
         double n = 0;
-        for (int v = 0; v < s->nv; v++) n += s->f[(size_t)i * s->nv + v];
+        for (int v = 0; v < s->nv; v++)
+            if (!is_chi(s, v)) n += s->f[(size_t)i * s->nv + v];
         m += s->vol[i] * n;
     }
     return m;

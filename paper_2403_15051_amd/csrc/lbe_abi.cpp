@@ -124,7 +124,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Byte layout of one instance inside the workspace.
 struct Layout {
     size_t fraw[3], f[3], mom, node, snap, resid, flags, nw, scratch;
-    size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qrec0, geo, r, wlo, wb, gwl, gwr;
+    size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qrec0, pgx0, pgw0, geo, r, wlo, wb, gwl, gwr;
     size_t simg;
     size_t total;
 };
@@ -174,6 +174,8 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t img_doubles, siz
     L.qy0 = take(t.ax[0].qy.size() * D);
     L.qlam0 = take(t.ax[0].qlam.size() * D);
     L.qrec0 = take(t.ax[0].qrec.size() * D);
+    L.pgx0 = take(kProjGauss * D);
+    L.pgw0 = take(kProjGauss * D);
     L.geo = take(t.geo.size() * D);
     L.r = take(t.r.size() * D);
     L.wlo = take(t.wlo.size() * sizeof(int32_t));
@@ -218,7 +220,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     const double Tlow = 0.5 * std::min(p.t_wall_inner, p.t_wall_outer);
     const double hwidth = std::min(1.5, std::max(0.1875, 3.35 * std::sqrt(std::max(Tlow, 0.0))));
     const size_t M = (size_t)(16 * (std::ceil((3 + 13 * std::sqrt(1.5 * Tmax) + std::fabs(p.u_wall_inner)) / hwidth) + 1));
-    b += 2 * align256(M * D) + align256((size_t)(3 * N + 1) * D);
+    b += 2 * align256(M * D) + align256((size_t)(3 * N + 1) * D) + 2 * align256(kProjGauss * D);
     b += 3 * align256(nr * 4 * D) + align256(nr * sizeof(int32_t)) + align256(nr * nr * D) + 2 * align256(nv * D);
     b += align256(nr * n2 * sizeof(WorkItem));
     b += 4 * align256(nr * (size_t)(n0 + n1 + n2) * D);
@@ -415,7 +417,7 @@ lbe_status plan_groups(lbe_ctx* c)
         for (size_t q = 0; q < c->groups.size(); q++) {
             const StageGroup& G = c->groups[q];
             if (G.n0 == t.n0 && G.n1 == t.n1 && G.n2 == t.n2 && G.geometry == t.prm.geometry &&
-                G.f32 == (t.prm.precision == LBE_FP32_STORE))
+                G.f32 == (t.prm.precision == LBE_FP32_STORE) && G.reduced == t.prm.reduced)
                 g = (int)q;
         }
         if (g < 0) {
@@ -427,6 +429,7 @@ lbe_status plan_groups(lbe_ctx* c)
             G.nv = t.nv;
             G.geometry = t.prm.geometry;
             G.f32 = t.prm.precision == LBE_FP32_STORE;
+            G.reduced = t.prm.reduced;
             G.S = 1;
             G.pstride = 1;
             c->groups.push_back(G);
@@ -993,6 +996,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.n2 = t.n2;
         d.geometry = t.prm.geometry;
         d.f32 = t.prm.precision == LBE_FP32_STORE;
+        d.reduced = t.prm.reduced;
         d.N0 = t.ax[0].N;
         d.N1 = t.ax[1].N;
         d.N2 = t.ax[2].N;
@@ -1038,6 +1042,8 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.qy0 = (const double*)(ws + L.qy0);
         d.qlam0 = (const double*)(ws + L.qlam0);
         d.qrec0 = (const double*)(ws + L.qrec0);
+        d.pgx0 = (const double*)(ws + L.pgx0);
+        d.pgw0 = (const double*)(ws + L.pgw0);
         d.M0 = (int32_t)t.ax[0].qy.size();
         d.qpw = t.ax[0].qpanel;
         d.nslices = nsl;
@@ -1063,6 +1069,8 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         if (e == hipSuccess) e = put(ws, L.qy0, t.ax[0].qy, c->stream);
         if (e == hipSuccess) e = put(ws, L.qlam0, t.ax[0].qlam, c->stream);
         if (e == hipSuccess) e = put(ws, L.qrec0, t.ax[0].qrec, c->stream);
+        if (e == hipSuccess) e = put(ws, L.pgx0, t.ax[0].gx, c->stream);
+        if (e == hipSuccess) e = put(ws, L.pgw0, t.ax[0].gw, c->stream);
         if (e == hipSuccess) e = put(ws, L.geo, t.geo, c->stream);
         if (e == hipSuccess) e = put(ws, L.r, t.r, c->stream);
         if (e == hipSuccess) e = put(ws, L.wlo, t.wlo, c->stream);
@@ -1378,6 +1386,7 @@ uint64_t params_fingerprint(const lbe_ctx* c)
         mix(dv, sizeof(dv));
         mix(iv, sizeof(iv));
         mix(&q.n_expand[2], sizeof(int32_t));
+        mix(&q.reduced, sizeof(int32_t));
     }
     return h;
 }
@@ -1623,8 +1632,9 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
         if (!extra) return LBE_EINVAL;
         if (len_out) *len_out = 1;
         if (cap < 1 || !out) return LBE_EINVAL;
-        out[0] = p->geometry == LBE_CYL ? ball_in_cylinder(extra[0], extra[1], extra[2])
-                                        : ball_in_sphere(extra[0], extra[1], extra[2]);
+        out[0] = p->geometry == LBE_CYL   ? ball_in_cylinder(extra[0], extra[1], extra[2])
+                 : p->geometry == LBE_SPH ? ball_in_sphere(extra[0], extra[1], extra[2])
+                                          : ball_below_plane(extra[0], extra[1], extra[2]);
         return LBE_OK;
     }
     InstanceTables t;
@@ -1663,6 +1673,10 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
             break;
         }
         case 10: v = t.K2r; break;
+        case 11:
+            v = t.ax[0].gx;
+            v.insert(v.end(), t.ax[0].gw.begin(), t.ax[0].gw.end());
+            break;
         default: return LBE_EINVAL;
     }
     if (len_out) *len_out = (int64_t)v.size();

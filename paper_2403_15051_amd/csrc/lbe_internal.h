@@ -15,6 +15,7 @@ constexpr int kMaxQ = 64;    // largest quadrature order per axis
 constexpr int kMaxN = 15;    // largest equilibrium expansion order
 constexpr int kNodeStride = 96;  // doubles per node in the node-coefficient block
 constexpr int kMomStride = 16;   // doubles per node in the moment-sum block
+constexpr int kProjGauss = 32;   // nodes per side of the projection kernel's half-range Gauss rule
 
 // Node-coefficient block layout (doubles, per node), written by the node kernel.
 enum NodeField {
@@ -48,6 +49,8 @@ struct AxisTables {
     std::vector<double> qh;        // half-range: h_l(qy_m), M x (N+1)
     std::vector<double> qrec;      // half-range, from x h_l = b_{l+1} h_{l+1} + a_l h_l + b_l h_{l-1}:
                                    // (a_l, b_l^2) for l < N, then h_0 / (b_1 ... b_l) for l <= N
+    std::vector<double> gx, gw;    // half-range: the kProjGauss-point Gauss rule for exp(-x^2/2)/sqrt(2 pi)
+                                   // on [0, inf) (projection at moderate u / sqrt(T))
 };
 
 // Everything the host precomputes for one instance.
@@ -70,7 +73,8 @@ struct InstanceTables {
 // Device descriptor of one instance (lives in device memory; pointers into the workspace).
 struct DevInstance {
     int32_t nr, nv, n0, n1, n2, geometry;
-    int32_t f32, pad_;  // 1: state buffers hold FP32 deviations from base[] (LBE_FP32_STORE)
+    int32_t f32, reduced;  // f32 1: state buffers hold FP32 deviations from base[] (LBE_FP32_STORE);
+                           // reduced 1: the planes i2 = 0, 1 are phi, chi (p_z integrated out)
     int32_t N0, N1, N2, wband;
     double dt, dr, eta0, kn, chi0, L, gin_l, gin_r;
     double rcl, rcr, uw, tratio;  // computational walls, inner wall speed, T_outer / T_inner
@@ -88,6 +92,7 @@ struct DevInstance {
     const double* poly0; const double* poly1; const double* poly2;
     const double* qy0; const double* qlam0;  // projection rule, M0 nodes
     const double* qrec0;    // recurrence of the half-range polynomials (AxisTables::qrec)
+    const double* pgx0; const double* pgw0;  // half-range Gauss rule of the projection (kProjGauss nodes)
     int32_t M0, nslices;    // equilibrium projection nodes; velocity slices of the stage kernel
     double qpw;             // panel width of the projection rule
     const double* geo;      // [nr][4]
@@ -115,7 +120,7 @@ constexpr int kTileDescStride = 16;  // ints per MFMA tile descriptor of the sta
 // Launch group of the stage kernel: instances sharing one velocity set (n0, n1, n2, geometry).
 // All sizes are uniform over the group; LDS offsets are in doubles.
 struct StageGroup {
-    int32_t n0, n1, n2, nv, geometry, f32;
+    int32_t n0, n1, n2, nv, geometry, f32, reduced;
     int32_t S, ns2, nvs, ncols_s, ncols16, plane_cols;  // slices, i2 / velocities / columns per slice
     int32_t ncp16;                                       // d2 columns (n0 n1, sphere) padded to 16
     int32_t plane_sz, op_sz, ib_sz;                      // doubles per plane / output / term buffer
@@ -135,7 +140,7 @@ struct StageGroup {
     int32_t off_sb, off_fb, bstride;  // f32: base factors of the window rows / own rows (stride bstride)
 };
 
-constexpr int kCoefStride = 18;  // doubles per node of the stage kernel's coefficient block
+constexpr int kCoefStride = 20;  // doubles per node of the stage kernel's coefficient block
 
 // Network of the learned warm start (lbe_mlp.hip): buffers and the forward pass used by
 // lbe_warm_start.  Outputs are standardised: physical = mean + scale * output.
@@ -151,6 +156,7 @@ lbe_status build_instance(const lbe_params& p, InstanceTables* t, std::string* e
 void equilibrium_axis(const AxisTables& ax, double u, double T, double* g);
 double ball_in_cylinder(double s, double R, double b);
 double ball_in_sphere(double s, double R, double b);
+double ball_below_plane(double s, double X, double b);
 double chi_cs(double eta);
 
 }  // namespace lbe

@@ -256,6 +256,13 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
         const double x = I.p0[i0], y = I.p1[i1], z = I.p2[i2];
         const double fv = (from_scratch == 1 || (from_scratch == 2 && I.f32)) ? I.scratch[(size_t)i * I.nv + v]
                                                                                 : f_at(I, buf, tab, i, v);
+        if (I.reduced && i2 == 1) {
+            // chi = int p_z^2 f dp_z: the z-energy and its part of the energy flux, no mass
+            acc[MF_SZZ] += fv;
+            acc[MF_S3X] += fv * x;
+            acc[MF_S3Y] += fv * y;
+            continue;
+        }
         const double x2 = x * x + y * y + z * z;
         acc[MF_S0] += fv;
         acc[MF_S1X] += fv * x;
@@ -299,6 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
             const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
             auto F = [&](int row) { return f_at3(I, src, bsrc, row, v, i0, i1, i2); };
             const double pr = I.p0[i0];
+            if (I.reduced && i2 == 1) continue;  // chi carries no mass
             if (left && pr < 0) {
                 const double f0 = F(0), f1 = F(1), f2 = F(2);
                 const double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
@@ -459,7 +467,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         nd[NF_SHAK] = (1 - Pr) / (n * T * T);
         nd[NF_INVTAU] = 1 / tau;
         // divergence and the covariant shear pieces of zeta zeta : grad u (reading of eq. (j1))
-        if (I.geometry == LBE_CYL) {
+        if (I.geometry != LBE_SPH) {  // cylinder; plates have 1/r = 0 (Cartesian gradients)
             nd[NF_DIVU] = du0 + m.u[0] * invr;
             nd[NF_SHEAR01] = du1 - m.u[1] * invr;
         } else {
@@ -476,14 +484,17 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     }
 }
 
-// Half-range projection coefficients I_l^+- (Sec. III.C) of one node by one wave: the 64 lanes
-// share the quadrature nodes of the panels within 9.6 sqrt(T) of +-u (farther panels contribute
-// below 1e-20 of the peak) and the 2 (N0+1) sums are reduced with the register reduce-scatter.
+// Half-range projection coefficients I_l^+- (Sec. III.C) of one node by one wave.  For |u| <= 2
+// sqrt(T) and N0 < 8 a 32-point half-range Gauss rule in the scaled variable (below); otherwise the
+// 64 lanes share the nodes of the composite Gauss-Legendre panels within 9.6 sqrt(T) of +-u
+// (farther panels contribute below 1e-20 of the peak) and the 2 (N0+1) sums are reduced with the
+// register reduce-scatter.
 // h_l at a quadrature node comes from the monic form of its three-term recurrence,
 // p_{l+1} = (x - a_l) p_l - b_l^2 p_{l-1}, h_l = p_l n_l with n_l = h_0 / (b_1 ... b_l) applied to
 // the reduced sums: cheaper than reading a table row per node, which made the kernel L2-bound.
 // NH bounds N0 + 1; with NH <= 8 the recurrence coefficients stay in scalar registers.
 typedef const __attribute__((address_space(4))) double* cdptr;
+static_assert(kProjGauss == 32, "the projection's Gauss rule takes one half of the wave per side");
 template <int NH>
 __device__ inline void proj_node(const DevInstance& I, double* nd, int lane)
 {
@@ -500,6 +511,40 @@ __device__ inline void proj_node(const DevInstance& I, double* nd, int lane)
         rb[l] = REG && l < N0 ? q[2 * l + 1] : 0.0;
     }
     const int which = (lane >> 2) & 15;
+    // Moderate shifts |u| <= 2 sqrt(T): with y = sqrt(T) x the integral of h_l(y) times the Gaussian
+    // of (u, T) over y >= 0 is the integral of h_l(sqrt(T) x) exp(b x - b^2/2), b = u / sqrt(T),
+    // against exp(-x^2/2)/sqrt(2 pi) on x >= 0, which the 32-point half-range Gauss rule of that
+    // weight gives to rounding (the exponential factor is smooth on the rule's scale; measured
+    // against 30-digit quadrature: 1.4e-15 of the integral of |h_l| times the Gaussian for l <= 15,
+    // |b| <= 2).  One rule node per lane and side: lanes 0-31 take side +, lanes 32-63 side -, and
+    // one reduce-scatter sums both sides' coefficients.
+    if (REG) {
+        const double sT = sqrt(T), bsh = u / sT;
+        if (fabs(bsh) <= 2.0) {
+            const int side = lane >> 5, m = lane & (kProjGauss - 1);
+            const double xs = I.pgx0[m], bb = side ? -bsh : bsh;
+            const double gw = I.pgw0[m] * exp(fma(bb, xs, -0.5 * bb * bb));
+            const double x = sT * xs;
+            double acc[8];
+            double pm = 0.0, p = 1.0;
+#pragma unroll
+            for (int l = 0; l < 8; l++) {
+                acc[l] = l <= N0 ? gw * p : 0.0;
+                if (l + 1 < 8 && l < N0) {
+                    const double pn = fma(x - ra[l < NR ? l : 0], p, -rb[l < NR ? l : 0] * pm);
+                    pm = p;
+                    p = pn;
+                }
+            }
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) v[k] = ((k < 8) == (side == 0)) ? acc[k & 7] : 0.0;
+            const double tot = reduce_scatter16(v, lane);
+            const int l = which & 7;
+            if ((lane & 3) == 0 && l <= N0) nd[((which >> 3) ? NF_IMINUS : NF_IPLUS) + l] = tot * q[2 * N0 + l];
+            return;
+        }
+    }
     for (int side = 0; side < 2; side++) {
         double acc[NH];
 #pragma unroll
@@ -617,7 +662,7 @@ enum TileDesc {
 //          + |y|^2 (H0 y0 + H1 y1 + H2 y2).
 enum StageCoef {
     SC_C0 = 0, SC_G0, SC_G1, SC_G2, SC_E00, SC_E01, SC_E02, SC_E11, SC_E12, SC_E22, SC_H0, SC_H1, SC_H2,
-    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_N, SC_COUNT
+    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_N, SC_T, SC_COUNT
 };
 static_assert(SC_COUNT <= kCoefStride, "stage coefficient block");
 
@@ -689,6 +734,7 @@ __device__ inline void stage_coefs(const double* nd, const double* geo4, const d
     out[SC_AR] = sigma * geo4[1];
     out[SC_FFAC] = sigma * geo4[2];
     out[SC_N] = n;
+    out[SC_T] = nd[NF_T];
 }
 
 // Stage image of one instance and velocity slice, written to R: the tables the stage kernel
@@ -1052,7 +1098,12 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     for (int e = tid; e < G.ncols16 * 16; e += B) {
         const int col = e >> 4, m = e & 15;
         double val = 0.0;
-        if (col < ncol && m < 9) {
+        if (col < ncol && m < 9 && G.reduced && (c_s0 + col) / n1 == 1) {
+            // a chi column (p_z integrated out): chi is int p_z^2 f, so it adds to the z-energy
+            // (factor 4) and, as |y|^2, to the energy fluxes (6: y_r |y|^2, 7: y_1 |y|^2)
+            const double y1 = pc1[col] - csh[1];
+            val = (m == 4 || m == 6) ? 1.0 : m == 7 ? y1 : 0.0;
+        } else if (col < ncol && m < 9) {
             const double y1 = pc1[col] - csh[1], y2 = pc2[col] - csh[2];
             const double rho = y1 * y1 + y2 * y2;
             switch (m) {
@@ -1412,7 +1463,13 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 const double a1 = fma(cf[SC_E12], Y2, fma(cf[SC_E11], Y1, cf[SC_G1]));
                 const double a2 = fma(cf[SC_E22], Y2, cf[SC_G2]);
                 const double hy = fma(cf[SC_H2], Y2, fma(cf[SC_H1], Y1, cf[SC_H0] * Y0));
-                const double Pc = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
+                double Pc = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
+                if (G.reduced) {
+                    // reduced distributions (y_z = 0): the terms in xi_z^2 of the cubic, at xi_z^2 = T
+                    // for phi and 3T for chi (chi's own factor T is its equilibrium factor g2 = T)
+                    const double s2 = (gx2[j] != n0 + n1 ? 3.0 : 1.0) * cf[SC_T];
+                    Pc = fma(s2, fma(cf[SC_H1], Y1, fma(cf[SC_H0], Y0, cf[SC_E22])), Pc);
+                }
                 const double A = fma(cf[SC_AR], Fr[j], -cf[SC_AL] * Fl[j]);
                 double o = fma(fmb, Pc, -(A + Iv));
                 o = fma(cf[SC_CF], sl[j][(P + 2) % 7], o);
@@ -1714,7 +1771,8 @@ __global__ void __launch_bounds__(kBlock) k_grad13(const DevInstance* __restrict
     for (int v = threadIdx.x; v < I.nv; v += kBlock) {
         const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
         const double xr = I.p0[i0], xt = I.p1[i1] - ut, xz = I.p2[i2];
-        const double xi2 = xr * xr + xt * xt + xz * xz;
+        // reduced distributions: xi_z^2 at T for phi, 3T for chi (their factor g2 is 1 or T)
+        const double xi2 = xr * xr + xt * xt + (I.reduced ? (i2 ? 3 * T : T) : xz * xz);
         const double fmb = n * g[i0] * g[n0 + i1] * g[n0 + n1 + i2];
         f[v] = fmb * (1 + cP * xr * xt + cq * xr * (xi2 * inv5T - 1));
     }
@@ -1756,7 +1814,7 @@ __global__ void __launch_bounds__(kBlock) k_renorm(const DevInstance* __restrict
     const double dr = I.dr;
     for (int i = threadIdx.x; i < I.nr; i += kBlock) {
         const double r = I.r[i];
-        const double V = I.geometry == LBE_CYL ? r * dr : r * r * dr + dr * dr * dr / 12;
+        const double V = I.geometry == LBE_CYL ? r * dr : I.geometry == LBE_SPH ? r * r * dr + dr * dr * dr / 12 : dr;
         double n = 0;
         for (int sl = 0; sl < I.nslices; sl++) n += I.mom[((size_t)i * I.nslices + sl) * kMomStride + MF_S0];
         acc[0] += V * n;
@@ -1790,11 +1848,11 @@ __global__ void __launch_bounds__(kBlock) k_base_copy(const DevInstance* __restr
     if (e < n) I.base[0][e] = I.base[3][e];
 }
 
-// Cell measure V_i: r_i dr (cylinder) or (r_{i+1/2}^3 - r_{i-1/2}^3) / 3 (sphere).
+// Cell measure V_i: r_i dr (cylinder), (r_{i+1/2}^3 - r_{i-1/2}^3) / 3 (sphere), dr (plates).
 __device__ inline double cell_volume(const DevInstance& I, int i)
 {
     const double r = I.r[i], dr = I.dr;
-    return I.geometry == LBE_CYL ? r * dr : r * r * dr + dr * dr * dr / 12;
+    return I.geometry == LBE_CYL ? r * dr : I.geometry == LBE_SPH ? r * r * dr + dr * dr * dr / 12 : dr;
 }
 
 // Total mass sum_i V_i n_i of every instance (only >= 0: that instance; -2: the FP32-storage

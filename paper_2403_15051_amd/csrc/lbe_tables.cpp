@@ -6,6 +6,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,6 +174,42 @@ static void half_eval(int n, const std::vector<ld>& a, const std::vector<ld>& b,
     }
 }
 
+// Half-range Gauss rule of order M for the weight exp(-x^2/2)/sqrt(2 pi) on [0, inf): the zeros of
+// h_M (Jacobi-matrix eigenvalues, Newton-polished) and the Christoffel weights 1 / sum_{l<M} h_l^2.
+// Built once and shared (the projection kernel's rule for the equilibrium at moderate u/sqrt(T)).
+static void half_gauss_rule(int M, std::vector<double>& xo, std::vector<double>& wo)
+{
+    static std::mutex mu;
+    static std::vector<double> cx, cw;
+    static int cm = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cm != M) {
+        std::vector<ld> a, b;
+        half_recurrence(M + 1, a, b);
+        std::vector<ld> d(a.begin(), a.begin() + M), e(M, 0), roots;
+        for (int k = 1; k < M; k++) e[k] = b[k];
+        tridiag_eigenvalues(d, e, roots);
+        std::vector<ld> h(M + 2), dh(M + 2);
+        cx.assign(M, 0);
+        cw.assign(M, 0);
+        for (int i = 0; i < M; i++) {
+            ld x = roots[i];
+            for (int it = 0; it < 3; it++) {
+                half_eval(M, a, b, x, h.data(), dh.data());
+                x -= h[M] / dh[M];
+            }
+            half_eval(M, a, b, x, h.data(), nullptr);
+            ld sum = 0;
+            for (int l = 0; l < M; l++) sum += h[l] * h[l];
+            cx[i] = (double)x;
+            cw[i] = (double)(1 / sum);
+        }
+        cm = M;
+    }
+    xo = cx;
+    wo = cw;
+}
+
 // Orthonormal probabilists' Hermite functions psi_l = He_l / sqrt(l!), l = 0..n.
 static void herm_eval(int n, ld x, ld* psi)
 {
@@ -256,6 +293,7 @@ static void build_half_axis(int Q, int N, double Y, double hwidth, AxisTables* a
         if (l > 0) nrm /= b[l];
         ax->qrec.push_back((double)nrm);
     }
+    half_gauss_rule(kProjGauss, ax->gx, ax->gw);
     half_eval(Q, a, b, 0, h.data(), nullptr);
     std::vector<ld> hzero(h.begin(), h.begin() + Q);
 
@@ -364,6 +402,24 @@ static void build_full_axis(int Q, int N, AxisTables* ax, std::vector<double>* K
         }
 }
 
+// The p_z "axis" of the reduced distributions (cylinder, p_z integrated out): two planes, phi =
+// int f dp_z (i2 = 0) and chi = int p_z^2 f dp_z (i2 = 1).  Written as a full-range axis so that the
+// equilibrium machinery applies unchanged: nodes p = 0 (no p_z dependence is left), weights 1, and
+// the expansion rows [1, 0, 0] and [1, 0, 2] with N = 2, so that with the full-range coefficients
+// c_0 = 1, c_2 = (T - 1 + u^2) / 2 at u_z = 0 the factors are int G dp_z = 1 and int p_z^2 G dp_z =
+// T.  No force term acts along it (K2 is zero; the cylinder has none along z anyway).
+static void build_reduced_axis(AxisTables* ax, std::vector<double>* K2)
+{
+    ax->half = false;
+    ax->Q = 2;
+    ax->nq = 2;
+    ax->N = 2;
+    ax->p.assign(2, 0.0);
+    ax->w.assign(2, 1.0);
+    ax->poly = {1.0, 0.0, 0.0, 1.0, 0.0, 2.0};
+    K2->assign(4, 0.0);
+}
+
 // ------------------------------------------------------------------ equilibrium (Sec. III.C)
 
 void equilibrium_axis(const AxisTables& ax, double u, double T, double* g)
@@ -457,6 +513,16 @@ double ball_in_cylinder(double s_, double R_, double b_)
     return (double)V;
 }
 
+// Volume of the part x < X of the ball of radius s centred at x = b (plates: a spherical cap of
+// height h = X - b + s, of volume pi h^2 (3 s - h) / 3).
+double ball_below_plane(double s_, double X_, double b_)
+{
+    const ld s = s_, h = (ld)X_ - b_ + s;
+    if (h <= 0) return 0;
+    if (h >= 2 * s) return (double)(4 * kPi * s * s * s / 3);
+    return (double)(kPi * h * h * (3 * s - h) / 3);
+}
+
 // Volume of the ball of radius s centred at distance b from the origin inside the ball of
 // radius R about the origin (Appendix A, lens of two spheres).
 double ball_in_sphere(double s_, double R_, double b_)
@@ -479,7 +545,8 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
         if (err) *err = m;
         return LBE_EINVAL;
     };
-    if (p.geometry != LBE_CYL && p.geometry != LBE_SPH) return bad("geometry must be LBE_CYL or LBE_SPH");
+    if (p.geometry != LBE_CYL && p.geometry != LBE_SPH && p.geometry != LBE_PLANAR)
+        return bad("geometry must be LBE_CYL, LBE_SPH or LBE_PLANAR");
     if (!(p.r_inner > 0) || !(p.r_outer > p.r_inner) || !std::isfinite(p.r_outer))
         return bad("need 0 < r_inner < r_outer");
     if (!(p.eta0 > 0 && p.eta0 < 0.5)) return bad("eta0 must lie in (0, 0.5)");
@@ -488,6 +555,12 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
     if (!(p.cfl > 0) || !std::isfinite(p.cfl)) return bad("cfl must be positive");
     if (!std::isfinite(p.u_wall_inner)) return bad("u_wall_inner must be finite");
     if (p.geometry == LBE_SPH && p.u_wall_inner != 0) return bad("a spherical instance cannot have a wall velocity");
+    if (p.reduced != 0 && p.reduced != 1) return bad("reduced must be 0 or 1");
+    if (p.reduced && p.geometry == LBE_SPH) return bad("the reduced distributions are for cylinders and plates");
+    if (p.reduced) {  // the (phi, chi) planes take the place of the p_z axis
+        p.q_t2 = 2;
+        p.n_expand[2] = 2;
+    }
     if (p.nr < 8 || p.nr > 1024) return bad("nr must lie in [8, 1024]");
     if (p.precision != LBE_FP64 && p.precision != LBE_FP32_STORE) return bad("precision must be LBE_FP64 or LBE_FP32_STORE");
     const int Q[3] = {p.q_radial, p.q_t1, p.q_t2};
@@ -495,7 +568,8 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
         if (Q[a] < 2 || Q[a] > kMaxQ) return bad("quadrature orders must lie in [2, 64]");
         int N = p.n_expand[a];
         if (N == 0) N = std::min(7, Q[a] - 1);
-        if (N < 1 || N >= Q[a] || N > kMaxN) return bad("expansion orders need 1 <= N_a < Q_a and N_a <= 15");
+        if (a == 2 && p.reduced) N = 2;  // the pseudo-axis of the reduced distributions (below)
+        else if (N < 1 || N >= Q[a] || N > kMaxN) return bad("expansion orders need 1 <= N_a < Q_a and N_a <= 15");
         p.n_expand[a] = N;
     }
     const double C = 1 / (6 * std::sqrt(2.0) * p.eta0 * chi_cs(p.eta0) * p.kn);
@@ -521,7 +595,10 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
     const double hwidth = std::min(1.5, std::max(0.1875, 3.35 * std::sqrt(Tlow)));
     build_half_axis(p.q_radial, p.n_expand[0], Y, hwidth, &t->ax[0], &t->K1, &t->K2r);
     build_full_axis(p.q_t1, p.n_expand[1], &t->ax[1], &t->K2a);
-    build_full_axis(p.q_t2, p.n_expand[2], &t->ax[2], &t->K2b);
+    if (p.reduced)
+        build_reduced_axis(&t->ax[2], &t->K2b);
+    else
+        build_full_axis(p.q_t2, p.n_expand[2], &t->ax[2], &t->K2b);
     t->n0 = t->ax[0].nq;
     t->n1 = t->ax[1].nq;
     t->n2 = t->ax[2].nq;
@@ -551,6 +628,12 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
     t->geo.resize(4 * nr);
     for (int i = 0; i < nr; i++) {
         const ld rl = t->ri[i], rr = t->ri[i + 1], rc = t->r[i];
+        if (p.geometry == LBE_PLANAR) {  // Cartesian: no radius weights, no force terms
+            t->geo[4 * i + 0] = t->geo[4 * i + 1] = (double)(1 / (ld)t->dr);
+            t->geo[4 * i + 2] = 0.0;
+            t->geo[4 * i + 3] = 0.0;
+            continue;
+        }
         if (p.geometry == LBE_CYL) {
             const ld V = rc * (ld)t->dr;
             t->geo[4 * i + 0] = (double)(rl / V);
@@ -588,8 +671,9 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
             const int lo = t->wlo[i], hi = whi[i];
             std::vector<double> V(hi - lo + 2);
             for (int j = lo; j <= hi + 1; j++)
-                V[j - lo] = p.geometry == LBE_CYL ? ball_in_cylinder(s, t->ri[j], t->r[i])
-                                                  : ball_in_sphere(s, t->ri[j], t->r[i]);
+                V[j - lo] = p.geometry == LBE_CYL   ? ball_in_cylinder(s, t->ri[j], t->r[i])
+                            : p.geometry == LBE_SPH ? ball_in_sphere(s, t->ri[j], t->r[i])
+                                                    : ball_below_plane(s, t->ri[j], t->r[i]);
             for (int j = lo; j <= hi; j++) t->wb[(size_t)i * wb + (j - lo)] = (double)(((ld)V[j + 1 - lo] - V[j - lo]) / ball);
         }
     }
@@ -611,6 +695,7 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
                 const int i0 = v % t->n0, i1 = (v / t->n0) % t->n1, i2 = v / (t->n0 * t->n1);
                 gw[v] = g0[i0] * g1[i1] * g2[i2];
                 const double pr = t->ax[0].p[i0];
+                if (p.reduced && i2 == 1) continue;  // the mass flux is carried by phi alone
                 if ((side == 0 && pr > 0) || (side == 1 && pr < 0)) gin += (ld)pr * gw[v];
             }
             (side == 0 ? t->gin_l : t->gin_r) = (double)gin;

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBE_LIB") or os.path.join(_HERE, "liblbe.so")
 
 LBE_OK, LBE_EINVAL, LBE_ENOMEM, LBE_EDEVICE, LBE_ENOTCONV, LBE_ENAN, LBE_ESTATE = 0, -1, -2, -3, -4, -5, -6
-CYL, SPH = 0, 1
+CYL, SPH, PLANAR = 0, 1, 2
 FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
 WARM_FIELDS = ("n", "u_t1", "T", "q_r", "P_rt1")
 GEMM_BF16, GEMM_FP32 = 0, 1
@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
         ("n_expand", ctypes.c_int32 * 3),
         ("cfl", ctypes.c_double),
         ("precision", ctypes.c_int32),
+        ("reduced", ctypes.c_int32),
     ]
 
 
@@ -63,6 +64,7 @@ def make_params(d: dict) -> Params:
     for k in PARAM_KEYS:
         setattr(p, k, d[k])
     p.precision = int(d.get("precision", FP64))
+    p.reduced = int(d.get("reduced", 0))
     ne = d.get("n_expand", (0, 0, 0))
     for a in range(3):
         p.n_expand[a] = int(ne[a])

@@ -140,10 +140,14 @@ def read_golden(name):
     return prof, steps
 
 
-@pytest.mark.parametrize("name,p", [
+STEADY_CASES = [
     ("steady_fourier_cyl_small", dict(W.FOURIER_CYL, nr=32, q_radial=4, q_t1=4, q_t2=4)),
     ("steady_fourier_cyl", dict(W.FOURIER_CYL)),
-])
+    ("steady_fourier_sph", dict(W.FOURIER_SPH)),
+]
+
+
+@pytest.mark.parametrize("name,p", STEADY_CASES)
 def test_steady_state_fp32_vs_oracle(name, p):
     """Cylindrical Fourier (T 1 / 1.5, eta0 0.1, Kn 0.5) with FP32 storage for 1.5x the oracle's
     steps to 1e-8.  Each stage rounds the stored deviations, which leaves a residual floor of a
@@ -188,19 +192,21 @@ def test_steady_state_fp32_vs_oracle(name, p):
     check(g64.moments(), mo, name + " fp64", tol=1e-12, ufloor=1.0)
 
 
-def test_steady_solve_switches_to_fp64_storage_and_converges():
-    """lbe_run_to_steady on FP32-storage instances of the cylindrical Fourier case (Nr 32 and the
-    full Nr 128): the FP32 solve stops improving at its rounding floor, the library switches the
-    launch group to FP64 storage in place and the solve reaches 1e-8; the converged profiles
-    match the converged FP64 oracle to 1e-7 (n, T, q) and the instances report the switch."""
-    for name, p in (("steady_fourier_cyl_small", dict(W.FOURIER_CYL, nr=32, q_radial=4, q_t1=4, q_t2=4)),
-                    ("steady_fourier_cyl", dict(W.FOURIER_CYL))):
-        mo, steps_o = read_golden(name)
-        g = lbe.Solver(f32(p))
-        st, steps, res = g.run_to_steady(1e-8, 400000, 50)
-        info = g.info(0)
-        print(name, "steps", steps[0], "oracle", steps_o, "residual", res[0], "switched at", info.get("promoted_at"),
-              flush=True)
-        assert st == lbe.LBE_OK and res[0] <= 1e-8
-        assert info["fp32_now"] == 0 and info["promoted_at"] > 0
-        check(g.moments(), mo, name + " fp32 then fp64", fields=("n", "T", "q_r"), tol=1e-7)
+@pytest.mark.parametrize("name,p", STEADY_CASES)
+def test_steady_solve_switches_to_fp64_storage_and_converges(name, p):
+    """lbe_run_to_steady on FP32-storage instances of the Fourier cases (cylinder Nr 32 and 128,
+    sphere Nr 256 with 4608 velocities): the FP32 solve stops improving at its rounding floor, the
+    library switches the launch group to FP64 storage in place and the solve reaches 1e-8; the
+    converged profiles match the converged FP64 oracle to 1e-7 (n, T, q) and the instances report
+    the switch."""
+    if not os.path.exists(os.path.join(GOLDEN, name + ".txt")):
+        pytest.skip("fixture not generated")
+    mo, steps_o = read_golden(name)
+    g = lbe.Solver(f32(p))
+    st, steps, res = g.run_to_steady(1e-8, 400000, 50)
+    info = g.info(0)
+    print(name, "steps", steps[0], "oracle", steps_o, "residual", res[0], "switched at", info["promoted_at"],
+          flush=True)
+    assert st == lbe.LBE_OK and res[0] <= 1e-8
+    assert info["fp32_now"] == 0 and info["promoted_at"] > 0
+    check(g.moments(), mo, name + " fp32 then fp64", fields=("n", "T", "q_r"), tol=1e-7)

@@ -1,0 +1,106 @@
+"""Reduced distributions (cylinder, p_z integrated out) on the GPU through the C ABI against the
+oracle, on the paper's production velocity sets: HHLB(7,20) x HLB(7,8) with the (phi, chi) planes
+(640 values per node), in the paper's units (sigma = 1, R_L = 1, C = 4 and 7, dr = sigma/10,
+dt ~ 1e-3).  FP64: f and the profiles at 1e-12 normwise; FP32 storage: profiles at 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15051_amd import lbe, workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    lbe.load()
+
+
+def nrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+COUETTE = W.paper_case("couette", 0, 0.1, 4, 1)
+FOURIER = W.paper_case("fourier", 0, 0.2, 7, 3)
+SPHERE = W.paper_case("fourier", 1, 0.1, 4, 1)
+
+
+def profile_errors(mg, mo):
+    uscale = max(np.abs(mo[k]).max() for k in ("u_r", "u_t1"))
+    nT = np.abs(mo["n"]).max() * np.abs(mo["T"]).max()
+    out = {}
+    for k in ("n", "u_r", "u_t1", "T", "q_r", "P_rt1", "nbar", "chi"):
+        scale = uscale if k.startswith("u_") else np.abs(mo[k]).max()
+        if k == "q_r":
+            scale = max(scale, nT * np.sqrt(np.abs(mo["T"]).max()))
+        elif k == "P_rt1":
+            scale = max(scale, nT)
+        out[k] = float(np.abs(mg[k] - mo[k]).max() / scale)
+    return out
+
+
+@pytest.mark.parametrize("p", [COUETTE, FOURIER])
+def test_reduced_rhs_of_an_oracle_state(p):
+    print("case", p, flush=True)
+    o = oracle.Solver(W.oracle_params(p))
+    assert o.nv == 640
+    o.step(30)
+    g = lbe.Solver(p)
+    g.set_state(0, o.get_f())
+    e = nrel(g.rhs(), o.rhs())
+    print("rhs", e, flush=True)
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("p", [COUETTE, FOURIER])
+def test_reduced_500_steps_fp64(p):
+    o = oracle.Solver(W.oracle_params(p))
+    g = lbe.Solver(p)
+    o.step(500)
+    g.step(500)
+    e = nrel(g.get_state(), o.get_f())
+    errs = profile_errors(g.moments(), o.moments())
+    print("f", e, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert e <= TOL
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+
+
+def test_reduced_500_steps_fp32_storage():
+    p = dict(COUETTE, precision=lbe.FP32_STORE)
+    o = oracle.Solver(W.oracle_params(p))
+    g = lbe.Solver(p)
+    o.step(500)
+    g.step(500)
+    errs = profile_errors(g.moments(), o.moments())
+    print({k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+
+
+def test_paper_grid_batch_with_reduced_and_full_velocity_sets():
+    """Reduced cylinders, a sphere on HHLB(7,20) x HLB(7,8) x HLB(7,8) (2560 velocities) and a
+    three-axis cylinder advance in one context; each matches its own oracle run."""
+    ps = [COUETTE, FOURIER, SPHERE, dict(W.COUETTE_SMALL, nr=20, q_t2=4)]
+    g = lbe.Solver(ps)
+    g.step(100)
+    for k, p in enumerate(ps):
+        o = oracle.Solver(W.oracle_params(p))
+        o.step(100)
+        e = nrel(g.get_state(k), o.get_f())
+        print("instance", k, "f", e, flush=True)
+        assert e <= TOL, k
+
+
+def test_reduced_mass_conserved():
+    g = lbe.Solver(COUETTE)
+    vol = oracle.Solver(W.oracle_params(COUETTE)).grid()["vol"]
+    m0 = (vol * g.moments()["n"]).sum()
+    g.step(300)
+    assert abs((vol * g.moments()["n"]).sum() / m0 - 1) < 1e-13

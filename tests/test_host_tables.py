@@ -35,7 +35,8 @@ def test_library_exports_every_declared_symbol():
 BAD = [
     dict(eta0=0.0), dict(eta0=0.5), dict(kn=-1.0), dict(nr=7), dict(q_radial=1), dict(q_t1=65),
     dict(n_expand=(4, 0, 0)), dict(cfl=0.0), dict(t_wall_outer=0.0), dict(r_outer=0.5),
-    dict(geometry=1, u_wall_inner=0.1), dict(geometry=2), dict(eta0=0.01, kn=100.0),  # C < 1
+    dict(geometry=1, u_wall_inner=0.1), dict(geometry=3), dict(geometry=-1),
+    dict(geometry=1, u_wall_inner=0.0, reduced=1), dict(reduced=2), dict(eta0=0.01, kn=100.0),  # C < 1
 ]
 
 
@@ -78,6 +79,16 @@ def test_force_matrices_match_oracle(p):
         Q = p["q_t1"] if axis == 1 else p["q_t2"]
         K = lbe.tables(p, which).reshape(Q, Q)
         assert np.allclose(K, oracle.kmat_full(Q, 2), rtol=1e-12, atol=1e-14 * max(1, np.abs(K).max()))
+
+
+def test_projection_gauss_rule_matches_oracle_rule():
+    """The equilibrium projection's 32-point half-range rule is the half-range quadrature of
+    order 32 (Sec. III), built here by the library's own algorithm: nodes and weights against the
+    oracle's."""
+    t = lbe.tables(workloads.COUETTE_SMALL, 11)
+    x, w = oracle.quad_half(32)
+    assert np.allclose(t[:32], x[:32], rtol=1e-15, atol=1e-15)
+    assert np.allclose(t[32:], w[:32], rtol=1e-13, atol=1e-300)
 
 
 @pytest.mark.parametrize("p", CASES)

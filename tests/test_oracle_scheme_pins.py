@@ -27,6 +27,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 @pytest.fixture(scope="module", autouse=True)
 def _build_oracle():
     oracle.build(force=False)
+    # the problems here are small: one thread avoids the OpenMP start-up cost of every stage
+    n = oracle.get_threads()
+    oracle.set_threads(1)
+    yield
+    oracle.set_threads(n)
 
 
 def equilibrium_state(s, prof):
@@ -232,7 +237,7 @@ J1_MUTANTS = {
     "sphere transverse shear dropped": (1, [
         ("zeta[0] * zeta[0] * dur + (zeta[1] * zeta[1] + zeta[2] * zeta[2]) * m->u[0] / s->r[i]",
          "zeta[0] * zeta[0] * dur")]),
-    "axial shear dropped": (0, [(" + zeta[0] * zeta[2] * du[2 * nr + i]", "")]),
+    "axial shear dropped": (0, [("m->u[0] / s->r[i] + zeta[0] * zeta[2] * du[2 * nr + i]", "m->u[0] / s->r[i]")]),
 }
 
 
