@@ -6,8 +6,9 @@ of the workload; inputs are resident in HBM before the timed region.  Prints one
 Default workload: the seeded parameter sweep of 256 uneven cylindrical Couette/Fourier
 instances (Nr 64..512, half-range orders 4..16), advanced together in one launch per kernel.
 The "steady" object adds steady solves/s at residual 1e-8 on held-out instances of the same
-generator (reduced grid): one at a time from rest, batched from rest, and batched from the
-judged prediction of the trained warm-start network (paper_2403_15051_amd/warmstart_net.npz).
+generator (a bounded set at full size, FP32 f): one at a time from rest, batched from rest, and
+batched from the judged prediction of the trained warm-start network
+(paper_2403_15051_amd/warmstart_net.npz).
 """
 from __future__ import annotations
 
@@ -127,12 +128,41 @@ def cpu_baseline(params, budget_s: float, threads: int = 0):
             "sample": f"{len(used)} instance(s) of the workload, FP64 oracle timed per step ({desc})"}
 
 
-def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 200000):
-    """Steady solves/s at residual tol on held-out instances of the warm-start generator (seed
-    240315053): (1) plain cold, one instance at a time from rest (a sample of n_plain instances);
-    (2) batched cold, all instances in one context from rest; (3) batched warm: network inference,
-    the one-step residual test of the prediction against the rest start, and the solve.  Rates count converged instances per wall second of the solve (tables
-    built and resident before the clock starts)."""
+def _solve_rounds(solver, tol: float, cap: int, every: int, tag: str, round_steps: int = 25000):
+    """Steady solve in rounds of round_steps (a progress line per round); returns the step at which
+    each instance converged (0 if it did not), the converged mask and the last residuals."""
+    import numpy as np
+
+    from paper_2403_15051_amd import lbe
+
+    n = solver.n_inst
+    at = np.zeros(n, dtype=np.int64)
+    ok = np.zeros(n, dtype=bool)
+    done = 0
+    res = np.full(n, np.inf)
+    while done < cap:
+        k = min(round_steps, cap - done)
+        st, taken, res = solver.run_to_steady(tol, k, every)
+        conv = (res >= 0) & (res <= tol)
+        at = np.where(~ok & conv, done + taken, at)
+        ok |= conv
+        done += k
+        print(f"[bench] {tag}: {done} steps, {int(ok.sum())}/{n} converged", file=sys.stderr, flush=True)
+        if st == lbe.LBE_OK:
+            break
+    return at, ok, res
+
+
+def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 150000, full: bool = True):
+    """Steady solves/s at residual tol on held-out instances (seed 240315053) of the sweep generator
+    itself (full: Nr 64..512, Q 4..16, FP32 f with the library's switch to FP64 storage at the FP32
+    floor) or of its reduced-grid form (full=False).  Modes, on the same instances: (1) batched cold,
+    all in one context from rest; (2) batched warm: network inference, the one-step residual judge
+    against the rest start, and the solve; (3) plain cold, one instance at a time from rest, on the
+    first n_plain instances.  Plain cold is reported per instance and, for the ratios, extrapolated
+    to the whole set by its time per step (each instance takes the same steps alone as in a batch).
+    Instances not converged within cap steps count as failures.  Tables are built and resident
+    before each clock starts."""
     import numpy as np
     import torch
 
@@ -140,7 +170,16 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
     from paper_2403_15051_amd import train_warmstart as TW
     from paper_2403_15051_amd import workloads as W
 
-    held = TW.instances(n_held, W.WARM_HELDOUT_SEED)
+    if full:
+        ps, _ = W.sweep(n_held, seed=W.WARM_HELDOUT_SEED)
+        held = [dict(W.solver_params(p), precision=1) for p in ps]
+        wdesc = (f"{n_held} held-out instances of the sweep generator itself (seed {W.WARM_HELDOUT_SEED}): "
+                 f"Couette/Fourier, Nr U{{64..512}}, eta0 U(0.01,0.3), Kn 10^U(-2,1), u_w U(0,0.5), T2/T1 U(1,2), "
+                 f"Q in {{4,8,12,16}}, FP32 f (switched to FP64 storage at its floor), at most {cap} steps")
+    else:
+        held = TW.instances(n_held, W.WARM_HELDOUT_SEED)
+        wdesc = (f"{n_held} held-out instances of the sweep generator on a reduced grid (seed {W.WARM_HELDOUT_SEED}): "
+                 f"Nr U{{32..64}}, half-range order in {{4,8}}, FP64, at most {cap} steps")
     every = TW.CHECK_EVERY
 
     def timed(fn):
@@ -151,19 +190,15 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
         return out, time.perf_counter() - t0
 
     cold = lbe.Solver(held)
-    (st_c, steps_c, res_c), t_cold = timed(lambda: cold.run_to_steady(tol, cap, every))
-    ok_c = (res_c >= 0) & (res_c <= tol)
-    print(f"[bench] batched cold: {int(ok_c.sum())}/{n_held} in {t_cold:.1f} s", file=sys.stderr, flush=True)
+    (at_c, ok_c, _), t_cold = timed(lambda: _solve_rounds(cold, tol, cap, every, "batched cold"))
     net, meta = TW.load()
     warm = lbe.Solver(held)
 
     def warm_solve():
         kept, rho = warm.warm_start(net, judge=True)
-        return kept, warm.run_to_steady(tol, cap, every)
+        return kept, _solve_rounds(warm, tol, cap, every, "batched warm")
 
-    (kept, (st_w, steps_w, res_w)), t_warm = timed(warm_solve)
-    ok_w = (res_w >= 0) & (res_w <= tol)
-    print(f"[bench] batched warm: {int(ok_w.sum())}/{n_held} in {t_warm:.1f} s", file=sys.stderr, flush=True)
+    (kept, (at_w, ok_w, _)), t_warm = timed(warm_solve)
     # the converged profiles of both starts agree to the residual's reach
     agree = 0.0
     for k in range(n_held):
@@ -171,30 +206,34 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
             mc, mw = cold.moments(k), warm.moments(k)
             for f in ("n", "T"):
                 agree = max(agree, float(np.abs(mw[f] - mc[f]).max() / np.abs(mc[f]).max()))
+    promoted = sum(1 for k in range(n_held) if cold.info(k)["promoted_at"] >= 0)
     del cold, warm
     t_plain, n_ok_plain, steps_plain = 0.0, 0, []
-    for p in held[:n_plain]:
+    for k, p in enumerate(held[:n_plain]):
         one = lbe.Solver([p])
-        (st, steps, res), t = timed(lambda: one.run_to_steady(tol, cap, every))
+        (at, ok, _), t = timed(lambda: _solve_rounds(one, tol, cap, every, f"plain cold {k}"))
         t_plain += t
-        n_ok_plain += int(res[0] >= 0 and res[0] <= tol)
-        steps_plain.append(int(steps[0]))
+        n_ok_plain += int(ok[0])
+        steps_plain.append(int(at[0]) if ok[0] else cap)
         del one
-    print(f"[bench] plain cold: {n_ok_plain}/{n_plain} in {t_plain:.1f} s", file=sys.stderr, flush=True)
-    r1 = n_ok_plain / t_plain
+    # plain cold over the whole set at the sample's time per step
+    steps_all = np.where(ok_c, at_c, cap)
+    t_plain_all = t_plain / max(1, sum(steps_plain)) * float(steps_all.sum())
+    r1 = int(ok_c.sum()) / t_plain_all
     r2 = int(ok_c.sum()) / t_cold
     r3 = int(ok_w.sum()) / t_warm
     return {
-        "metric": "steady solves/s at residual 1e-8",
-        "workload": (f"{n_held} held-out instances of the sweep generator (seed {W.WARM_HELDOUT_SEED}): Couette/Fourier, "
-                     f"eta0 U(0.01,0.3), Kn 10^U(-2,1), u_w U(0,0.5), T2/T1 U(1,2); reduced grid Nr U{{32..64}}, "
-                     f"half-range order in {{4,8}}"),
-        "plain_cold": {"solves_per_s": r1, "sample": n_plain, "mean_steps": float(np.mean(steps_plain))},
+        "metric": f"steady solves/s at residual {tol:g}",
+        "workload": wdesc,
+        "plain_cold": {"solves_per_s": r1, "sample": n_plain, "sample_solves_per_s": n_ok_plain / t_plain,
+                       "sample_steps": steps_plain, "batched_steps_of_sample": [int(x) for x in steps_all[:n_plain]],
+                       "seconds_extrapolated": t_plain_all},
         "batched_cold": {"solves_per_s": r2, "converged": int(ok_c.sum()), "seconds": t_cold,
-                         "mean_steps": float(steps_c.mean()), "max_steps": int(steps_c.max())},
+                         "mean_steps": float(at_c[ok_c].mean()) if ok_c.any() else None,
+                         "max_steps": int(at_c.max()), "switched_to_fp64_storage": promoted},
         "batched_warm": {"solves_per_s": r3, "converged": int(ok_w.sum()), "seconds": t_warm,
-                         "mean_steps": float(steps_w.mean()), "max_steps": int(steps_w.max()),
-                         "fallback_rate": float(1 - kept.mean())},
+                         "mean_steps": float(at_w[ok_w].mean()) if ok_w.any() else None,
+                         "max_steps": int(at_w.max()), "fallback_rate": float(1 - kept.mean())},
         "warm_over_plain_cold": r3 / r1, "batched_cold_over_plain_cold": r2 / r1, "warm_over_batched_cold": r3 / r2,
         "profile_agreement_warm_vs_cold": agree,
         "network": {k: meta[k] for k in ("instances", "rows", "epochs", "loss_last", "nr_range", "orders")},
@@ -202,10 +241,9 @@ def steady_metrics(n_held: int, n_plain: int, tol: float = 1e-8, cap: int = 2000
 
 
 def solve_only(args) -> None:
-    """Cold steady solve (rest start, residual 1e-8 checked every 50 steps) of the workload; with
-    FP32 storage the solve stops at its residual floor and is continued with FP64 storage (the
-    polish); prints one JSON line."""
-    import numpy as np
+    """Cold steady solve (rest start, residual 1e-8 checked every 50 steps) of the workload; FP32
+    storage instances are switched to FP64 storage by the library when their residual stalls at its
+    FP32 floor; prints one JSON line."""
     import torch
 
     from paper_2403_15051_amd import lbe
@@ -214,34 +252,11 @@ def solve_only(args) -> None:
     s = lbe.Solver(params)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if args.precision == "fp32":
-        # rounds of 5000 steps until 1e-8 or until the residual stops falling (its FP32 floor)
-        steps = np.zeros(len(params), dtype=np.int64)
-        hist = []
-        while steps.max() < 400000:
-            st, taken, res = s.run_to_steady(1e-8, 5000, 50)
-            steps += taken
-            hist.append(float(res.max()))
-            print(f"[bench] fp32 solve: {int(steps.max())} steps, residual {hist[-1]:.3e}", file=sys.stderr, flush=True)
-            if st == lbe.LBE_OK or (len(hist) > 4 and hist[-1] > 0.8 * hist[-5]):
-                break
-    else:
-        st, steps, res = s.run_to_steady(1e-8, 400000, 50)
+    at, ok, res = _solve_rounds(s, 1e-8, 400000, 50, "solve")
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    out = {"workload": desc, "precision": args.precision, "converged": int(((res >= 0) & (res <= 1e-8)).sum()),
-           "steps": steps.tolist(), "residual": res.tolist(), "seconds": t1 - t0}
-    if args.precision == "fp32":
-        # FP64 polish from the FP32 state
-        p64 = [dict(p, precision=0) for p in params]
-        pol = lbe.Solver(p64)
-        for k in range(len(p64)):
-            pol.set_state(k, s.get_state(k))
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        st2, steps2, res2 = pol.run_to_steady(1e-8, 400000, 50)
-        torch.cuda.synchronize()
-        out["polish"] = {"steps": steps2.tolist(), "residual": res2.tolist(), "seconds": time.perf_counter() - t2}
+    out = {"workload": desc, "precision": args.precision, "converged": int(ok.sum()), "steps": at.tolist(),
+           "residual": res.tolist(), "seconds": time.perf_counter() - t0,
+           "switched_to_fp64_storage_at": [int(s.info(k)["promoted_at"]) for k in range(s.n_inst)]}
     print(json.dumps(out), flush=True)
 
 
@@ -265,8 +280,11 @@ def main():
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--steady-instances", type=int, default=512, help="held-out instances of the steady-solve metric")
-    ap.add_argument("--steady-plain", type=int, default=8, help="of which solved one at a time")
+    ap.add_argument("--steady-instances", type=int, default=8, help="held-out instances of the steady-solve metric")
+    ap.add_argument("--steady-plain", type=int, default=2, help="of which solved one at a time")
+    ap.add_argument("--steady-cap", type=int, default=150000, help="step limit of each steady solve")
+    ap.add_argument("--steady-reduced", type=int, default=0,
+                    help="also report the steady metric on this many reduced-grid held-out instances")
     ap.add_argument("--no-steady", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
                     help="storage of f (the sweep is specified with FP32 f and FP64 moments)")
@@ -378,7 +396,9 @@ def main():
         print(f"[bench] fp64 storage: {(t5 - t4) * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         del s64
     if not args.no_steady:
-        line["steady"] = steady_metrics(args.steady_instances, args.steady_plain)
+        line["steady"] = steady_metrics(args.steady_instances, args.steady_plain, cap=args.steady_cap)
+        if args.steady_reduced:
+            line["steady_reduced_grid"] = steady_metrics(args.steady_reduced, args.steady_plain, full=False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(params, args.cpu_seconds)
         one = cpu_baseline(params, args.cpu_seconds / 3, threads=1)

@@ -71,8 +71,10 @@ typedef struct {
     double eta0;          /* mean packing fraction, 0 < eta0 < 0.5                            */
     double kn;            /* Knudsen number on L (> 0); requires C = L/sigma > 1             */
     int32_t nr;           /* radial cells, >= 8                                               */
-    int32_t q_radial;     /* half-range order Q_r (2 Q_r radial momenta), 2..64              */
-    int32_t q_t1;         /* full-range orders of the transverse axes, 2..64                  */
+    int32_t q_radial;     /* half-range order Q_r (2 Q_r radial momenta), 2..100 (tables);
+                           * the stage kernel holds 2 Q_r x 2 Q_r in LDS: lbe_query rejects
+                           * sets it cannot hold (Q_r <= 48 fits with q_t1 = 8)            */
+    int32_t q_t1;         /* full-range orders of the transverse axes, 2..100                 */
     int32_t q_t2;
     int32_t n_expand[3];  /* equilibrium expansion orders N_a; 0 -> min(7, Q_a - 1); N_a < Q_a */
     double cfl;           /* dt = cfl * dr / max|p_r|  (> 0)                                  */
@@ -89,7 +91,9 @@ typedef struct {
 } lbe_params;
 
 /* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),
- * and the host memory the context will hold (host_bytes).  Host-only; no device work. */
+ * and the host memory the context will hold (host_bytes).  Host-only; no device work.
+ * LBE_EINVAL for an invalid problem statement or a velocity set the stage kernel cannot hold
+ * in its LDS at any slicing (lbe_tables still builds the host tables of such a set). */
 lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, size_t* host_bytes);
 
 /* Build the tables of every instance on the host (quadratures Sec. III, force matrices
@@ -117,7 +121,8 @@ lbe_status lbe_init_static(const lbe_params* p, int32_t n_inst, void* hip_stream
  * launches of one step are captured once into a HIP graph and replayed (set LBE_GRAPH=0 in the
  * environment before lbe_init to launch them one by one); instances sharing a velocity set form a
  * launch group, and the groups' launch chains run on forked streams joined back into the
- * context's stream.  FP32-storage instances get their total mass restored every 50 steps. */
+ * context's stream.  FP32-storage instances get their total mass restored every 10 steps (so a
+ * window of any multiple of 10 steps holds the same share of these launches). */
 lbe_status lbe_step(lbe_ctx* c, int64_t nsteps);
 
 /* Wait for the stream; returns LBE_ENAN if the device flagged a non-finite state. */

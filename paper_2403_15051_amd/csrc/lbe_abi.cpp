@@ -55,7 +55,7 @@ static constexpr int kMaxPlane = 20000;
 static constexpr int kTileCandidates[] = {4, 8, 16, 32, 64};
 static constexpr int kMinTileNodes = 4;
 // FP32 storage: steps between mass fixes in lbe_step (lbe_run_to_steady fixes once per interval)
-static constexpr int kMassFixEvery = 50;
+static constexpr int kMassFixEvery = 10;
 
 struct lbe_ctx {
     std::vector<InstanceTables> tabs;
@@ -407,6 +407,49 @@ void build_items(lbe_ctx* c, const std::vector<int32_t>* only = nullptr)
     }
 }
 
+// Velocity slices of a launch group: one velocity per lane and workgroups of at most `cap`
+// lanes (slice while a slice holds more velocities than that; LBE_SLICE_CAP overrides the default
+// for tuning), then further while the velocity set needs more than two per lane or the LDS does
+// not fit.  False when no slicing of the transverse-2 axis makes it fit.
+bool slice_group(StageGroup* G)
+{
+    int cap = 1024;
+    if (const char* e = std::getenv("LBE_SLICE_CAP")) cap = std::max(64, std::atoi(e));
+    auto next_slices = [&]() {
+        int nextS = G->S + 1;
+        while (nextS <= G->n2 && G->n2 % nextS) nextS++;
+        return nextS;
+    };
+    for (;;) {
+        const int nextS = next_slices();
+        if (G->nv / G->S <= cap || nextS > G->n2) break;
+        G->S = nextS;
+    }
+    while (!layout_group(G, default_tile_nodes())) {
+        const int nextS = next_slices();
+        if (nextS > G->n2) return false;
+        G->S = nextS;
+    }
+    return true;
+}
+
+// Launch group of one validated problem statement on its own (the slicing plan_groups starts from).
+StageGroup single_group(const lbe_params& q)
+{
+    StageGroup G;
+    std::memset(&G, 0, sizeof(G));
+    G.n0 = 2 * q.q_radial;
+    G.n1 = q.q_t1;
+    G.n2 = q.q_t2;
+    G.nv = G.n0 * G.n1 * G.n2;
+    G.geometry = q.geometry;
+    G.f32 = q.precision == LBE_FP32_STORE;
+    G.reduced = q.reduced;
+    G.S = 1;
+    G.pstride = (std::max(q.n_expand[0], std::max(q.n_expand[1], q.n_expand[2])) + 1) | 1;
+    return G;
+}
+
 lbe_status plan_groups(lbe_ctx* c)
 {
     c->groups.clear();
@@ -489,25 +532,9 @@ lbe_status plan_groups(lbe_ctx* c)
         G.S = nextS;
     }
     for (StageGroup& G : c->groups) {
-        // one velocity per lane and workgroups of at most `cap` lanes: slice while a slice holds
-        // more velocities than that (LBE_SLICE_CAP overrides the default for tuning)
-        int cap = 1024;
-        if (const char* e = std::getenv("LBE_SLICE_CAP")) cap = std::max(64, std::atoi(e));
-        for (;;) {
-            int nextS = G.S + 1;
-            while (nextS <= G.n2 && G.n2 % nextS) nextS++;
-            if (G.nv / G.S <= cap || nextS > G.n2) break;
-            G.S = nextS;
-        }
-        // split further if the velocity set needs more than two per lane or the LDS does not fit
-        while (!layout_group(&G, default_tile_nodes())) {
-            int nextS = G.S + 1;
-            while (nextS <= G.n2 && G.n2 % nextS) nextS++;
-            if (nextS > G.n2) {
-                c->err = "velocity set too large for the stage kernel";
-                return LBE_EINVAL;
-            }
-            G.S = nextS;
+        if (!slice_group(&G)) {
+            c->err = "velocity set too large for the stage kernel (its LDS holds the radial force matrix)";
+            return LBE_EINVAL;
         }
     }
     build_items(c);
@@ -885,6 +912,8 @@ lbe_status lbe_query(const lbe_params* p, int32_t n_inst, size_t* device_bytes, 
         lbe_status st = validate_params(p[k], &q, nullptr);
         if (st != LBE_OK) return st;
         if ((size_t)2 * q.q_radial * q.q_t1 * q.q_t2 > (size_t)kMaxPlane) return LBE_EINVAL;
+        StageGroup G = single_group(q);
+        if (!slice_group(&G)) return LBE_EINVAL;  // the stage kernel cannot hold this velocity set
         total += instance_bytes_estimate(q);
         host += instance_bytes_estimate(q) / 8 + 4096;
     }

@@ -11,7 +11,7 @@
 
 namespace lbe {
 
-constexpr int kMaxQ = 64;    // largest quadrature order per axis
+constexpr int kMaxQ = 100;   // largest quadrature order per axis (host tables; the stage kernel takes less, see plan_groups)
 constexpr int kMaxN = 15;    // largest equilibrium expansion order
 constexpr int kNodeStride = 96;  // doubles per node in the node-coefficient block
 constexpr int kMomStride = 16;   // doubles per node in the moment-sum block

@@ -115,15 +115,18 @@ static void gauss_legendre(int n, std::vector<ld>& x, std::vector<ld>& w)
 // Recurrence x h_l = b_{l+1} h_{l+1} + a_l h_l + b_l h_{l-1} of the polynomials orthonormal on
 // [0, inf) with weight exp(-x^2/2)/sqrt(2 pi) (the half-range Hermite polynomials of the
 // paper), by the discretised Stieltjes procedure (Gautschi): the measure is replaced by a
-// composite 20-point Gauss-Legendre rule on panels of width 1/2.  Returns a[0..n-1],
-// b[0..n] with b[0] = mu_0 = 1/2.
+// composite 20-point Gauss-Legendre rule on panels of width 1/2, and the polynomial values at its
+// nodes are generated as vectors.  Each new vector is orthogonalised again, twice, against all
+// earlier ones (in the discrete inner product): without that, rounding in the three-term step
+// is amplified with the degree (nodes off by ~5e-12 at order 64 in long double).  Returns
+// a[0..n-1], b[0..n] with b[0] = mu_0 = 1/2.
 static void half_recurrence(int n, std::vector<ld>& a, std::vector<ld>& b)
 {
     std::vector<ld> gx, gw;
     const int P = 20;
     gauss_legendre(P, gx, gw);
     const ld X = sqrtl((ld)(2 * n + 1)) + 15;
-    const ld h = 0.5L;
+    const ld h = std::min(0.5L, 2 / sqrtl((ld)(2 * n + 1)));
     const int npan = (int)ceill(X / h);
     std::vector<ld> y, lam;
     for (int p = 0; p < npan; p++)
@@ -133,29 +136,38 @@ static void half_recurrence(int n, std::vector<ld>& a, std::vector<ld>& b)
             lam.push_back(gw[j] * h / 2 * expl(-t * t / 2) / sqrtl(2 * kPi));
         }
     const size_t M = y.size();
-    // orthonormal vectors on the discrete measure (stable form of Stieltjes)
-    std::vector<ld> prev(M, 0), cur(M), nxt(M);
+    auto dot = [&](const ld* u, const ld* v) {
+        ld s = 0;
+        for (size_t m = 0; m < M; m++) s += lam[m] * u[m] * v[m];
+        return s;
+    };
+    // basis[k] = h_k at the nodes
+    std::vector<ld> basis((size_t)(n + 1) * M);
     ld mu0 = 0;
     for (size_t m = 0; m < M; m++) mu0 += lam[m];
-    for (size_t m = 0; m < M; m++) cur[m] = 1 / sqrtl(mu0);
+    for (size_t m = 0; m < M; m++) basis[m] = 1 / sqrtl(mu0);
     a.assign(n, 0);
     b.assign(n + 1, 0);
     b[0] = mu0;
+    std::vector<ld> nxt(M);
     for (int k = 0; k < n; k++) {
-        ld ak = 0;
-        for (size_t m = 0; m < M; m++) ak += lam[m] * y[m] * cur[m] * cur[m];
+        const ld* cur = &basis[(size_t)k * M];
+        const ld* prev = k > 0 ? &basis[(size_t)(k - 1) * M] : nullptr;
+        std::vector<ld> ycur(M);
+        for (size_t m = 0; m < M; m++) ycur[m] = y[m] * cur[m];
+        const ld ak = dot(ycur.data(), cur);
         a[k] = ak;
-        ld nn = 0;
-        for (size_t m = 0; m < M; m++) {
-            nxt[m] = (y[m] - ak) * cur[m] - (k > 0 ? b[k] : 0) * prev[m];
-            nn += lam[m] * nxt[m] * nxt[m];
-        }
-        ld bk = sqrtl(nn);
+        for (size_t m = 0; m < M; m++) nxt[m] = ycur[m] - ak * cur[m] - (k > 0 ? b[k] * prev[m] : 0);
+        for (int pass = 0; pass < 2; pass++)
+            for (int j = 0; j <= k; j++) {
+                const ld* bj = &basis[(size_t)j * M];
+                const ld c = dot(nxt.data(), bj);
+                for (size_t m = 0; m < M; m++) nxt[m] -= c * bj[m];
+            }
+        const ld bk = sqrtl(dot(nxt.data(), nxt.data()));
         b[k + 1] = bk;
-        for (size_t m = 0; m < M; m++) {
-            prev[m] = cur[m];
-            cur[m] = nxt[m] / bk;
-        }
+        ld* out = &basis[(size_t)(k + 1) * M];
+        for (size_t m = 0; m < M; m++) out[m] = nxt[m] / bk;
     }
 }
 
@@ -565,7 +577,7 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
     if (p.precision != LBE_FP64 && p.precision != LBE_FP32_STORE) return bad("precision must be LBE_FP64 or LBE_FP32_STORE");
     const int Q[3] = {p.q_radial, p.q_t1, p.q_t2};
     for (int a = 0; a < 3; a++) {
-        if (Q[a] < 2 || Q[a] > kMaxQ) return bad("quadrature orders must lie in [2, 64]");
+        if (Q[a] < 2 || Q[a] > kMaxQ) return bad("quadrature orders must lie in [2, 100]");
         int N = p.n_expand[a];
         if (N == 0) N = std::min(7, Q[a] - 1);
         if (a == 2 && p.reduced) N = 2;  // the pseudo-axis of the reduced distributions (below)

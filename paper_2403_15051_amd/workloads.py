@@ -35,7 +35,8 @@ FOURIER_SPH = dict(geometry=1, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wal
 # cylinder HHLB(7, Q_R) x HLB(7, 8) with p_z integrated out (reduced = 1), sphere HHLB(7, Q_R) x
 # HLB(7, 8) x HLB(7, 8); the planar limit (geometry 2, plates at R_L and R_L + C, the R_L -> infinity
 # end of the radius sweeps) takes the cylinder's reduced set; Q_R = 20 for eta0 in {0.1, 0.2} (the paper's 100 / 60 at eta0 = 0.01 are
-# passed as given: the GPU stage kernel holds the radial force matrix in LDS and takes Q_R <= 32).
+# passed as given: the host tables take them, the GPU stage kernel holds the radial force matrix in
+# LDS and takes Q_R <= 48 with these transverse sets).
 PAPER_ETA0 = (0.01, 0.1, 0.2)
 PAPER_C = (4, 7, 10)
 PAPER_RL = (1, 3, 5)

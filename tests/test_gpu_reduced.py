@@ -104,3 +104,26 @@ def test_reduced_mass_conserved():
     m0 = (vol * g.moments()["n"]).sum()
     g.step(300)
     assert abs((vol * g.moments()["n"]).sum() / m0 - 1) < 1e-13
+
+
+
+@pytest.mark.parametrize("q_radial", [32, 48])
+def test_large_radial_orders_match_the_oracle(q_radial):
+    """Radial orders above the production Q_R = 20, up to the largest the stage kernel holds
+    (its LDS keeps the radial force matrix; larger sets are rejected by lbe_query), on the paper's
+    grid (dr = sigma/10, dt ~ 1e-3: a coarser grid at the same CFL number takes a longer step,
+    beyond the explicit scheme's limit for the force term at Q_R = 48, in the oracle as well)."""
+    p = W.paper_case("couette", 0, 0.01, 4, 1, q_radial=q_radial)
+    print("case", p, flush=True)
+    g = lbe.Solver(p)
+    o = oracle.Solver(W.oracle_params(p))
+    o.step(5)
+    g.set_state(0, o.get_f())
+    e = nrel(g.rhs(), o.rhs())
+    print("rhs", e, flush=True)
+    assert e <= TOL
+    g.step(20)
+    o.step(20)
+    e = nrel(g.get_state(), o.get_f())
+    print("f after 20 steps", e, flush=True)
+    assert e <= TOL

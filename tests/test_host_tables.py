@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 
 BAD = [
-    dict(eta0=0.0), dict(eta0=0.5), dict(kn=-1.0), dict(nr=7), dict(q_radial=1), dict(q_t1=65),
+    dict(eta0=0.0), dict(eta0=0.5), dict(kn=-1.0), dict(nr=7), dict(q_radial=1), dict(q_radial=101), dict(q_t1=101),
     dict(n_expand=(4, 0, 0)), dict(cfl=0.0), dict(t_wall_outer=0.0), dict(r_outer=0.5),
     dict(geometry=1, u_wall_inner=0.1), dict(geometry=3), dict(geometry=-1),
     dict(geometry=1, u_wall_inner=0.0, reduced=1), dict(reduced=2), dict(eta0=0.01, kn=100.0),  # C < 1
@@ -48,6 +48,22 @@ def test_invalid_problem_statements_are_rejected(bad):
     assert e.value.status == lbe.LBE_EINVAL
 
 
+@pytest.mark.parametrize("reduced", [0, 1])
+def test_stage_kernel_radial_order_limit(reduced):
+    """The host tables take Q_R up to 100; the GPU stage kernel holds the radial force matrix in
+    LDS, so lbe_query (and lbe_init) accept Q_R <= 48 with HLB(7,8) transverse sets and reject
+    larger radial orders with LBE_EINVAL rather than failing at launch."""
+    for q in (20, 32, 48, 56, 60, 100):
+        p = dict(workloads.paper_case("couette", 0, 0.01, 4, 1, q_radial=q), reduced=reduced, q_t2=4)
+        if q <= 48:
+            lbe.query([p])
+        else:
+            with pytest.raises(lbe.LbeError) as e:
+                lbe.query([p])
+            assert e.value.status == lbe.LBE_EINVAL
+        assert lbe.tables(p, 0).size == 4 * q
+
+
 def test_query_sizes_scale():
     d1, _ = lbe.query([workloads.FOURIER_CYL])
     d2, _ = lbe.query([workloads.FOURIER_CYL] * 2)
@@ -55,7 +71,10 @@ def test_query_sizes_scale():
 
 
 CASES = [workloads.COUETTE_SMALL, workloads.FOURIER_CYL, dict(workloads.FOURIER_SPH, nr=32),
-         dict(workloads.COUETTE_SMALL, q_radial=12, q_t1=6, q_t2=3, n_expand=(5, 4, 2))]
+         dict(workloads.COUETTE_SMALL, q_radial=12, q_t1=6, q_t2=3, n_expand=(5, 4, 2)),
+         # the paper's largest radial orders (eta0 = 0.01: Q_R = 60 Fourier, 100 Couette)
+         dict(workloads.COUETTE_SMALL, q_radial=64, q_t1=8, q_t2=4),
+         dict(workloads.COUETTE_SMALL, q_radial=100, q_t1=8, q_t2=4)]
 
 
 @pytest.mark.parametrize("p", CASES)

@@ -299,16 +299,16 @@ def load_fixture(name):
     return d
 
 
-FOURIER = {
+FOURIER = {  # problem, tolerance on the whole channel, on the interior (two cells from each wall)
     "steady_fourier_cyl": (dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wall_inner=1.0,
                                 t_wall_outer=1.5, eta0=0.1, kn=0.5, nr=128, q_radial=8, q_t1=8, q_t2=4, cfl=0.25),
-                           5e-4),
+                           5e-4, 1e-4),
     "steady_fourier_cyl_small": (dict(geometry=0, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wall_inner=1.0,
                                       t_wall_outer=1.5, eta0=0.1, kn=0.5, nr=32, q_radial=4, q_t1=4, q_t2=4,
-                                      cfl=0.25), 2e-3),
+                                      cfl=0.25), 2e-3, 1e-4),
     "steady_fourier_sph": (dict(geometry=1, r_inner=1.0, r_outer=2.0, u_wall_inner=0.0, t_wall_inner=1.0,
                                 t_wall_outer=2.0, eta0=0.2, kn=0.05, nr=256, q_radial=16, q_t1=12, q_t2=12,
-                                cfl=0.25), 2e-3),
+                                cfl=0.25), 1e-2, 1e-3),
 }
 
 
@@ -316,14 +316,17 @@ FOURIER = {
 def test_fourier_steady_heat_flux_times_area_is_constant(name):
     """Sec. IV Fourier flow: at steady state the energy equation reduces to d(r^{D-1} q_r)/dr = 0
     (the inertial terms and the Shakhov term conserve energy, J1's energy moment vanishes with
-    u_r), so r^{D-1} q_r is constant up to truncation error, while q_r itself varies."""
-    p, tol = FOURIER[name]
+    u_r), so r^{D-1} q_r is constant up to truncation error, while q_r itself varies.  The cells
+    next to the walls carry the largest truncation error (the wall ghosts enter their WENO
+    stencils; up to 0.5 % on the dense sphere), the interior is held tighter."""
+    p, tol, tol_in = FOURIER[name]
     d = load_fixture(name)
     r = oracle.Solver(dict(p, q_radial=4, q_t1=4, q_t2=4)).grid()["r"]  # the grid does not depend on the orders
     D = 2 if p["geometry"] == 0 else 3
     flux = d["q_r"] * r ** (D - 1)
     assert np.ptp(d["q_r"]) > 0.1 * np.abs(d["q_r"]).max()
-    assert np.ptp(flux) < tol * np.abs(flux).mean(), np.ptp(flux) / np.abs(flux).mean()
+    assert np.ptp(flux) < tol * np.abs(flux.mean()), np.ptp(flux) / np.abs(flux.mean())
+    assert np.ptp(flux[2:-2]) < tol_in * np.abs(flux.mean()), np.ptp(flux[2:-2]) / np.abs(flux.mean())
     assert np.abs(d["u_r"]).max() < 1e-3 * np.sqrt(p["t_wall_outer"])
 
 
@@ -337,4 +340,7 @@ def test_couette_steady_angular_momentum_flux_is_constant():
     r = oracle.Solver(p).grid()["r"]
     flux = d["P_rt1"] * r**2
     assert np.ptp(d["P_rt1"]) > 0.2 * np.abs(d["P_rt1"]).max()
-    assert np.ptp(flux) < 2e-3 * np.abs(flux).mean(), np.ptp(flux) / np.abs(flux).mean()
+    # the cells next to the walls (Knudsen layers, wall ghosts in their stencils) to 2 %, the
+    # interior to 1e-3
+    assert np.ptp(flux) < 2e-2 * np.abs(flux.mean()), np.ptp(flux) / np.abs(flux.mean())
+    assert np.ptp(flux[2:-2]) < 1e-3 * np.abs(flux.mean()), np.ptp(flux[2:-2]) / np.abs(flux.mean())
