@@ -26,6 +26,7 @@ namespace lbe {
 constexpr int kBlock = 256;
 constexpr int kNodeChunk = 32;  // nodes per node-kernel workgroup
 constexpr int kHalo = 4;        // gradient stencils reach 4 nodes (one-sided at the walls)
+constexpr int kWallBatch = 4;   // velocities per thread and round trip in the node kernel's wall blocks
 constexpr int kMaxNr = 1024;    // largest radial grid (node-kernel LDS)
 
 // ------------------------------------------------------------------ helpers
@@ -300,21 +301,38 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 
     if (bx >= nchunks) {
         // Wall density of diffuse reflection: n_w = - sum_{leaving} p_r f_hat / sum_{entering} p_r g_w.
+        // Each thread takes kWallBatch velocities at a time and issues all their loads before the
+        // arithmetic (one dependent round trip per batch instead of per velocity); the leaving
+        // velocities of the left wall are those with radial index i0 >= n0/2 (p_r < 0), of the right
+        // wall those with i0 < n0/2, so only that half is visited.
         const int left = bx == nchunks;
+        const int hq = n0 >> 1, nhalf = I.nv >> 1;
         double acc[1] = {0};
-        for (int v = threadIdx.x; v < I.nv; v += kBlock) {
-            const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
-            auto F = [&](int row) { return f_at3(I, src, bsrc, row, v, i0, i1, i2); };
-            const double pr = I.p0[i0];
-            if (I.reduced && i2 == 1) continue;  // chi carries no mass
-            if (left && pr < 0) {
-                const double f0 = F(0), f1 = F(1), f2 = F(2);
-                const double gm1 = 3 * f0 - 3 * f1 + f2, gm2 = 6 * f0 - 8 * f1 + 3 * f2;
-                acc[0] += pr * weno5(f2, f1, f0, gm1, gm2);
-            } else if (!left && pr > 0) {
-                const double a = F(nr - 1), b = F(nr - 2), c = F(nr - 3);
-                const double gp1 = 3 * a - 3 * b + c, gp2 = 6 * a - 8 * b + 3 * c;
-                acc[0] += pr * weno5(c, b, a, gp1, gp2);
+        for (int e0 = threadIdx.x; e0 < nhalf; e0 += kBlock * kWallBatch) {
+            double fa[kWallBatch], fb[kWallBatch], fc[kWallBatch], pr[kWallBatch];
+            bool use[kWallBatch];
+#pragma unroll
+            for (int u = 0; u < kWallBatch; u++) {
+                const int e = e0 + u * kBlock;
+                const int i0 = (left ? hq : 0) + e % hq, col = e / hq;
+                const int i1 = col % n1, i2 = col / n1, v = i0 + n0 * col;
+                // chi (the reduced distributions' second plane) carries no mass
+                use[u] = e < nhalf && !(I.reduced && i2 == 1);
+                pr[u] = I.p0[i0];
+                fa[u] = fb[u] = fc[u] = 0.0;
+                if (use[u]) {
+                    const int r0 = left ? 0 : nr - 1, dr1 = left ? 1 : -1;
+                    fa[u] = f_at3(I, src, bsrc, r0, v, i0, i1, i2);
+                    fb[u] = f_at3(I, src, bsrc, r0 + dr1, v, i0, i1, i2);
+                    fc[u] = f_at3(I, src, bsrc, r0 + 2 * dr1, v, i0, i1, i2);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kWallBatch; u++) {
+                if (!use[u]) continue;
+                // wall cell a, then b, c inwards; the two ghost values by quadratic extrapolation
+                const double g1 = 3 * fa[u] - 3 * fb[u] + fc[u], g2 = 6 * fa[u] - 8 * fb[u] + 3 * fc[u];
+                acc[0] += pr[u] * weno5(fc[u], fb[u], fa[u], g1, g2);
             }
         }
         block_sum<1>(acc, red);
@@ -323,32 +341,32 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // ghost cells of this wall (cells -1, -2, or nr, nr + 1, stored in the two rows the
         // state buffers hold on each side): n_w g_w for entering velocities, the quadratic
         // extrapolation of the three nearest cells for leaving ones
-        for (int v = threadIdx.x; v < I.nv; v += kBlock) {
-            const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
-            auto F = [&](int row) { return f_at3(I, src, bsrc, row, v, i0, i1, i2); };
-            const double pr = I.p0[i0];
-            if (left) {
-                double g1, g2;
-                if (pr > 0) {
-                    g1 = g2 = nw * I.gwl[v];
+        for (int v0 = threadIdx.x; v0 < I.nv; v0 += kBlock * kWallBatch) {
+            double g1[kWallBatch], g2[kWallBatch];
+#pragma unroll
+            for (int u = 0; u < kWallBatch; u++) {
+                const int v = v0 + u * kBlock;
+                if (v >= I.nv) continue;
+                const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+                const bool entering = left ? i0 < hq : i0 >= hq;
+                if (entering) {
+                    g1[u] = g2[u] = nw * (left ? I.gwl[v] : I.gwr[v]);
                 } else {
-                    const double f0 = F(0), f1 = F(1), f2 = F(2);
-                    g1 = 3 * f0 - 3 * f1 + f2;
-                    g2 = 6 * f0 - 8 * f1 + 3 * f2;
+                    const int r0 = left ? 0 : nr - 1, dr1 = left ? 1 : -1;
+                    const double a = f_at3(I, src, bsrc, r0, v, i0, i1, i2);
+                    const double b = f_at3(I, src, bsrc, r0 + dr1, v, i0, i1, i2);
+                    const double c = f_at3(I, src, bsrc, r0 + 2 * dr1, v, i0, i1, i2);
+                    g1[u] = 3 * a - 3 * b + c;
+                    g2[u] = 6 * a - 8 * b + 3 * c;
                 }
-                f_put3(I, src, bsrc, -1, v, i0, i1, i2, g1);
-                f_put3(I, src, bsrc, -2, v, i0, i1, i2, g2);
-            } else {
-                double g1, g2;
-                if (pr < 0) {
-                    g1 = g2 = nw * I.gwr[v];
-                } else {
-                    const double a = F(nr - 1), b = F(nr - 2), c = F(nr - 3);
-                    g1 = 3 * a - 3 * b + c;
-                    g2 = 6 * a - 8 * b + 3 * c;
-                }
-                f_put3(I, src, bsrc, nr, v, i0, i1, i2, g1);
-                f_put3(I, src, bsrc, nr + 1, v, i0, i1, i2, g2);
+            }
+#pragma unroll
+            for (int u = 0; u < kWallBatch; u++) {
+                const int v = v0 + u * kBlock;
+                if (v >= I.nv) continue;
+                const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+                f_put3(I, src, bsrc, left ? -1 : nr, v, i0, i1, i2, g1[u]);
+                f_put3(I, src, bsrc, left ? -2 : nr + 1, v, i0, i1, i2, g2[u]);
             }
         }
         return;
@@ -363,9 +381,11 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __shared__ Macro smac[kNodeChunk];
     __shared__ double sdens[kMaxNr];
     __shared__ double snb[kNodeChunk + 2 * kHalo];
-    // densities of every node (slice sums), then the averaged density of the chunk + halo,
-    // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row, loads batched by 8
-    for (int j = threadIdx.x; j < nr; j += kBlock) {
+    // densities (slice sums) of the nodes the band of W reaches from the chunk + halo (wlo is
+    // nondecreasing), then the averaged density of the chunk + halo, eq. (fm): nbar_j = sum_k W_jk
+    // n_k over the band, 8 lanes per row, loads batched by 8
+    const int jlo = I.wlo[h0], jhi = min(nr, I.wlo[h1 - 1] + I.wband);
+    for (int j = jlo + (int)threadIdx.x; j < jhi; j += kBlock) {
         const double* b = I.mom + (size_t)j * I.nslices * kMomStride;
         double n = b[MF_S0];
         for (int sl = 1; sl < I.nslices; sl++) n += b[sl * kMomStride + MF_S0];

@@ -97,3 +97,30 @@ def test_paper_grid_batches_advance_and_conserve_mass():
         m = g.moments(k)
         assert np.isfinite(m["n"]).all() and (m["n"] > 0).all()
         assert abs(mass(g, k, cases[k]["geometry"]) / m0[k] - 1) < 1e-12, (k, cases[k])
+
+
+def test_larger_radial_orders_do_not_change_the_steady_profiles():
+    """Sec. IV: the paper checks that larger quadrature orders do not change its results.  The
+    Couette flow at eta0 = 0.1, C = 4, R_L = 1 solved to 1e-9 with Q_R = 20 (the paper's order),
+    32 and 48 (the largest the stage kernel holds): n, u_phi and T agree to a small fraction of
+    their variation across the channel."""
+    cases = [W.paper_case("couette", 0, 0.1, 4, 1, q_radial=q) for q in (20, 32, 48)]
+    g = lbe.Solver(cases)
+    for chunk in range(40):
+        st, steps, res = g.run_to_steady(1e-9, 25000, 100)
+        print(f"Q_R 20/32/48: chunk {chunk}, residuals {res}", flush=True)
+        if st == lbe.LBE_OK:
+            break
+    assert st == lbe.LBE_OK
+    m = [g.moments(k) for k in range(3)]
+    for f in ("n", "u_t1", "T"):
+        # against the field's size (the wall speed for u_phi) and against its variation across the
+        # channel: the differences shrink as Q_R grows and stay well inside the profiles' features
+        size = 1.0 if f == "u_t1" else np.abs(m[2][f]).max()
+        var = np.ptp(m[2][f])
+        d20 = np.abs(m[0][f] - m[2][f]).max()
+        d32 = np.abs(m[1][f] - m[2][f]).max()
+        print(f, "Q_R 20 vs 48:", d20 / size, "of the size,", d20 / var, "of the variation; 32 vs 48:", d32 / size,
+              d32 / var, flush=True)
+        assert d20 < 1e-2 * size and d20 < 5e-2 * var
+        assert d32 < 0.5 * d20
