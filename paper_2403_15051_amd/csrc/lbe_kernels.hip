@@ -190,12 +190,34 @@ __device__ inline const double* base_row(const DevInstance& I, int tab, int row)
     return I.base[tab] + (size_t)rb * (I.n0 + I.n1 + I.n2);
 }
 
+// Position of velocity v = i0 + n0 c (c the transverse column) in a row of an FP32 state buffer.
+// The stage kernel's waves hold one sign of p_r each, so a wave reads, per column, the half of it
+// with its sign: n0/2 values, 64 bytes at Q = 16.  FP32 rows therefore keep the columns in groups
+// of g, with the p_r > 0 halves of the group's columns first and then its p_r < 0 halves, g the
+// smallest power of two (dividing the column count) for which a group's halves of one sign span
+// 128 bytes: a wave reading consecutive columns reads whole lines.  FP64 rows keep the plain
+// order v (g = 1 is the plain order).
+__device__ inline int f32_group(int hq, int ncols)
+{
+    int g = 1;
+    while (g * hq < 32 && ncols % (2 * g) == 0) g *= 2;
+    return g;
+}
+
+__device__ inline int f32_slot(int v, int n0, int ncols)
+{
+    const int hq = n0 >> 1, g = f32_group(hq, ncols);
+    const int i0 = v % n0, c = v / n0;
+    const int h = i0 % hq, sgn = i0 / hq;
+    return h + hq * (c % g) + g * hq * sgn + g * n0 * (c / g);
+}
+
 // f of buffer `buf` at row `row` (-2 .. nr + 1) and velocity v; FP32 storage reconstructs the
 // deviation on top of base table `tab`: f = dev + B0[i0] (B1[i1] B2[i2]).
 __device__ inline double f_at(const DevInstance& I, int buf, int tab, int row, int v)
 {
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
-    if (!I.f32) return I.f[buf][e];
+    if (!I.f32) return I.f[buf][(ptrdiff_t)row * I.nv + v];
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
     const double* b = base_row(I, tab, row);
     const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
     return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
@@ -204,8 +226,8 @@ __device__ inline double f_at(const DevInstance& I, int buf, int tab, int row, i
 // The same with the velocity's axis indices already known.
 __device__ inline double f_at3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2)
 {
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
-    if (!I.f32) return I.f[buf][e];
+    if (!I.f32) return I.f[buf][(ptrdiff_t)row * I.nv + v];
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
     const double* b = base_row(I, tab, row);
     return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
 }
@@ -213,22 +235,22 @@ __device__ inline double f_at3(const DevInstance& I, int buf, int tab, int row, 
 __device__ inline void f_put3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2,
                               double val)
 {
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
     if (!I.f32) {
-        I.f[buf][e] = val;
+        I.f[buf][(ptrdiff_t)row * I.nv + v] = val;
         return;
     }
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
     const double* b = base_row(I, tab, row);
     ((float*)I.f[buf])[e] = (float)(val - b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]));
 }
 
 __device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, int v, double val)
 {
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + v;
     if (!I.f32) {
-        I.f[buf][e] = val;
+        I.f[buf][(ptrdiff_t)row * I.nv + v] = val;
         return;
     }
+    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
     const double* b = base_row(I, tab, row);
     const int i0 = v % I.n0, rest = v / I.n0, i1 = rest % I.n1, i2 = rest / I.n1;
     ((float*)I.f[buf])[e] = (float)(val - b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]));
@@ -1143,7 +1165,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
 
     // ---- per-lane velocities
     const int nh = hq * ncol;
-    unsigned voff[VPT];
+    unsigned voff[VPT], vcan[VPT];
     int ibx[VPT], gx0[VPT], gx1[VPT], gx2[VPT], bcol[VPT];
     bool valid[VPT];
     double prv[VPT], y0[VPT], y1[VPT], y2[VPT], yy[VPT];
@@ -1155,7 +1177,10 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         const int i0h = e % hq, col = e / hq;
         const int i0 = pos ? i0h : hq + i0h;
         const int cg = c_s0 + col, i1 = cg % n1, i2 = cg / n1;
-        voff[j] = (unsigned)(i0 + n0 * cg) * (unsigned)esz;
+        // FP32 rows keep the columns in pairs (f32_slot); the right-hand side output is FP64 in the
+        // plain order (vcan)
+        voff[j] = (unsigned)(F32 ? f32_slot(i0 + n0 * cg, n0, n1 * n2) : i0 + n0 * cg) * (unsigned)esz;
+        vcan[j] = (unsigned)(i0 + n0 * cg) * 8u;
         bcol[j] = n0 + (cg - cp0);
         ibx[j] = i0 + cs * col;
         gx0[j] = i0;
@@ -1217,7 +1242,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         double* pl = plane + buf * G.plane_sz;
         for (int v = tid; v < nv; v += B)
             if (v < vs0 || v >= vs1) {
-                double x = cell(it.i0 + t, (unsigned)(esz * v));
+                double x = cell(it.i0 + t, (unsigned)(esz * (F32 ? f32_slot(v, n0, n1 * n2) : v)));
                 if constexpr (F32) {
                     const int wr = t + 3;  // cell i0 + t
                     x += sbase[wr * bst + v % n0] * sbase[wr * bst + n0 + v / n0];  // sphere: cp0 = 0
@@ -1504,7 +1529,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 if (valid[j]) {
                     if constexpr (F32) {
                         if (rhs) {
-                            bstore(ro, voff[j] * 2u, i * nv * 8, o);
+                            bstore(ro, vcan[j], i * nv * 8, o);
                         } else {
                             const double dev = o - (nnode * g0) * (g1 * g2);
                             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)dev), ro, voff[j],
