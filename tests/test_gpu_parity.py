@@ -200,10 +200,17 @@ def kn_for_confinement(eta0: float, C: float) -> float:
     # cold walls: the projection rule's panels shrink with the colder wall's temperature
     ("cold walls", dict(workloads.FOURIER_CYL, nr=24, q_radial=6, q_t1=6, q_t2=4, t_wall_inner=0.1,
                         t_wall_outer=0.3, kn=0.2), 20),
+    # the largest grid with the largest radial order the stage kernel holds, p_z integrated out
+    ("max size, reduced", dict(workloads.paper_case("couette", 0, 0.1, 4, 1, q_radial=48), nr=1024,
+                               cfl=0.04), 2),
+    # the smallest grid between plates, the three-axis set with a wall velocity
+    ("plates, Nr 8", dict(workloads.COUETTE_SMALL, geometry=2, nr=8, q_t2=4), 20),
+    # plates with p_z integrated out, Knudsen number 10 (nearly free-molecular)
+    ("plates, reduced, Kn 10", dict(workloads.paper_case("fourier", 2, 0.01, 4, 1, q_radial=20), kn=10.0), 20),
 ])
 def test_edge_cases_match_oracle(name, p, steps):
     print("case", name, flush=True)
-    o = oracle.Solver(p)
+    o = oracle.Solver(workloads.oracle_params(p))
     g = lbe.Solver(p)
     o.step(steps)
     g.step(steps)
