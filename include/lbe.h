@@ -73,7 +73,8 @@ typedef struct {
     int32_t nr;           /* radial cells, >= 8                                               */
     int32_t q_radial;     /* half-range order Q_r (2 Q_r radial momenta), 2..100 (tables);
                            * the stage kernel holds 2 Q_r x 2 Q_r in LDS: lbe_query rejects
-                           * sets it cannot hold (Q_r <= 48 fits with q_t1 = 8)            */
+                           * sets it cannot hold (with 8-point transverse orders: Q_r <= 48
+                           * for reduced cylinders and plates, Q_r <= 30 for spheres)      */
     int32_t q_t1;         /* full-range orders of the transverse axes, 2..100                 */
     int32_t q_t2;
     int32_t n_expand[3];  /* equilibrium expansion orders N_a; 0 -> min(7, Q_a - 1); N_a < Q_a */
