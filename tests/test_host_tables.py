@@ -64,6 +64,18 @@ def test_stage_kernel_radial_order_limit(reduced):
         assert lbe.tables(p, 0).size == 4 * q
 
 
+def test_stage_kernel_radial_order_limit_on_spheres():
+    """Spheres keep both transverse axes (HLB(7,8) x HLB(7,8)): the stage kernel holds Q_R <= 30."""
+    for q, ok in ((20, True), (30, True), (32, False), (48, False)):
+        p = workloads.paper_case("fourier", 1, 0.1, 4, 1, q_radial=q)
+        if ok:
+            lbe.query([p])
+        else:
+            with pytest.raises(lbe.LbeError) as e:
+                lbe.query([p])
+            assert e.value.status == lbe.LBE_EINVAL
+
+
 def test_query_sizes_scale():
     d1, _ = lbe.query([workloads.FOURIER_CYL])
     d2, _ = lbe.query([workloads.FOURIER_CYL] * 2)
