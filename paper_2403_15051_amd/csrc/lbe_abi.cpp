@@ -531,7 +531,10 @@ lbe_status plan_groups(lbe_ctx* c)
         while (G.n2 % nextS) nextS++;
         G.S = nextS;
     }
+    int xcdmap = 1;
+    if (const char* e = std::getenv("LBE_XCD_MAP")) xcdmap = std::atoi(e) != 0;
     for (StageGroup& G : c->groups) {
+        G.xcdmap = xcdmap;
         if (!slice_group(&G)) {
             c->err = "velocity set too large for the stage kernel (its LDS holds the radial force matrix)";
             return LBE_EINVAL;

@@ -137,6 +137,8 @@ struct StageGroup {
     int32_t pstride;   // and weights of every factor (even); off_poly is the term buffers when they
     int32_t off_poly;  // have room (they are written before they are read), else a region of its own
     int32_t ntiles;    // MFMA tiles per node (moment, d0, d1, d2 tiles)
+    int32_t xcdmap;    // 1: workgroup b runs work item xcd_item(b), so each XCD takes a contiguous
+                       // run of the item list (LBE_XCD_MAP=0 in the environment: item b)
     int32_t off_sb, off_fb, bstride;  // f32: base factors of the window rows / own rows (stride bstride)
 };
 

@@ -306,17 +306,31 @@ __global__ void __launch_bounds__(kBlock) k_moments(const DevInstance* __restric
         I.mom[(size_t)i * I.nslices * kMomStride + k] = (k < 13) ? red[k * 4] : 0.0;
 }
 
+// Workgroups are handed to the eight XCDs in turn (workgroup b to XCD b mod 8), each XCD with its
+// own L2.  Work item of workgroup b when every XCD is to take a contiguous run of the item list:
+// XCD x takes items [x q + min(x, r), ...) with q = n / 8, r = n mod 8, so consecutive items (the tiles of an
+// instance, which share halo rows and the slice's table image; the node chunks of an instance,
+// which read overlapping moment rows) meet in one L2.  A bijection on
+// [0, n) whatever the dispatch order; only the L2 sharing depends on it.
+__device__ inline int xcd_item(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+    return x * q + min(x, r) + j;
+}
+
 // ------------------------------------------------------------------ node kernel
 
 // ilist (may be null): the instances of grid row y are ilist[y] (one launch group's instances).
 __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist,
                                                  int src, int bsrc)
 {
-    const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
+    // (chunk, instance) of this workgroup: the grid's blocks in XCD-contiguous order (xcd_item)
+    const int lin = xcd_item(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+    const int bx = lin % gridDim.x, by = lin / gridDim.x;
+    const DevInstance& I = insts[ilist ? ilist[by] : by];
     if (!I.flags[1]) return;
     const int nr = I.nr;
     const int nchunks = (nr + kNodeChunk - 1) / kNodeChunk;
-    const int bx = blockIdx.x;
     __shared__ double red[16 * 4];
     if (bx >= nchunks + 2) return;
     const int n0 = I.n0, n1 = I.n1;
@@ -981,7 +995,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
 {
     constexpr int rhs = RHS ? 1 : 0;
     extern __shared__ double lds[];
-    const WorkItem it = items[blockIdx.x];
+    const WorkItem it = items[G.xcdmap ? xcd_item(blockIdx.x, gridDim.x) : blockIdx.x];
     const DevInstance& I = insts[it.inst];
     if (!I.flags[1]) return;
     const int nr = I.nr, nv = G.nv, n0 = G.n0, n1 = G.n1, n2 = G.n2, hq = n0 >> 1;
