@@ -58,6 +58,7 @@ class Params(ctypes.Structure):
         ("n_expand", ctypes.c_int32 * 3),
         ("cfl", ctypes.c_double),
         ("reduced", ctypes.c_int32),
+        ("phi_a", ctypes.c_double),
     ]
 
 
@@ -118,6 +119,8 @@ def _setup(lib):
     lib.orc_vol_slab.restype = ctypes.c_double
     lib.orc_vol_cyl.argtypes = [ctypes.c_double] * 3
     lib.orc_vol_cyl.restype = ctypes.c_double
+    lib.orc_mf_potential.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4
+    lib.orc_mf_potential.restype = ctypes.c_double
     lib.orc_fd4.argtypes = [_D, ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.orc_fd4.restype = ctypes.c_double
     lib.orc_weno5.argtypes = [ctypes.c_double] * 5
@@ -129,10 +132,11 @@ def _setup(lib):
     lib.orc_run_to_steady.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int64), _D]
     for name in ("orc_moments", "orc_node_coeffs", "orc_node_grads", "orc_rhs", "orc_get_f", "orc_set_f",
-                 "orc_get_W", "orc_info"):
+                 "orc_get_W", "orc_get_attraction", "orc_info"):
         getattr(lib, name).argtypes = [vp, _D]
     lib.orc_grid.argtypes = [vp, _D, _D, _D, _D]
     lib.orc_rhs_terms.argtypes = [vp, _D, _D, _D, _D]
+    lib.orc_mean_field.argtypes = [vp, _D, _D]
     lib.orc_mass.argtypes = [vp]
     lib.orc_mass.restype = ctypes.c_double
     lib.orc_set_threads.argtypes = [ctypes.c_int]
@@ -225,6 +229,12 @@ def vol_cyl(s: float, R: float, b: float) -> float:
     return _load().orc_vol_cyl(s, R, b)
 
 
+def mf_potential(geometry: int, sigma: float, phi_a: float, r: float, s: float) -> float:
+    """Integral of the attractive tail -phi_a (sigma/t)^6 (t > sigma) over the region of radius s
+    (ball, infinite cylinder, or the half space x' < s for the plane) seen from radius r."""
+    return _load().orc_mf_potential(geometry, sigma, phi_a, r, s)
+
+
 def fd4(phi: np.ndarray, i: int, dr: float) -> float:
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     return _load().orc_fd4(_ptr(phi), i, len(phi), dr)
@@ -247,7 +257,7 @@ FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
 
 
 def make_params(geometry, r_inner, r_outer, u_wall_inner, t_wall_inner, t_wall_outer, eta0, kn, nr,
-                q_radial, q_t1, q_t2, cfl, n_expand=(0, 0, 0), reduced=0, precision=0) -> Params:
+                q_radial, q_t1, q_t2, cfl, n_expand=(0, 0, 0), reduced=0, precision=0, phi_a=0.0) -> Params:
     p = Params()
     p.geometry = geometry
     p.r_inner = r_inner
@@ -265,6 +275,7 @@ def make_params(geometry, r_inner, r_outer, u_wall_inner, t_wall_inner, t_wall_o
         p.n_expand[a] = n_expand[a]
     p.cfl = cfl
     p.reduced = int(reduced)
+    p.phi_a = float(phi_a)
     return p
 
 
@@ -362,6 +373,19 @@ class Solver:
         out = np.zeros(self.nr * self.nr)
         self._lib.orc_get_W(self._h, _ptr(out))
         return out.reshape(self.nr, self.nr)
+
+    def attraction(self) -> np.ndarray:
+        """Mean-field weights A (Phi = A n); zeros without attraction."""
+        out = np.zeros(self.nr * self.nr)
+        self._lib.orc_get_attraction(self._h, _ptr(out))
+        return out.reshape(self.nr, self.nr)
+
+    def mean_field(self):
+        """(Phi, F) of the current state: mean-field potential and radial force per node."""
+        phi = np.zeros(self.nr)
+        F = np.zeros(self.nr)
+        self._lib.orc_mean_field(self._h, _ptr(phi), _ptr(F))
+        return phi, F
 
     def mass(self) -> float:
         return self._lib.orc_mass(self._h)

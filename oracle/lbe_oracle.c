@@ -23,6 +23,8 @@
  *   - schemes: Sec. III (TVD RK3, WENO-5, 4th-order central differences);
  *   - non-local density: eqs. (chi_ret), (fm) and Appendix A (volume intersections);
  *   - walls: Sec. IV (diffuse reflection at R_L + sigma/2 and R_R - sigma/2).
+ *   - attractive mean field (beyond the paper, the step Sec. V names next): section 6b, an
+ *     Enskog-Vlasov force from a Sutherland tail, evaluated by direct quadrature.
  * Readings of points the paper leaves open are marked "Reading:" where they are used.
  *
  * Parity status of each part is stated next to it; every public routine is pinned by a
@@ -805,6 +807,182 @@ double orc_vol_cyl(double s, double R, double b)
 }
 
 /* ======================================================================================
+ * 6b. Attractive mean field (Enskog-Vlasov), beyond the paper: Sec. V names attractive forces
+ *     between molecules as the next step towards multiphase flows.
+ *
+ * Reading: the attraction is a Sutherland tail phi(t) = -phi_a (sigma / t)^6 for t > sigma
+ * (zero inside the core, whose effect stays with the Enskog collision terms), treated in the
+ * mean-field (Vlasov) approximation: the potential energy of a molecule at x is
+ *   Phi(x) = n0 int n(x') phi(|x - x'|) d^3x',   n0 sigma^3 = 6 eta0 / pi,
+ * with n in units of n0 and n = 0 outside the computational domain (as for nbar), and the
+ * force F = -dPhi/dr acts along the radial axis, adding F df/dp_r to the left-hand side of
+ * the kinetic equation.  With n piecewise constant on cells, Phi_i = sum_j A_ij n_j with
+ *   A_ij = n0 [U(r_i; ri_{j+1}) - U(r_i; ri_j)],
+ * where U(r; s) is the integral of phi over the region of "radius" s (the ball |x'| < s, the
+ * infinite cylinder R' < s, or the half space x' < s) seen from a point at radius r.
+ *
+ * The oracle evaluates U from its definition, about the point: t is the distance from the
+ * point and M(t) the measure of the sphere of radius t about it inside the region,
+ *   U = int_sigma^inf phi(t) M(t) dt,
+ * (sphere: M is a spherical cap area, plane: the part of the sphere on one side of a plane).
+ * For the cylinder the axial direction is integrated first, the line integral
+ *   lam(d) = int phi(sqrt(d^2 + z^2)) dz  (d: distance from the point's axis-parallel line),
+ * then U = int_0^{r+s} lam(d) d arc(d) dd with arc(d) the angle of the circle of radius d
+ * about the point inside the disk of radius s.  Every one-dimensional integral is adaptive
+ * 10-point Gauss-Legendre on the pieces between the points where the integrand has a kink
+ * (t = sigma, t = |r - s|); pieces with square-root ends (the cylinder's arc and lam) are
+ * taken in the variable theta of d = p + (q - p)(1 - cos theta) / 2, which makes them smooth.
+ * ====================================================================================== */
+
+typedef double (*mf_fn)(double x, const void* ctx);
+
+static double mf_gl10(mf_fn f, const void* c, double lo, double hi)
+{
+    double m = (lo + hi) / 2, h = (hi - lo) / 2, acc = 0;
+    for (int i = 0; i < 10; i++) acc += GL10W[i] * f(m + h * GL10X[i], c);
+    return acc * h;
+}
+
+static double mf_adapt(mf_fn f, const void* c, double lo, double hi, double whole, double tol, int depth)
+{
+    double m = (lo + hi) / 2;
+    double left = mf_gl10(f, c, lo, m), right = mf_gl10(f, c, m, hi);
+    if (depth >= 30 || fabs(left + right - whole) <= tol) return left + right;
+    return mf_adapt(f, c, lo, m, left, tol, depth + 1) + mf_adapt(f, c, m, hi, right, tol, depth + 1);
+}
+
+static double mf_integrate(mf_fn f, const void* c, double lo, double hi, double tol)
+{
+    if (!(hi > lo)) return 0;
+    return mf_adapt(f, c, lo, hi, mf_gl10(f, c, lo, hi), tol, 0);
+}
+
+/* Line integral of t^-6 (t = sqrt(d^2 + z^2)) over the z with t > sigma, by z = d cot(beta):
+ * 2 d^-5 int_0^beta0 sin^4(beta) dbeta with beta0 = atan(d / z0), z0 = sqrt(sigma^2 - d^2)
+ * (beta0 = pi/2 for d >= sigma); four 10-point panels. */
+static double mf_line(double d, double sigma)
+{
+    double z0 = d < sigma ? sqrt((sigma - d) * (sigma + d)) : 0;
+    double b0 = atan2(d, z0), acc = 0;
+    for (int p = 0; p < 4; p++) {
+        double lo = b0 * p / 4, hi = b0 * (p + 1) / 4, m = (lo + hi) / 2, h = (hi - lo) / 2;
+        for (int k = 0; k < 10; k++) {
+            double sb = sin(m + h * GL10X[k]);
+            acc += h * GL10W[k] * sb * sb * sb * sb;
+        }
+    }
+    return 2 * acc / (d * d * d * d * d);
+}
+
+typedef struct {
+    int geo;
+    double sigma, r, s;
+    double p, q;   /* piece of the cylinder integral (theta substitution) */
+    double t1;     /* start of the plane's mapped tail */
+} mf_ctx;
+
+/* Measure of the sphere of radius t about the point inside the region (ball or half space). */
+static double mf_measure(const mf_ctx* c, double t)
+{
+    if (c->geo == 1) { /* ball |x'| < s about the origin, point at distance r */
+        if (t + c->r <= c->s) return 4 * PI * t * t;
+        if (t >= c->r + c->s || t + c->s <= c->r) return 0;
+        /* cap: directions w with |x + t w| < s, i.e. cos(angle to x) < (s^2 - r^2 - t^2)/(2 r t) */
+        double mu = (c->s * c->s - c->r * c->r - t * t) / (2 * c->r * t);
+        return 2 * PI * t * t * (1 + mu);
+    }
+    /* half space x' < s, point at x = r: signed distance h = s - x */
+    double h = c->s - c->r;
+    if (t <= -h) return 0;
+    if (t <= h) return 4 * PI * t * t;
+    return 2 * PI * t * (t + h);
+}
+
+static double mf_radial_integrand(double t, const void* vc)
+{
+    const mf_ctx* c = vc;
+    double t2 = t * t;
+    return mf_measure(c, t) / (t2 * t2 * t2);
+}
+
+/* plane tail t >= t1 in u = t1 / t */
+static double mf_tail_integrand(double u, const void* vc)
+{
+    const mf_ctx* c = vc;
+    if (u <= 0) return 0;
+    double t = c->t1 / u;
+    return mf_radial_integrand(t, c) * c->t1 / (u * u);
+}
+
+/* angle of the circle of radius d about the point (distance r from the axis) inside the disk
+ * of radius s */
+static double mf_arc(double d, double r, double s)
+{
+    if (r + d <= s) return 2 * PI;
+    if (d >= r + s || d + s <= r) return 0;
+    double cz = (r * r + d * d - s * s) / (2 * r * d);
+    if (cz > 1) cz = 1;
+    if (cz < -1) cz = -1;
+    return 2 * acos(cz);
+}
+
+static double mf_cyl_integrand(double th, const void* vc)
+{
+    const mf_ctx* c = vc;
+    double hw = (c->q - c->p) / 2;
+    double d = c->p + hw * (1 - cos(th));
+    if (d <= 0) return 0;
+    return mf_line(d, c->sigma) * d * mf_arc(d, c->r, c->s) * hw * sin(th);
+}
+
+static int mf_cmp(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+/* U(r; s) (see above) for geometry 0 cylinder, 1 sphere, 2 plane; the point at radius (plane:
+ * position) r, the region of radius (plane: x' <) s. */
+double orc_mf_potential(int geometry, double sigma, double phi_a, double r, double s)
+{
+    gl10_init();
+    mf_ctx c = {geometry, sigma, r, s, 0, 0, 0};
+    const double s3 = sigma * sigma * sigma, amp = -phi_a * s3 * s3; /* phi(t) = amp t^-6 */
+    const double tol = 4e-16 / s3; /* absolute, per interval: the integrals are of order 1 / sigma^3 */
+    double acc = 0;
+    if (geometry == 0) {
+        double bp[4] = {0, sigma, fabs(r - s), r + s};
+        qsort(bp, 4, sizeof(double), mf_cmp);
+        for (int k = 0; k < 3; k++) {
+            double lo = bp[k], hi = fmin(bp[k + 1], r + s);
+            if (!(hi > lo)) continue;
+            c.p = lo;
+            c.q = hi;
+            acc += mf_integrate(mf_cyl_integrand, &c, 0, PI, tol);
+        }
+        return amp * acc;
+    }
+    if (geometry == 1) {
+        /* kinks at |r - s| and r + s (equal at the centre, r = 0) */
+        double top = r + s, mid = fabs(r - s);
+        if (mid > sigma) acc += mf_integrate(mf_radial_integrand, &c, sigma, fmin(mid, top), tol);
+        acc += mf_integrate(mf_radial_integrand, &c, fmax(sigma, mid), top, tol);
+        return amp * acc;
+    }
+    /* plane: kink at |h|, then the tail beyond t1 = 2 max(sigma, |h|) mapped to (0, 1] */
+    double ah = fabs(s - r);
+    c.t1 = 2 * fmax(sigma, ah);
+    if (ah > sigma) {
+        acc += mf_integrate(mf_radial_integrand, &c, sigma, ah, tol);
+        acc += mf_integrate(mf_radial_integrand, &c, ah, c.t1, tol);
+    } else {
+        acc += mf_integrate(mf_radial_integrand, &c, sigma, c.t1, tol);
+    }
+    acc += mf_integrate(mf_tail_integrand, &c, 0, 1, tol);
+    return amp * acc;
+}
+
+/* ======================================================================================
  * 7. The solver
  * ====================================================================================== */
 
@@ -818,6 +996,7 @@ typedef struct {
     int32_t n_expand[3];
     double cfl;
     int32_t reduced; /* cylinder only: p_z integrated out (see "Reduced distributions" below) */
+    double phi_a;    /* depth of the attractive tail in units of k_B T (section 6b); 0: none */
 } orc_params;
 
 typedef struct {
@@ -829,6 +1008,7 @@ typedef struct {
     double* ri;    /* interface radii, nr + 1 */
     double* vol;   /* cell measures (r_i dr or (ri_{i+1}^3 - ri_i^3)/3) */
     double* W;     /* nr x nr averaged-density weights */
+    double* Amf;   /* nr x nr mean-field weights A_ij (section 6b), NULL without attraction */
     double* K1;    /* (n0 x n0) d/dp along the radial axis (half-range) */
     double* K2a;   /* (n1 x n1) d(f p)/dp along transverse axis 1 */
     double* K2b;   /* (n2 x n2) d(f p)/dp along transverse axis 2 (spherical only) */
@@ -851,6 +1031,7 @@ typedef struct {
 typedef struct {
     double n, u[3], T, q[3], P[3][3];
     double nbar, chi, tau, Pr, brhochi;
+    double phi, F; /* mean-field potential and radial force (zero without attraction) */
     double dlog_nnchiT, dlogT, du[3]; /* radial gradients used by J1 */
 } node_t;
 
@@ -1013,6 +1194,7 @@ static int validate(const orc_params* p)
     if (p->q_radial > QMAX || p->q_t1 > QMAX || p->q_t2 > QMAX) return ORC_EINVAL;
     if (p->geometry == 1 && p->u_wall_inner != 0) return ORC_EINVAL;
     if (p->reduced && p->geometry == 1) return ORC_EINVAL;
+    if (!isfinite(p->phi_a)) return ORC_EINVAL;
     double C = orc_confinement(p->eta0, p->kn);
     if (!(C > 1)) return ORC_EINVAL;
     int Q[3] = {p->q_radial, p->q_t1, p->q_t2};
@@ -1112,6 +1294,23 @@ orc_solver* orc_create(const orc_params* prm_in, int* status)
         free(Vtab);
     }
 
+    /* Mean-field weights (section 6b): A_ij = n0 [U(r_i; ri_{j+1}) - U(r_i; ri_j)],
+     * n0 = 6 eta0 / (pi sigma^3). */
+    s->Amf = NULL;
+    if (prm.phi_a != 0) {
+        const double n0 = 6 * prm.eta0 / (PI * s->sigma * s->sigma * s->sigma);
+        double* Utab = malloc(sizeof(double) * nr * (nr + 1));
+#pragma omp parallel for schedule(dynamic)
+        for (int i = 0; i < nr; i++)
+            for (int j = 0; j <= nr; j++)
+                Utab[i * (nr + 1) + j] = orc_mf_potential(prm.geometry, s->sigma, prm.phi_a, s->r[i], s->ri[j]);
+        s->Amf = malloc(sizeof(double) * nr * nr);
+        for (int i = 0; i < nr; i++)
+            for (int j = 0; j < nr; j++)
+                s->Amf[i * nr + j] = n0 * (Utab[i * (nr + 1) + j + 1] - Utab[i * (nr + 1) + j]);
+        free(Utab);
+    }
+
     /* Unit wall Maxwellians (diffuse reflection, Sec. IV): g_R(0,T_w) g_1(u_w,T_w) g_2(0,T_w). */
     s->gwl = malloc(sizeof(double) * nv);
     s->gwr = malloc(sizeof(double) * nv);
@@ -1171,6 +1370,7 @@ void orc_free(orc_solver* s)
     free(s->ri);
     free(s->vol);
     free(s->W);
+    free(s->Amf);
     free(s->K1);
     free(s->K2a);
     free(s->K2b);
@@ -1207,6 +1407,23 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
         for (int j = 0; j < nr; j++) acc += s->W[i * nr + j] * nd[j].n;
         nd[i].nbar = acc;
         nd[i].chi = orc_chi(P->eta0 * acc);
+    }
+
+    /* (2b) attractive mean field (section 6b): Phi_i = sum_j A_ij n_j, and the radial force
+     * F_i = -dPhi/dr by the same fourth-order stencil as every other radial gradient. */
+    {
+        double* phi = malloc(sizeof(double) * nr);
+        for (int i = 0; i < nr; i++) {
+            double acc = 0;
+            if (s->Amf)
+                for (int j = 0; j < nr; j++) acc += s->Amf[i * nr + j] * nd[j].n;
+            phi[i] = acc;
+        }
+        for (int i = 0; i < nr; i++) {
+            nd[i].phi = phi[i];
+            nd[i].F = s->Amf ? -fd4(phi, i, nr, s->dr) : 0;
+        }
+        free(phi);
     }
 
     /* (3) local coefficients.  Reading: b rho, tau and Pr use the local n with chi(nbar). */
@@ -1346,7 +1563,8 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
             else
                 A = (rr * rr * F[(size_t)(i + 1) * nv + v] - rl * rl * F[(size_t)i * nv + v]) * adv_fac;
             /* inertial terms: (1/R)[p_phi^2 (df/dp_R) - p_R d(f p_phi)/dp_phi] (cylinder),
-             * G[(p_th^2 + p_ph^2) df/dp_r - p_r (d(f p_th)/dp_th + d(f p_ph)/dp_ph)] (sphere). */
+             * G[(p_th^2 + p_ph^2) df/dp_r - p_r (d(f p_th)/dp_th + d(f p_ph)/dp_ph)] (sphere),
+             * plus the mean-field force term F df/dp_r (section 6b) in every geometry. */
             double d0 = 0;
             for (int k = 0; k < n0; k++) d0 += s->K1[i0 * n0 + k] * fi[k + n0 * (i1 + n1 * i2)];
             double d1 = 0;
@@ -1354,6 +1572,7 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
             double I;
             if (planar) {
                 I = 0;
+                if (s->Amf) I = m->F * d0;
             } else if (!sph) {
                 I = force_fac * (p[1] * p[1] * d0 - p[0] * d1);
             } else {
@@ -1361,6 +1580,7 @@ static void compute_rhs_terms(orc_solver* s, const double* f, double* Lout, node
                 for (int k = 0; k < n2; k++) d2 += s->K2b[i2 * n2 + k] * fi[i0 + n0 * (i1 + n1 * k)];
                 I = force_fac * ((p[1] * p[1] + p[2] * p[2]) * d0 - p[0] * (d1 + d2));
             }
+            if (s->Amf && !planar) I += m->F * d0;
             /* collision: Shakhov J0 (eq. (j0), sign as in eq. (enskog_approx)) and J1[f^MB]
              * (eq. (j1)) on the discrete equilibrium f^MB = n g_R g_1 g_2. */
             double fmb = m->n * gR[i0] * gA[i1] * gB[i2];
@@ -1602,6 +1822,30 @@ int orc_set_f(orc_solver* s, const double* in)
 int orc_get_W(orc_solver* s, double* out)
 {
     memcpy(out, s->W, sizeof(double) * (size_t)s->nr * s->nr);
+    return ORC_OK;
+}
+
+/* Mean-field weights A (nr x nr; zeros without attraction). */
+int orc_get_attraction(orc_solver* s, double* out)
+{
+    if (s->Amf)
+        memcpy(out, s->Amf, sizeof(double) * (size_t)s->nr * s->nr);
+    else
+        memset(out, 0, sizeof(double) * (size_t)s->nr * s->nr);
+    return ORC_OK;
+}
+
+/* Mean-field potential Phi [nr] and radial force F [nr] of the current state. */
+int orc_mean_field(orc_solver* s, double* phi, double* F)
+{
+    const int nr = s->nr;
+    node_t* nd = malloc(sizeof(node_t) * nr);
+    compute_rhs(s, s->f, s->Lbuf, nd);
+    for (int i = 0; i < nr; i++) {
+        phi[i] = nd[i].phi;
+        F[i] = nd[i].F;
+    }
+    free(nd);
     return ORC_OK;
 }
 
