@@ -89,6 +89,13 @@ typedef struct {
                            * choice"): the state holds phi = int f dp_z and chi = int p_z^2 f dp_z
                            * on the (p_R, p_phi) quadrature, as the two planes i2 = 0, 1 of the
                            * velocity index (q_t2 and n_expand[2] are then ignored; n2 = 2).   */
+    double phi_a;         /* attractive mean field, beyond the paper (its Sec. V names attractive
+                           * forces as the next step): depth, in units of k_B T, of the Sutherland
+                           * tail phi(t) = -phi_a (sigma/t)^6 for t > sigma.  The potential energy
+                           * Phi(x) = n0 int n(x') phi(|x - x'|) d^3x' (n0 sigma^3 = 6 eta0 / pi,
+                           * n = 0 outside the computational domain) gives the radial force
+                           * F = -dPhi/dr (fourth-order stencil) and the term F df/dp_r of the
+                           * Enskog-Vlasov equation.  0: none (the paper's model); finite.     */
 } lbe_params;
 
 /* Device workspace needed for n_inst instances described by p[0..n_inst-1] (device_bytes),
@@ -131,7 +138,8 @@ lbe_status lbe_sync(lbe_ctx* c);
 
 /* Macroscopic profiles of instance inst (synchronises): host_out[field * nr + i] for
  * fields n, u_r, u_t1, u_t2, T, q_r, P_{r t1}, nbar, chi (eqs. (macro_def), (fm), (chi)),
- * all FP64; cap >= 9 * nr doubles. */
+ * all FP64; cap >= 9 * nr doubles.  With cap >= 11 * nr also the mean-field potential Phi
+ * and the radial force F of lbe_params.phi_a (zero without attraction). */
 lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap);
 
 /* Step every instance until its one-step residual
@@ -192,7 +200,11 @@ lbe_status lbe_info(lbe_ctx* c, int32_t inst, double* out, int64_t cap);
  *          10: d(f p)/dp matrix of the radial half-range axis (n0 x n0; not used by the
  *              reduced equations, exported for checks);
  *          11: nodes then weights of the 32-point half-range Gauss rule the equilibrium
- *              projection uses at moderate u / sqrt(T) [64].
+ *              projection uses at moderate u / sqrt(T) [64];
+ *          12: mean-field weights A (nr x nr): Phi_i = sum_j A_ij n_j (zeros when phi_a = 0);
+ *          13: integral of the tail phi over the region of radius extra[0] (ball, infinite
+ *              cylinder, or the half space x' < extra[0] for plates) seen from radius extra[1],
+ *              for the geometry, sigma and phi_a of p [1].
  * len_out receives the number of doubles written (or needed when cap is too small). */
 lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, double* out, int64_t cap,
                       int64_t* len_out);

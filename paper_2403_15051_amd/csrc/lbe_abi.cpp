@@ -125,6 +125,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Layout {
     size_t fraw[3], f[3], mom, node, snap, resid, flags, nw, scratch;
     size_t base[4], rest, p0, p1, p2, K1, K2a, K2b, w0, w1, w2, poly0, poly1, poly2, qy0, qlam0, qrec0, pgx0, pgw0, geo, r, wlo, wb, gwl, gwr;
+    size_t amf;  // mean-field weights (0 without attraction)
     size_t simg;
     size_t total;
 };
@@ -182,6 +183,7 @@ Layout make_layout(const InstanceTables& t, int nslices, size_t img_doubles, siz
     L.wb = take(t.wb.size() * D);
     L.gwl = take(t.nv * D);
     L.gwr = take(t.nv * D);
+    L.amf = t.amf.empty() ? 0 : take(t.amf.size() * D);
     L.simg = take(img_doubles * D);
     L.total = o;
     return L;
@@ -225,6 +227,7 @@ size_t instance_bytes_estimate(const lbe_params& p)
     b += align256(nr * n2 * sizeof(WorkItem));
     b += 4 * align256(nr * (size_t)(n0 + n1 + n2) * D);
     b += align256((size_t)n2 * stage_image_bound(n0, n1, n2, p.geometry == LBE_SPH) * D);
+    if (p.phi_a != 0) b += align256(nr * nr * D);  // mean-field weights
     return b + 4096;
 }
 
@@ -1085,6 +1088,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         d.wb = (const double*)(ws + L.wb);
         d.gwl = (const double*)(ws + L.gwl);
         d.gwr = (const double*)(ws + L.gwr);
+        d.amf = t.amf.empty() ? nullptr : (const double*)(ws + L.amf);
         d.simg = (double*)(ws + L.simg);
         if (e == hipSuccess) e = put(ws, L.p0, t.ax[0].p, c->stream);
         if (e == hipSuccess) e = put(ws, L.p1, t.ax[1].p, c->stream);
@@ -1109,6 +1113,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
         if (e == hipSuccess) e = put(ws, L.wb, t.wb, c->stream);
         if (e == hipSuccess) e = put(ws, L.gwl, t.gwl, c->stream);
         if (e == hipSuccess) e = put(ws, L.gwr, t.gwr, c->stream);
+        if (e == hipSuccess && !t.amf.empty()) e = put(ws, L.amf, t.amf, c->stream);
         // rest start: n = 1, u = 0, T = 1 (its axis factors are kept for resets on the device)
         if (e == hipSuccess) {
             std::vector<double> g0(t.n0), g1(t.n1), g2(t.n2), f((size_t)t.nr * t.nv);
@@ -1240,8 +1245,9 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     lbe_status st2 = upload_flags(c);
     if (st != LBE_OK) return st;
     if (st2 != LBE_OK) return st2;
-    const int fields[9] = {NF_N, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_P01, NF_NBAR, NF_CHI};
-    for (int fi = 0; fi < 9; fi++)
+    const int fields[11] = {NF_N, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_P01, NF_NBAR, NF_CHI, NF_PHI, NF_FR};
+    const int nf = cap >= 11 * (int64_t)d.nr ? 11 : 9;
+    for (int fi = 0; fi < nf; fi++)
         for (int i = 0; i < d.nr; i++) host_out[fi * d.nr + i] = node[(size_t)i * kNodeStride + fields[fi]];
     return check_nan(c);
 }
@@ -1419,6 +1425,7 @@ uint64_t params_fingerprint(const lbe_ctx* c)
         mix(iv, sizeof(iv));
         mix(&q.n_expand[2], sizeof(int32_t));
         mix(&q.reduced, sizeof(int32_t));
+        mix(&q.phi_a, sizeof(double));
     }
     return h;
 }
@@ -1669,6 +1676,16 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
                                           : ball_below_plane(extra[0], extra[1], extra[2]);
         return LBE_OK;
     }
+    if (which == 13) {
+        lbe_params q;
+        if (!extra || validate_params(*p, &q, nullptr) != LBE_OK) return LBE_EINVAL;
+        if (len_out) *len_out = 1;
+        if (cap < 1 || !out) return LBE_EINVAL;
+        const double C = 1 / (6 * std::sqrt(2.0) * q.eta0 * chi_cs(q.eta0) * q.kn);
+        const double sigma = (q.r_outer - q.r_inner) / C;  // as build_instance
+        out[0] = mf_potential(q.geometry, sigma, q.phi_a, extra[1], extra[0]);
+        return LBE_OK;
+    }
     InstanceTables t;
     std::string err;
     lbe_status st = build_instance(*p, &t, &err);
@@ -1708,6 +1725,10 @@ lbe_status lbe_tables(const lbe_params* p, int32_t which, const double* extra, d
         case 11:
             v = t.ax[0].gx;
             v.insert(v.end(), t.ax[0].gw.begin(), t.ax[0].gw.end());
+            break;
+        case 12:
+            v = t.amf;
+            if (v.empty()) v.assign((size_t)t.nr * t.nr, 0.0);
             break;
         default: return LBE_EINVAL;
     }

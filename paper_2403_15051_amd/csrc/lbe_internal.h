@@ -17,16 +17,18 @@ constexpr int kNodeStride = 96;  // doubles per node in the node-coefficient blo
 constexpr int kMomStride = 16;   // doubles per node in the moment-sum block
 constexpr int kProjGauss = 32;   // nodes per side of the projection kernel's half-range Gauss rule
 
-// Node-coefficient block layout (doubles, per node), written by the node kernel.
+// Node-coefficient block layout (doubles, per node), written by the node kernel.  NF_PHI, NF_FR:
+// mean-field potential and radial force of the attractive tail (zero without attraction).
 enum NodeField {
     NF_N = 0, NF_U0, NF_U1, NF_U2, NF_T, NF_Q0, NF_Q1, NF_Q2,
     NF_TAU, NF_PR, NF_BRHOCHI, NF_D1, NF_D2, NF_DU0, NF_DU1, NF_DU2,
     NF_NBAR, NF_CHI, NF_P01, NF_SHAK, NF_INVTAU, NF_DIVU, NF_SHEAR01, NF_UPHI_R,
-    NF_UR_R, NF_INV2T, NF_INV5T, NF_COUNT,
+    NF_UR_R, NF_INV2T, NF_INV5T, NF_PHI, NF_FR, NF_COUNT,
     // equilibrium projection coefficients (Sec. III.C): half-range I_l^+ and I_l^- of the
     // radial axis, full-range c_l of the two transverse axes (16 slots each)
     NF_IPLUS = 32, NF_IMINUS = 48, NF_C1 = 64, NF_C2 = 80
 };
+static_assert(NF_COUNT <= NF_IPLUS, "node scalars overlap the projection coefficients");
 
 // Moment-sum block layout (doubles, per node), written by the stage kernel: sums of f times
 // powers of xi' = p - c, where c is the shift stored with the block.
@@ -68,6 +70,7 @@ struct InstanceTables {
     std::vector<double> wb;               // nr x wband band of W
     std::vector<double> gwl, gwr;         // unit wall Maxwellians [nv]
     double gin_l = 0, gin_r = 0;          // sum over entering velocities of p_r * g_w
+    std::vector<double> amf;              // nr x nr mean-field weights (empty without attraction)
 };
 
 // Device descriptor of one instance (lives in device memory; pointers into the workspace).
@@ -106,6 +109,7 @@ struct DevInstance {
     double* nw;             // [2] wall densities of the current stage
     double* scratch;        // [nr][nv] rhs output (lbe_rhs); staging of lbe_set_init_moments
     const double* rest;     // [n0 + n1 + n2] equilibrium factors at rest (n = 1, u = 0, T = 1)
+    const double* amf;      // [nr][nr] mean-field weights, null without attraction
     double* simg;           // [nslices][img_sz] constant part of the stage kernel's LDS per slice
 };
 
@@ -160,5 +164,6 @@ double ball_in_cylinder(double s, double R, double b);
 double ball_in_sphere(double s, double R, double b);
 double ball_below_plane(double s, double X, double b);
 double chi_cs(double eta);
+double mf_potential(int geometry, double sigma, double phi_a, double r, double s);
 
 }  // namespace lbe

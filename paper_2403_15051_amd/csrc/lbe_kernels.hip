@@ -416,11 +416,12 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo];
     __shared__ Macro smac[kNodeChunk];
     __shared__ double sdens[kMaxNr];
-    __shared__ double snb[kNodeChunk + 2 * kHalo];
+    __shared__ double snb[kNodeChunk + 2 * kHalo], sphi[kNodeChunk + 2 * kHalo];
     // densities (slice sums) of the nodes the band of W reaches from the chunk + halo (wlo is
-    // nondecreasing), then the averaged density of the chunk + halo, eq. (fm): nbar_j = sum_k W_jk
-    // n_k over the band, 8 lanes per row, loads batched by 8
-    const int jlo = I.wlo[h0], jhi = min(nr, I.wlo[h1 - 1] + I.wband);
+    // nondecreasing; every node with attraction), then the averaged density of the chunk + halo,
+    // eq. (fm): nbar_j = sum_k W_jk n_k over the band, 8 lanes per row, loads batched by 8
+    const bool attract = I.amf != nullptr;
+    const int jlo = attract ? 0 : I.wlo[h0], jhi = attract ? nr : min(nr, I.wlo[h1 - 1] + I.wband);
     for (int j = jlo + (int)threadIdx.x; j < jhi; j += kBlock) {
         const double* b = I.mom + (size_t)j * I.nslices * kMomStride;
         double n = b[MF_S0];
@@ -455,6 +456,29 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
             part += __shfl_down(part, 1, 8);
             if (sub == 0) snb[k] = part;
         }
+        // attractive mean field: Phi_j = sum_k A_jk n_k over every node (A dense), same pattern
+        if (attract)
+            for (int k = grp; k < nh; k += kBlock / 8) {
+                const double* arow = I.amf + (size_t)(h0 + k) * nr;
+                double part = 0;
+                for (int base = sub; base < nr; base += 64) {
+                    double av[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int col = base + 8 * u;
+                        av[u] = col < nr ? arow[col] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int col = base + 8 * u;
+                        if (col < nr) part += av[u] * sdens[col];
+                    }
+                }
+                part += __shfl_down(part, 4, 8);
+                part += __shfl_down(part, 2, 8);
+                part += __shfl_down(part, 1, 8);
+                if (sub == 0) sphi[k] = part;
+            }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nh; k += kBlock) {
@@ -533,6 +557,9 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         nd[NF_UR_R] = m.u[0] * invr;
         nd[NF_INV2T] = 1 / (2 * T);
         nd[NF_INV5T] = 1 / (5 * T);
+        // mean-field force F = -dPhi/dr by the same stencil as every radial gradient
+        nd[NF_PHI] = attract ? sphi[li] : 0.0;
+        nd[NF_FR] = attract ? -g(sphi) : 0.0;
         if (!(n > 0) || !(T > 0) || !isfinite(n) || !isfinite(T)) I.flags[0] = 1;
         // equilibrium coefficients of the full-range axes (eq. (eq_gak_H))
         full_coeffs<kMaxN>(m.u[1], T, I.N1, nd + NF_C1);
@@ -703,7 +730,8 @@ __device__ inline double weno_flux(double a, double b, double c, double d, doubl
 // where col = q16 * bcol, or the table ctab[q16] when bcol = 0.  Contraction tiles then write
 // fac * D[q4 + 4r][q16] (fac = ffac * lftab[q16], lanes q16 < okl, rows q4 + 4r < rowlim) to
 // out + obase + col + (q4 + 4r) * orow.  Type: 0 a contraction tile with a ragged edge, 2 a whole
-// one (okl and rowlim >= 16), 1 moment sums (over column tile ct, nk = n0k).  The first four
+// one (okl and rowlim >= 16), 1 moment sums (over column tile ct, nk = n0k); plus 4 for the tiles
+// of d0 = K1 P (radial derivative), whose factor adds the mean-field force: fac + FR.  The first four
 // fields are the ones a wave reads at every node; the rest fix its per-lane offsets.
 enum TileDesc {
     TD_TYPE = 0, TD_NK, TD_BK, TD_OROW, TD_OKL, TD_ROWLIM, TD_ABASE, TD_AROW, TD_BBASE, TD_BCOL, TD_CTAB, TD_LFTAB,
@@ -713,12 +741,13 @@ enum TileDesc {
 // Per-node coefficients of the stage update, written by the workgroup set-up:
 //   o = an f^n + CF f + fmb P(y) - (AR F_r - AL F_l) - I
 // with y = p - c (c: velocity shift of the tile), fmb = gR(i0) g1(i1) g2(i2) the discrete
-// equilibrium without its density, I the inertial contractions (scaled by FFAC) and the cubic
+// equilibrium without its density, I the inertial contractions (scaled by FFAC; the radial
+// derivative d0 also by FR, the mean-field force) and the cubic
 //   P(y) = C0 + y0 (G0 + E00 y0 + E01 y1 + E02 y2) + y1 (G1 + E11 y1 + E12 y2) + y2 (G2 + E22 y2)
 //          + |y|^2 (H0 y0 + H1 y1 + H2 y2).
 enum StageCoef {
     SC_C0 = 0, SC_G0, SC_G1, SC_G2, SC_E00, SC_E01, SC_E02, SC_E11, SC_E12, SC_E22, SC_H0, SC_H1, SC_H2,
-    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_N, SC_T, SC_COUNT
+    SC_CF, SC_AL, SC_AR, SC_FFAC, SC_N, SC_T, SC_FR, SC_COUNT
 };
 static_assert(SC_COUNT <= kCoefStride, "stage coefficient block");
 
@@ -791,6 +820,7 @@ __device__ inline void stage_coefs(const double* nd, const double* geo4, const d
     out[SC_FFAC] = sigma * geo4[2];
     out[SC_N] = n;
     out[SC_T] = nd[NF_T];
+    out[SC_FR] = sigma * nd[NF_FR];
 }
 
 // Stage image of one instance and velocity slice, written to R: the tables the stage kernel
@@ -923,7 +953,7 @@ __device__ void stage_image(const DevInstance& I, const StageGroup& G, int slice
             d[TD_ROWLIM] = G.ns2 - 16 * mt;
             d[TD_OUT] = G.off_ibuf + 2 * cs * ncol;
         }
-        d[TD_TYPE] = d[TD_OKL] >= 16 && d[TD_ROWLIM] >= 16 ? 2 : 0;
+        d[TD_TYPE] = (d[TD_OKL] >= 16 && d[TD_ROWLIM] >= 16 ? 2 : 0) | (tl < nT1 ? 4 : 0);
     }
     for (int e = tid; e < G.n0p; e += B) pv0[e] = e < n0 ? I.p0[e] : 0.0;
     for (int e = tid; e < G.ncols16; e += B) {
@@ -1369,9 +1399,10 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     };
 
     // One contraction tile of node t (plane and term buffers t mod 2).  whole: no lane or row
-    // guard; otherwise lanes q16 < okl and rows q4 + 4r < rowlim are written.
+    // guard; otherwise lanes q16 < okl and rows q4 + 4r < rowlim are written.  d0: a tile of the
+    // radial derivative, whose factor adds the mean-field force.
     auto contraction_tile = [&](const TileOffs& f, int t, int nk, int bk, int orow, bool whole, int okl,
-                                int rowlim) {
+                                int rowlim, bool d0) {
         const int buf = t & 1;
         const double lf = lds[f.l];
         const double* ap = lds + f.a;
@@ -1408,7 +1439,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             for (int m = 0; m < 4; m++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[m], acc, 0, 0, 0);
         }
         for (; ks < nk; ks += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[ks], bp[ks * bk], acc, 0, 0, 0);
-        const double fac = scoef[t * kCoefStride + SC_FFAC] * lf;
+        const double fac = fma(scoef[t * kCoefStride + SC_FFAC], lf, d0 ? scoef[t * kCoefStride + SC_FR] : 0.0);
         double* o = lds + f.o + buf * G.ib_sz;
         if (whole) {
 #pragma unroll
@@ -1441,12 +1472,13 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         } else if (cok) {
             const int nk = __builtin_amdgcn_readfirstlane(h.y), bk = __builtin_amdgcn_readfirstlane(h.z);
             const int orow = __builtin_amdgcn_readfirstlane(h.w);
-            if (type == 2) {
-                contraction_tile(f, tc, nk, bk, orow, true, 16, 16);
+            const bool d0 = (type & 4) != 0;
+            if (type & 2) {
+                contraction_tile(f, tc, nk, bk, orow, true, 16, 16, d0);
             } else {
                 const int2 g = *(const int2*)(tdesc + slot * kTileDescStride + TD_OKL);
                 contraction_tile(f, tc, nk, bk, orow, false, __builtin_amdgcn_readfirstlane(g.x),
-                                 __builtin_amdgcn_readfirstlane(g.y));
+                                 __builtin_amdgcn_readfirstlane(g.y), d0);
             }
         }
     };
@@ -1471,7 +1503,8 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
             if (T.type == 1) {
                 if (mok) moment_tile(moment_offs(T.ct), tm);
             } else if (cok) {
-                contraction_tile(contraction_offs(T), tc, T.nk, T.bk, T.orow, T.type == 2, T.okl, T.rowlim);
+                contraction_tile(contraction_offs(T), tc, T.nk, T.bk, T.orow, (T.type & 2) != 0, T.okl, T.rowlim,
+                                 (T.type & 4) != 0);
             }
         }
     };

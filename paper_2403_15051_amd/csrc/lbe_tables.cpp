@@ -548,6 +548,169 @@ double ball_in_sphere(double s_, double R_, double b_)
     return (double)(kPi * t * t * (b * b + 2 * b * (s + R) - 3 * (s - R) * (s - R)) / (12 * b));
 }
 
+// ------------------------------------------------------------------ attractive mean field
+// Enskog-Vlasov mean field of a Sutherland tail phi(t) = -phi_a (sigma / t)^6, t > sigma (beyond
+// the paper; its Sec. V names attractive forces as the next step).  mf_potential(r; s) is the
+// integral of phi over the region of radius s (ball, infinite cylinder, or the half space x' < s)
+// seen from a point at radius r:
+//   plane:    over the transverse plane first, g(D) = -(pi/2) phi_a sigma^6 / max(D^2, sigma^2)^2,
+//             then the integral of g over D > r - s in closed form;
+//   sphere:   shells about the origin: by the shell theorem a shell of radius rho seen from r
+//             contributes (2 pi rho / r) int_{|r-rho|}^{r+rho} t phi(t) dt = -(2 pi rho / r)
+//             phi_a sigma^6 [h(|r - rho|) - h(r + rho)], h(t) = max(t, sigma)^-4 / 4; the rho
+//             integral in closed form from the running integrals of h and t h;
+//   cylinder: the axial direction first, lam(d) = int phi(sqrt(d^2 + z^2)) dz in closed form,
+//             then int_0^{r+s} lam(d) d arc(d) dd over the disk about the point (arc: the angle
+//             of the circle of radius d inside the disk of radius s).  On each piece [p, q]
+//             between the kinks (sigma, |r - s|) d = p + (q - p)(1 - cos th)/2 makes the
+//             square-root ends smooth; 16-point Gauss-Legendre panels in th, graded towards an
+//             end where a singular point outside the piece comes close.
+
+// int_0^t h, int_0^t tau h(tau) for h = max(tau, sigma)^-4 / 4
+static ld mf_c0(ld t, ld sg)
+{
+    return t <= sg ? t / (4 * sg * sg * sg * sg) : 1 / (4 * sg * sg * sg) + (1 / (sg * sg * sg) - 1 / (t * t * t)) / 12;
+}
+static ld mf_c1(ld t, ld sg)
+{
+    return t <= sg ? t * t / (8 * sg * sg * sg * sg) : 1 / (8 * sg * sg) + (1 / (sg * sg) - 1 / (t * t)) / 8;
+}
+
+// int_0^beta sin^4: Taylor series (no cancellation) below 1/2, else 3b/8 - sin(2b)/4 + sin(4b)/32
+static ld sin4_integral(ld b)
+{
+    if (b < 0.5L) {
+        // sum_{k>=2} (-1)^k (16^k - 4^(k+1)) b^(2k+1) / (8 (2k+1)!)
+        ld b2 = b * b, pw = b2 * b2 * b, fact = 120, p16 = 256, p4 = 64, sum = 0;
+        for (int k = 2; k < 24; k++) {
+            const ld term = (p16 - p4) * pw / (8 * fact);
+            sum += (k % 2 ? -term : term);
+            pw *= b2;
+            fact *= (ld)(2 * k + 2) * (2 * k + 3);
+            p16 *= 16;
+            p4 *= 4;
+        }
+        return sum;
+    }
+    return 3 * b / 8 - sinl(2 * b) / 4 + sinl(4 * b) / 32;
+}
+
+// line integral of t^-6 over the z with t = sqrt(d^2 + z^2) > sigma: with z = d cot(beta),
+// 2 d^-5 int_0^beta0 sin^4, beta0 = asin(d / sigma) (pi / 2 for d >= sigma)
+static double mf_line(double d, double sg)
+{
+    const ld dd = d, d5 = dd * dd * dd * dd * dd;
+    if (d >= sg) return (double)(3 * kPi / (8 * d5));
+    return (double)(2 * sin4_integral(asinl(dd / sg)) / d5);
+}
+
+static double mf_arc(double d, double r, double s)
+{
+    if (r + d <= s) return 2 * M_PI;
+    if (d >= r + s || d + s <= r) return 0.0;
+    double c = (r * r + d * d - s * s) / (2 * r * d);
+    c = std::min(1.0, std::max(-1.0, c));
+    return 2 * std::acos(c);
+}
+
+static const std::vector<double>& gl16()
+{
+    static std::vector<double> xw;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::vector<ld> x, w;
+        gauss_legendre(16, x, w);
+        for (int i = 0; i < 16; i++) xw.push_back((double)x[i]);
+        for (int i = 0; i < 16; i++) xw.push_back((double)w[i]);
+    });
+    return xw;
+}
+
+double mf_potential(int geometry, double sigma, double phi_a, double r, double s)
+{
+    const ld sg = sigma, sg3 = sg * sg * sg, amp = -(ld)phi_a * sg3 * sg3;
+    if (geometry == LBE_PLANAR) {
+        const ld t = (ld)r - s;  // U = int_t^inf g(D) dD
+        ld k;
+        if (t >= sg)
+            k = 1 / (3 * t * t * t);
+        else if (t >= -sg)
+            k = (sg - t) / (sg3 * sg) + 1 / (3 * sg3);
+        else
+            k = 8 / (3 * sg3) + 1 / (3 * t * t * t);
+        return (double)(amp * kPi / 2 * k);
+    }
+    if (geometry == LBE_SPH) {
+        const ld R = r, S = s;
+        if (R <= 0) return S > sg ? (double)(4 * kPi * amp * (1 / sg3 - 1 / (S * S * S)) / 3) : 0.0;
+        const ld i1 = mf_c1(R + S, sg) - mf_c1(R, sg) - R * (mf_c0(R + S, sg) - mf_c0(R, sg));
+        const ld m = std::min(R, S);
+        ld i2 = R * (mf_c0(R, sg) - mf_c0(R - m, sg)) - (mf_c1(R, sg) - mf_c1(R - m, sg));
+        if (S > R) i2 += R * mf_c0(S - R, sg) + mf_c1(S - R, sg);
+        return (double)(2 * kPi * amp / R * (i2 - i1));
+    }
+    // singular points of lam(d) d arc(d) on the real d axis: 0 (pole), sigma (lam), |r - s| and
+    // r + s (arc); each piece [p, q] lies between two of them.  A singular point at distance e
+    // outside the piece sits at th = i acosh(1 + 2 e / (q - p)), so the panels are graded from each
+    // end down to a quarter of that.
+    const std::vector<double>& xw = gl16();
+    double bp[4] = {0.0, sigma, std::fabs(r - s), r + s};
+    std::sort(bp, bp + 4);
+    ld acc = 0;
+    std::vector<double> edges;
+    for (int k = 0; k < 3; k++) {
+        const double p = bp[k], q = std::min(bp[k + 1], r + s);
+        if (!(q > p)) continue;
+        const double hw = (q - p) / 2;
+        double eL = HUGE_VAL, eR = HUGE_VAL;
+        for (double x : bp) {
+            if (x < p) eL = std::min(eL, p - x);
+            if (x > q) eR = std::min(eR, x - q);
+        }
+        auto reach = [&](double e) { return e == HUGE_VAL ? M_PI : std::acosh(1 + 2 * e / (q - p)); };
+        edges.assign(1, 0.0);
+        for (double h = std::min(reach(eL), M_PI) / 4, x = 0; x + h < M_PI / 2; h = x) {
+            x += h;
+            edges.push_back(x);
+        }
+        std::vector<double> right;
+        for (double h = std::min(reach(eR), M_PI) / 4, x = 0; x + h < M_PI / 2; h = x) {
+            x += h;
+            right.push_back(M_PI - x);
+        }
+        edges.push_back(M_PI / 2);
+        for (auto it = right.rbegin(); it != right.rend(); ++it) edges.push_back(*it);
+        edges.push_back(M_PI);
+        for (size_t e = 0; e + 1 < edges.size(); e++) {
+            const double c = (edges[e] + edges[e + 1]) / 2, h = (edges[e + 1] - edges[e]) / 2;
+            ld part = 0;
+            for (int g = 0; g < 16; g++) {
+                const double th = c + h * xw[g];
+                const double d = p + hw * (1 - std::cos(th));
+                if (d <= 0) continue;
+                part += (ld)xw[16 + g] * mf_line(d, sigma) * d * mf_arc(d, r, s) * hw * std::sin(th);
+            }
+            acc += part * h;
+        }
+    }
+    return (double)(amp * acc);
+}
+
+// Mean-field weights: Phi_i = sum_j A_ij n_j, A_ij = n0 [U(r_i; ri_{j+1}) - U(r_i; ri_j)] with
+// n0 = 6 eta0 / (pi sigma^3) (n in units of the mean density, zero outside the domain).
+static void mf_weights(InstanceTables* t)
+{
+    const int nr = t->nr;
+    const lbe_params& p = t->prm;
+    const ld n0 = 6 * (ld)p.eta0 / (kPi * (ld)t->sigma * t->sigma * t->sigma);
+    t->amf.assign((size_t)nr * nr, 0.0);
+    std::vector<double> U(nr + 1);
+    for (int i = 0; i < nr; i++) {
+        for (int j = 0; j <= nr; j++) U[j] = mf_potential(p.geometry, t->sigma, p.phi_a, t->r[i], t->ri[j]);
+        for (int j = 0; j < nr; j++) t->amf[(size_t)i * nr + j] = (double)(n0 * ((ld)U[j + 1] - U[j]));
+    }
+}
+
 // ------------------------------------------------------------------ instance set-up
 
 lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* err)
@@ -569,6 +732,7 @@ lbe_status validate_params(const lbe_params& in, lbe_params* out, std::string* e
     if (p.geometry == LBE_SPH && p.u_wall_inner != 0) return bad("a spherical instance cannot have a wall velocity");
     if (p.reduced != 0 && p.reduced != 1) return bad("reduced must be 0 or 1");
     if (p.reduced && p.geometry == LBE_SPH) return bad("the reduced distributions are for cylinders and plates");
+    if (!std::isfinite(p.phi_a)) return bad("phi_a must be finite");
     if (p.reduced) {  // the (phi, chi) planes take the place of the p_z axis
         p.q_t2 = 2;
         p.n_expand[2] = 2;
@@ -689,6 +853,8 @@ lbe_status build_instance(const lbe_params& pin, InstanceTables* t, std::string*
             for (int j = lo; j <= hi; j++) t->wb[(size_t)i * wb + (j - lo)] = (double)(((ld)V[j + 1 - lo] - V[j - lo]) / ball);
         }
     }
+
+    if (p.phi_a != 0) mf_weights(t);
 
     // Unit wall Maxwellians g_r(0, T_w) g_1(u_w, T_w) g_2(0, T_w) and the entering flux sums.
     t->gwl.resize(t->nv);

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("LBE_LIB") or os.path.join(_HERE, "liblbe.so")
 LBE_OK, LBE_EINVAL, LBE_ENOMEM, LBE_EDEVICE, LBE_ENOTCONV, LBE_ENAN, LBE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 CYL, SPH, PLANAR = 0, 1, 2
 FIELDS = ("n", "u_r", "u_t1", "u_t2", "T", "q_r", "P_rt1", "nbar", "chi")
+MF_FIELDS = ("Phi", "F")  # mean-field potential and radial force (lbe_moments with 11 fields)
 WARM_FIELDS = ("n", "u_t1", "T", "q_r", "P_rt1")
 GEMM_BF16, GEMM_FP32 = 0, 1
 FP64, FP32_STORE = 0, 1
@@ -52,6 +53,7 @@ class Params(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("reduced", ctypes.c_int32),
+        ("phi_a", ctypes.c_double),
     ]
 
 
@@ -65,6 +67,7 @@ def make_params(d: dict) -> Params:
         setattr(p, k, d[k])
     p.precision = int(d.get("precision", FP64))
     p.reduced = int(d.get("reduced", 0))
+    p.phi_a = float(d.get("phi_a", 0.0))
     ne = d.get("n_expand", (0, 0, 0))
     for a in range(3):
         p.n_expand[a] = int(ne[a])
@@ -248,12 +251,13 @@ class Solver:
     def sync(self) -> None:
         self._check(self._lib.lbe_sync(self._h), "lbe_sync")
 
-    def moments(self, inst: int = 0) -> dict:
+    def moments(self, inst: int = 0, mean_field: bool = False) -> dict:
         nr = int(self._infos[inst]["nr"])
-        out = np.zeros(9 * nr)
+        keys = FIELDS + (MF_FIELDS if mean_field else ())
+        out = np.zeros(len(keys) * nr)
         self._check(self._lib.lbe_moments(self._h, inst, _ptr(out), out.size), "lbe_moments")
-        out = out.reshape(9, nr)
-        return {k: out[i].copy() for i, k in enumerate(FIELDS)}
+        out = out.reshape(len(keys), nr)
+        return {k: out[i].copy() for i, k in enumerate(keys)}
 
     def run_to_steady(self, tol: float, max_steps: int, check_every: int):
         steps = np.zeros(self.n_inst, dtype=np.int64)

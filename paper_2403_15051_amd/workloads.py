@@ -61,6 +61,21 @@ def paper_case(flow: str, geometry: int, eta0: float, C: float, R_L: float, q_ra
     return d
 
 
+def attraction_case(geometry: int, phi_a: float = 0.5, eta0: float = 0.2, C: float = 5.0, R_L: float = 1.0,
+                    nr: int = 40, q: int = 4, flow: str = "rest", precision: int = 0) -> dict:
+    """A problem with the attractive mean field (beyond the paper: Enskog-Vlasov force of a
+    Sutherland tail of depth phi_a k_B T), in units of sigma = 1 like the paper's grid: walls at
+    R_L and R_L + C, Kn from the Kn map, half-range order q and full-range order q (p_z integrated
+    out for cylinders and plates).  flow 'rest' (walls at T = 1), 'fourier' (T 1.1 / 0.9) or
+    'couette' (inner wall speed 0.3)."""
+    kn = 1.0 / (6 * np.sqrt(2.0) * eta0 * ((2 - eta0) / (2 * (1 - eta0) ** 3)) * C)
+    tl, tr = (1.1, 0.9) if flow == "fourier" else (1.0, 1.0)
+    uw = 0.3 if (flow == "couette" and geometry != 1) else 0.0
+    return dict(geometry=geometry, r_inner=float(R_L), r_outer=float(R_L + C), u_wall_inner=uw, t_wall_inner=tl,
+                t_wall_outer=tr, eta0=eta0, kn=kn, nr=nr, q_radial=q, q_t1=q, q_t2=q, cfl=0.25,
+                reduced=0 if geometry == 1 else 1, precision=precision, phi_a=phi_a)
+
+
 SWEEP_SEED = 240315051
 SWEEP_ORDERS = (4, 8, 12, 16)
 

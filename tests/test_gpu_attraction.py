@@ -1,0 +1,142 @@
+"""GPU parity of the attractive mean field (Enskog-Vlasov force of a Sutherland tail; beyond the
+paper, whose Sec. V names attractive forces as the next step) against the CPU oracle, through
+the C ABI.
+
+The node kernel forms Phi = A n from the dense mean-field weights and F = -dPhi/dr with the
+fourth-order stencil; the stage kernel adds F to the factor of its radial-derivative (d0) tiles.
+Tolerance as for the rest of the FP64 path: normwise relative error 1e-12 at equal step counts
+(f, Phi, F and the profiles); FP32 storage 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15051_amd import lbe, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def nrel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    lbe.load()
+
+
+CASES = {
+    "plates, reduced, Fourier": workloads.attraction_case(2, flow="fourier"),
+    "cylinder, reduced, Couette": workloads.attraction_case(0, flow="couette"),
+    "cylinder, full set, Couette": dict(workloads.attraction_case(0, flow="couette", R_L=3.0), reduced=0),
+    "sphere, Fourier": workloads.attraction_case(1, flow="fourier", nr=32),
+    "cylinder, repulsive tail": workloads.attraction_case(0, phi_a=-0.4, flow="fourier", C=7.0, nr=60),
+    "plates, strong, wide": workloads.attraction_case(2, phi_a=1.0, eta0=0.1, C=10.0, nr=90, q=6),
+}
+
+
+def pair(p):
+    print("case", p, flush=True)
+    return oracle.Solver(workloads.oracle_params(p)), lbe.Solver(p)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_mean_field_of_the_rest_start(name):
+    o, g = pair(CASES[name])
+    m = g.moments(mean_field=True)
+    phi, F = o.mean_field()
+    e_phi, e_F = nrel(m["Phi"], phi), nrel(m["F"], F)
+    print(name, "Phi", e_phi, "F", e_F, flush=True)
+    assert e_phi <= TOL and e_F <= TOL
+    assert np.abs(F).max() > 0.05
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_rhs_parity_with_attraction(name):
+    o, g = pair(CASES[name])
+    assert nrel(g.rhs(), o.rhs()) <= TOL
+    o.step(30)
+    g.set_state(0, o.get_f())
+    e = nrel(g.rhs(), o.rhs())
+    print(name, "rhs after 30 oracle steps", e, flush=True)
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_500_steps_with_attraction(name):
+    o, g = pair(CASES[name])
+    o.step(500)
+    g.step(500)
+    g.sync()
+    e = nrel(g.get_state(), o.get_f())
+    mg, mo = g.moments(mean_field=True), o.moments()
+    phi, F = o.mean_field()
+    errs = {"f": e, "n": nrel(mg["n"], mo["n"]), "T": nrel(mg["T"], mo["T"]), "Phi": nrel(mg["Phi"], phi),
+            "F": nrel(mg["F"], F)}
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (name, k, v)
+
+
+def test_batch_with_and_without_attraction():
+    """Instances with attraction, without, and with a repulsive tail share one launch group; each
+    matches its own oracle solve."""
+    base = workloads.attraction_case(2, flow="fourier")
+    ps = [base, dict(base, phi_a=0.0), dict(base, phi_a=-0.3, eta0=0.1)]
+    g = lbe.Solver(ps)
+    g.step(200)
+    g.sync()
+    for k, p in enumerate(ps):
+        o = oracle.Solver(workloads.oracle_params(p))
+        o.step(200)
+        e = nrel(g.get_state(k), o.get_f())
+        print("batch", k, e, flush=True)
+        assert e <= TOL, k
+        m = g.moments(k, mean_field=True)
+        if p["phi_a"] == 0:
+            assert not m["Phi"].any() and not m["F"].any()
+
+
+def test_fp32_storage_with_attraction():
+    p = workloads.attraction_case(0, flow="fourier", precision=lbe.FP32_STORE)
+    o = oracle.Solver(workloads.oracle_params(p))
+    g = lbe.Solver(p)
+    o.step(500)
+    g.step(500)
+    g.sync()
+    mg, mo = g.moments(mean_field=True), o.moments()
+    phi, F = o.mean_field()
+    errs = {"n": nrel(mg["n"], mo["n"]), "T": nrel(mg["T"], mo["T"]), "Phi": nrel(mg["Phi"], phi),
+            "F": nrel(mg["F"], F), "q_r": nrel(mg["q_r"], mo["q_r"])}
+    print("fp32", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+
+
+def test_steady_rest_channel_with_attraction():
+    """Gas at rest between plates at T = 1 with the mean field: the library's steady solve stops on
+    the oracle's step and matches its profiles; the attraction pulls the fluid off the walls."""
+    p = workloads.attraction_case(2, nr=40, C=5.0)
+    o = oracle.Solver(workloads.oracle_params(p))
+    g = lbe.Solver(p)
+    rc_o, steps_o, res_o = o.run_to_steady(1e-8, 100000, 50)
+    st, steps_g, res_g = g.run_to_steady(1e-8, 100000, 50)
+    print("steady", steps_o, res_o, steps_g[0], res_g[0], flush=True)
+    assert rc_o == 0 and st == lbe.LBE_OK
+    assert steps_g[0] == steps_o
+    mg, mo = g.moments(mean_field=True), o.moments()
+    for k in ("n", "T", "nbar"):
+        assert nrel(mg[k], mo[k]) <= 1e-11, k
+    # the discrete steady state keeps a truncation-level radial velocity (largest in the wall
+    # cells, ~1e-4 of the thermal speed here); both sides have the same one
+    print("spurious u_r", np.abs(mo["u_r"]).max(), flush=True)
+    assert np.abs(mg["u_r"] - mo["u_r"]).max() <= 1e-11
+    n = mg["n"]
+    assert n[0] < n[len(n) // 2] and n[-1] < n[len(n) // 2]

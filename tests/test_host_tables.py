@@ -37,6 +37,7 @@ BAD = [
     dict(n_expand=(4, 0, 0)), dict(cfl=0.0), dict(t_wall_outer=0.0), dict(r_outer=0.5),
     dict(geometry=1, u_wall_inner=0.1), dict(geometry=3), dict(geometry=-1),
     dict(geometry=1, u_wall_inner=0.0, reduced=1), dict(reduced=2), dict(eta0=0.01, kn=100.0),  # C < 1
+    dict(phi_a=float("nan")), dict(phi_a=float("inf")),
 ]
 
 
@@ -159,6 +160,36 @@ def test_ball_cylinder_volume_elliptic_matches_slice_integral():
     p = dict(workloads.FOURIER_SPH)
     for R, b in ((1.0, 0.8), (1.0, 1.2), (1.3, 1.05), (1.0, 1.31)):
         assert lbe.tables(p, 9, [s, R, b])[0] == pytest.approx(oracle.vol_sph(s, R, b), rel=1e-14, abs=1e-17)
+
+
+@pytest.mark.parametrize("geometry", [0, 1, 2])
+def test_mean_field_potential_matches_oracle(geometry):
+    """The tail integral U(r; s): closed forms (plane, sphere) and the graded theta rule (cylinder)
+    against the oracle's adaptive quadrature about the point."""
+    p = workloads.attraction_case(geometry, phi_a=0.7)
+    sig = lbe.tables(p, 13, [2.0, 2.0])  # any point: checks the call
+    assert sig.shape == (1,)
+    C = oracle.confinement(p["eta0"], p["kn"])
+    sigma = (p["r_outer"] - p["r_inner"]) / C
+    pts = [(0.0, 2.5), (0.3, 1.9), (1.0, 1.0), (2.0, 1.5), (3.3, 4.1), (5.0, 9.0), (9.0, 5.0), (1.7, 1.2),
+           (4.0, 4.0 + 1e-9), (50.0, 51.5), (51.5, 50.0)]
+    for r, s in pts:
+        if geometry == 2 and r == 0.0:
+            continue
+        u = lbe.tables(p, 13, [s * sigma, r * sigma])[0]
+        ref = oracle.mf_potential(geometry, sigma, 0.7, r * sigma, s * sigma)
+        assert abs(u - ref) <= 3e-14 * 0.7 * sigma ** 3 + 1e-14 * abs(ref), (geometry, r, s, u, ref)
+
+
+@pytest.mark.parametrize("geometry", [0, 1, 2])
+def test_mean_field_weights_match_oracle(geometry):
+    for kw in (dict(), dict(C=10.0, R_L=5.0, nr=90, phi_a=-0.3)):
+        p = workloads.attraction_case(geometry, **kw)
+        nr = p["nr"]
+        A = lbe.tables(p, 12).reshape(nr, nr)
+        Ao = oracle.Solver(workloads.oracle_params(p)).attraction()
+        assert np.abs(A - Ao).max() < 1e-13 * np.abs(Ao).max(), np.abs(A - Ao).max()
+    assert not lbe.tables(dict(p, phi_a=0.0), 12).any()
 
 
 def test_sweep_generator_is_seeded_and_valid():

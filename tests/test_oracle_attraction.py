@@ -141,7 +141,7 @@ def cylinder_axis_polar(r, s, sigma, phi_a):
     return float(mp.quad(lambda rho: rho * inner(rho), pts))
 
 
-CYL_POINTS = [(3.3, 4.1), (2.0, 1.5), (1.7, 1.2)]
+CYL_POINTS = [(3.3, 4.1), (2.0, 1.5), (1.7, 1.2), (1.5, 2.49)]  # the last: |r - s| close to sigma
 
 
 def pin_cylinder(lib=None, points=CYL_POINTS):
@@ -309,6 +309,29 @@ def test_attraction_matrix_entries():
         ref = n0 * (plane_closed_form(x - g["ri"][j + 1], sig, 0.5) - plane_closed_form(x - g["ri"][j], sig, 0.5))
         assert abs(A[i, j] - ref) < 1e-13 * n0, (i, j, A[i, j], ref)
     assert not np.any(oracle.Solver(dict(p, phi_a=0.0)).attraction())
+
+
+def test_attraction_thins_the_wall_layer():
+    """Gas at rest between plates at T = 1 (eta0 0.2): hard spheres pile up against a hard wall
+    (contact density above the middle), while the mean field pulls molecules back into the bulk,
+    so with phi_a = 0.5 the wall layer is thinner than the middle.  Both steady states keep the
+    mass of the uniform start."""
+    from paper_2403_15051_amd import workloads
+
+    p = workloads.attraction_case(2, nr=40, C=5.0)
+    prof = {}
+    for pa in (0.0, 0.5):
+        s = oracle.Solver(workloads.oracle_params(dict(p, phi_a=pa)))
+        m0 = s.mass()
+        rc, steps, res = s.run_to_steady(1e-8, 100000, 50)
+        assert rc == 0
+        assert abs(s.mass() / m0 - 1) < 1e-12
+        prof[pa] = s.moments()["n"]
+    n0, n1 = prof[0.0], prof[0.5]
+    mid = len(n0) // 2
+    assert n0[0] > n0[mid] + 0.05 and n0[-1] > n0[mid] + 0.05
+    assert n1[0] < n1[mid] and n1[-1] < n1[mid]
+    assert n0[0] - n1[0] > 0.05
 
 
 def test_rejects_non_finite_depth():
