@@ -140,3 +140,37 @@ def test_steady_rest_channel_with_attraction():
     assert np.abs(mg["u_r"] - mo["u_r"]).max() <= 1e-11
     n = mg["n"]
     assert n[0] < n[len(n) // 2] and n[-1] < n[len(n) // 2]
+
+
+def test_checkpoint_resume_with_attraction_is_bitwise():
+    ps = [workloads.attraction_case(2, flow="fourier"), workloads.attraction_case(1, flow="fourier", nr=32)]
+    a = lbe.Solver(ps)
+    a.step(37)
+    blob = a.checkpoint()
+    a.step(23)
+    b = lbe.Solver(ps)
+    b.restore(blob)
+    b.step(23)
+    for k in range(len(ps)):
+        assert np.array_equal(a.get_state(k), b.get_state(k)), k
+    # the fingerprint covers the tail depth: a context with another phi_a refuses the checkpoint
+    c = lbe.Solver([dict(p, phi_a=0.25) for p in ps])
+    with pytest.raises(lbe.LbeError) as e:
+        c.restore(blob)
+    assert e.value.status == lbe.LBE_EINVAL
+
+
+def test_static_workspace_with_attraction():
+    """lbe_init_static holds the mean-field weights in its static workspace like the other tables."""
+    p = workloads.attraction_case(0, flow="couette")
+    g = lbe.Solver(p, static_ws=True)
+    try:
+        o = oracle.Solver(workloads.oracle_params(p))
+        g.step(100)
+        g.sync()
+        o.step(100)
+        e = nrel(g.get_state(), o.get_f())
+        print("static workspace", e, flush=True)
+        assert e <= TOL
+    finally:
+        g.close()  # one static context per device at a time
