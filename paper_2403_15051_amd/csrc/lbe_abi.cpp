@@ -19,7 +19,7 @@
 namespace lbe {
 hipError_t launch_moments(const DevInstance* d, int ninst, int maxnr, int buf, int tab, int from_scratch, int only,
                           hipStream_t s);
-hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int src, int bsrc,
+hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxn0, int src, int bsrc,
                        hipStream_t s);
 hipError_t launch_base_copy(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxng, hipStream_t s);
 hipError_t launch_expand(const DevInstance* d, int inst, int nr, hipStream_t s);
@@ -65,6 +65,7 @@ struct lbe_ctx {
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int ninst = 0, maxnr = 0, maxnv = 0, maxng = 0;
+    int maxn0 = 0;  // largest radial expansion order (the node kernel projects orders below 8 itself)
     bool any_f32 = false;
     std::vector<int64_t> steps;
     std::vector<int32_t> active;
@@ -634,7 +635,7 @@ hipError_t run_stage(lbe_ctx* c, int src, int fn, int dst, double an, double bs,
     int a = -1, b = -1, x = -1, y = -1;
     hipError_t e;
     if (c->timing) (void)hipEventRecord(next_event(c, &a), c->stream);
-    e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, src, bsrc, c->stream);
+    e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, src, bsrc, c->stream);
     if (e != hipSuccess) return e;
     if (c->timing) {
         (void)hipEventRecord(next_event(c, &b), c->stream);
@@ -683,7 +684,7 @@ hipError_t launch_steps_group(lbe_ctx* c, int q, int nsteps, hipStream_t s)
     hipError_t e = hipSuccess;
     for (int k = 0; k < nsteps && e == hipSuccess; k++) {
         for (int j = 0; j < 3 && e == hipSuccess; j++) {
-            e = launch_node(c->dev_desc, il, cnt, mnr, st[j].src, st[j].bsrc, s);
+            e = launch_node(c->dev_desc, il, cnt, mnr, c->maxn0, st[j].src, st[j].bsrc, s);
             if (e == hipSuccess)
                 e = launch_stage(c->dev_desc, c->dev_items + c->item_off[q], c->item_cnt[q], c->groups[q], st[j].src,
                                  st[j].fn, st[j].dst, st[j].an, st[j].bs, 0, st[j].bsrc, st[j].bfn, st[j].bdst, s);
@@ -972,6 +973,7 @@ lbe_status lbe_init(const lbe_params* p, int32_t n_inst, void* device_ws, size_t
                 return st;
             }
             c->maxnr = std::max(c->maxnr, c->tabs[k].nr);
+            c->maxn0 = std::max(c->maxn0, c->tabs[k].prm.n_expand[0]);
             c->maxnv = std::max(c->maxnv, c->tabs[k].nv);
             c->maxng = std::max(c->maxng, c->tabs[k].n0 + c->tabs[k].n1 + c->tabs[k].n2);
             if (c->tabs[k].prm.precision == LBE_FP32_STORE) c->any_f32 = true;
@@ -1234,7 +1236,7 @@ lbe_status lbe_moments(lbe_ctx* c, int32_t inst, double* host_out, int64_t cap)
     c->active[inst] = 1;
     st = upload_flags(c);
     if (st == LBE_OK)
-        st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "moments pass");
+        st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, 0, 0, c->stream), "moments pass");
     std::vector<double> node((size_t)d.nr * kNodeStride);
     if (st == LBE_OK)
         st = dev_err(c, hipMemcpyAsync(node.data(), d.node, node.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -1637,7 +1639,7 @@ lbe_status lbe_set_state(lbe_ctx* c, int32_t inst, const double* host_f, int64_t
     st = upload_flags(c);
     if (st == LBE_OK)
         st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 1, inst, c->stream), "moments");
-    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, 0, 0, c->stream), "node");
     if (st == LBE_OK) st = dev_err(c, launch_rebase(c->dev_desc, inst, d.nr, c->stream), "rebase");
     if (st == LBE_OK)
         st = dev_err(c, launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, inst, c->stream), "moments");
@@ -1761,7 +1763,7 @@ lbe_status lbe_targets(lbe_ctx* c, float* dev_t, int64_t cap_rows)
     std::vector<int32_t> saved = c->active;
     std::fill(c->active.begin(), c->active.end(), 1);
     st = upload_flags(c);
-    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node pass");
+    if (st == LBE_OK) st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, 0, 0, c->stream), "node pass");
     std::vector<float> out((size_t)rows * 5);
     const int fields[5] = {NF_N, NF_U1, NF_T, NF_Q0, NF_P01};
     for (int k = 0; k < c->ninst && st == LBE_OK; k++) {
@@ -1808,7 +1810,7 @@ hipError_t build_warm_state(lbe_ctx* c)
     if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 2, -1, c->stream);
     if (c->any_f32) {
         if (e == hipSuccess) e = launch_mass(c->dev_desc, c->ninst, -2, c->dev_mass, c->stream, c->dev_mask);
-        if (e == hipSuccess) e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream);
+        if (e == hipSuccess) e = launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, 0, 0, c->stream);
         if (e == hipSuccess) e = launch_rebase_masked(c->dev_desc, c->ninst, c->maxnr, c->dev_mask, c->stream);
         if (e == hipSuccess) e = launch_moments(c->dev_desc, c->ninst, c->maxnr, 0, 0, 0, -1, c->stream);
     }
@@ -1949,7 +1951,7 @@ lbe_status lbe_autotune(lbe_ctx* c, int32_t reps, double* out, int64_t cap, int3
     }
     if (st != LBE_OK) return st;
     // coefficients of the state, so that the timed launches see the real data
-    st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, 0, 0, c->stream), "node");
+    st = dev_err(c, launch_node(c->dev_desc, nullptr, c->ninst, c->maxnr, c->maxn0, 0, 0, c->stream), "node");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e0), "event");
     if (st == LBE_OK) st = dev_err(c, hipEventCreate(&e1), "event");

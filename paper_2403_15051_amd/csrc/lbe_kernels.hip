@@ -1,11 +1,11 @@
 // Device kernels of liblbe (gfx950; FP64 arithmetic, f stored in FP64 or as FP32 deviations).
 //
-// One RK stage of every instance is three launches:
+// One RK stage of every instance is two launches:
 //   k_node  - per-node coefficients from the moment sums of the stage input (eqs. (macro_def),
-//             (fm), (chi), (viscosity)-(tau), (prandtl)), 4th-order radial gradients (Sec. III)
-//             and, in two extra blocks, the wall densities of diffuse reflection (zero net mass
-//             flux through each wall);
-//   k_proj  - the half-range equilibrium projection coefficients of every node (Sec. III.C);
+//             (fm), (chi), (viscosity)-(tau), (prandtl)), 4th-order radial gradients (Sec. III),
+//             the half-range equilibrium projection coefficients (Sec. III.C; k_proj computes
+//             them alone for node blocks written otherwise) and, in two extra blocks, the wall
+//             densities of diffuse reflection (zero net mass flux through each wall);
 //   k_stage - per launch group (instances sharing a velocity set), one workgroup per tile of
 //             consecutive nodes x velocity slice: WENO-5 fluxes in flux form (Sec. II.B/II.C),
 //             the momentum-derivative contractions (eqs. (force1)/(force2)) as FP64 MFMA tiles
@@ -320,6 +320,9 @@ __device__ inline int xcd_item(int b, int n)
 
 // ------------------------------------------------------------------ node kernel
 
+template <int NH>
+__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane);
+
 // ilist (may be null): the instances of grid row y are ilist[y] (one launch group's instances).
 __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist,
                                                  int src, int bsrc)
@@ -565,6 +568,15 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         full_coeffs<kMaxN>(m.u[1], T, I.N1, nd + NF_C1);
         full_coeffs<kMaxN>(m.u[2], T, I.N2, nd + NF_C2);
     }
+    // half-range projection coefficients of the chunk's nodes (Sec. III.C) for expansion orders
+    // N0 < 8, one wave per node at the node's u_r and T (in LDS since the barrier above), as k_proj
+    // computes them; higher orders are left to k_proj (their register-resident form would lower
+    // this kernel's occupancy)
+    if (I.N0 < 8) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int k = wave; k < c1 - c0; k += kBlock / 64)
+            proj_node<8>(I, smac[k].u[0], smac[k].T, I.node + (size_t)(c0 + k) * kNodeStride, lane);
+    }
 }
 
 // Half-range projection coefficients I_l^+- (Sec. III.C) of one node by one wave.  For |u| <= 2
@@ -579,9 +591,8 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 typedef const __attribute__((address_space(4))) double* cdptr;
 static_assert(kProjGauss == 32, "the projection's Gauss rule takes one half of the wave per side");
 template <int NH>
-__device__ inline void proj_node(const DevInstance& I, double* nd, int lane)
+__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane)
 {
-    const double u = nd[NF_U0], T = nd[NF_T];
     const int N0 = I.N0, M = I.M0, npan = M / 16;
     const double reach = 9.6 * sqrt(T), c = kInvSqrt2Pi / sqrt(T), inv2T = 1 / (2 * T);
     const cdptr q = (cdptr)I.qrec0;  // read-only in the kernel: scalar loads
@@ -661,20 +672,22 @@ __device__ inline void proj_node(const DevInstance& I, double* nd, int lane)
     }
 }
 
-// Projection coefficients of every node (one wave per node).  Runs after k_node (needs u_r and
-// T of the node).
-__global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist)
+// Projection coefficients of every node (one wave per node) from the node blocks' u_r and T, for
+// the instances with expansion order N0 >= min_n0: after k_node (which does N0 < 8 itself) with
+// min_n0 = 8, and with min_n0 = 0 for node blocks written otherwise (the warm start's profiles).
+__global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist,
+                                                 int min_n0)
 {
     const DevInstance& I = insts[ilist ? ilist[blockIdx.y] : blockIdx.y];
-    if (!I.flags[1]) return;
+    if (!I.flags[1] || I.N0 < min_n0) return;
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (i >= I.nr) return;
     double* nd = I.node + (size_t)i * kNodeStride;
     if (I.N0 < 8)
-        proj_node<8>(I, nd, lane);
+        proj_node<8>(I, nd[NF_U0], nd[NF_T], nd, lane);
     else
-        proj_node<kMaxN + 1>(I, nd, lane);
+        proj_node<kMaxN + 1>(I, nd[NF_U0], nd[NF_T], nd, lane);
 }
 
 // ------------------------------------------------------------------ stage kernel
@@ -2096,14 +2109,14 @@ hipError_t launch_rebase_masked(const DevInstance* d, int ninst, int maxnr, cons
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int src, int bsrc,
+hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, int maxnr, int maxn0, int src, int bsrc,
                        hipStream_t s)
 {
     const int nchunks = (maxnr + kNodeChunk - 1) / kNodeChunk;
     hipLaunchKernelGGL(k_node, dim3(nchunks + 2, ninst), dim3(kBlock), 0, s, d, ilist, src, bsrc);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, ilist);
+    if (e != hipSuccess || maxn0 < 8) return e;
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, ilist, 8);
     return hipGetLastError();
 }
 
@@ -2180,7 +2193,7 @@ hipError_t launch_residual(const DevInstance* d, int ninst, hipStream_t s)
 
 hipError_t launch_proj(const DevInstance* d, int ninst, int maxnr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, nullptr);
+    hipLaunchKernelGGL(k_proj, dim3((maxnr + 3) / 4, ninst), dim3(kBlock), 0, s, d, nullptr, 0);
     return hipGetLastError();
 }
 

@@ -137,6 +137,21 @@ def test_uneven_batch_matches_independent_solves():
         compare_profiles(g.moments(k), o.moments(), ctx=f"batch{k}")
 
 
+def test_high_radial_expansion_order_in_a_batch():
+    """Radial expansion orders N0 >= 8 take the separate projection launch after the node kernel
+    (which projects lower orders itself); a batch mixing both matches the oracle."""
+    ps = [dict(workloads.FOURIER_CYL, nr=24, q_radial=12, q_t1=6, q_t2=4, n_expand=(11, 0, 0)), SMALL_CYL]
+    g = lbe.Solver(ps)
+    g.step(50)
+    for k, p in enumerate(ps):
+        o = oracle.Solver(p)
+        o.step(50)
+        e = nrel(g.get_state(k), o.get_f())
+        print("N0 batch", k, e, flush=True)
+        assert e <= TOL, k
+    assert g.info(0)["N0"] == 11
+
+
 def test_run_to_steady_matches_oracle():
     p = dict(workloads.COUETTE_SMALL, nr=16, q_t2=4, kn=0.3)
     o = oracle.Solver(p)
