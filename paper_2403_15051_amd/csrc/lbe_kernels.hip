@@ -223,27 +223,6 @@ __device__ inline double f_at(const DevInstance& I, int buf, int tab, int row, i
     return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
 }
 
-// The same with the velocity's axis indices already known.
-__device__ inline double f_at3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2)
-{
-    if (!I.f32) return I.f[buf][(ptrdiff_t)row * I.nv + v];
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
-    const double* b = base_row(I, tab, row);
-    return (double)((const float*)I.f[buf])[e] + b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]);
-}
-
-__device__ inline void f_put3(const DevInstance& I, int buf, int tab, int row, int v, int i0, int i1, int i2,
-                              double val)
-{
-    if (!I.f32) {
-        I.f[buf][(ptrdiff_t)row * I.nv + v] = val;
-        return;
-    }
-    const ptrdiff_t e = (ptrdiff_t)row * I.nv + f32_slot(v, I.n0, I.nv / I.n0);
-    const double* b = base_row(I, tab, row);
-    ((float*)I.f[buf])[e] = (float)(val - b[i0] * (b[I.n0 + i1] * b[I.n0 + I.n1 + i2]));
-}
-
 __device__ inline void f_put(const DevInstance& I, int buf, int tab, int row, int v, double val)
 {
     if (!I.f32) {
@@ -318,6 +297,14 @@ __device__ inline int xcd_item(int b, int n)
     return x * q + min(x, r) + j;
 }
 
+// Quotients by a divisor fixed for a block: q = umulhi(x, m) with m = ceil(2^32 / d), exact while
+// x d < 2^32 (velocity indices: x < 2e6, d <= 200).
+struct FastDiv {
+    unsigned d, m;
+    __device__ explicit FastDiv(int dd) : d((unsigned)dd), m(dd > 1 ? 0xFFFFFFFFu / (unsigned)dd + 1u : 0u) {}
+    __device__ int div(int x) const { return d > 1 ? (int)__umulhi((unsigned)x, m) : x; }
+};
+
 // ------------------------------------------------------------------ node kernel
 
 template <int NH>
@@ -343,9 +330,32 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // Each thread takes kWallBatch velocities at a time and issues all their loads before the
         // arithmetic (one dependent round trip per batch instead of per velocity); the leaving
         // velocities of the left wall are those with radial index i0 >= n0/2 (p_r < 0), of the right
-        // wall those with i0 < n0/2, so only that half is visited.
+        // wall those with i0 < n0/2, so only that half is visited.  Fixed per block: the three rows
+        // next to the wall, their base factors (FP32 storage; the ghost rows share the wall row's)
+        // and the FP32 rows' column grouping; per velocity, its axis indices (multiply-high
+        // quotients) and its place in an FP32 row, the same in every row.
         const int left = bx == nchunks;
-        const int hq = n0 >> 1, nhalf = I.nv >> 1;
+        const int hq = n0 >> 1, nhalf = I.nv >> 1, nv = I.nv, n01 = n0 + n1;
+        const int r0 = left ? 0 : nr - 1, dr1 = left ? 1 : -1;
+        const bool f32 = I.f32 != 0;
+        const int g = f32 ? f32_group(hq, nv / n0) : 1, lg = __builtin_ctz(g);
+        double* fd = I.f[src];
+        float* ff = (float*)I.f[src];
+        const double* bw[3];
+        for (int k = 0; k < 3; k++) bw[k] = f32 ? base_row(I, bsrc, r0 + k * dr1) : nullptr;
+        const FastDiv dhq(hq), dn0(n0), dn1(n1);
+        // place of velocity i0 + n0 col in an FP32 row (f32_slot with g a power of two)
+        auto slot = [&](int i0, int col) {
+            const int sgn = i0 >= hq ? 1 : 0, h = i0 - sgn * hq;
+            return h + hq * (col & (g - 1)) + g * hq * sgn + g * n0 * (col >> lg);
+        };
+        // f at row r0 + k dr1 (FP32: the stored deviation on top of the row's base factors)
+        auto fval = [&](int k, int v, int sl, int i0, int i1, int i2) -> double {
+            const ptrdiff_t row = (ptrdiff_t)(r0 + k * dr1) * nv;
+            if (!f32) return fd[row + v];
+            const double* bb = bw[k];
+            return (double)ff[row + sl] + bb[i0] * (bb[n0 + i1] * bb[n01 + i2]);
+        };
         double acc[1] = {0};
         for (int e0 = threadIdx.x; e0 < nhalf; e0 += kBlock * kWallBatch) {
             double fa[kWallBatch], fb[kWallBatch], fc[kWallBatch], pr[kWallBatch];
@@ -353,17 +363,17 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 #pragma unroll
             for (int u = 0; u < kWallBatch; u++) {
                 const int e = e0 + u * kBlock;
-                const int i0 = (left ? hq : 0) + e % hq, col = e / hq;
-                const int i1 = col % n1, i2 = col / n1, v = i0 + n0 * col;
+                const int col = dhq.div(e), i0 = (left ? hq : 0) + (e - col * hq);
+                const int i2 = dn1.div(col), i1 = col - i2 * n1, v = i0 + n0 * col;
                 // chi (the reduced distributions' second plane) carries no mass
                 use[u] = e < nhalf && !(I.reduced && i2 == 1);
                 pr[u] = I.p0[i0];
                 fa[u] = fb[u] = fc[u] = 0.0;
                 if (use[u]) {
-                    const int r0 = left ? 0 : nr - 1, dr1 = left ? 1 : -1;
-                    fa[u] = f_at3(I, src, bsrc, r0, v, i0, i1, i2);
-                    fb[u] = f_at3(I, src, bsrc, r0 + dr1, v, i0, i1, i2);
-                    fc[u] = f_at3(I, src, bsrc, r0 + 2 * dr1, v, i0, i1, i2);
+                    const int sl = f32 ? slot(i0, col) : 0;
+                    fa[u] = fval(0, v, sl, i0, i1, i2);
+                    fb[u] = fval(1, v, sl, i0, i1, i2);
+                    fc[u] = fval(2, v, sl, i0, i1, i2);
                 }
             }
 #pragma unroll
@@ -380,21 +390,30 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // ghost cells of this wall (cells -1, -2, or nr, nr + 1, stored in the two rows the
         // state buffers hold on each side): n_w g_w for entering velocities, the quadratic
         // extrapolation of the three nearest cells for leaving ones
-        for (int v0 = threadIdx.x; v0 < I.nv; v0 += kBlock * kWallBatch) {
-            double g1[kWallBatch], g2[kWallBatch];
+        const ptrdiff_t gr1 = (ptrdiff_t)(left ? -1 : nr) * nv, gr2 = (ptrdiff_t)(left ? -2 : nr + 1) * nv;
+        const double* gw = left ? I.gwl : I.gwr;
+        for (int v0 = threadIdx.x; v0 < nv; v0 += kBlock * kWallBatch) {
+            double g1[kWallBatch], g2[kWallBatch], bv[kWallBatch];
+            int sls[kWallBatch];
 #pragma unroll
             for (int u = 0; u < kWallBatch; u++) {
                 const int v = v0 + u * kBlock;
-                if (v >= I.nv) continue;
-                const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
+                g1[u] = g2[u] = bv[u] = 0.0;
+                sls[u] = 0;
+                if (v >= nv) continue;
+                const int col = dn0.div(v), i0 = v - col * n0;
+                const int i2 = dn1.div(col), i1 = col - i2 * n1;
+                const int sl = f32 ? slot(i0, col) : 0;
+                sls[u] = sl;
+                // the ghost rows' base is the wall row's
+                if (f32) bv[u] = bw[0][i0] * (bw[0][n0 + i1] * bw[0][n01 + i2]);
                 const bool entering = left ? i0 < hq : i0 >= hq;
                 if (entering) {
-                    g1[u] = g2[u] = nw * (left ? I.gwl[v] : I.gwr[v]);
+                    g1[u] = g2[u] = nw * gw[v];
                 } else {
-                    const int r0 = left ? 0 : nr - 1, dr1 = left ? 1 : -1;
-                    const double a = f_at3(I, src, bsrc, r0, v, i0, i1, i2);
-                    const double b = f_at3(I, src, bsrc, r0 + dr1, v, i0, i1, i2);
-                    const double c = f_at3(I, src, bsrc, r0 + 2 * dr1, v, i0, i1, i2);
+                    const double a = fval(0, v, sl, i0, i1, i2);
+                    const double b = fval(1, v, sl, i0, i1, i2);
+                    const double c = fval(2, v, sl, i0, i1, i2);
                     g1[u] = 3 * a - 3 * b + c;
                     g2[u] = 6 * a - 8 * b + 3 * c;
                 }
@@ -402,10 +421,14 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 #pragma unroll
             for (int u = 0; u < kWallBatch; u++) {
                 const int v = v0 + u * kBlock;
-                if (v >= I.nv) continue;
-                const int i0 = v % n0, i1 = (v / n0) % n1, i2 = v / (n0 * n1);
-                f_put3(I, src, bsrc, left ? -1 : nr, v, i0, i1, i2, g1[u]);
-                f_put3(I, src, bsrc, left ? -2 : nr + 1, v, i0, i1, i2, g2[u]);
+                if (v >= nv) continue;
+                if (!f32) {
+                    fd[gr1 + v] = g1[u];
+                    fd[gr2 + v] = g2[u];
+                } else {
+                    ff[gr1 + sls[u]] = (float)(g1[u] - bv[u]);
+                    ff[gr2 + sls[u]] = (float)(g2[u] - bv[u]);
+                }
             }
         }
         return;
