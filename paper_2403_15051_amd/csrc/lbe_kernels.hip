@@ -1318,17 +1318,26 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
         }
     }
     // other slices' columns of a plane (sphere: the d2 contraction runs over all i2)
+    // FP32: the rows' column grouping g of f32_slot (a power of two) and the split v = i0 + n0 col by
+    // a multiply-high quotient are uniform, so no integer division per velocity (measured slower
+    // in the FP64 form, which keeps the plain split)
     auto fill_other_slices = [&](int t, int buf) {
         double* pl = plane + buf * G.plane_sz;
-        for (int v = tid; v < nv; v += B)
-            if (v < vs0 || v >= vs1) {
-                double x = cell(it.i0 + t, (unsigned)(esz * (F32 ? f32_slot(v, n0, n1 * n2) : v)));
-                if constexpr (F32) {
+        if constexpr (F32) {
+            const int hq = n0 >> 1, g = f32_group(hq, n1 * n2), lg = __builtin_ctz(g);
+            const FastDiv dn0(n0);
+            for (int v = tid; v < nv; v += B)
+                if (v < vs0 || v >= vs1) {
+                    const int col = dn0.div(v), i0 = v - col * n0, sgn = i0 >= hq ? 1 : 0;
+                    const int e = (i0 - sgn * hq) + hq * (col & (g - 1)) + g * hq * sgn + g * n0 * (col >> lg);
                     const int wr = t + 3;  // cell i0 + t
-                    x += sbase[wr * bst + v % n0] * sbase[wr * bst + n0 + v / n0];  // sphere: cp0 = 0
+                    pl[i0 + cs * col] = cell(it.i0 + t, (unsigned)(esz * e)) +
+                                        sbase[wr * bst + i0] * sbase[wr * bst + n0 + col];  // sphere: cp0 = 0
                 }
-                pl[(v % n0) + cs * (v / n0)] = x;
-            }
+        } else {
+            for (int v = tid; v < nv; v += B)
+                if (v < vs0 || v >= vs1) pl[(v % n0) + cs * (v / n0)] = cell(it.i0 + t, (unsigned)(esz * v));
+        }
     };
     if (sph && G.S > 1) {
         fill_other_slices(0, 0);
