@@ -308,7 +308,7 @@ struct FastDiv {
 // ------------------------------------------------------------------ node kernel
 
 template <int NH>
-__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane);
+__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane, double gx, double gwt);
 
 // ilist (may be null): the instances of grid row y are ilist[y] (one launch group's instances).
 __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__ insts, const int32_t* __restrict__ ilist,
@@ -597,8 +597,9 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     // this kernel's occupancy)
     if (I.N0 < 8) {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const double gx = I.pgx0[lane & (kProjGauss - 1)], gwt = I.pgw0[lane & (kProjGauss - 1)];
         for (int k = wave; k < c1 - c0; k += kBlock / 64)
-            proj_node<8>(I, smac[k].u[0], smac[k].T, I.node + (size_t)(c0 + k) * kNodeStride, lane);
+            proj_node<8>(I, smac[k].u[0], smac[k].T, I.node + (size_t)(c0 + k) * kNodeStride, lane, gx, gwt);
     }
 }
 
@@ -613,8 +614,10 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
 // NH bounds N0 + 1; with NH <= 8 the recurrence coefficients stay in scalar registers.
 typedef const __attribute__((address_space(4))) double* cdptr;
 static_assert(kProjGauss == 32, "the projection's Gauss rule takes one half of the wave per side");
+// gx, gwt: the lane's node and weight of the 32-point rule, I.pgx0[lane % 32] and I.pgw0[lane % 32]
+// (loaded once by a caller that projects several nodes).
 template <int NH>
-__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane)
+__device__ inline void proj_node(const DevInstance& I, double u, double T, double* nd, int lane, double gx, double gwt)
 {
     const int N0 = I.N0, M = I.M0, npan = M / 16;
     const double reach = 9.6 * sqrt(T), c = kInvSqrt2Pi / sqrt(T), inv2T = 1 / (2 * T);
@@ -638,9 +641,9 @@ __device__ inline void proj_node(const DevInstance& I, double u, double T, doubl
     if (REG) {
         const double sT = sqrt(T), bsh = u / sT;
         if (fabs(bsh) <= 2.0) {
-            const int side = lane >> 5, m = lane & (kProjGauss - 1);
-            const double xs = I.pgx0[m], bb = side ? -bsh : bsh;
-            const double gw = I.pgw0[m] * exp(fma(bb, xs, -0.5 * bb * bb));
+            const int side = lane >> 5;
+            const double xs = gx, bb = side ? -bsh : bsh;
+            const double gw = gwt * exp(fma(bb, xs, -0.5 * bb * bb));
             const double x = sT * xs;
             double acc[8];
             double pm = 0.0, p = 1.0;
@@ -708,9 +711,9 @@ __global__ void __launch_bounds__(kBlock) k_proj(const DevInstance* __restrict__
     if (i >= I.nr) return;
     double* nd = I.node + (size_t)i * kNodeStride;
     if (I.N0 < 8)
-        proj_node<8>(I, nd[NF_U0], nd[NF_T], nd, lane);
+        proj_node<8>(I, nd[NF_U0], nd[NF_T], nd, lane, I.pgx0[lane & (kProjGauss - 1)], I.pgw0[lane & (kProjGauss - 1)]);
     else
-        proj_node<kMaxN + 1>(I, nd[NF_U0], nd[NF_T], nd, lane);
+        proj_node<kMaxN + 1>(I, nd[NF_U0], nd[NF_T], nd, lane, 0.0, 0.0);
 }
 
 // ------------------------------------------------------------------ stage kernel
