@@ -1056,8 +1056,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // earlier than in the FP64 path.
 // VPT: velocities per lane (1 or 2); RHS: write the right-hand side L(f) to the instance's
 // scratch instead of the RK combination (lbe_rhs); MT: MFMA tiles a wave holds over the node loop, 1 or 2 (the
-// launch requires ntiles <= MT * waves), or 0 for workgroups with more tiles (descriptors reread).
-template <int VPT, bool F32, bool RHS, int MT>
+// launch requires ntiles <= MT * waves), or 0 for workgroups with more tiles (descriptors reread);
+// SPH: the group's geometry is the sphere (its third contraction and sliced planes compile only there).
+template <int VPT, bool F32, bool RHS, int MT, bool SPH>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
                                                  int fn, int dst, double an, double bs, int bsrc, int bfn, int bdst)
@@ -1073,7 +1074,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     const int wh = G.wh;
     const bool pos = wave < wh;
     const int cs = n0 + 1;  // LDS column stride of the planes
-    const bool sph = G.geometry == LBE_SPH;
+    constexpr bool sph = SPH;
     const bool need_fn = an != 0.0;
     const double sigma = rhs ? 1.0 : bs * I.dt, bsv = rhs ? 0.0 : bs;
     const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
@@ -2155,7 +2156,7 @@ hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, in
     return hipGetLastError();
 }
 
-template <int VPT, bool F32>
+template <int VPT, bool F32, bool SPH>
 static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
                                  int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst,
                                  hipStream_t s)
@@ -2168,13 +2169,13 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
                            bdst);
     };
     if (rhs) {
-        if (mt == 1) go(k_stage<VPT, F32, true, 1>);
-        else if (mt == 2) go(k_stage<VPT, F32, true, 2>);
-        else go(k_stage<VPT, F32, true, 0>);
+        if (mt == 1) go(k_stage<VPT, F32, true, 1, SPH>);
+        else if (mt == 2) go(k_stage<VPT, F32, true, 2, SPH>);
+        else go(k_stage<VPT, F32, true, 0, SPH>);
     } else {
-        if (mt == 1) go(k_stage<VPT, F32, false, 1>);
-        else if (mt == 2) go(k_stage<VPT, F32, false, 2>);
-        else go(k_stage<VPT, F32, false, 0>);
+        if (mt == 1) go(k_stage<VPT, F32, false, 1, SPH>);
+        else if (mt == 2) go(k_stage<VPT, F32, false, 2, SPH>);
+        else go(k_stage<VPT, F32, false, 0, SPH>);
     }
     return hipGetLastError();
 }
@@ -2182,14 +2183,20 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
                         int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst, hipStream_t s)
 {
-    const int key = G.vpt * 2 + (G.f32 ? 1 : 0);
+    const int key = (G.geometry == LBE_SPH ? 8 : 0) + G.vpt * 2 + (G.f32 ? 1 : 0);
+#define LBE_GO(V, F, S) launch_stage_t<V, F, S>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s)
     switch (key) {
-        case 2: return launch_stage_t<1, false>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
-        case 3: return launch_stage_t<1, true>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
-        case 4: return launch_stage_t<2, false>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
-        case 5: return launch_stage_t<2, true>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s);
+        case 2: return LBE_GO(1, false, false);
+        case 3: return LBE_GO(1, true, false);
+        case 4: return LBE_GO(2, false, false);
+        case 5: return LBE_GO(2, true, false);
+        case 10: return LBE_GO(1, false, true);
+        case 11: return LBE_GO(1, true, true);
+        case 12: return LBE_GO(2, false, true);
+        case 13: return LBE_GO(2, true, true);
         default: return hipErrorInvalidValue;
     }
+#undef LBE_GO
 }
 
 hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ninst, const StageGroup& G, hipStream_t s)
@@ -2201,15 +2208,16 @@ hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ni
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-#define LBE_STAGE_FNS(MT)                                                                                   \
-    (const void*)k_stage<1, false, false, MT>, (const void*)k_stage<2, false, false, MT>,                   \
-        (const void*)k_stage<1, true, false, MT>, (const void*)k_stage<2, true, false, MT>,                 \
-        (const void*)k_stage<1, false, true, MT>, (const void*)k_stage<2, false, true, MT>,                 \
-        (const void*)k_stage<1, true, true, MT>, (const void*)k_stage<2, true, true, MT>
-    const void* fns[24] = {LBE_STAGE_FNS(0), LBE_STAGE_FNS(1), LBE_STAGE_FNS(2)};
+#define LBE_STAGE_FNS(MT, SPH)                                                                              \
+    (const void*)k_stage<1, false, false, MT, SPH>, (const void*)k_stage<2, false, false, MT, SPH>,         \
+        (const void*)k_stage<1, true, false, MT, SPH>, (const void*)k_stage<2, true, false, MT, SPH>,       \
+        (const void*)k_stage<1, false, true, MT, SPH>, (const void*)k_stage<2, false, true, MT, SPH>,       \
+        (const void*)k_stage<1, true, true, MT, SPH>, (const void*)k_stage<2, true, true, MT, SPH>
+    const void* fns[48] = {LBE_STAGE_FNS(0, false), LBE_STAGE_FNS(1, false), LBE_STAGE_FNS(2, false),
+                           LBE_STAGE_FNS(0, true),  LBE_STAGE_FNS(1, true),  LBE_STAGE_FNS(2, true)};
 #undef LBE_STAGE_FNS
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 24 && e == hipSuccess; k++)
+    for (int k = 0; k < 48 && e == hipSuccess; k++)
         e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
