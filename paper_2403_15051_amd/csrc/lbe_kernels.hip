@@ -1057,8 +1057,10 @@ __global__ void __launch_bounds__(kBlock) k_stage_image(const DevInstance* __res
 // VPT: velocities per lane (1 or 2); RHS: write the right-hand side L(f) to the instance's
 // scratch instead of the RK combination (lbe_rhs); MT: MFMA tiles a wave holds over the node loop, 1 or 2 (the
 // launch requires ntiles <= MT * waves), or 0 for workgroups with more tiles (descriptors reread);
-// SPH: the group's geometry is the sphere (its third contraction and sliced planes compile only there).
-template <int VPT, bool F32, bool RHS, int MT, bool SPH>
+// GK: the group's kind, 0 cylinder or plates with three velocity axes, 1 sphere (its third contraction
+// and sliced planes), 2 cylinder or plates with p_z integrated out (reduced): each kind's code compiles
+// only into its own variants, which keeps the others' registers free.
+template <int VPT, bool F32, bool RHS, int MT, int GK>
 __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ insts,
                                                  const WorkItem* __restrict__ items, const StageGroup G, int src,
                                                  int fn, int dst, double an, double bs, int bsrc, int bfn, int bdst)
@@ -1074,7 +1076,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     const int wh = G.wh;
     const bool pos = wave < wh;
     const int cs = n0 + 1;  // LDS column stride of the planes
-    constexpr bool sph = SPH;
+    constexpr bool sph = GK == 1, reduced = GK == 2;
     const bool need_fn = an != 0.0;
     const double sigma = rhs ? 1.0 : bs * I.dt, bsv = rhs ? 0.0 : bs;
     const int vs0 = it.slice * G.nvs, vs1 = vs0 + G.nvs;
@@ -1224,7 +1226,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
     for (int e = tid; e < G.ncols16 * 16; e += B) {
         const int col = e >> 4, m = e & 15;
         double val = 0.0;
-        if (col < ncol && m < 9 && G.reduced && (c_s0 + col) / n1 == 1) {
+        if (col < ncol && m < 9 && reduced && (c_s0 + col) / n1 == 1) {
             // a chi column (p_z integrated out): chi is int p_z^2 f, so it adds to the z-energy
             // (factor 4) and, as |y|^2, to the energy fluxes (6: y_r |y|^2, 7: y_1 |y|^2)
             const double y1 = pc1[col] - csh[1];
@@ -1605,7 +1607,7 @@ __global__ void __launch_bounds__(1024) k_stage(const DevInstance* __restrict__ 
                 const double a2 = fma(cf[SC_E22], Y2, cf[SC_G2]);
                 const double hy = fma(cf[SC_H2], Y2, fma(cf[SC_H1], Y1, cf[SC_H0] * Y0));
                 double Pc = fma(yy[j], hy, fma(Y2, a2, fma(Y1, a1, fma(Y0, a0, cf[SC_C0]))));
-                if (G.reduced) {
+                if (reduced) {
                     // reduced distributions (y_z = 0): the terms in xi_z^2 of the cubic, at xi_z^2 = T
                     // for phi and 3T for chi (chi's own factor T is its equilibrium factor g2 = T)
                     const double s2 = (gx2[j] != n0 + n1 ? 3.0 : 1.0) * cf[SC_T];
@@ -2156,7 +2158,7 @@ hipError_t launch_node(const DevInstance* d, const int32_t* ilist, int ninst, in
     return hipGetLastError();
 }
 
-template <int VPT, bool F32, bool SPH>
+template <int VPT, bool F32, int GK>
 static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src,
                                  int fn, int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst,
                                  hipStream_t s)
@@ -2169,13 +2171,13 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
                            bdst);
     };
     if (rhs) {
-        if (mt == 1) go(k_stage<VPT, F32, true, 1, SPH>);
-        else if (mt == 2) go(k_stage<VPT, F32, true, 2, SPH>);
-        else go(k_stage<VPT, F32, true, 0, SPH>);
+        if (mt == 1) go(k_stage<VPT, F32, true, 1, GK>);
+        else if (mt == 2) go(k_stage<VPT, F32, true, 2, GK>);
+        else go(k_stage<VPT, F32, true, 0, GK>);
     } else {
-        if (mt == 1) go(k_stage<VPT, F32, false, 1, SPH>);
-        else if (mt == 2) go(k_stage<VPT, F32, false, 2, SPH>);
-        else go(k_stage<VPT, F32, false, 0, SPH>);
+        if (mt == 1) go(k_stage<VPT, F32, false, 1, GK>);
+        else if (mt == 2) go(k_stage<VPT, F32, false, 2, GK>);
+        else go(k_stage<VPT, F32, false, 0, GK>);
     }
     return hipGetLastError();
 }
@@ -2183,17 +2185,22 @@ static hipError_t launch_stage_t(const DevInstance* d, const WorkItem* items, in
 hipError_t launch_stage(const DevInstance* d, const WorkItem* items, int nitems, const StageGroup& G, int src, int fn,
                         int dst, double an, double bs, int rhs, int bsrc, int bfn, int bdst, hipStream_t s)
 {
-    const int key = (G.geometry == LBE_SPH ? 8 : 0) + G.vpt * 2 + (G.f32 ? 1 : 0);
-#define LBE_GO(V, F, S) launch_stage_t<V, F, S>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s)
+    const int gk = G.geometry == LBE_SPH ? 1 : G.reduced ? 2 : 0;
+    const int key = gk * 8 + G.vpt * 2 + (G.f32 ? 1 : 0);
+#define LBE_GO(V, F, K) launch_stage_t<V, F, K>(d, items, nitems, G, src, fn, dst, an, bs, rhs, bsrc, bfn, bdst, s)
     switch (key) {
-        case 2: return LBE_GO(1, false, false);
-        case 3: return LBE_GO(1, true, false);
-        case 4: return LBE_GO(2, false, false);
-        case 5: return LBE_GO(2, true, false);
-        case 10: return LBE_GO(1, false, true);
-        case 11: return LBE_GO(1, true, true);
-        case 12: return LBE_GO(2, false, true);
-        case 13: return LBE_GO(2, true, true);
+        case 2: return LBE_GO(1, false, 0);
+        case 3: return LBE_GO(1, true, 0);
+        case 4: return LBE_GO(2, false, 0);
+        case 5: return LBE_GO(2, true, 0);
+        case 10: return LBE_GO(1, false, 1);
+        case 11: return LBE_GO(1, true, 1);
+        case 12: return LBE_GO(2, false, 1);
+        case 13: return LBE_GO(2, true, 1);
+        case 18: return LBE_GO(1, false, 2);
+        case 19: return LBE_GO(1, true, 2);
+        case 20: return LBE_GO(2, false, 2);
+        case 21: return LBE_GO(2, true, 2);
         default: return hipErrorInvalidValue;
     }
 #undef LBE_GO
@@ -2208,16 +2215,17 @@ hipError_t launch_stage_image(const DevInstance* d, const int32_t* ilist, int ni
 hipError_t set_stage_smem_limit()
 {
     const int bytes = 160 * 1024;
-#define LBE_STAGE_FNS(MT, SPH)                                                                              \
-    (const void*)k_stage<1, false, false, MT, SPH>, (const void*)k_stage<2, false, false, MT, SPH>,         \
-        (const void*)k_stage<1, true, false, MT, SPH>, (const void*)k_stage<2, true, false, MT, SPH>,       \
-        (const void*)k_stage<1, false, true, MT, SPH>, (const void*)k_stage<2, false, true, MT, SPH>,       \
-        (const void*)k_stage<1, true, true, MT, SPH>, (const void*)k_stage<2, true, true, MT, SPH>
-    const void* fns[48] = {LBE_STAGE_FNS(0, false), LBE_STAGE_FNS(1, false), LBE_STAGE_FNS(2, false),
-                           LBE_STAGE_FNS(0, true),  LBE_STAGE_FNS(1, true),  LBE_STAGE_FNS(2, true)};
+#define LBE_STAGE_FNS(MT, GK)                                                                               \
+    (const void*)k_stage<1, false, false, MT, GK>, (const void*)k_stage<2, false, false, MT, GK>,           \
+        (const void*)k_stage<1, true, false, MT, GK>, (const void*)k_stage<2, true, false, MT, GK>,         \
+        (const void*)k_stage<1, false, true, MT, GK>, (const void*)k_stage<2, false, true, MT, GK>,         \
+        (const void*)k_stage<1, true, true, MT, GK>, (const void*)k_stage<2, true, true, MT, GK>
+    const void* fns[72] = {LBE_STAGE_FNS(0, 0), LBE_STAGE_FNS(1, 0), LBE_STAGE_FNS(2, 0),
+                           LBE_STAGE_FNS(0, 1), LBE_STAGE_FNS(1, 1), LBE_STAGE_FNS(2, 1),
+                           LBE_STAGE_FNS(0, 2), LBE_STAGE_FNS(1, 2), LBE_STAGE_FNS(2, 2)};
 #undef LBE_STAGE_FNS
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 48 && e == hipSuccess; k++)
+    for (int k = 0; k < 72 && e == hipSuccess; k++)
         e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e;
 }
