@@ -6,7 +6,9 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -704,11 +706,21 @@ static void mf_weights(InstanceTables* t)
     const lbe_params& p = t->prm;
     const ld n0 = 6 * (ld)p.eta0 / (kPi * (ld)t->sigma * t->sigma * t->sigma);
     t->amf.assign((size_t)nr * nr, 0.0);
-    std::vector<double> U(nr + 1);
-    for (int i = 0; i < nr; i++) {
-        for (int j = 0; j <= nr; j++) U[j] = mf_potential(p.geometry, t->sigma, p.phi_a, t->r[i], t->ri[j]);
-        for (int j = 0; j < nr; j++) t->amf[(size_t)i * nr + j] = (double)(n0 * ((ld)U[j + 1] - U[j]));
-    }
+    // rows are independent: spread over host threads (each row's arithmetic is the same whatever the
+    // thread, so the weights do not depend on the thread count)
+    std::atomic<int> next{0};
+    auto rows = [&]() {
+        std::vector<double> U(nr + 1);
+        for (int i = next++; i < nr; i = next++) {
+            for (int j = 0; j <= nr; j++) U[j] = mf_potential(p.geometry, t->sigma, p.phi_a, t->r[i], t->ri[j]);
+            for (int j = 0; j < nr; j++) t->amf[(size_t)i * nr + j] = (double)(n0 * ((ld)U[j + 1] - U[j]));
+        }
+    };
+    const int nth = p.geometry == LBE_CYL ? std::max(1, std::min<int>(nr, (int)std::thread::hardware_concurrency())) : 1;
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nth; k++) pool.emplace_back(rows);
+    rows();
+    for (std::thread& th : pool) th.join();
 }
 
 // ------------------------------------------------------------------ instance set-up
