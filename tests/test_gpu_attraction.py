@@ -39,6 +39,10 @@ CASES = {
     "sphere, Fourier": workloads.attraction_case(1, flow="fourier", nr=32),
     "cylinder, repulsive tail": workloads.attraction_case(0, phi_a=-0.4, flow="fourier", C=7.0, nr=60),
     "plates, strong, wide": workloads.attraction_case(2, phi_a=1.0, eta0=0.1, C=10.0, nr=90, q=6),
+    # the paper's production set for cylinders, HHLB(7, 20) x HLB(7, 8) with p_z integrated out (640
+    # values per node), on its grid spacing sigma / 10 at C = 4
+    "cylinder, paper set": dict(workloads.attraction_case(0, flow="couette", C=4.0, nr=30, q=8), q_radial=20,
+                                cfl=workloads.paper_case("couette", 0, 0.2, 4, 1)["cfl"]),
 }
 
 
