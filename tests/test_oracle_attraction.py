@@ -11,7 +11,8 @@ about it, the cylinder's axial direction first); each pin reaches the same numbe
     value -2 a n with a = 2 pi sigma^3 phi_a / 3, i.e. Phi = -8 eta0 phi_a n);
   * the solver: Phi in a wide channel, the force within sigma of a wall (3 eta0 phi_a), its
     sign (into the fluid), Newton's third law in the plane, and the velocity moments of the
-    force term (mass 0, radial momentum n F, transverse momentum 0).
+    force term (mass 0, radial momentum n F, transverse momentum 0), and the steady channel's
+    momentum balance (the Enskog pressure gradient equals n F).
 Tests marked "mutant" plant a mistake in a copy of the oracle and check that a pin fails.
 """
 import math
@@ -334,6 +335,32 @@ def test_attraction_thins_the_wall_layer():
     assert n0[0] - n1[0] > 0.05
 
 
+def pin_steady_balance(lib=None):
+    """Steady gas at rest between plates with the mean field: the momentum equation leaves
+    d P / dx = n F, with P the local Enskog pressure n T (1 + 4 eta0 n chi) (n on the mean density),
+    so P minus the integral of n F from the first node is flat.  Here P varies by about 0.36 across
+    the channel; the balance holds to the truncation level that P keeps without the field (7e-4)."""
+    from paper_2403_15051_amd import workloads
+
+    p = workloads.attraction_case(2, nr=40, C=5.0)
+    s = oracle.Solver(workloads.oracle_params(p), lib=lib)
+    rc, steps, res = s.run_to_steady(1e-8, 100000, 50)
+    assert rc == 0
+    m = s.moments()
+    _, F = s.mean_field()
+    n, T, chi = m["n"], m["T"], m["chi"]
+    P = n * T * (1 + 4 * p["eta0"] * n * chi)
+    dx = s.grid()["r"][1] - s.grid()["r"][0]
+    nF = n * F
+    work = np.concatenate([[0.0], np.cumsum(0.5 * (nF[1:] + nF[:-1]) * dx)])
+    assert np.ptp(P) > 0.3
+    assert np.ptp(P - work) < 3e-3, (np.ptp(P), np.ptp(P - work))
+
+
+def test_steady_momentum_balance():
+    pin_steady_balance()
+
+
 def test_rejects_non_finite_depth():
     with pytest.raises(ValueError):
         oracle.Solver(channel(phi_a=float("nan"), nr=16))
@@ -352,6 +379,7 @@ MUTANTS = {
     "force term sign (plane)": ((("if (s->Amf) I = m->F * d0;", "if (s->Amf) I = -m->F * d0;"),), "moments plane"),
     "force term sign (curved)": ((("if (s->Amf && !planar) I += m->F * d0;", "if (s->Amf && !planar) I -= m->F * d0;"),),
                                  "moments sphere"),
+    "force term scale": ((("if (s->Amf) I = m->F * d0;", "if (s->Amf) I = 0.5 * m->F * d0;"),), "steady balance"),
     "force on the wrong axis": ((("if (s->Amf && !planar) I += m->F * d0;", "if (s->Amf && !planar) I += m->F * d1;"),),
                                 "moments sphere"),
     "transposed weights": ((("for (int j = 0; j < nr; j++) acc += s->Amf[i * nr + j] * nd[j].n;",
@@ -374,6 +402,8 @@ def _run_pin(kind, lib):
         pin_force_moments(2, 1, lib)
     elif kind == "moments sphere":
         pin_force_moments(1, 0, lib)
+    elif kind == "steady balance":
+        pin_steady_balance(lib)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
