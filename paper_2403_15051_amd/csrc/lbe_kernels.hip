@@ -158,11 +158,12 @@ __device__ inline double dpp_or_old(double old, double x)
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline double reduce_scatter16(const double* v, int lane)
+// Reduce-scatter of 8 per-lane doubles within each half of a wave64: after the call, every lane
+// holds the total over its 32-lane half of value (lane >> 2) & 7.  The steps after the first of
+// reduce_scatter16.
+__device__ inline double reduce_scatter8_halves(const double* r, int lane)
 {
-    double r[8], t[4], u[2];
-#pragma unroll
-    for (int k = 0; k < 8; k++) r[k] = swap32_sum(v[k], v[k + 8]);
+    double t[4], u[2];
 #pragma unroll
     for (int k = 0; k < 4; k++) t[k] = swap16_sum(r[k], r[k + 4]);
     const bool b3 = lane & 8, b2 = lane & 4;
@@ -178,6 +179,14 @@ __device__ inline double reduce_scatter16(const double* v, int lane)
     w += dpp_or_old<0x4e, 0xf>(0.0, w);  // quad_perm [2,3,0,1]
     w += dpp_or_old<0xb1, 0xf>(0.0, w);  // quad_perm [1,0,3,2]
     return w;
+}
+
+__device__ inline double reduce_scatter16(const double* v, int lane)
+{
+    double r[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) r[k] = swap32_sum(v[k], v[k + 8]);
+    return reduce_scatter8_halves(r, lane);
 }
 
 // ------------------------------------------------------------------ state access
@@ -656,10 +665,8 @@ __device__ inline void proj_node(const DevInstance& I, double u, double T, doubl
                     p = pn;
                 }
             }
-            double v[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) v[k] = ((k < 8) == (side == 0)) ? acc[k & 7] : 0.0;
-            const double tot = reduce_scatter16(v, lane);
+            // each half sums its own side's 8 values: lane (lane >> 2) & 15 = 8 side + l holds I_l of the side
+            const double tot = reduce_scatter8_halves(acc, lane);
             const int l = which & 7;
             if ((lane & 3) == 0 && l <= N0) nd[((which >> 3) ? NF_IMINUS : NF_IPLUS) + l] = tot * q[2 * N0 + l];
             return;
