@@ -28,6 +28,9 @@ constexpr int kNodeChunk = 32;  // nodes per node-kernel workgroup
 constexpr int kHalo = 4;        // gradient stencils reach 4 nodes (one-sided at the walls)
 constexpr int kWallBatch = 4;   // velocities per thread and round trip in the node kernel's wall blocks
 constexpr int kMaxNr = 1024;    // largest radial grid (node-kernel LDS)
+// node-kernel LDS buffer: the chunk blocks' densities (kMaxNr) or the wall blocks' three base rows
+// (n0 + n1 + n2 <= 4 kMaxQ values each)
+constexpr int kNodeLds = kMaxNr > 12 * kMaxQ ? kMaxNr : 12 * kMaxQ;
 
 // ------------------------------------------------------------------ helpers
 
@@ -331,6 +334,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     const int nr = I.nr;
     const int nchunks = (nr + kNodeChunk - 1) / kNodeChunk;
     __shared__ double red[16 * 4];
+    __shared__ double sbuf[kNodeLds];
     if (bx >= nchunks + 2) return;
     const int n0 = I.n0, n1 = I.n1;
 
@@ -340,8 +344,8 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         // arithmetic (one dependent round trip per batch instead of per velocity); the leaving
         // velocities of the left wall are those with radial index i0 >= n0/2 (p_r < 0), of the right
         // wall those with i0 < n0/2, so only that half is visited.  Fixed per block: the three rows
-        // next to the wall, their base factors (FP32 storage; the ghost rows share the wall row's)
-        // and the FP32 rows' column grouping; per velocity, its axis indices (multiply-high
+        // next to the wall, their base factors (FP32 storage, staged in LDS; the ghost rows share the
+        // wall row's) and the FP32 rows' column grouping; per velocity, its axis indices (multiply-high
         // quotients) and its place in an FP32 row, the same in every row.
         const int left = bx == nchunks;
         const int hq = n0 >> 1, nhalf = I.nv >> 1, nv = I.nv, n01 = n0 + n1;
@@ -350,8 +354,15 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         const int g = f32 ? f32_group(hq, nv / n0) : 1, lg = __builtin_ctz(g);
         double* fd = I.f[src];
         float* ff = (float*)I.f[src];
-        const double* bw[3];
-        for (int k = 0; k < 3; k++) bw[k] = f32 ? base_row(I, bsrc, r0 + k * dr1) : nullptr;
+        const int nb = n01 + I.n2;
+        if (f32) {
+            for (int k = threadIdx.x; k < 3 * nb; k += kBlock) {
+                const int row = k / nb;
+                sbuf[k] = base_row(I, bsrc, r0 + row * dr1)[k - row * nb];
+            }
+            __syncthreads();
+        }
+        const double* bw[3] = {sbuf, sbuf + nb, sbuf + 2 * nb};
         const FastDiv dhq(hq), dn0(n0), dn1(n1);
         // place of velocity i0 + n0 col in an FP32 row (f32_slot with g a power of two)
         auto slot = [&](int i0, int col) {
@@ -450,7 +461,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     __shared__ double sT[kNodeChunk + 2 * kHalo], su[3][kNodeChunk + 2 * kHalo];
     __shared__ double sG1[kNodeChunk + 2 * kHalo], sG2[kNodeChunk + 2 * kHalo], schi[kNodeChunk + 2 * kHalo];
     __shared__ Macro smac[kNodeChunk];
-    __shared__ double sdens[kMaxNr];
+    double* const sdens = sbuf;
     __shared__ double snb[kNodeChunk + 2 * kHalo], sphi[kNodeChunk + 2 * kHalo];
     // densities (slice sums) of the nodes the band of W reaches from the chunk + halo (wlo is
     // nondecreasing; every node with attraction), then the averaged density of the chunk + halo,
