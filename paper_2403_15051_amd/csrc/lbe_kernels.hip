@@ -607,9 +607,20 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
         nd[NF_PHI] = attract ? sphi[li] : 0.0;
         nd[NF_FR] = attract ? -g(sphi) : 0.0;
         if (!(n > 0) || !(T > 0) || !isfinite(n) || !isfinite(T)) I.flags[0] = 1;
-        // equilibrium coefficients of the full-range axes (eq. (eq_gak_H))
-        full_coeffs<kMaxN>(m.u[1], T, I.N1, nd + NF_C1);
-        full_coeffs<kMaxN>(m.u[2], T, I.N2, nd + NF_C2);
+    }
+    // equilibrium coefficients of the full-range axes (eq. (eq_gak_H)): waves 1 and 2, beside wave 0's
+    // node coefficients above
+    {
+        const int wv = threadIdx.x >> 6;
+        if (wv == 1 || wv == 2)
+            for (int k = threadIdx.x & 63; k < c1 - c0; k += 64) {
+                const Macro& m = smac[k];
+                double* nd = I.node + (size_t)(c0 + k) * kNodeStride;
+                if (wv == 1)
+                    full_coeffs<kMaxN>(m.u[1], m.T, I.N1, nd + NF_C1);
+                else
+                    full_coeffs<kMaxN>(m.u[2], m.T, I.N2, nd + NF_C2);
+            }
     }
     // half-range projection coefficients of the chunk's nodes (Sec. III.C) for expansion orders
     // N0 < 8, one wave per node at the node's u_r and T (in LDS since the barrier above), as k_proj
