@@ -42,15 +42,20 @@ def kernel_sha() -> str:
     return hashlib.sha256(text[a:b].encode()).hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, algorithmic_bytes: float):
     """Bytes per stage launch from the committed counter measurement, or None when the kernel
-    source has changed since (or no measurement exists)."""
+    source has changed since, the measurement is of another workload (its algorithmic bytes per
+    launch differ from this run's), or no measurement exists."""
     try:
         with open(TRAFFIC_FILES[precision]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    return t["traffic_bytes_per_launch"] if t.get("kernel_source_sha256") == kernel_sha() else None
+    if t.get("kernel_source_sha256") != kernel_sha():
+        return None
+    if abs(t.get("algorithmic_bytes_per_launch", -1.0) - algorithmic_bytes) > 1e-9 * algorithmic_bytes:
+        return None
+    return t["traffic_bytes_per_launch"]
 
 
 def copy_calibration(nbytes: int, reps: int) -> None:
@@ -414,7 +419,7 @@ def main():
                    "tiles": ([{"nv": r["nv"], "tile_nodes": r["tile_nodes"]} for r in tuned] if tuned else "default"),
                    "parallelism": "single GPU, instances batched per launch"},
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision, bytes_per_launch),
                      "stage_ms_avg": stage_avg_s * 1e3, "node_ms_avg": tm["node_ms"] / max(1, tm["node_launches"]),
                      "stage_share_of_step": tm["stage_ms"] / ((t3 - t2) * 1e3),
                      "ms_per_step_eager_timed": (t3 - t2) * 1e3 / args.steps},
