@@ -610,6 +610,7 @@ __global__ void __launch_bounds__(kBlock) k_node(const DevInstance* __restrict__
     }
     // equilibrium coefficients of the full-range axes (eq. (eq_gak_H)): waves 1 and 2, beside wave 0's
     // node coefficients above
+    static_assert(kBlock / 64 >= 3, "the node kernel puts the two full-range axes on waves 1 and 2");
     {
         const int wv = threadIdx.x >> 6;
         if (wv == 1 || wv == 2)
